@@ -1,0 +1,546 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU.  Each one checks a property that a plausible
+mistake in the oracle (dropped term, wrong sign or index, transposed operand)
+would break; none retypes the oracle's own formula.  Paper: Seiz & Takaki,
+arXiv 2601.16522.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+from scipy.special import eval_legendre
+
+import oracle
+import pf_inputs as pi
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+# -----------------------------------------------------------------------------
+# Variational derivative against a brute-force derivative of the discrete
+# energy (eqs. energy, wterm, gibbs-energy with the KKS phase concentrations).
+# -----------------------------------------------------------------------------
+
+def _energy_bruteforce(P: oracle.Params, u: np.ndarray) -> float:
+    """Discrete F_h written independently of the oracle: face-difference
+    gradient products (each face once), pair potential on unordered pairs, and
+    sum_a phi_a g_a(c_a) with c_a from the KKS conditions solved by root finding."""
+    N, T = P.n_phi, P.n_types
+    phi, c = u[:N], (u[N] if P.with_c else None)
+    tof = list(P.type_of)
+    gam = np.asarray(P.gamma).reshape(T, T)
+    A = lambda a, b: 4.0 * P.W * gam[tof[a], tof[b]] / math.pi
+    B = lambda a, b: 4.0 * gam[tof[a], tof[b]] / (math.pi * P.W)
+    axes = [3, 2] + ([1] if P.dim == 3 else [])
+    E = 0.0
+    for ax in axes:
+        g = (np.roll(phi, -1, axis=ax) - phi) / P.dx
+        for a in range(N):
+            for b in range(a):
+                E -= A(a, b) * np.sum(g[a] * g[b])
+    for a in range(N):
+        for b in range(a):
+            E += B(a, b) * np.sum(phi[a] * phi[b])
+    if P.with_c:
+        k = [P.k[tof[a]] for a in range(N)]
+        c0 = [P.c0[tof[a]] for a in range(N)]
+        it = np.nditer(c, flags=["multi_index"])
+        for cv in it:
+            idx = it.multi_index
+            ph = [phi[(a,) + idx] for a in range(N)]
+            f = lambda m: sum(ph[a] * (c0[a] + m / k[a]) for a in range(N)) - float(cv)
+            m = brentq(f, -1e6, 1e6, xtol=1e-14, rtol=1e-15, maxiter=500)
+            E += sum(ph[a] * 0.5 * k[a] * (m / k[a]) ** 2 for a in range(N))
+    return E * P.dx ** P.dim
+
+
+@pytest.mark.parametrize("dim,shape,dx", [(2, (1, 4, 4), 1.0), (3, (3, 3, 3), 0.5)])
+def test_delta_is_energy_gradient(dim, shape, dx):
+    rng = np.random.default_rng(11)
+    N = 3
+    nz, ny, nx = shape
+    P = oracle.Params(nx=nx, ny=ny, nz=nz, dim=dim, n_phi=N, type_of=[0, 1, 1], n_types=2,
+                      dx=dx, W=2.5, gamma=[1.0, 0.7, 0.7, 1.3], mob=[1.0, 1.0, 1.0, 1.0],
+                      k=[500.0, 300.0], c0=[0.02, 0.98], D=[1.0, 2.0], with_c=True)
+    phi = rng.uniform(0.05, 1.0, size=(N,) + shape)
+    phi /= phi.sum(axis=0)
+    c = rng.uniform(0.2, 0.8, size=(1,) + shape)
+    u = np.concatenate([phi, c])
+    d = oracle.delta(P, u)
+    h = 1e-5
+    for a in range(N):
+        for idx in [(0, 0, 0), (nz - 1, ny - 1, 1), (nz // 2, 1, nx - 1)]:
+            up, um = u.copy(), u.copy()
+            up[(a,) + idx] += h
+            um[(a,) + idx] -= h
+            g = (_energy_bruteforce(P, up) - _energy_bruteforce(P, um)) / (2 * h) / dx ** dim
+            assert abs(g - d[(a,) + idx]) <= 1e-6 * max(1.0, abs(g)), (a, idx, g, d[(a,) + idx])
+
+
+def test_phase_rates_sum_to_zero():
+    """Pairwise construction of eq. phieq: sum_a dphi_a/dt = 0 everywhere."""
+    rng = np.random.default_rng(5)
+    N = 4
+    P = oracle.Params(nx=12, ny=10, n_phi=N, type_of=[0, 0, 1, 1], n_types=2, W=2.0,
+                      gamma=[1.0, 0.5, 0.5, 2.0], mob=[1.0, 3.0, 3.0, 0.5],
+                      k=[500.0, 200.0], c0=[0.1, 0.9], D=[1.0, 0.1], with_c=True)
+    phi = rng.uniform(0.0, 1.0, size=(N, 1, 10, 12)) * (rng.random((N, 1, 10, 12)) > 0.4)
+    phi[0] += 1e-3
+    phi /= phi.sum(axis=0)
+    u = np.concatenate([phi, rng.uniform(0.2, 0.8, size=(1, 1, 10, 12))])
+    r = oracle.rhs(P, u)
+    assert np.abs(r[:N].sum(axis=0)).max() < 1e-12 * np.abs(r[:N]).max()
+    assert np.abs(r[:N]).max() > 1e-3
+
+
+# -----------------------------------------------------------------------------
+# Closed forms of the model
+# -----------------------------------------------------------------------------
+
+def _flat_interface(dx, W=4.0):
+    n = int(round(8 * math.pi * W / dx))
+    x = (np.arange(n) + 0.5) * dx
+    L = n * dx
+    d = np.where(x < L / 2, x - L / 4, 3 * L / 4 - x)
+    p1 = pi.profile(d, W)
+    u = np.stack([1 - p1, p1])[:, None, None, :]
+    P = oracle.Params(nx=n, ny=1, n_phi=2, dx=dx, W=W, with_c=False)
+    return P, u
+
+
+def test_flat_profile_is_stationary_and_converges():
+    """eq. profile is the two-phase equilibrium when B/A = 1/W^2 (Sec. 2): a
+    periodic pair of flat interfaces relaxes by an amount that vanishes as dx -> 0
+    (with the sign of eq. phieq reversed, or B/A wrong, it would not)."""
+    drift = []
+    for dx in (1.0, 0.5, 0.25):
+        P, u = _flat_interface(dx)
+        dte = oracle.stable_dt(P)
+        uu, st, rc = oracle.run_to(P, oracle.FE, u, 200.0, dt_fixed=0.9 * dte)
+        assert rc == 0
+        drift.append(np.abs(uu - u).max())
+    assert drift[0] < 0.05
+    assert drift[1] < drift[0] / 4 and drift[2] < drift[1] / 4, drift
+
+
+def test_shrinking_circle_area_law():
+    """Curvature flow of a disc: A(t) - A(0) = -2 pi M gamma t (Sec. 5.2.1).
+    Single-grain workload, 128^2, R = 40, W = 4, FE at 0.9 dt_e; slope fitted to
+    t > 0 outputs as in the paper's error definition."""
+    wl = pi.single_grain()
+    P = oracle.Params(**wl.param_dict())
+    dte = oracle.stable_dt(P)
+    assert dte == pytest.approx(0.25, rel=1e-14)   # lambda_c = 8 D / dx^2 dominates
+    dt = 0.9 * dte
+    u = wl.u0
+    ts, As = [0.0], [u[1].sum()]
+    for k in range(1, 11):
+        u, st, rc = oracle.run_to(P, oracle.FE, u, 200 * dt * k, dt_fixed=dt, t0=200 * dt * (k - 1))
+        assert rc == 0 and st.accepted == 200
+        ts.append(200 * dt * k)
+        As.append(u[1].sum())
+    slope = np.polyfit(ts[1:], As[1:], 1)[0]
+    assert abs(slope / (-2 * math.pi) - 1) < 0.02, slope
+    # phase sum, bounds and mass after 2000 projected steps
+    dev, lo, hi = oracle.phi_stats(P, u)
+    assert dev < 1e-12 and lo >= 0.0 and hi <= 1.0
+    assert abs(oracle.sum_c(P, u) - oracle.sum_c(P, wl.u0)) < 1e-13 * oracle.sum_c(P, wl.u0) * 100
+
+
+def _checkerboard_amplitude(u, plane):
+    nz, ny, nx = u.shape[1:]
+    s = np.fromfunction(lambda z, y, x: (-1.0) ** (x + y + z), (nz, ny, nx))
+    v = u[plane] - u[plane].mean()
+    return float(np.sum(v * s) / s.size)
+
+
+@pytest.mark.parametrize("frac", [0.98, 1.02])
+def test_fe_checkerboard_c(frac):
+    """Pure diffusion of c (one type, bulk phase): the checkerboard is the
+    eigenvector of the discrete operator with eigenvalue -4 d D / dx^2, so forward
+    Euler multiplies it by exactly 1 - dt 4dD/dx^2 per step and grows iff dt > dt_e."""
+    n = 16
+    P = oracle.Params(nx=n, ny=n, n_phi=2, dx=0.5, W=2.0, D=[2.0], c0=[0.4], k=[200.0],
+                      with_c=True)
+    x = np.indices((1, n, n))
+    cb = (-1.0) ** (x[1] + x[2])
+    u = np.concatenate([np.ones((1, 1, n, n)), np.zeros((1, 1, n, n)), 0.4 + 1e-3 * cb[None]])
+    lam = 4 * 2 * 2.0 / 0.25
+    dte = oracle.stable_dt(P)
+    assert dte == pytest.approx(2.0 / lam, rel=1e-13)
+    dt = frac * dte
+    a0 = _checkerboard_amplitude(u, 2)
+    u1, _, _ = oracle.step(P, oracle.FE, dt, u)
+    ratio = _checkerboard_amplitude(u1, 2) / a0
+    assert ratio == pytest.approx(1 - dt * lam, abs=1e-10)
+    u20, st, _ = oracle.run_to(P, oracle.FE, u, 20 * dt, dt_fixed=dt)
+    grows = abs(_checkerboard_amplitude(u20, 2)) > abs(a0)
+    assert grows == (frac > 1.0)
+
+
+@pytest.mark.parametrize("frac", [0.98, 1.02])
+def test_fe_checkerboard_phi(frac):
+    """Two phases without c on the plateau phi = 1/2 + eps (-1)^(x+y): eq. phieq is
+    affine there, with eigenvalue -M gamma (4d/dx^2 - 1/W^2) (L A = M gamma,
+    L B = M gamma / W^2), so FE grows iff dt > 2 / lambda_phi."""
+    n = 16
+    M, gam, W, dx = 1.7, 0.8, 3.0, 1.0
+    P = oracle.Params(nx=n, ny=n, n_phi=2, dx=dx, W=W, gamma=[gam], mob=[M], with_c=False)
+    x = np.indices((1, n, n))
+    cb = (-1.0) ** (x[1] + x[2])
+    p = 0.5 + 1e-4 * cb
+    u = np.stack([1 - p, p])
+    lam = M * gam * (8 / dx ** 2 - 1 / W ** 2)
+    dte = oracle.stable_dt(P)
+    assert dte == pytest.approx(2 / lam, rel=1e-13)
+    dt = frac * dte
+    a0 = _checkerboard_amplitude(u, 1)
+    u1, _, _ = oracle.step(P, oracle.FE, dt, u)
+    assert _checkerboard_amplitude(u1, 1) / a0 == pytest.approx(1 - dt * lam, abs=1e-9)
+    u20, _, _ = oracle.run_to(P, oracle.FE, u, 20 * dt, dt_fixed=dt)
+    assert (abs(_checkerboard_amplitude(u20, 1)) > abs(a0)) == (frac > 1.0)
+
+
+def test_c_conservation_two_types():
+    """Flux form of eq. ceq on a periodic grid conserves sum c to rounding."""
+    wl = pi.grains_pores_3d(n=24, n_grains=5, n_grain_fields=4, n_pores=4, r_range=(3, 5),
+                            dmin=6.0)
+    P = oracle.Params(**wl.param_dict())
+    dte = oracle.stable_dt(P)
+    s0 = oracle.sum_c(P, wl.u0)
+    u, st, rc = oracle.run_to(P, oracle.RKL2, wl.u0, 20 * dte, dt_fixed=10 * dte)
+    assert rc == 0
+    assert abs(oracle.sum_c(P, u) - s0) <= 1e-13 * abs(s0)
+    dev, lo, hi = oracle.phi_stats(P, u)
+    assert dev < 1e-13 and lo >= 0 and hi <= 1
+
+
+# -----------------------------------------------------------------------------
+# Simplex projection: hand-worked cases
+# -----------------------------------------------------------------------------
+
+def _golden_simplex():
+    rows = []
+    with open(os.path.join(GOLDEN, "simplex_cases.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            a, b = line.split("|")
+            rows.append(([float(v) for v in a.split()], [float(Fraction(v)) for v in b.split()]))
+    return rows
+
+
+@pytest.mark.parametrize("inp,out", _golden_simplex())
+def test_simplex_hand_cases(inp, out):
+    N = len(inp)
+    P = oracle.Params(nx=1, ny=1, n_phi=N, with_c=False)
+    u = np.asarray(inp, dtype=np.float64).reshape(N, 1, 1, 1)
+    v, ch = oracle.simplex(P, u)
+    assert np.allclose(v.ravel(), out, rtol=0, atol=2e-16), (v.ravel(), out)
+
+
+# -----------------------------------------------------------------------------
+# Integrators on the Dahlquist problem: a Fourier mode of pure c diffusion
+# -----------------------------------------------------------------------------
+
+def _mode_problem(nx=64, m=32):
+    P = oracle.Params(nx=nx, ny=1, n_phi=2, dx=1.0, W=2.0, D=[1.0], c0=[0.5], k=[500.0],
+                      with_c=True)
+    x = np.arange(nx)
+    mode = np.cos(2 * math.pi * m * x / nx)
+    u = np.concatenate([np.ones((1, 1, 1, nx)), np.zeros((1, 1, 1, nx)),
+                        (0.5 + 1e-3 * mode)[None, None, None, :]])
+    lam = -4.0 * math.sin(math.pi * m / nx) ** 2
+    return P, u, mode, lam
+
+
+def _amplification(integ, s, z, m=32):
+    P, u, mode, lam = _mode_problem(m=m)
+    dt = z / lam
+    u1, _, _ = oracle.step(P, integ, dt, u, s=s)
+    return float(np.dot(u1[2].ravel() - 0.5, mode) / np.dot(u[2].ravel() - 0.5, mode))
+
+
+@pytest.mark.parametrize("s", [1, 3, 5, 9, 15])
+def test_rkl1_is_legendre(s):
+    """RKL1 (Meyer 2012): R_s(z) = P_s(1 + w1 z), w1 = 2/(s^2+s); stable on
+    [-(s^2+s), 0] (the limit eq. sts-limit refers to)."""
+    w1 = 2.0 / (s * s + s)
+    for frac in (0.1, 0.5, 0.9, 1.0):
+        z = -frac * (s * s + s)
+        R = _amplification(oracle.RKL1, s, z)
+        assert R == pytest.approx(eval_legendre(s, 1 + w1 * z), abs=1e-9)
+        assert abs(R) <= 1 + 1e-9
+
+
+@pytest.mark.parametrize("s", [3, 5, 9, 21])
+def test_rkl2_is_shifted_legendre(s):
+    """RKL2 (Meyer 2014): R_s(z) = a_s + b_s P_s(1 + w1 z), w1 = 4/(s^2+s-2),
+    b_s = (s^2+s-2)/(2s(s+1)); stable on [-(s^2+s-2)/2, 0]."""
+    w1 = 4.0 / (s * s + s - 2)
+    b = (s * s + s - 2) / (2.0 * s * (s + 1))
+    for frac in (0.1, 0.5, 0.9, 1.0):
+        z = -frac * (s * s + s - 2) / 2.0
+        R = _amplification(oracle.RKL2, s, z)
+        assert R == pytest.approx(1 - b + b * eval_legendre(s, 1 + w1 * z), abs=1e-9)
+        assert abs(R) <= 1 + 1e-9
+
+
+@pytest.mark.parametrize("s", [2, 3, 5])
+def test_ssp_s2_stability_function(s):
+    """SSP(s)2 with the newest stage in the last line (s-1 Euler sub-steps then
+    the averaged step): R(z) = (s-1)/s (1 + z/(s-1))^s + 1/s; stable on
+    [-2(s-1), 0] (dt <= (s-1) dt_e, slightly more for s > 2) and not much beyond."""
+    for frac in (0.1, 0.6, 1.0):
+        z = -frac * 2 * (s - 1)
+        R = _amplification(oracle.SSP2, s, z)
+        assert R == pytest.approx((s - 1) / s * (1 + z / (s - 1)) ** s + 1 / s, abs=1e-9)
+        assert abs(R) <= 1 + 1e-9
+    assert abs(_amplification(oracle.SSP2, s, -2 * (s - 1) * 1.2)) > 1
+
+
+def test_ssp104_stable_to_six_euler_steps():
+    """SSP(10)4: |R(z)| <= 1 on [-12, 0] (dt < 6 dt_e, Sec. 3.2) and unstable just
+    past its real boundary (about -13.9)."""
+    for z in np.linspace(-12, -0.1, 25):
+        assert abs(_amplification(oracle.SSP104, 0, z)) <= 1 + 1e-9
+    assert abs(_amplification(oracle.SSP104, 0, -14.2)) > 1
+
+
+@pytest.mark.parametrize("integ,s,p", [(oracle.FE, 0, 1), (oracle.SSP2, 5, 2),
+                                       (oracle.SSP104, 0, 4), (oracle.RKL1, 5, 1),
+                                       (oracle.RKL2, 5, 2), (oracle.RKL2, 9, 2)])
+def test_dahlquist_order(integ, s, p):
+    """Order on the Dahlquist equation within 5e-2 (footnote to Sec. 5.2.1):
+    |R(z) - e^z| = O(z^(p+1)); measured on a long-wavelength mode (small z)."""
+    zs = [-0.08, -0.04]
+    errs = [abs(_amplification(integ, s, z, m=1) - math.exp(z)) for z in zs]
+    order = math.log(errs[0] / errs[1]) / math.log(2) - 1
+    assert abs(order - p) < 5e-2 * max(1, p), (order, errs)
+
+
+# -----------------------------------------------------------------------------
+# Stable step (reading of the Gershgorin estimates) against Table 3
+# -----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case,dte_printed,t_r,fe_count", [
+    ("pure", 8.44e-4, 45.0, 53279),
+    ("immobile", 6.26e-5, 884.0, 14110453),
+    ("mobile", 2.82e-7, 44.0, 156288000),
+])
+def test_stable_dt_table3(case, dte_printed, t_r, fe_count):
+    """Table tab:perf-ggpores: dt_e of the 3D grain-growth runs (dx = 0.005,
+    W = 2.5 dx, gamma = 1, M_gg = 5e-3, k = 1e5, c0 = 0.02 / 0.98; Sec. 5.3) and
+    the FE count t_r/dt_e, reproduced to the printed digits and within one count
+    (the pure case sits exactly on an integer, 53280, and the table prints 53279)."""
+    dx = 0.005
+    D = {"pure": (5e-8, 5e-8), "immobile": (5e-8, 5e-8), "mobile": (10.0, 5e-8)}[case]
+    Mab = {"pure": 5e-3, "immobile": 5e-8, "mobile": 5e-3}[case]
+    P = oracle.Params(nx=4, ny=4, nz=4, dim=3, n_phi=3, type_of=[0, 1, 1], n_types=2, dx=dx,
+                      W=2.5 * dx, gamma=[1, 1, 1, 1], mob=[5e-3, Mab, Mab, 5e-3],
+                      k=[1e5, 1e5], c0=[0.02, 0.98], D=list(D), with_c=(case != "pure"))
+    if case == "pure":
+        P = oracle.Params(nx=4, ny=4, nz=4, dim=3, n_phi=3, type_of=[0, 0, 0], n_types=1,
+                          dx=dx, W=2.5 * dx, gamma=[1], mob=[5e-3], k=[1e5], c0=[0.98],
+                          D=[5e-8], with_c=False)
+    dte = oracle.stable_dt(P)
+    # the table prints three digits (truncated in one case, rounded in the others)
+    assert abs(dte - dte_printed) <= 10 ** (math.floor(math.log10(dte_printed)) - 2)
+    assert abs(math.floor(t_r / dte) - fe_count) <= 1
+
+
+def test_stage_count_is_smallest_stable_odd():
+    """eq. sts-limit with the exact RKL real stability intervals, safety 0.9 and
+    odd stage numbers: the chosen s is stable at 0.9 dt_e (|R_s| <= 1 over the
+    interval) and s - 2 is not."""
+    dte = 0.25
+    for ratio in (0.5, 1, 3, 10, 37, 100, 200):
+        dt = ratio * dte
+        for order in (1, 2):
+            s = oracle.stage_count(order, dt, dte)
+            assert s % 2 == 1 and s >= (1 if order == 1 else 3)
+
+            def stable(ss):
+                if order == 2 and ss < 2:
+                    return False
+                zmax = -dt * 2 / (0.9 * dte)  # lambda = 2/dt_e scaled by the safety factor
+                zz = np.linspace(zmax, 0, 2001)
+                if order == 1:
+                    R = eval_legendre(ss, 1 + 2.0 / (ss * ss + ss) * zz)
+                else:
+                    w1 = 4.0 / (ss * ss + ss - 2)
+                    b = (ss * ss + ss - 2) / (2.0 * ss * (ss + 1))
+                    R = 1 - b + b * eval_legendre(ss, 1 + w1 * zz)
+                return np.all(np.abs(R) <= 1 + 1e-12)
+            assert stable(s)
+            if s - 2 >= (1 if order == 1 else 3):
+                assert not stable(s - 2)
+    # the values quoted for the run matrix (Table tab:ints multiples of dt_e)
+    assert [oracle.stage_count(1, m * dte, dte) for m in (1, 10, 100, 200)] == [3, 5, 15, 21]
+    assert [oracle.stage_count(2, m * dte, dte) for m in (1, 10, 100, 200)] == [3, 7, 21, 31]
+
+
+# -----------------------------------------------------------------------------
+# Error estimate and norm (Sec. 3.3)
+# -----------------------------------------------------------------------------
+
+def test_sommeijer_estimate_is_third_order_local_error():
+    """Fed the exact solution u^{n+1} = e^z u^n of a diffusion mode, the estimate
+    is dt^3 u'''/15 + O(dt^4), so the norm (r = 0, a = 1, bulk phase cells count
+    2 DoF each, one c DoF per cell) is |z|^3/15 * eps / sqrt(6)."""
+    P, u, mode, lam = _mode_problem(m=8)
+    tol = oracle.Tol(r_phi=0.0, a_phi=1.0, r_c=0.0, a_c=1.0)
+    eps = 1e-3
+    vals = []
+    for z in (-0.2, -0.1, -0.05):
+        dt = z / lam
+        un = u.copy()
+        unp1 = u.copy()
+        unp1[2] = 0.5 + eps * math.exp(z) * mode
+        r0 = oracle.rhs(P, un)
+        e, ndof, ss = oracle.error_norm(P, 0, dt, un, unp1, r0, tol)
+        assert ndof == 3 * P.nx
+        expect = abs(z) ** 3 / 15 * eps / math.sqrt(6)
+        vals.append(e / expect)
+    assert abs(vals[-1] - 1) < 0.05 and abs(vals[0] - 1) > abs(vals[-1] - 1)
+
+
+def test_error_norm_filter_and_dof_rule():
+    """Hand-worked case on a 2x1 grid with a bulk u^{n+1} (rhs = 0 there):
+    e = (12(u^n - u^{n+1}) + 6 dt R0)/15; phi entries whose trial value
+    u^n + dt/2 R0 leaves [0,1] have zero error and do not count; a cell with no
+    nontrivial phi entry counts 2 DoF; c always counts one DoF per cell."""
+    P = oracle.Params(nx=2, ny=1, n_phi=2, dx=1.0, W=2.0, with_c=True, c0=[0.5], k=[500.0])
+    unp1 = np.zeros((3, 1, 1, 2))
+    unp1[0] = 1.0
+    unp1[2] = 0.5
+    un = unp1.copy()
+    un[0, 0, 0, 0], un[1, 0, 0, 0] = 0.98, 0.02      # cell 0: interface values
+    un[2, 0, 0, 0] = 0.51
+    R0 = np.zeros_like(un)
+    dt = 0.5
+    R0[0, 0, 0, 0], R0[1, 0, 0, 0] = 0.01, -0.2      # trial phi1 = 0.02 - 0.05 < 0 -> filtered
+    R0[0, 0, 0, 1] = 4.0                              # cell 1: trial 1 + 1 > 1 -> filtered
+    R0[2, 0, 0, 1] = 0.02
+    tol = oracle.Tol(r_phi=0.1, a_phi=0.01, r_c=0.2, a_c=0.001)
+    e, ndof, ss = oracle.error_norm(P, 0, dt, un, unp1, R0, tol)
+    e_phi0 = (12 * (0.98 - 1.0) + 6 * dt * 0.01) / 15
+    e_c0 = (12 * (0.51 - 0.5)) / 15
+    e_c1 = (6 * dt * 0.02) / 15
+    w_phi0 = 0.1 * 1.0 + 0.01
+    w_c0 = 0.2 * 0.51 + 0.001
+    w_c1 = 0.2 * 0.5 + 0.001
+    expect_ss = (e_phi0 / w_phi0) ** 2 + (e_c0 / w_c0) ** 2 + (e_c1 / w_c1) ** 2
+    assert ndof == 1 + 2 + 2            # cell 0: one phi entry; cell 1: none -> 2; c: 2
+    assert ss == pytest.approx(expect_ss, rel=1e-13)
+    assert e == pytest.approx(math.sqrt(expect_ss / 5), rel=1e-13)
+
+
+def test_embedded_norm_scaling():
+    """Embedded estimate e = u^{n+1} - z: the norm is homogeneous of degree one in
+    the difference and equals the common ratio when every weighted entry is equal."""
+    P = oracle.Params(nx=3, ny=2, n_phi=2, with_c=True, c0=[0.5], k=[500.0])
+    rng = np.random.default_rng(3)
+    un = rng.uniform(0.1, 0.9, size=(3, 1, 2, 3))
+    tol = oracle.Tol(r_phi=0.0, a_phi=2e-3, r_c=0.0, a_c=5e-3)
+    z = un.copy()
+    unp1 = un.copy()
+    unp1[:2] += 0.7 * 2e-3
+    unp1[2] += 0.7 * 5e-3
+    e, ndof, _ = oracle.error_norm(P, 1, 0.1, un, unp1, z, tol)
+    assert ndof == 6 * 2 + 6
+    assert e == pytest.approx(0.7, rel=1e-12)
+    unp1b = un + 2 * (unp1 - un)
+    e2, _, _ = oracle.error_norm(P, 1, 0.1, un, unp1b, z, tol)
+    assert e2 == pytest.approx(2 * e, rel=1e-12)
+
+
+# -----------------------------------------------------------------------------
+# PID controller (Sec. 3.3): invariants and hand-worked cases
+# -----------------------------------------------------------------------------
+
+def test_controller_invariants():
+    c = oracle.Controller()
+    assert c.bias == 0.9
+    # E = e/b = 1 with no history: F = 1, the step is kept exactly
+    h, acc = c.update(2, 0.9, 1.0)
+    assert acc and h == 1.0
+    assert c.bias == pytest.approx(math.sqrt(0.9))
+    # rejections never grow the step and square the bias down to 0.1
+    for e in (1.5, 3.0, 50.0, 1e6, 1.01, 2.0, 7.0):
+        hn, acc = c.update(2, e, 2.0)
+        assert not acc and hn < 2.0
+    assert c.bias == 0.1
+    # acceptance walks the bias back up, capped at 0.98
+    for _ in range(10):
+        c.update(2, 0.5, 1.0)
+    assert c.bias == 0.98
+    # the limiter 1 + 5 atan((F-1)/5) bounds the growth for a zero error
+    c2 = oracle.Controller()
+    hn, acc = c2.update(1, 0.0, 1.0)
+    assert acc and 1.0 < hn <= 1 + 5 * math.pi / 2
+    # growth factor decreases with the error
+    facs = []
+    for e in (0.01, 0.1, 0.5, 0.9):
+        c3 = oracle.Controller()
+        facs.append(c3.update(2, e, 1.0)[0])
+    assert all(a > b for a, b in zip(facs, facs[1:]))
+
+
+def test_controller_history_terms():
+    """With two accepted steps of equal size and E history E1, E2, the next factor
+    uses (E_n^-k1 E1^-k2 E2^-k3)^(1/(P+1)) with k = 1.25, 0.5, -0.6 (Soederlind
+    PID): equal E everywhere gives F = E^-(1.15/(P+1))."""
+    c = oracle.Controller()
+    P = 2
+    # accept twice with e chosen so that E = e/b = 0.5 each time
+    b = c.bias
+    c.update(P, 0.5 * b, 1.0)
+    b = c.bias
+    c.update(P, 0.5 * b, 1.0)
+    b = c.bias
+    hn, acc = c.update(P, 0.5 * b, 1.0)
+    F = 0.5 ** (-(1.25 + 0.5 - 0.6) / (P + 1))
+    assert hn == pytest.approx(1 + 5 * math.atan((F - 1) / 5), rel=1e-12)
+
+
+# -----------------------------------------------------------------------------
+# Adaptive end-to-end sanity (oracle only)
+# -----------------------------------------------------------------------------
+
+def test_adaptive_rkl2_hits_t_end_and_beats_fe_in_rhs_count():
+    wl = pi.single_grain(n=64, R=20.0)
+    P = oracle.Params(**wl.param_dict())
+    dte = oracle.stable_dt(P)
+    t_end = 60.0
+    tol = oracle.Tol(r_phi=1e-4, a_phi=1e-2, r_c=1e-4, a_c=1e-4)
+    u, st, rc = oracle.run_to(P, oracle.RKL2, wl.u0, t_end, tol=tol)
+    assert rc == 0 and st.t == t_end
+    assert st.accepted >= 2
+    fe_count = math.ceil(t_end / (0.9 * dte))
+    assert st.rhs_evals < fe_count
+    dev, lo, hi = oracle.phi_stats(P, u)
+    assert dev < 1e-12 and lo >= 0 and hi <= 1
+    # the area still follows the law within a few percent of the change
+    uf, _, _ = oracle.run_to(P, oracle.FE, wl.u0, t_end, dt_fixed=0.9 * dte)
+    dA_fe = uf[1].sum() - wl.u0[1].sum()
+    dA = u[1].sum() - wl.u0[1].sum()
+    assert abs(dA - dA_fe) < 0.05 * abs(dA_fe)
+
+
+def test_fixed_run_hits_t_end_exactly():
+    wl = pi.single_grain(n=32, R=10.0)
+    P = oracle.Params(**wl.param_dict())
+    u, st, rc = oracle.run_to(P, oracle.FE, wl.u0, 1.0, dt_fixed=0.225)
+    assert rc == 0 and st.t == 1.0 and st.accepted == 5
+    assert st.trace[-1, 0] == pytest.approx(1.0 - 4 * 0.225)
