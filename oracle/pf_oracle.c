@@ -358,7 +358,7 @@ static void step_ssp2(const pfo_params *P, int s, double dt, double *u, double *
     for (int i = 1; i <= s - 1; ++i) {
         pfo_rhs(P, q1, r);
         st->rhs_evals++; st->stages++;
-        for (long long e = 0; e < n; ++e) q3[e] = q1[e] + dt * r[e] / (s - 1);
+        for (long long e = 0; e < n; ++e) q3[e] = q1[e] + dt / (s - 1) * r[e];
         project(P, q3);
         double *tmp = q1; q1 = q3; q3 = tmp;
     }
