@@ -1,0 +1,203 @@
+/*
+ * pf.h -- C-ABI of libpf, an MI355X (gfx950) implementation of the explicit
+ * method-of-lines time step for coupled multi-phase-field + concentration
+ * models (Seiz & Takaki, "Numerical efficiency of explicit time integrators
+ * for phase-field models", arXiv 2601.16522).
+ *
+ * The model (Sec. 2): N order parameters phi_a on the simplex, evolved by the
+ * pairwise multi-phase Allen-Cahn equation with an obstacle potential
+ * (eq. phieq), and one concentration c evolved by the KKS diffusion equation
+ * with parabolic Gibbs energies (eqs. ceq, gibbs-energy).  Space: second-order
+ * finite differences on a periodic, cell-centred Cartesian grid (Sec. 3).
+ * Time: forward Euler, SSP(s)2, SSP(10)4, RKL1, RKL2 (Sec. 3.2), with the
+ * simplex projection after every stage, and adaptive RKL/SSP steps with the
+ * error estimates, norm and PID controller of Sec. 3.3.
+ *
+ * Field layout everywhere (host and device): a state vector is F = n_phi +
+ * with_c planes of V = nx*ny*nz values, plane a < n_phi is phi_a, plane
+ * n_phi is c; inside a plane x is fastest, then y, then z.  Host arrays are
+ * always double; device arrays use the handle's precision (double for
+ * PF_FP64, float for PF_FP32).
+ *
+ * Errors: every call returns a pf_status; a negative value is a failure and
+ * leaves the state unchanged, except PF_ENONFINITE and PF_EDTMIN, which leave
+ * the last accepted state.  pf_last_error() gives a message valid until the
+ * next call on the same handle.
+ * Ownership: the handle owns its device memory; host pointers are borrowed for
+ * the duration of a call; device pointers passed in must be valid device
+ * memory of the stated size and are only read during the call (stream
+ * ordered on the handle's stream).
+ * Threads: a handle is not thread safe; separate handles are independent.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_sim pf_sim;
+
+typedef enum {
+    PF_OK = 0,
+    PF_EINVAL = -1,        /* bad argument or parameter */
+    PF_ENOMEM = -2,        /* device or host allocation failed */
+    PF_EHIP = -3,          /* HIP runtime error */
+    PF_ENONFINITE = -4,    /* non-finite error norm three times in a row */
+    PF_EDTMIN = -5,        /* adaptive step fell below 1e-12 dt_e */
+    PF_ESTATE = -6,        /* call not valid in the current state (e.g. no fields) */
+    PF_EUNSUPPORTED = -7   /* valid request that this build does not implement */
+} pf_status;
+
+/* Integrators of Sec. 3.2 (Table tab:ints). */
+typedef enum {
+    PF_FEULER = 0,    /* forward Euler */
+    PF_SSP_S2 = 1,    /* SSP(s)2, s = pf_params.ssp_stages (Alg. ssp2) */
+    PF_SSP_10_4 = 2,  /* SSP(10)4 (Ketcheson 2008, low storage) */
+    PF_RKL1 = 3,      /* first-order Runge-Kutta-Legendre (Alg. sts1) */
+    PF_RKL2 = 4       /* second-order Runge-Kutta-Legendre (eq. sts) */
+} pf_integrator;
+
+typedef enum {
+    PF_FP64 = 0,  /* everything in double */
+    PF_FP32 = 1   /* stencil, stage and projection arithmetic in float; time,
+                     error norm and conservation sums in double */
+} pf_precision;
+
+/* Model and grid parameters.  Pair tables are symmetric n_types x n_types,
+ * row-major; phase a has type type_of[a].  Pair constants follow Sec. 2:
+ * A = 4 W gamma / pi, B = 4 gamma / (pi W), L = pi M / (4 W).  All arrays are
+ * copied by pf_create. */
+typedef struct {
+    int dim;               /* 2 or 3 */
+    int nx, ny, nz;        /* grid (nz = 1 for dim 2) */
+    double dx;             /* grid spacing */
+    double W;              /* interface parameter (interface width pi W) */
+    int n_phi;             /* N, 2 <= N <= 16 (kernels exist for N in
+                              pf_supported_nphi) */
+    const int *type_of;    /* [n_phi], values in [0, n_types) */
+    int n_types;           /* 1..4 */
+    const double *gamma;   /* [n_types^2] interface energies */
+    const double *mob;     /* [n_types^2] interface mobilities M */
+    const double *k;       /* [n_types] Gibbs-energy curvatures (eq. gibbs-energy) */
+    const double *c0;      /* [n_types] equilibrium concentrations */
+    const double *D;       /* [n_types] diffusivities */
+    int with_c;            /* 0: phase-field only (no c plane, no chemical term) */
+    pf_precision prec;
+    int ssp_stages;        /* s of SSP(s)2, >= 2 */
+} pf_params;
+
+/* Adaptive-step tolerances (Sec. 3.3): per-field relative r and absolute a,
+ * the step cap in units of dt_e (<= 0 means 200) and the first step (<= 0
+ * means 0.9 dt_e). */
+typedef struct {
+    double r_phi, a_phi, r_c, a_c;
+    double dt_max_over_dte;
+    double dt0;
+} pf_tol;
+
+/* Counters of a pf_step / pf_run_to call (RHS evaluations include the
+ * estimator's extra one, Sec. 3.3 footnote). */
+typedef struct {
+    long long rhs_evals, stages, accepted, rejected;
+    double t, last_dt, last_err;
+} pf_stats;
+
+/* Handle life cycle. */
+pf_status pf_create(const pf_params *p, pf_sim **out);
+pf_status pf_destroy(pf_sim *sim);
+
+/* Use this HIP stream (hipStream_t) for every launch and copy of the handle;
+ * NULL selects the null stream.  The stream must outlive its use. */
+pf_status pf_set_stream(pf_sim *sim, void *hip_stream);
+
+/* Set the state from host doubles [F*V] (c may be NULL when with_c = 0, else
+ * c is read from the same array after the phi planes when c == NULL) and the
+ * time t0. phi is [n_phi*V], c is [V]. */
+pf_status pf_init_fields(pf_sim *sim, const double *phi, const double *c, double t0);
+/* Same from a device array of F*V values in the handle's precision. */
+pf_status pf_init_fields_device(pf_sim *sim, const void *state, double t0);
+/* Copy the state to host doubles (phi [n_phi*V], c [V] or NULL) and t. */
+pf_status pf_get_fields(pf_sim *sim, double *phi, double *c, double *t);
+/* Copy the state to a device array of F*V values in the handle's precision. */
+pf_status pf_get_fields_device(pf_sim *sim, void *state);
+
+/* One RHS evaluation of the current state (eqs. phieq, ceq; no projection)
+ * into host doubles: dphi [n_phi*V], dc [V] (may be NULL). */
+pf_status pf_rhs(pf_sim *sim, double *dphi, double *dc);
+/* Same into a device array of F*V values in the handle's precision. */
+pf_status pf_rhs_device(pf_sim *sim, void *out);
+
+/* Stable forward-Euler step dt_e = 2 / max(lambda_phi, lambda_c) from the
+ * Gershgorin-type estimates of Sec. 3.2 (formulas reconstructed from the
+ * two-phase linearisation; reproduces the dt_e values of Table 3). */
+pf_status pf_stable_dt(pf_sim *sim, double *dt_e);
+/* RKL stage count for a step dt: smallest odd s with dt inside the exact real
+ * stability interval scaled by the 0.9 safety factor (eq. sts-limit). */
+pf_status pf_stage_count(pf_sim *sim, pf_integrator integ, double dt, int *s);
+
+/* One step of size dt (RKL stage count from pf_stage_count).  stats may be
+ * NULL; otherwise it is overwritten with this call's counters. */
+pf_status pf_step(pf_sim *sim, pf_integrator integ, double dt, pf_stats *stats);
+
+/* Integrate to t_end, landing on it exactly (Sec. 5 opening).  tol == NULL:
+ * fixed steps of dt_fixed, the last clipped.  tol != NULL: adaptive RKL1,
+ * RKL2 (estimate of Sec. 3.3 after Sommeijer) or SSP(s)2 (embedded first-order
+ * solution), PID controller; SSP(10)4 and FE return PF_EUNSUPPORTED. */
+pf_status pf_run_to(pf_sim *sim, pf_integrator integ, double t_end, const pf_tol *tol,
+                    double dt_fixed, pf_stats *stats);
+
+/* Weighted RMS error norm of Sec. 3.3 (eq. error_norm) on device state
+ * vectors in the handle's precision, computed on the GPU with FP64
+ * accumulation.  kind 0: Sommeijer estimate from u_old = u^n, u_new =
+ * u^{n+1}, aux = rhs(u^n), step dt (one extra RHS of u_new is evaluated);
+ * kind 1: embedded estimate e = u_new - aux.  Writes the norm and, if
+ * non-NULL, the DoF count N. */
+pf_status pf_error_norm(pf_sim *sim, int kind, double dt, const void *u_old, const void *u_new,
+                        const void *aux, const pf_tol *tol, double *norm, long long *ndof);
+
+/* FP64 sum of c over all cells of the current state (GPU reduction, fixed
+ * order, so repeated calls give identical bits). */
+pf_status pf_conservation(pf_sim *sim, double *sum_c);
+/* Constraint diagnostics of the current state: out[0] = sum c,
+ * out[1] = max |sum_a phi_a - 1|, out[2] = min phi, out[3] = max phi,
+ * out[4] = number of non-finite values. */
+pf_status pf_diagnostics(pf_sim *sim, double out[5]);
+
+/* Attempt log of the last pf_run_to: 4 doubles per attempt (dt, s, e,
+ * accepted).  Copies min(n, cap) rows into buf and writes n. */
+pf_status pf_get_trace(pf_sim *sim, double *buf, long long cap, long long *n);
+
+/* Checkpoint: the state in the handle's precision plus t, the controller
+ * state and the counters.  With buf == NULL, *len receives the size. */
+pf_status pf_get_state(pf_sim *sim, void *buf, size_t *len);
+pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
+
+/* Launch shape of the stencil kernels: tile width tx (32, 64 or 128 cells in
+ * x; the block is 256 threads, 256/tx rows in y) and the number of z planes a
+ * block marches through (3D only, >= 1).  pf_autotune times the candidates on
+ * the current state and keeps the fastest. */
+pf_status pf_set_tiling(pf_sim *sim, int tx, int zchunk);
+pf_status pf_get_tiling(pf_sim *sim, int *tx, int *zchunk);
+pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch while enabled.  Families: 0 stage kernels (all stage kinds),
+ * 1 estimator, 2 reductions, 3 RKL2 inner stages (j >= 2) only, 4 FE stages.
+ * pf_get_kernel_time synchronises the stream and returns the total ms and the
+ * number of launches of a family since timing was enabled. */
+pf_status pf_set_timing(pf_sim *sim, int enable);
+pf_status pf_get_kernel_time(pf_sim *sim, int family, double *ms, long long *launches);
+
+/* Values of N for which kernels are compiled; returns the count. */
+int pf_supported_nphi(int *out, int cap);
+
+const char *pf_last_error(const pf_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H */

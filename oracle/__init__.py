@@ -92,7 +92,8 @@ def lib():
         L.pfo_ctrl_update.argtypes = [C.POINTER(_Ctrl), I, C.c_double, C.c_double, C.POINTER(I)]
         L.pfo_ctrl_update.restype = C.c_double
         L.pfo_run_to.argtypes = [P, I, I, C.c_double, C.c_double, C.POINTER(_Tol), C.c_double,
-                                 D, C.POINTER(_Stats), D, LL, C.POINTER(LL)]
+                                 D, C.POINTER(_Stats), D, LL, C.POINTER(LL),
+                                 C.POINTER(_Ctrl), C.POINTER(C.c_double)]
         L.pfo_run_to.restype = I
         L.pfo_sum_c.argtypes = [P, D]
         L.pfo_sum_c.restype = C.c_double
@@ -268,15 +269,27 @@ class Controller:
         return hn, bool(acc.value)
 
 
+class Carry:
+    """Controller state and proposed step carried between adaptive run_to calls."""
+
+    def __init__(self):
+        self.ctrl = _Ctrl()
+        lib().pfo_ctrl_init(C.byref(self.ctrl))
+        self.dt = C.c_double(0.0)
+
+
 def run_to(P: Params, integ: int, u, t_end: float, tol: Optional[Tol] = None,
-           dt_fixed: float = 0.0, s: int = 0, t0: float = 0.0, trace_cap: int = 100000):
+           dt_fixed: float = 0.0, s: int = 0, t0: float = 0.0, trace_cap: int = 100000,
+           carry: Optional[Carry] = None):
     u = _state(P, u).copy()
     st = _Stats()
     tr = np.zeros(4 * trace_cap)
     nt = C.c_longlong()
     rc = lib().pfo_run_to(C.byref(P._c()), integ, s, t0, t_end,
                           C.byref(tol._c()) if tol is not None else None, dt_fixed,
-                          _dp(u), C.byref(st), _dp(tr), trace_cap, C.byref(nt))
+                          _dp(u), C.byref(st), _dp(tr), trace_cap, C.byref(nt),
+                          C.byref(carry.ctrl) if carry else None,
+                          C.byref(carry.dt) if carry else None)
     out = _stats(st)
     out.trace = tr[: 4 * min(nt.value, trace_cap)].reshape(-1, 4)
     return u, out, rc

@@ -695,12 +695,14 @@ static int method_order(int integ) {
  * estimate), PID controller, dt <= dt_max_over_dte * dt_e (SSP(s)2 also
  * <= 0.9 (s-1) dt_e), dt0 = tol->dt0 or 0.9 dt_e when that is <= 0.
  * trace (optional, 4 doubles per attempt: dt, s, e, accepted) records up to
- * trace_cap attempts.  Returns 0, or -5 when dt underflows, -4 after three
+ * trace_cap attempts.  ctrl_io/dt_io (optional): when *dt_io > 0 the adaptive
+ * loop resumes that controller state and proposed step; both are written back.  Returns 0, or -5 when dt underflows, -4 after three
  * consecutive non-finite error norms (state = last accepted).
  * ------------------------------------------------------------------------- */
 int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_end,
                const pfo_tol *tol, double dt_fixed, double *u, pfo_stats *st,
-               double *trace, long long trace_cap, long long *ntrace) {
+               double *trace, long long trace_cap, long long *ntrace,
+               pfo_ctrl *ctrl_io, double *dt_io) {
     long long n = (long long)nfields(P) * ncells(P);
     double dte = pfo_stable_dt(P);
     double t = t0;
@@ -743,6 +745,12 @@ int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_en
     double *aux = (double *)calloc((size_t)n, sizeof(double));
     pfo_ctrl ctrl;
     pfo_ctrl_init(&ctrl);
+    /* carry the controller over from a previous call (integration with output
+     * times continues the same step-size sequence) */
+    if (ctrl_io && dt_io && *dt_io > 0.0) {
+        ctrl = *ctrl_io;
+        if (!(tol->dt0 > 0.0)) dt = *dt_io;
+    }
     int nonfinite = 0;
     int rc = 0;
     for (;;) {
@@ -776,6 +784,10 @@ int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_en
             if (!isfinite(e) && ++nonfinite >= 3) { rc = -4; break; }
         }
         dt = hn;
+    }
+    if (ctrl_io && dt_io) {
+        *ctrl_io = ctrl;
+        *dt_io = dt;
     }
     free(y);
     free(aux);

@@ -1,0 +1,340 @@
+"""MI355X (gfx950) explicit phase-field + concentration time stepping.
+
+Python binding of ``libpf.so`` (C-ABI declared in ``include/pf.h``).  This
+module only marshals arguments: every step of the time integration runs in the
+library's HIP kernels.  PyTorch is used for device memory and streams only
+(device arrays are passed as ``torch.Tensor`` data pointers).
+
+If the library has not been built, every entry point raises; there is no CPU
+fallback.  Build with ``python -m paper_2601_16522_amd.build`` or
+``__graft_entry__.build()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpf.so")
+
+PF_FEULER, PF_SSP_S2, PF_SSP_10_4, PF_RKL1, PF_RKL2 = 0, 1, 2, 3, 4
+PF_FP64, PF_FP32 = 0, 1
+INTEGRATORS = {"fe": PF_FEULER, "ssp2": PF_SSP_S2, "ssp104": PF_SSP_10_4, "rkl1": PF_RKL1,
+               "rkl2": PF_RKL2}
+PRECISIONS = {"fp64": PF_FP64, "fp32": PF_FP32}
+STATUS = {0: "PF_OK", -1: "PF_EINVAL", -2: "PF_ENOMEM", -3: "PF_EHIP", -4: "PF_ENONFINITE",
+          -5: "PF_EDTMIN", -6: "PF_ESTATE", -7: "PF_EUNSUPPORTED"}
+
+# every symbol include/pf.h declares
+EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_init_fields_device",
+           "pf_get_fields", "pf_get_fields_device", "pf_rhs", "pf_rhs_device", "pf_stable_dt",
+           "pf_stage_count", "pf_step", "pf_run_to", "pf_error_norm", "pf_conservation",
+           "pf_diagnostics", "pf_get_trace", "pf_get_state", "pf_set_state", "pf_set_tiling",
+           "pf_get_tiling", "pf_autotune", "pf_set_timing", "pf_get_kernel_time",
+           "pf_supported_nphi", "pf_last_error"]
+
+
+class PFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("W", C.c_double), ("n_phi", C.c_int),
+                ("type_of", C.POINTER(C.c_int)), ("n_types", C.c_int),
+                ("gamma", C.POINTER(C.c_double)), ("mob", C.POINTER(C.c_double)),
+                ("k", C.POINTER(C.c_double)), ("c0", C.POINTER(C.c_double)),
+                ("D", C.POINTER(C.c_double)), ("with_c", C.c_int), ("prec", C.c_int),
+                ("ssp_stages", C.c_int)]
+
+
+class _Tol(C.Structure):
+    _fields_ = [("r_phi", C.c_double), ("a_phi", C.c_double), ("r_c", C.c_double),
+                ("a_c", C.c_double), ("dt_max_over_dte", C.c_double), ("dt0", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("rhs_evals", C.c_longlong), ("stages", C.c_longlong),
+                ("accepted", C.c_longlong), ("rejected", C.c_longlong),
+                ("t", C.c_double), ("last_dt", C.c_double), ("last_err", C.c_double)]
+
+
+@dataclass
+class Tol:
+    r_phi: float = 1e-4
+    a_phi: float = 1e-2
+    r_c: float = 1e-4
+    a_c: float = 1e-4
+    dt_max_over_dte: float = 200.0
+    dt0: float = 0.0
+
+    def _c(self):
+        return _Tol(self.r_phi, self.a_phi, self.r_c, self.a_c, self.dt_max_over_dte, self.dt0)
+
+
+@dataclass
+class Stats:
+    rhs_evals: int
+    stages: int
+    accepted: int
+    rejected: int
+    t: float
+    last_dt: float
+    last_err: float
+
+
+_lib = None
+
+
+def lib():
+    """Load libpf.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2601_16522_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, d, i, ll = C.c_void_p, C.c_double, C.c_int, C.c_longlong
+        pd = C.POINTER(C.c_double)
+        sigs = {
+            "pf_create": [C.POINTER(_Params), C.POINTER(vp)],
+            "pf_destroy": [vp],
+            "pf_set_stream": [vp, vp],
+            "pf_init_fields": [vp, pd, pd, d],
+            "pf_init_fields_device": [vp, vp, d],
+            "pf_get_fields": [vp, pd, pd, pd],
+            "pf_get_fields_device": [vp, vp],
+            "pf_rhs": [vp, pd, pd],
+            "pf_rhs_device": [vp, vp],
+            "pf_stable_dt": [vp, pd],
+            "pf_stage_count": [vp, i, d, C.POINTER(i)],
+            "pf_step": [vp, i, d, C.POINTER(_Stats)],
+            "pf_run_to": [vp, i, d, C.POINTER(_Tol), d, C.POINTER(_Stats)],
+            "pf_error_norm": [vp, i, d, vp, vp, vp, C.POINTER(_Tol), pd, C.POINTER(ll)],
+            "pf_conservation": [vp, pd],
+            "pf_diagnostics": [vp, pd],
+            "pf_get_trace": [vp, pd, ll, C.POINTER(ll)],
+            "pf_get_state": [vp, vp, C.POINTER(C.c_size_t)],
+            "pf_set_state": [vp, vp, C.c_size_t],
+            "pf_set_tiling": [vp, i, i],
+            "pf_get_tiling": [vp, C.POINTER(i), C.POINTER(i)],
+            "pf_autotune": [vp, C.POINTER(i), C.POINTER(i), pd],
+            "pf_set_timing": [vp, i],
+            "pf_get_kernel_time": [vp, i, pd, C.POINTER(ll)],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.pf_supported_nphi.argtypes = [C.POINTER(C.c_int), C.c_int]
+        L.pf_supported_nphi.restype = C.c_int
+        L.pf_last_error.argtypes = [vp]
+        L.pf_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def supported_nphi():
+    out = (C.c_int * 64)()
+    n = lib().pf_supported_nphi(out, 64)
+    return [out[i] for i in range(min(n, 64))]
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _tptr(t) -> C.c_void_p:
+    """Device pointer of a contiguous torch tensor."""
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Sim:
+    """One simulation handle (pf_sim).  Parameters as produced by
+    ``pf_inputs.Workload.param_dict()``."""
+
+    def __init__(self, params: dict, prec: str = "fp64", ssp_stages: int = 5):
+        self._L = lib()
+        p = params
+        self.N = int(p["n_phi"])
+        self.with_c = bool(p["with_c"])
+        self.F = self.N + (1 if self.with_c else 0)
+        self.shape = (self.F, int(p.get("nz", 1)), int(p["ny"]), int(p["nx"]))
+        self.V = self.shape[1] * self.shape[2] * self.shape[3]
+        self.prec = prec
+        T = int(p["n_types"])
+        self._keep = [
+            (C.c_int * self.N)(*[int(v) for v in p["type_of"]]),
+            (C.c_double * (T * T))(*p["gamma"]), (C.c_double * (T * T))(*p["mob"]),
+            (C.c_double * T)(*p["k"]), (C.c_double * T)(*p["c0"]), (C.c_double * T)(*p["D"]),
+        ]
+        cp = _Params(int(p["dim"]), int(p["nx"]), int(p["ny"]), int(p.get("nz", 1)),
+                     float(p["dx"]), float(p["W"]), self.N, self._keep[0], T,
+                     self._keep[1], self._keep[2], self._keep[3], self._keep[4], self._keep[5],
+                     int(self.with_c), PRECISIONS[prec], int(ssp_stages))
+        h = C.c_void_p()
+        self._chk(self._L.pf_create(C.byref(cp), C.byref(h)), None)
+        self._h = h
+
+    # -- plumbing -----------------------------------------------------------
+    def _chk(self, rc: int, h=...):
+        if rc != 0:
+            handle = self._h if h is ... else h
+            msg = self._L.pf_last_error(handle).decode() if handle else ""
+            raise PFError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _state_ptr(self, t) -> C.c_void_p:
+        """Pointer of a device tensor holding one full state vector (F*V values of
+        the handle's precision); anything else is refused before any launch."""
+        if t.numel() != self.F * self.V or t.dtype != self.torch_dtype:
+            raise ValueError(f"expected {self.F * self.V} values of {self.torch_dtype}, "
+                             f"got {t.numel()} of {t.dtype}")
+        return _tptr(t)
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.prec == "fp64" else torch.float32
+
+    def empty_device(self):
+        import torch
+        return torch.empty(self.shape, dtype=self.torch_dtype, device="cuda")
+
+    # -- API ----------------------------------------------------------------
+    def set_stream(self, stream):
+        ptr = None if stream is None else C.c_void_p(stream.cuda_stream)
+        self._chk(self._L.pf_set_stream(self._h, ptr))
+
+    def init_fields(self, u: np.ndarray, t0: float = 0.0):
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+        if u.size != self.F * self.V:
+            raise ValueError(f"expected {self.F * self.V} values, got {u.size}")
+        self._chk(self._L.pf_init_fields(self._h, _dp(u), None, t0))
+
+    def init_fields_device(self, t, t0: float = 0.0):
+        self._chk(self._L.pf_init_fields_device(self._h, self._state_ptr(t), t0))
+
+    def get_fields(self):
+        out = np.empty(self.shape, dtype=np.float64)
+        t = C.c_double()
+        flat = out.reshape(-1)
+        c_ptr = _dp(flat[self.N * self.V:]) if self.with_c else None
+        self._chk(self._L.pf_get_fields(self._h, _dp(flat), c_ptr, C.byref(t)))
+        return out, t.value
+
+    def get_fields_device(self, t):
+        self._chk(self._L.pf_get_fields_device(self._h, self._state_ptr(t)))
+
+    def rhs(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float64)
+        flat = out.reshape(-1)
+        c_ptr = _dp(flat[self.N * self.V:]) if self.with_c else None
+        self._chk(self._L.pf_rhs(self._h, _dp(flat), c_ptr))
+        return out
+
+    def rhs_device(self, t):
+        self._chk(self._L.pf_rhs_device(self._h, self._state_ptr(t)))
+
+    def stable_dt(self) -> float:
+        v = C.c_double()
+        self._chk(self._L.pf_stable_dt(self._h, C.byref(v)))
+        return v.value
+
+    def stage_count(self, integ: str, dt: float) -> int:
+        v = C.c_int()
+        self._chk(self._L.pf_stage_count(self._h, INTEGRATORS[integ], dt, C.byref(v)))
+        return v.value
+
+    def step(self, integ: str, dt: float) -> Stats:
+        st = _Stats()
+        self._chk(self._L.pf_step(self._h, INTEGRATORS[integ], dt, C.byref(st)))
+        return Stats(*[getattr(st, f) for f, _ in _Stats._fields_])
+
+    def run_to(self, integ: str, t_end: float, tol: Optional[Tol] = None,
+               dt_fixed: float = 0.0) -> Stats:
+        st = _Stats()
+        ctol = tol._c() if tol is not None else None
+        self._chk(self._L.pf_run_to(self._h, INTEGRATORS[integ], t_end,
+                                    C.byref(ctol) if ctol is not None else None, dt_fixed,
+                                    C.byref(st)))
+        return Stats(*[getattr(st, f) for f, _ in _Stats._fields_])
+
+    def error_norm(self, kind: int, dt: float, u_old, u_new, aux, tol: Tol):
+        v = C.c_double()
+        n = C.c_longlong()
+        ctol = tol._c()
+        self._chk(self._L.pf_error_norm(self._h, kind, dt, self._state_ptr(u_old),
+                                        self._state_ptr(u_new), self._state_ptr(aux),
+                                        C.byref(ctol), C.byref(v), C.byref(n)))
+        return v.value, n.value
+
+    def conservation(self) -> float:
+        v = C.c_double()
+        self._chk(self._L.pf_conservation(self._h, C.byref(v)))
+        return v.value
+
+    def diagnostics(self):
+        out = (C.c_double * 5)()
+        self._chk(self._L.pf_diagnostics(self._h, out))
+        return dict(sum_c=out[0], max_sum_dev=out[1], min_phi=out[2], max_phi=out[3],
+                    nonfinite=out[4])
+
+    def trace(self) -> np.ndarray:
+        n = C.c_longlong()
+        self._chk(self._L.pf_get_trace(self._h, None, 0, C.byref(n)))
+        buf = np.zeros(4 * max(n.value, 1))
+        self._chk(self._L.pf_get_trace(self._h, _dp(buf), n.value, C.byref(n)))
+        return buf[: 4 * n.value].reshape(-1, 4)
+
+    def get_state(self) -> bytes:
+        n = C.c_size_t()
+        self._chk(self._L.pf_get_state(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._chk(self._L.pf_get_state(self._h, buf, C.byref(n)))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._chk(self._L.pf_set_state(self._h, buf, len(blob)))
+
+    def set_tiling(self, tx: int, zchunk: int):
+        self._chk(self._L.pf_set_tiling(self._h, tx, zchunk))
+
+    def get_tiling(self):
+        a, b = C.c_int(), C.c_int()
+        self._chk(self._L.pf_get_tiling(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def autotune(self):
+        a, b, ms = C.c_int(), C.c_int(), C.c_double()
+        self._chk(self._L.pf_autotune(self._h, C.byref(a), C.byref(b), C.byref(ms)))
+        return a.value, b.value, ms.value
+
+    def set_timing(self, on: bool):
+        self._chk(self._L.pf_set_timing(self._h, int(bool(on))))
+
+    def kernel_time(self, family: int):
+        ms, n = C.c_double(), C.c_longlong()
+        self._chk(self._L.pf_get_kernel_time(self._h, family, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+FAM_STAGE, FAM_EST, FAM_RED, FAM_RKL2, FAM_FE = 0, 1, 2, 3, 4

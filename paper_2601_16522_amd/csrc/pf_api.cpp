@@ -1,0 +1,1082 @@
+// pf_api.cpp -- host engine and C-ABI of libpf (see include/pf.h).
+//
+// The engine owns the device state vectors, sequences the fused stage kernels
+// of each integrator (Sec. 3.2 of Seiz & Takaki, arXiv 2601.16522), runs the
+// adaptive loop with the error norm and PID controller of Sec. 3.3 and keeps
+// the time in FP64.  Every arithmetic step on field data runs in the kernels
+// of pf_kernels.hip; the host only computes scalar coefficients.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "pf_internal.h"
+
+using namespace pf;
+
+namespace {
+
+constexpr int NBUF = 7;
+constexpr double PI = 3.14159265358979323846;
+
+struct Ctrl {
+    double b = 0.9;
+    int nhist = 0;
+    double E1 = 0, E2 = 0, h1 = 0, h2 = 0;
+};
+
+struct Pending {
+    unsigned mask;
+    hipEvent_t e0, e1;
+};
+
+enum Family : unsigned {
+    FAM_STAGE = 1u << 0,
+    FAM_EST = 1u << 1,
+    FAM_RED = 1u << 2,
+    FAM_RKL2 = 1u << 3,
+    FAM_FE = 1u << 4,
+};
+
+}  // namespace
+
+struct pf_sim {
+    int dim, nx, ny, nz, N, T, with_c, ssp_s;
+    pf_precision prec;
+    double dx, W;
+    std::vector<int> type_of;
+    std::vector<double> gamma, mob, k, c0, D;
+    int F;
+    long long V;
+    size_t esz;
+    hipStream_t stream = nullptr;
+    void *buf[NBUF] = {nullptr};
+    int cur = 0;
+    bool have_fields = false;
+    void *dparams = nullptr;
+    double *red = nullptr;
+    long long *redn = nullptr;
+    int red_cap = 0;
+    double *dres = nullptr;
+    double *hres = nullptr;  // pinned
+    double t = 0.0;
+    Ctrl ctrl;
+    double dt_next = 0.0;   // controller proposal carried between pf_run_to calls
+    std::vector<double> trace;
+    std::string err;
+    int tx = 64, zchunk = 16;
+    bool timing = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double fam_ms[5] = {0, 0, 0, 0, 0};
+    long long fam_n[5] = {0, 0, 0, 0, 0};
+    pf_stats st{};
+};
+
+namespace {
+
+pf_status fail(pf_sim *s, pf_status code, const char *fmt, ...) {
+    if (s) {
+        char b[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(b, sizeof b, fmt, ap);
+        va_end(ap);
+        s->err = b;
+    }
+    return code;
+}
+
+#define HIPCHK(s, expr)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail((s), PF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+size_t state_bytes(const pf_sim *s) { return (size_t)s->F * (size_t)s->V * s->esz; }
+
+pf_status ensure_buf(pf_sim *s, int i) {
+    if (!s->buf[i]) {
+        if (hipMalloc(&s->buf[i], state_bytes(s)) != hipSuccess) {
+            s->buf[i] = nullptr;
+            return fail(s, PF_ENOMEM, "hipMalloc of %zu bytes failed", state_bytes(s));
+        }
+    }
+    return PF_OK;
+}
+
+// Work buffer number k (0-based) other than the current state.
+int work_index(const pf_sim *s, int k) {
+    int idx = 0;
+    for (int i = 0; i < NBUF; ++i) {
+        if (i == s->cur) continue;
+        if (idx == k) return i;
+        ++idx;
+    }
+    return -1;
+}
+
+void tiles(const pf_sim *s, int &ntx, int &nty, int &nzc, int &ntiles, int &nblocks) {
+    const int tx = s->tx, ty = 256 / s->tx;
+    ntx = (s->nx + tx - 1) / tx;
+    nty = (s->ny + ty - 1) / ty;
+    nzc = s->dim == 3 ? (s->nz + s->zchunk - 1) / s->zchunk : 1;
+    ntiles = ntx * nty * nzc;
+    nblocks = (ntiles + 7) / 8 * 8;
+}
+
+pf_status ensure_red(pf_sim *s, int n) {
+    if (n <= s->red_cap) return PF_OK;
+    if (s->red) hipFree(s->red);
+    if (s->redn) hipFree(s->redn);
+    s->red = nullptr;
+    s->redn = nullptr;
+    if (hipMalloc(&s->red, sizeof(double) * 5 * (size_t)n) != hipSuccess ||
+        hipMalloc(&s->redn, sizeof(long long) * (size_t)n) != hipSuccess) {
+        s->red_cap = 0;
+        return fail(s, PF_ENOMEM, "reduction buffers");
+    }
+    s->red_cap = n;
+    return PF_OK;
+}
+
+hipEvent_t get_event(pf_sim *s) {
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+void begin_timed(pf_sim *s, unsigned mask, Pending &p) {
+    p.mask = mask;
+    p.e0 = p.e1 = nullptr;
+    if (!s->timing) return;
+    p.e0 = get_event(s);
+    p.e1 = get_event(s);
+    hipEventRecord(p.e0, s->stream);
+}
+
+void end_timed(pf_sim *s, Pending &p) {
+    if (!s->timing || !p.e0) return;
+    hipEventRecord(p.e1, s->stream);
+    s->pending.push_back(p);
+}
+
+void collect_timing(pf_sim *s) {
+    if (s->pending.empty()) return;
+    hipStreamSynchronize(s->stream);
+    for (auto &p : s->pending) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, p.e0, p.e1);
+        for (int f = 0; f < 5; ++f)
+            if (p.mask & (1u << f)) {
+                s->fam_ms[f] += ms;
+                s->fam_n[f] += 1;
+            }
+        s->pool.push_back(p.e0);
+        s->pool.push_back(p.e1);
+    }
+    s->pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// Constants (Sec. 2): A = 4 W gamma / pi, B = 4 gamma / (pi W), L = pi M / (4 W)
+// ---------------------------------------------------------------------------
+template <typename T>
+void fill_params(const pf_sim *s, DevParams<T> &P) {
+    std::memset(&P, 0, sizeof P);
+    P.nx = s->nx;
+    P.ny = s->ny;
+    P.nz = s->nz;
+    P.n_phi = s->N;
+    P.with_c = s->with_c;
+    P.n_types = s->T;
+    P.V = s->V;
+    P.idx2 = (T)(1.0 / (s->dx * s->dx));
+    for (int a = 0; a < s->N; ++a) {
+        const int ta = s->type_of[a];
+        for (int b = 0; b < s->N; ++b) {
+            const int tb = s->type_of[b];
+            const double g = s->gamma[ta * s->T + tb];
+            const double m = s->mob[ta * s->T + tb];
+            P.A[a * NMAX + b] = (T)(4.0 * s->W * g / PI);
+            P.B[a * NMAX + b] = (T)(4.0 * g / (PI * s->W));
+            P.L[a * NMAX + b] = (T)(PI * m / (4.0 * s->W));
+        }
+        const double ik = 1.0 / s->k[ta];
+        P.c0[a] = (T)s->c0[ta];
+        P.ik[a] = (T)ik;
+        P.Dk[a] = (T)(s->D[ta] * ik);
+        P.tphi[a] = ta;
+    }
+    for (int t = 0; t < s->T; ++t) {
+        P.k2t[t] = (T)(2.0 * s->k[t]);
+        P.c0t[t] = (T)s->c0[t];
+    }
+}
+
+// Stable Euler step (Sec. 3.2, Gershgorin estimates of the two-phase system):
+//   lambda_phi = Mx gx (4d/dx^2 - 1/W^2) + [c, dc0 != 0] (pi Mx/(8W)) kx (dc0^2 + |dc0|)
+//   lambda_c   = 4 d Dx / dx^2 (1 + |dc0|/2),   dt_e = 2 / max.
+double stable_dt(const pf_sim *s) {
+    const int T = s->T;
+    double Mx = 0, gx = 0, kx = 0, Dx = 0, dc0 = 0;
+    std::vector<int> used(T, 0);
+    for (int a = 0; a < s->N; ++a) used[s->type_of[a]] = 1;
+    for (int i = 0; i < T; ++i) {
+        if (!used[i]) continue;
+        kx = std::max(kx, s->k[i]);
+        Dx = std::max(Dx, s->D[i]);
+        for (int j = 0; j < T; ++j) {
+            if (!used[j]) continue;
+            Mx = std::max(Mx, s->mob[i * T + j]);
+            gx = std::max(gx, s->gamma[i * T + j]);
+            dc0 = std::max(dc0, std::fabs(s->c0[i] - s->c0[j]));
+        }
+    }
+    const double idx2 = 1.0 / (s->dx * s->dx);
+    double lam = Mx * gx * (4.0 * s->dim * idx2 - 1.0 / (s->W * s->W));
+    if (s->with_c) {
+        if (dc0 != 0.0) lam += (PI * Mx / (8.0 * s->W)) * kx * (dc0 * dc0 + dc0);
+        const double lc = 4.0 * s->dim * Dx * idx2 * (1.0 + dc0 / 2.0);
+        lam = std::max(lam, lc);
+    }
+    return 2.0 / lam;
+}
+
+// Smallest odd stage count inside the exact RKL stability bound times 0.9.
+int stage_count(int order, double dt, double dte) {
+    if (!(dt > 0.0) || !(dte > 0.0)) return -1;
+    const double h = 0.9 * dte;
+    for (int s = order == 1 ? 1 : 3; s < 1000000; s += 2) {
+        const double lim = order == 1 ? h * ((double)s * s + s) / 2.0
+                                      : h * ((double)s * s + s - 2.0) / 4.0;
+        if (dt <= lim) return s;
+    }
+    return -1;
+}
+
+// RKL coefficients (Meyer et al. 2012/2014), stage j of s.
+double rkl2_b(int j) {
+    if (j < 3) return 1.0 / 3.0;
+    return ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+}
+
+void rkl_coeffs(int order, int s, int j, double &mu, double &nu, double &mut, double &gam) {
+    if (order == 1) {
+        const double w1 = 2.0 / ((double)s * s + s);
+        if (j == 1) {
+            mu = nu = gam = 0.0;
+            mut = w1;
+            return;
+        }
+        mu = (2.0 * j - 1.0) / j;
+        nu = (1.0 - j) / j;
+        mut = w1 * mu;
+        gam = 0.0;
+        return;
+    }
+    const double w1 = 4.0 / ((double)s * s + s - 2.0);
+    if (j == 1) {
+        mu = nu = gam = 0.0;
+        mut = rkl2_b(1) * w1;
+        return;
+    }
+    mu = (2.0 * j - 1.0) / j * (rkl2_b(j) / rkl2_b(j - 1));
+    nu = -(j - 1.0) / j * (rkl2_b(j) / rkl2_b(j - 2));
+    mut = mu * w1;
+    gam = -(1.0 - rkl2_b(j - 1)) * mut;
+}
+
+int method_order(int integ) {
+    switch (integ) {
+    case PF_FEULER: return 1;
+    case PF_SSP_S2: return 2;
+    case PF_SSP_10_4: return 4;
+    case PF_RKL1: return 1;
+    default: return 2;
+    }
+}
+
+// PID controller of Sec. 3.3 (Soederlind), bias b in [0.1, 0.98].
+double ctrl_update(Ctrl &c, int order, double e, double h, bool &accept) {
+    const double k1 = 1.25, k2 = 0.5, k3 = -0.6, k4 = 0.25, k5 = 0.0;
+    const double p1 = order + 1.0;
+    const bool finite = std::isfinite(e);
+    const bool acc = finite && e < 1.0;
+    double F;
+    double E = e / c.b;
+    if (E < 1e-12) E = 1e-12;
+    if (!finite) {
+        F = 0.0;
+    } else {
+        double prod = std::pow(E, -k1);
+        if (c.nhist >= 1) prod = prod * std::pow(c.E1, -k2);
+        if (c.nhist >= 2) prod = prod * std::pow(c.E2, -k3);
+        F = std::pow(prod, 1.0 / p1);
+        if (c.nhist >= 1) F = F * std::pow(h / c.h1, k4);
+        if (c.nhist >= 2) F = F * std::pow(c.h1 / c.h2, k5);
+        if (!acc && F > 1.0) {
+            const double en = e < 1e-12 ? 1e-12 : e;
+            F = std::pow(en, -k1 / p1);
+        }
+    }
+    const double hn = h * (1.0 + 5.0 * std::atan((F - 1.0) / 5.0));
+    if (acc) {
+        c.E2 = c.E1;
+        c.h2 = c.h1;
+        c.E1 = E;
+        c.h1 = h;
+        if (c.nhist < 2) c.nhist++;
+        c.b = std::min(std::sqrt(c.b), 0.98);
+    } else {
+        c.b = std::max(c.b * c.b, 0.1);
+    }
+    accept = acc;
+    return hn;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launches
+// ---------------------------------------------------------------------------
+template <typename T>
+T *bp(pf_sim *s, int i) { return i < 0 ? nullptr : (T *)s->buf[i]; }
+
+template <typename T>
+pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, const T *r0, T *out,
+                T *out2, double a, double b, double c, double d, double e, double f,
+                unsigned fam) {
+    StageArgs<T> A;
+    std::memset(&A, 0, sizeof A);
+    A.P = (const DevParams<T> *)s->dparams;
+    A.y1 = y1;
+    A.y2 = y2;
+    A.u0 = u0;
+    A.r0 = r0;
+    A.out = out;
+    A.out2 = out2;
+    A.kind = kind;
+    A.a = (T)a; A.b = (T)b; A.c = (T)c; A.d = (T)d; A.e = (T)e; A.f = (T)f;
+    int ntx, nty, nzc, ntiles, nblocks;
+    tiles(s, ntx, nty, nzc, ntiles, nblocks);
+    A.tx = s->tx;
+    A.ty = 256 / s->tx;
+    A.zchunk = s->zchunk;
+    A.ntx = ntx;
+    A.nty = nty;
+    A.nzc = nzc;
+    A.ntiles = ntiles;
+    Pending p;
+    begin_timed(s, fam | FAM_STAGE, p);
+    hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
+    if (err != hipSuccess) return fail(s, PF_EHIP, "stage kernel launch: %s", hipGetErrorString(err));
+    end_timed(s, p);
+    return PF_OK;
+}
+
+// Sommeijer-type estimate (kind 0) or embedded estimate (kind 1) -> norm on host.
+template <typename T>
+pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *unew, const T *aux,
+                     const pf_tol &tol, double *norm, long long *ndof) {
+    int ntx, nty, nzc, ntiles, nblocks;
+    tiles(s, ntx, nty, nzc, ntiles, nblocks);
+    const int nred = kind == 0 ? ntiles : 1024;
+    pf_status rc = ensure_red(s, std::max(nred, 1024));
+    if (rc) return rc;
+    Pending p;
+    if (kind == 0) {
+        StageArgs<T> A;
+        std::memset(&A, 0, sizeof A);
+        A.P = (const DevParams<T> *)s->dparams;
+        A.y1 = unew;
+        A.u0 = uold;
+        A.r0 = aux;
+        A.kind = K_EST;
+        A.red = s->red;
+        A.redn = s->redn;
+        A.r_phi = (T)tol.r_phi; A.a_phi = (T)tol.a_phi;
+        A.r_c = (T)tol.r_c; A.a_c = (T)tol.a_c;
+        A.dt6 = (T)(6.0 * dt);
+        A.hdt = (T)(dt / 2.0);
+        A.tx = s->tx; A.ty = 256 / s->tx; A.zchunk = s->zchunk;
+        A.ntx = ntx; A.nty = nty; A.nzc = nzc; A.ntiles = ntiles;
+        begin_timed(s, FAM_EST, p);
+        hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
+        if (err != hipSuccess) return fail(s, PF_EHIP, "estimator launch: %s", hipGetErrorString(err));
+        end_timed(s, p);
+    } else {
+        begin_timed(s, FAM_EST, p);
+        hipError_t err = launch_embed_est<T>((const DevParams<T> *)s->dparams, s->N, s->with_c, s->V,
+                                             unew, aux, uold, (T)tol.r_phi, (T)tol.a_phi,
+                                             (T)tol.r_c, (T)tol.a_c, s->red, s->redn, nred,
+                                             s->stream);
+        if (err != hipSuccess) return fail(s, PF_EHIP, "embedded estimator launch: %s", hipGetErrorString(err));
+        end_timed(s, p);
+    }
+    begin_timed(s, FAM_RED, p);
+    HIPCHK(s, launch_finalize_norm(s->red, s->redn, nred, s->dres, s->stream));
+    end_timed(s, p);
+    HIPCHK(s, hipMemcpyAsync(s->hres, s->dres, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *norm = s->hres[2];
+    if (ndof) *ndof = (long long)s->hres[1];
+    s->st.rhs_evals += kind == 0 ? 1 : 0;
+    return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Integrator steps.  The state is buffer `cur`; work buffers are allocated on
+// demand.  On return *res is the buffer holding u^{n+1}, *aux the buffer with
+// rhs(u^n) (RKL, corrected for RKL2) or the embedded solution (SSP(s)2), or -1.
+// The state buffer is never written (keep_u) unless the RKL1 three-buffer
+// scheme of Alg. sts1 is requested for a fixed step.
+// ---------------------------------------------------------------------------
+template <typename T>
+pf_status do_step(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *res, int *aux) {
+    const int U = s->cur;
+    *aux = -1;
+    auto W = [&](int k) { return work_index(s, k); };
+    pf_status rc;
+    int need = 1;
+    if (integ == PF_SSP_S2) need = 2;
+    else if (integ == PF_SSP_10_4) need = 3;
+    else if (integ == PF_RKL1) need = want_aux ? 4 : 2;
+    else if (integ == PF_RKL2) need = 4;
+    for (int k = 0; k < need; ++k)
+        if ((rc = ensure_buf(s, W(k)))) return rc;
+    const T *u = bp<T>(s, U);
+    switch (integ) {
+    case PF_FEULER: {
+        rc = stage<T>(s, K_EULER, u, nullptr, nullptr, nullptr, bp<T>(s, W(0)), nullptr, dt, 0, 0, 0,
+                      0, 0, FAM_FE);
+        if (rc) return rc;
+        s->st.rhs_evals++;
+        s->st.stages++;
+        *res = W(0);
+        return PF_OK;
+    }
+    case PF_SSP_S2: {
+        const int ns = nst;
+        if (ns < 2) return fail(s, PF_EINVAL, "SSP(s)2 needs s >= 2");
+        int q1 = U;
+        int pp[2] = {W(0), W(1)};
+        int which = 0;
+        for (int i = 1; i <= ns - 1; ++i) {
+            const int dst = pp[which];
+            rc = stage<T>(s, K_EULER, bp<T>(s, q1), nullptr, nullptr, nullptr, bp<T>(s, dst), nullptr,
+                          dt / (ns - 1), 0, 0, 0, 0, 0, 0);
+            if (rc) return rc;
+            q1 = dst;
+            which ^= 1;
+            s->st.rhs_evals++;
+            s->st.stages++;
+        }
+        const int dst = pp[which];
+        rc = stage<T>(s, K_SSP2_FINAL, bp<T>(s, q1), nullptr, u, nullptr, bp<T>(s, dst), nullptr,
+                      (double)(ns - 1), dt, (double)ns, 0, 0, 0, 0);
+        if (rc) return rc;
+        s->st.rhs_evals++;
+        s->st.stages++;
+        *res = dst;
+        *aux = q1;  // embedded first-order solution Y_{s-1}
+        return PF_OK;
+    }
+    case PF_SSP_10_4: {
+        int q1 = U;
+        int pp[2] = {W(0), W(1)};
+        const int Q2 = W(2);
+        int which = 0;
+        const T *q2 = u;
+        for (int i = 1; i <= 9; ++i) {
+            const int dst = pp[which];
+            if (i == 5) {
+                rc = stage<T>(s, K_SSP104_S5, bp<T>(s, q1), nullptr, q2, nullptr, bp<T>(s, dst),
+                              bp<T>(s, Q2), dt / 6.0, 1.0 / 25.0, 9.0 / 25.0, 15.0, 5.0, 0, 0);
+                q2 = bp<T>(s, Q2);
+            } else {
+                rc = stage<T>(s, K_EULER, bp<T>(s, q1), nullptr, nullptr, nullptr, bp<T>(s, dst),
+                              nullptr, dt / 6.0, 0, 0, 0, 0, 0, 0);
+            }
+            if (rc) return rc;
+            q1 = dst;
+            which ^= 1;
+            s->st.rhs_evals++;
+            s->st.stages++;
+        }
+        const int dst = pp[which];
+        rc = stage<T>(s, K_SSP104_FINAL, bp<T>(s, q1), nullptr, q2, nullptr, bp<T>(s, dst), nullptr,
+                      3.0 / 5.0, dt / 10.0, 0, 0, 0, 0, 0);
+        if (rc) return rc;
+        s->st.rhs_evals++;
+        s->st.stages++;
+        *res = dst;
+        return PF_OK;
+    }
+    case PF_RKL1:
+    case PF_RKL2: {
+        const int order = integ == PF_RKL1 ? 1 : 2;
+        const int ns = nst;
+        if (ns < order) return fail(s, PF_EINVAL, "bad RKL stage count %d", ns);
+        const bool second = order == 2;
+        const bool keep_r0 = second || want_aux;
+        // ring of three stage slots; slot 0 starts as u^{n,0}.  A fixed RKL1 step
+        // is the three-buffer scheme of Alg. sts1 (u^{n,0} is overwritten by stage
+        // 3, it is not read again); otherwise slot 0 is backed by a work buffer
+        // from its first write on and u^{n,0} stays intact.
+        const bool inplace = !second && !want_aux;
+        const int R0 = keep_r0 ? W(3) : -1;
+        int slot[3] = {U, W(0), W(1)};
+        const int slot0_store = inplace ? U : W(2);
+        double mu, nu, mut, gam;
+        rkl_coeffs(order, ns, 1, mu, nu, mut, gam);
+        const double mut1 = mut;
+        if (second) {
+            rc = stage<T>(s, K_RKL2_FIRST, u, nullptr, nullptr, nullptr, bp<T>(s, slot[1]),
+                          bp<T>(s, R0), mut1 * dt, 0, 0, 0, 0, 0, 0);
+        } else {
+            rc = stage<T>(s, K_EULER, u, nullptr, nullptr, nullptr, bp<T>(s, slot[1]),
+                          keep_r0 ? bp<T>(s, R0) : nullptr, dt * mut1, 0, 0, 0, 0, 0, 0);
+        }
+        if (rc) return rc;
+        s->st.rhs_evals++;
+        s->st.stages++;
+        for (int j = 2; j <= ns; ++j) {
+            const int jc = j % 3, jp = (j - 1) % 3, jpp = (j - 2) % 3;
+            if (jc == 0) slot[0] = slot0_store;
+            rkl_coeffs(order, ns, j, mu, nu, mut, gam);
+            if (second) {
+                rc = stage<T>(s, K_RKL2, bp<T>(s, slot[jp]), bp<T>(s, slot[jpp]), u, bp<T>(s, R0),
+                              bp<T>(s, slot[jc]), nullptr, (1.0 - mu) - nu, mu, nu, dt, mut, gam,
+                              FAM_RKL2);
+            } else {
+                rc = stage<T>(s, K_RKL1, bp<T>(s, slot[jp]), bp<T>(s, slot[jpp]), nullptr, nullptr,
+                              bp<T>(s, slot[jc]), nullptr, mu, nu, dt * mut, 0, 0, 0, 0);
+            }
+            if (rc) return rc;
+            s->st.rhs_evals++;
+            s->st.stages++;
+        }
+        *res = slot[ns % 3];
+        *aux = R0;
+        return PF_OK;
+    }
+    default: return fail(s, PF_EINVAL, "unknown integrator %d", integ);
+    }
+}
+
+template <typename T>
+pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double dt_fixed) {
+    const double dte = stable_dt(s);
+    s->trace.clear();
+    pf_status rc;
+    if (!tol) {
+        if (!(dt_fixed > 0.0)) return fail(s, PF_EINVAL, "dt_fixed must be > 0");
+        for (;;) {
+            const double rem = t_end - s->t;
+            if (rem <= 1e-12 * dt_fixed) break;
+            double h = dt_fixed;
+            bool last = false;
+            if (rem <= h * (1.0 + 1e-10)) {
+                h = rem;
+                last = true;
+            }
+            int ns = s->ssp_s;
+            if (integ == PF_RKL1 || integ == PF_RKL2) ns = stage_count(integ == PF_RKL1 ? 1 : 2, h, dte);
+            int res, aux;
+            if ((rc = do_step<T>(s, integ, ns, h, false, &res, &aux))) return rc;
+            s->cur = res;
+            s->st.accepted++;
+            s->trace.insert(s->trace.end(), {h, (double)ns, 0.0, 1.0});
+            s->t = last ? t_end : s->t + h;
+            s->st.last_dt = h;
+        }
+        s->st.t = s->t;
+        return PF_OK;
+    }
+    if (integ != PF_RKL1 && integ != PF_RKL2 && integ != PF_SSP_S2)
+        return fail(s, PF_EUNSUPPORTED, "adaptive stepping needs RKL1, RKL2 or SSP(s)2");
+    const int order = method_order(integ);
+    const double dtmax_ratio = tol->dt_max_over_dte > 0.0 ? tol->dt_max_over_dte : 200.0;
+    double dtmax = dtmax_ratio * dte;
+    if (integ == PF_SSP_S2) dtmax = std::min(dtmax, 0.9 * (s->ssp_s - 1) * dte);
+    // the controller (bias, accepted history, proposed step) carries over from
+    // the previous pf_run_to of this handle; pf_init_fields resets it
+    double dt = tol->dt0 > 0.0 ? tol->dt0 : (s->dt_next > 0.0 ? s->dt_next : 0.9 * dte);
+    int nonfinite = 0;
+    for (;;) {
+        const double rem = t_end - s->t;
+        double h = std::min(dt, dtmax);
+        if (rem <= 1e-12 * h) break;
+        bool last = false;
+        if (rem <= h * (1.0 + 1e-10)) {
+            h = rem;
+            last = true;
+        }
+        if (!last && h < 1e-12 * dte) return fail(s, PF_EDTMIN, "adaptive step underflow (dt = %g)", h);
+        int ns = s->ssp_s;
+        if (integ != PF_SSP_S2) ns = stage_count(order, h, dte);
+        int res, aux;
+        if ((rc = do_step<T>(s, integ, ns, h, true, &res, &aux))) return rc;
+        double e;
+        if ((rc = error_norm<T>(s, integ == PF_SSP_S2 ? 1 : 0, h, bp<T>(s, s->cur), bp<T>(s, res),
+                                bp<T>(s, aux), *tol, &e, nullptr)))
+            return rc;
+        bool acc;
+        const double hn = ctrl_update(s->ctrl, order, e, h, acc);
+        s->trace.insert(s->trace.end(), {h, (double)ns, e, acc ? 1.0 : 0.0});
+        s->st.last_err = e;
+        if (acc) {
+            s->cur = res;
+            s->t = last ? t_end : s->t + h;
+            s->st.accepted++;
+            s->st.last_dt = h;
+            nonfinite = 0;
+        } else {
+            s->st.rejected++;
+            if (!std::isfinite(e) && ++nonfinite >= 3) {
+                s->st.t = s->t;
+                return fail(s, PF_ENONFINITE, "non-finite error norm three times in a row");
+            }
+        }
+        dt = hn;
+        s->dt_next = hn;
+    }
+    s->st.t = s->t;
+    return PF_OK;
+}
+
+template <typename T>
+pf_status upload(pf_sim *s, const double *phi, const double *c) {
+    const long long V = s->V;
+    std::vector<T> h((size_t)s->F * V);
+    for (long long i = 0; i < (long long)s->N * V; ++i) h[i] = (T)phi[i];
+    if (s->with_c) {
+        const double *cc = c ? c : phi + (long long)s->N * V;
+        for (long long i = 0; i < V; ++i) h[(long long)s->N * V + i] = (T)cc[i];
+    }
+    HIPCHK(s, hipMemcpyAsync(s->buf[s->cur], h.data(), state_bytes(s), hipMemcpyHostToDevice,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return PF_OK;
+}
+
+template <typename T>
+pf_status download(pf_sim *s, const void *dev, double *phi, double *c) {
+    const long long V = s->V;
+    std::vector<T> h((size_t)s->F * V);
+    HIPCHK(s, hipMemcpyAsync(h.data(), dev, state_bytes(s), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (phi)
+        for (long long i = 0; i < (long long)s->N * V; ++i) phi[i] = (double)h[i];
+    if (c && s->with_c)
+        for (long long i = 0; i < V; ++i) c[i] = (double)h[(long long)s->N * V + i];
+    return PF_OK;
+}
+
+#define DISPATCH(s, fn, ...) \
+    ((s)->prec == PF_FP64 ? fn<double>(s, __VA_ARGS__) : fn<float>(s, __VA_ARGS__))
+
+pf_status need_fields(pf_sim *s) {
+    return s->have_fields ? PF_OK : fail(s, PF_ESTATE, "fields not initialised");
+}
+
+struct CkptHeader {
+    char magic[8];
+    int prec, F;
+    long long V;
+    double t, dt_next;
+    double b, E1, E2, h1, h2;
+    int nhist, pad;
+    pf_stats st;
+};
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+pf_status pf_create(const pf_params *p, pf_sim **out) {
+    if (!p || !out) return PF_EINVAL;
+    *out = nullptr;
+    if (p->dim != 2 && p->dim != 3) return PF_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1 || (p->dim == 2 && p->nz != 1)) return PF_EINVAL;
+    if (p->n_phi < 1 || p->n_phi > NMAX || p->n_types < 1 || p->n_types > TMAX) return PF_EINVAL;
+    if (!(p->dx > 0) || !(p->W > 0) || !p->type_of || !p->gamma || !p->mob || !p->k || !p->c0 ||
+        !p->D)
+        return PF_EINVAL;
+    if (p->prec != PF_FP64 && p->prec != PF_FP32) return PF_EUNSUPPORTED;
+    if (!nphi_supported(p->n_phi)) return PF_EUNSUPPORTED;
+    for (int a = 0; a < p->n_phi; ++a)
+        if (p->type_of[a] < 0 || p->type_of[a] >= p->n_types) return PF_EINVAL;
+    for (int t = 0; t < p->n_types; ++t)
+        if (!(p->k[t] > 0)) return PF_EINVAL;
+    pf_sim *s = new (std::nothrow) pf_sim();
+    if (!s) return PF_ENOMEM;
+    s->dim = p->dim; s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
+    s->N = p->n_phi; s->T = p->n_types; s->with_c = p->with_c ? 1 : 0;
+    s->ssp_s = p->ssp_stages >= 2 ? p->ssp_stages : 5;
+    s->prec = p->prec;
+    s->dx = p->dx; s->W = p->W;
+    s->type_of.assign(p->type_of, p->type_of + p->n_phi);
+    const int TT = p->n_types * p->n_types;
+    s->gamma.assign(p->gamma, p->gamma + TT);
+    s->mob.assign(p->mob, p->mob + TT);
+    s->k.assign(p->k, p->k + p->n_types);
+    s->c0.assign(p->c0, p->c0 + p->n_types);
+    s->D.assign(p->D, p->D + p->n_types);
+    s->F = s->N + s->with_c;
+    s->V = (long long)p->nx * p->ny * p->nz;
+    s->esz = p->prec == PF_FP64 ? sizeof(double) : sizeof(float);
+    pf_status rc = PF_OK;
+    if (p->prec == PF_FP64) {
+        DevParams<double> P;
+        fill_params(s, P);
+        if (hipMalloc(&s->dparams, sizeof P) != hipSuccess) rc = PF_ENOMEM;
+        else if (hipMemcpy(s->dparams, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess) rc = PF_EHIP;
+    } else {
+        DevParams<float> P;
+        fill_params(s, P);
+        if (hipMalloc(&s->dparams, sizeof P) != hipSuccess) rc = PF_ENOMEM;
+        else if (hipMemcpy(s->dparams, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess) rc = PF_EHIP;
+    }
+    if (!rc && hipMalloc(&s->dres, 8 * sizeof(double)) != hipSuccess) rc = PF_ENOMEM;
+    if (!rc && hipHostMalloc(&s->hres, 8 * sizeof(double)) != hipSuccess) rc = PF_ENOMEM;
+    if (!rc) rc = ensure_buf(s, 0);
+    if (rc) {
+        pf_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return PF_OK;
+}
+
+pf_status pf_destroy(pf_sim *s) {
+    if (!s) return PF_EINVAL;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    else hipDeviceSynchronize();
+    for (int i = 0; i < NBUF; ++i)
+        if (s->buf[i]) hipFree(s->buf[i]);
+    if (s->dparams) hipFree(s->dparams);
+    if (s->red) hipFree(s->red);
+    if (s->redn) hipFree(s->redn);
+    if (s->dres) hipFree(s->dres);
+    if (s->hres) hipHostFree(s->hres);
+    for (auto &p : s->pending) {
+        hipEventDestroy(p.e0);
+        hipEventDestroy(p.e1);
+    }
+    for (auto e : s->pool) hipEventDestroy(e);
+    delete s;
+    return PF_OK;
+}
+
+pf_status pf_set_stream(pf_sim *s, void *stream) {
+    if (!s) return PF_EINVAL;
+    collect_timing(s);
+    s->stream = (hipStream_t)stream;
+    return PF_OK;
+}
+
+pf_status pf_init_fields(pf_sim *s, const double *phi, const double *c, double t0) {
+    if (!s || !phi) return PF_EINVAL;
+    pf_status rc = DISPATCH(s, upload, phi, c);
+    if (rc) return rc;
+    s->t = t0;
+    s->have_fields = true;
+    s->ctrl = Ctrl();
+    s->dt_next = 0.0;
+    return PF_OK;
+}
+
+pf_status pf_init_fields_device(pf_sim *s, const void *state, double t0) {
+    if (!s || !state) return PF_EINVAL;
+    HIPCHK(s, hipMemcpyAsync(s->buf[s->cur], state, state_bytes(s), hipMemcpyDeviceToDevice,
+                             s->stream));
+    s->t = t0;
+    s->have_fields = true;
+    s->ctrl = Ctrl();
+    s->dt_next = 0.0;
+    return PF_OK;
+}
+
+pf_status pf_get_fields(pf_sim *s, double *phi, double *c, double *t) {
+    if (!s) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    if (t) *t = s->t;
+    if (!phi && !c) return PF_OK;
+    return DISPATCH(s, download, s->buf[s->cur], phi, c);
+}
+
+pf_status pf_get_fields_device(pf_sim *s, void *state) {
+    if (!s || !state) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    HIPCHK(s, hipMemcpyAsync(state, s->buf[s->cur], state_bytes(s), hipMemcpyDeviceToDevice,
+                             s->stream));
+    return PF_OK;
+}
+
+pf_status pf_rhs_device(pf_sim *s, void *out) {
+    if (!s || !out) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    if (s->prec == PF_FP64)
+        return stage<double>(s, K_RHS, bp<double>(s, s->cur), nullptr, nullptr, nullptr,
+                             (double *)out, nullptr, 0, 0, 0, 0, 0, 0, 0);
+    return stage<float>(s, K_RHS, bp<float>(s, s->cur), nullptr, nullptr, nullptr, (float *)out,
+                        nullptr, 0, 0, 0, 0, 0, 0, 0);
+}
+
+pf_status pf_rhs(pf_sim *s, double *dphi, double *dc) {
+    if (!s || !dphi) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    const int w = work_index(s, 0);
+    if (pf_status rc = ensure_buf(s, w)) return rc;
+    if (pf_status rc = pf_rhs_device(s, s->buf[w])) return rc;
+    return DISPATCH(s, download, s->buf[w], dphi, dc);
+}
+
+pf_status pf_stable_dt(pf_sim *s, double *dte) {
+    if (!s || !dte) return PF_EINVAL;
+    *dte = stable_dt(s);
+    return PF_OK;
+}
+
+pf_status pf_stage_count(pf_sim *s, pf_integrator integ, double dt, int *ns) {
+    if (!s || !ns) return PF_EINVAL;
+    switch (integ) {
+    case PF_FEULER: *ns = 1; return PF_OK;
+    case PF_SSP_S2: *ns = s->ssp_s; return PF_OK;
+    case PF_SSP_10_4: *ns = 10; return PF_OK;
+    case PF_RKL1:
+    case PF_RKL2: {
+        const int v = stage_count(integ == PF_RKL1 ? 1 : 2, dt, stable_dt(s));
+        if (v < 0) return fail(s, PF_EINVAL, "dt must be > 0");
+        *ns = v;
+        return PF_OK;
+    }
+    default: return PF_EINVAL;
+    }
+}
+
+pf_status pf_step(pf_sim *s, pf_integrator integ, double dt, pf_stats *stats) {
+    if (!s) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    if (!(dt > 0.0)) return fail(s, PF_EINVAL, "dt must be > 0");
+    s->st = pf_stats{};
+    int ns = s->ssp_s;
+    if (integ == PF_RKL1 || integ == PF_RKL2) ns = stage_count(integ == PF_RKL1 ? 1 : 2, dt, stable_dt(s));
+    int res, aux;
+    pf_status rc = s->prec == PF_FP64 ? do_step<double>(s, integ, ns, dt, false, &res, &aux)
+                                      : do_step<float>(s, integ, ns, dt, false, &res, &aux);
+    if (rc) return rc;
+    s->cur = res;
+    s->t += dt;
+    s->st.accepted = 1;
+    s->st.t = s->t;
+    s->st.last_dt = dt;
+    if (stats) *stats = s->st;
+    return PF_OK;
+}
+
+pf_status pf_run_to(pf_sim *s, pf_integrator integ, double t_end, const pf_tol *tol,
+                    double dt_fixed, pf_stats *stats) {
+    if (!s) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    s->st = pf_stats{};
+    pf_status rc = s->prec == PF_FP64 ? run_to_t<double>(s, integ, t_end, tol, dt_fixed)
+                                      : run_to_t<float>(s, integ, t_end, tol, dt_fixed);
+    s->st.t = s->t;
+    if (stats) *stats = s->st;
+    return rc;
+}
+
+pf_status pf_error_norm(pf_sim *s, int kind, double dt, const void *u_old, const void *u_new,
+                        const void *aux, const pf_tol *tol, double *norm, long long *ndof) {
+    if (!s || !u_old || !u_new || !aux || !tol || !norm) return PF_EINVAL;
+    if (kind != 0 && kind != 1) return PF_EINVAL;
+    if (s->prec == PF_FP64)
+        return error_norm<double>(s, kind, dt, (const double *)u_old, (const double *)u_new,
+                                  (const double *)aux, *tol, norm, ndof);
+    return error_norm<float>(s, kind, dt, (const float *)u_old, (const float *)u_new,
+                             (const float *)aux, *tol, norm, ndof);
+}
+
+pf_status pf_diagnostics(pf_sim *s, double out[5]) {
+    if (!s || !out) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    const int nb = 1024;
+    if (pf_status rc = ensure_red(s, nb)) return rc;
+    Pending p;
+    begin_timed(s, FAM_RED, p);
+    hipError_t e = s->prec == PF_FP64
+                       ? launch_diag<double>((const double *)s->buf[s->cur], s->N, s->with_c, s->V,
+                                             s->red, nb, s->stream)
+                       : launch_diag<float>((const float *)s->buf[s->cur], s->N, s->with_c, s->V,
+                                            s->red, nb, s->stream);
+    if (e != hipSuccess) return fail(s, PF_EHIP, "diag launch: %s", hipGetErrorString(e));
+    HIPCHK(s, launch_finalize_diag(s->red, nb, s->dres, s->stream));
+    end_timed(s, p);
+    HIPCHK(s, hipMemcpyAsync(s->hres, s->dres, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int k = 0; k < 5; ++k) out[k] = s->hres[k];
+    return PF_OK;
+}
+
+pf_status pf_conservation(pf_sim *s, double *sum_c) {
+    if (!s || !sum_c) return PF_EINVAL;
+    double d[5];
+    pf_status rc = pf_diagnostics(s, d);
+    if (rc) return rc;
+    *sum_c = d[0];
+    return PF_OK;
+}
+
+pf_status pf_get_trace(pf_sim *s, double *buf, long long cap, long long *n) {
+    if (!s || !n) return PF_EINVAL;
+    const long long rows = (long long)s->trace.size() / 4;
+    *n = rows;
+    if (buf && cap > 0)
+        std::memcpy(buf, s->trace.data(), sizeof(double) * 4 * (size_t)std::min(rows, cap));
+    return PF_OK;
+}
+
+pf_status pf_get_state(pf_sim *s, void *buf, size_t *len) {
+    if (!s || !len) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    const size_t need = sizeof(CkptHeader) + state_bytes(s);
+    if (!buf) {
+        *len = need;
+        return PF_OK;
+    }
+    if (*len < need) return fail(s, PF_EINVAL, "buffer too small (%zu < %zu)", *len, need);
+    CkptHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "PFCKPT1", 8);
+    h.prec = s->prec; h.F = s->F; h.V = s->V; h.t = s->t; h.dt_next = s->dt_next;
+    h.b = s->ctrl.b; h.E1 = s->ctrl.E1; h.E2 = s->ctrl.E2; h.h1 = s->ctrl.h1; h.h2 = s->ctrl.h2;
+    h.nhist = s->ctrl.nhist; h.st = s->st;
+    std::memcpy(buf, &h, sizeof h);
+    HIPCHK(s, hipMemcpyAsync((char *)buf + sizeof h, s->buf[s->cur], state_bytes(s),
+                             hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *len = need;
+    return PF_OK;
+}
+
+pf_status pf_set_state(pf_sim *s, const void *buf, size_t len) {
+    if (!s || !buf) return PF_EINVAL;
+    CkptHeader h;
+    if (len < sizeof h) return fail(s, PF_EINVAL, "checkpoint too short");
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, "PFCKPT1", 8) != 0 || h.prec != s->prec || h.F != s->F || h.V != s->V ||
+        len < sizeof h + state_bytes(s))
+        return fail(s, PF_EINVAL, "checkpoint does not match this handle");
+    HIPCHK(s, hipMemcpyAsync(s->buf[s->cur], (const char *)buf + sizeof h, state_bytes(s),
+                             hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->t = h.t; s->dt_next = h.dt_next;
+    s->ctrl.b = h.b; s->ctrl.E1 = h.E1; s->ctrl.E2 = h.E2; s->ctrl.h1 = h.h1; s->ctrl.h2 = h.h2;
+    s->ctrl.nhist = h.nhist; s->st = h.st;
+    s->have_fields = true;
+    return PF_OK;
+}
+
+pf_status pf_set_tiling(pf_sim *s, int tx, int zchunk) {
+    if (!s) return PF_EINVAL;
+    if (tx != 32 && tx != 64 && tx != 128) return fail(s, PF_EINVAL, "tx must be 32, 64 or 128");
+    if (zchunk < 1) return fail(s, PF_EINVAL, "zchunk must be >= 1");
+    s->tx = tx;
+    s->zchunk = zchunk;
+    return PF_OK;
+}
+
+pf_status pf_get_tiling(pf_sim *s, int *tx, int *zchunk) {
+    if (!s || !tx || !zchunk) return PF_EINVAL;
+    *tx = s->tx;
+    *zchunk = s->zchunk;
+    return PF_OK;
+}
+
+pf_status pf_autotune(pf_sim *s, int *tx_out, int *zc_out, double *best_ms) {
+    if (!s) return PF_EINVAL;
+    if (pf_status rc = need_fields(s)) return rc;
+    const int w = work_index(s, 0);
+    if (pf_status rc = ensure_buf(s, w)) return rc;
+    const int txs[3] = {32, 64, 128};
+    const int zcs3[5] = {4, 8, 16, 32, 64};
+    const int nz_cands = s->dim == 3 ? 5 : 1;
+    hipEvent_t e0, e1;
+    HIPCHK(s, hipEventCreate(&e0));
+    HIPCHK(s, hipEventCreate(&e1));
+    double best = 1e300;
+    int btx = s->tx, bzc = s->zchunk;
+    const bool was_timing = s->timing;
+    s->timing = false;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < nz_cands; ++j) {
+            s->tx = txs[i];
+            s->zchunk = s->dim == 3 ? zcs3[j] : 1;
+            if (s->dim == 3 && s->zchunk > s->nz) continue;
+            pf_status rc = pf_rhs_device(s, s->buf[w]);  // warm-up
+            if (rc) { s->timing = was_timing; return rc; }
+            HIPCHK(s, hipEventRecord(e0, s->stream));
+            for (int r = 0; r < 5; ++r)
+                if ((rc = pf_rhs_device(s, s->buf[w]))) { s->timing = was_timing; return rc; }
+            HIPCHK(s, hipEventRecord(e1, s->stream));
+            HIPCHK(s, hipEventSynchronize(e1));
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms / 5.0 < best) {
+                best = ms / 5.0;
+                btx = s->tx;
+                bzc = s->zchunk;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    s->timing = was_timing;
+    s->tx = btx;
+    s->zchunk = bzc;
+    if (tx_out) *tx_out = btx;
+    if (zc_out) *zc_out = bzc;
+    if (best_ms) *best_ms = best;
+    return PF_OK;
+}
+
+pf_status pf_set_timing(pf_sim *s, int enable) {
+    if (!s) return PF_EINVAL;
+    collect_timing(s);
+    s->timing = enable != 0;
+    for (int f = 0; f < 5; ++f) {
+        s->fam_ms[f] = 0.0;
+        s->fam_n[f] = 0;
+    }
+    return PF_OK;
+}
+
+pf_status pf_get_kernel_time(pf_sim *s, int family, double *ms, long long *launches) {
+    if (!s || family < 0 || family > 4 || !ms) return PF_EINVAL;
+    collect_timing(s);
+    *ms = s->fam_ms[family];
+    if (launches) *launches = s->fam_n[family];
+    return PF_OK;
+}
+
+int pf_supported_nphi(int *out, int cap) { return supported_nphi_list(out, cap); }
+
+const char *pf_last_error(const pf_sim *s) { return s ? s->err.c_str() : "null handle"; }
+
+}  // extern "C"

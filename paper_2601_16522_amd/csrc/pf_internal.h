@@ -1,0 +1,89 @@
+// pf_internal.h -- structures shared by the gfx950 kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pf {
+
+constexpr int NMAX = 16;  // largest number of order parameters a kernel is built for
+constexpr int TMAX = 4;   // largest number of thermodynamic types
+
+// Per-simulation constants, resident in device memory and read through the
+// scalar cache (every address is uniform across the wavefront).  Pair tables
+// are full n_phi x n_phi, row-major; per-phase tables are indexed by phase.
+template <typename T>
+struct DevParams {
+    int nx, ny, nz, n_phi, with_c, n_types;
+    long long V;   // cells per plane-field (nx*ny*nz)
+    T idx2;        // 1/dx^2
+    T A[NMAX * NMAX];
+    T B[NMAX * NMAX];
+    T L[NMAX * NMAX];
+    T c0[NMAX];    // c0 of the phase's type
+    T ik[NMAX];    // 1/k of the phase's type
+    T Dk[NMAX];    // D/k of the phase's type
+    int tphi[NMAX];
+    T k2t[TMAX];   // 2k per type (grand potential)
+    T c0t[TMAX];   // c0 per type
+};
+
+// Stage kinds of the fused stencil kernel.  Each evaluates rhs(y1) at the
+// cell (eqs. phieq, ceq), forms one stage combination and projects the phi
+// planes onto the simplex (except RHS and EST, which project nothing).
+enum StageKind : int {
+    K_RHS = 0,          // out = rhs(y1)
+    K_EULER = 1,        // out = S(y1 + a r); out2 (optional) = r
+    K_SSP2_FINAL = 2,   // out = S(((a y1 + u0) + b r) / c)
+    K_SSP104_S5 = 3,    // y = S(y1 + a r); out2 = b u0 + c y; out = S(d out2 - e y)
+    K_SSP104_FINAL = 4, // out = S((u0 + a y1) + b r)
+    K_RKL1 = 5,         // out = S((a y1 + b y2) + c r)
+    K_RKL2_FIRST = 6,   // y* = y1 + a r; out = S(y*); out2 = R0 (corrected where S acted)
+    K_RKL2 = 7,         // out = S(((a u0 + b y1) + c y2) + d ((e r) + (f r0)))
+    K_EST = 8           // Sommeijer estimate of u^{n+1} = y1 against u^n = u0, R0 = r0
+};
+
+template <typename T>
+struct StageArgs {
+    const DevParams<T> *P;
+    const T *y1;    // stencil input
+    const T *y2;
+    const T *u0;
+    const T *r0;
+    T *out;
+    T *out2;
+    double *red;    // per-block partial sums (EST)
+    long long *redn;
+    int kind;
+    T a, b, c, d, e, f;
+    // estimator
+    T r_phi, a_phi, r_c, a_c, dt6, hdt;
+    // tiling
+    int tx, ty;      // tile (tx lanes in x, ty rows in y), tx*ty == blockDim.x
+    int zchunk;      // z planes per block (3D)
+    int ntx, nty, nzc;
+    int ntiles;
+};
+
+// Launchers (implemented in pf_kernels.hip).  Return hipSuccess or the launch
+// error; they never synchronise.
+template <typename T>
+hipError_t launch_stage(int dim, int nphi, const StageArgs<T> &args, int nblocks,
+                        hipStream_t stream);
+template <typename T>
+hipError_t launch_embed_est(const DevParams<T> *P, int nphi, int with_c, long long V,
+                            const T *unew, const T *z, const T *uold, T r_phi, T a_phi, T r_c,
+                            T a_c, double *red, long long *redn, int nblocks,
+                            hipStream_t stream);
+template <typename T>
+hipError_t launch_diag(const T *u, int nphi, int with_c, long long V, double *red,
+                       int nblocks, hipStream_t stream);
+hipError_t launch_finalize_norm(const double *red, const long long *redn, int nparts,
+                                double *out, hipStream_t stream);
+hipError_t launch_finalize_diag(const double *red, int nparts, double *out,
+                                hipStream_t stream);
+
+bool nphi_supported(int nphi);
+int supported_nphi_list(int *out, int cap);
+
+}  // namespace pf
