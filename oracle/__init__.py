@@ -101,6 +101,7 @@ def lib():
         L.pfo_energy.argtypes = [P, D]
         L.pfo_energy.restype = C.c_double
         L.pfo_pair_constants.argtypes = [P, D, D, D]
+        L.pfo_num_threads.restype = I
         _lib = L
     return _lib
 
@@ -318,3 +319,7 @@ def pair_constants(P: Params):
 
 def _stats(st: _Stats) -> Stats:
     return Stats(st.rhs_evals, st.stages, st.accepted, st.rejected, st.t, st.last_dt, st.last_err)
+
+
+def num_threads() -> int:
+    return lib().pfo_num_threads()

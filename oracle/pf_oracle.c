@@ -27,6 +27,7 @@
  *     worked example of either).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -874,3 +875,6 @@ double pfo_energy(const pfo_params *P, const double *u) {
     }
     return Etot;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int pfo_num_threads(void) { return omp_get_max_threads(); }

@@ -35,6 +35,7 @@ struct Ctrl {
 struct Pending {
     unsigned mask;
     hipEvent_t e0, e1;
+    int count;  // launches between the two events
 };
 
 enum Family : unsigned {
@@ -159,8 +160,25 @@ hipEvent_t get_event(pf_sim *s) {
     return e;
 }
 
+// Timing records one event pair around a run of back-to-back launches of one
+// family (the inner stages of a step, the stages of a fixed-step run, one
+// estimator launch), not around every launch, so that the events add no gap
+// between the kernels they measure.
+hipEvent_t mark(pf_sim *s) {
+    if (!s->timing) return nullptr;
+    hipEvent_t e = get_event(s);
+    hipEventRecord(e, s->stream);
+    return e;
+}
+
+void add_interval(pf_sim *s, unsigned mask, hipEvent_t e0, hipEvent_t e1, int count) {
+    if (!s->timing || !e0 || !e1 || count <= 0) return;
+    s->pending.push_back(Pending{mask, e0, e1, count});
+}
+
 void begin_timed(pf_sim *s, unsigned mask, Pending &p) {
     p.mask = mask;
+    p.count = 1;
     p.e0 = p.e1 = nullptr;
     if (!s->timing) return;
     p.e0 = get_event(s);
@@ -177,17 +195,23 @@ void end_timed(pf_sim *s, Pending &p) {
 void collect_timing(pf_sim *s) {
     if (s->pending.empty()) return;
     hipStreamSynchronize(s->stream);
+    // an event may close one interval and open the next: return each event to
+    // the pool once
+    std::vector<hipEvent_t> seen;
     for (auto &p : s->pending) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, p.e0, p.e1);
         for (int f = 0; f < 5; ++f)
             if (p.mask & (1u << f)) {
                 s->fam_ms[f] += ms;
-                s->fam_n[f] += 1;
+                s->fam_n[f] += p.count;
             }
-        s->pool.push_back(p.e0);
-        s->pool.push_back(p.e1);
+        seen.push_back(p.e0);
+        seen.push_back(p.e1);
     }
+    std::sort(seen.begin(), seen.end());
+    seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+    for (auto e : seen) s->pool.push_back(e);
     s->pending.clear();
 }
 
@@ -378,11 +402,9 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     A.nty = nty;
     A.nzc = nzc;
     A.ntiles = ntiles;
-    Pending p;
-    begin_timed(s, fam | FAM_STAGE, p);
+    (void)fam;
     hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
     if (err != hipSuccess) return fail(s, PF_EHIP, "stage kernel launch: %s", hipGetErrorString(err));
-    end_timed(s, p);
     return PF_OK;
 }
 
@@ -444,7 +466,29 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
 // scheme of Alg. sts1 is requested for a fixed step.
 // ---------------------------------------------------------------------------
 template <typename T>
-pf_status do_step(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *res, int *aux) {
+pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *res, int *aux,
+                       hipEvent_t *e_inner);
+
+// One step with its stage kernels timed as a run (see mark()); timed == false
+// leaves the timing to the caller (a fixed forward-Euler run times the whole
+// sequence of steps).
+template <typename T>
+pf_status do_step(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *res, int *aux,
+                  bool timed = true) {
+    const long long st0 = s->st.stages;
+    hipEvent_t e0 = timed ? mark(s) : nullptr, ei = nullptr;
+    pf_status rc = do_step_impl<T>(s, integ, nst, dt, want_aux, res, aux, timed ? &ei : nullptr);
+    if (rc || !timed) return rc;
+    hipEvent_t e1 = mark(s);
+    const int n = (int)(s->st.stages - st0);
+    add_interval(s, FAM_STAGE | (integ == PF_FEULER ? FAM_FE : 0u), e0, e1, n);
+    if (integ == PF_RKL2) add_interval(s, FAM_RKL2, ei, e1, n - 1);
+    return PF_OK;
+}
+
+template <typename T>
+pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *res, int *aux,
+                       hipEvent_t *e_inner) {
     const int U = s->cur;
     *aux = -1;
     auto W = [&](int k) { return work_index(s, k); };
@@ -552,6 +596,7 @@ pf_status do_step(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *
         if (rc) return rc;
         s->st.rhs_evals++;
         s->st.stages++;
+        if (e_inner) *e_inner = mark(s);
         for (int j = 2; j <= ns; ++j) {
             const int jc = j % 3, jp = (j - 1) % 3, jpp = (j - 2) % 3;
             if (jc == 0) slot[0] = slot0_store;
@@ -583,6 +628,9 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
     pf_status rc;
     if (!tol) {
         if (!(dt_fixed > 0.0)) return fail(s, PF_EINVAL, "dt_fixed must be > 0");
+        const bool fe = integ == PF_FEULER;
+        hipEvent_t e_run = fe ? mark(s) : nullptr;
+        const long long st_run = s->st.stages;
         for (;;) {
             const double rem = t_end - s->t;
             if (rem <= 1e-12 * dt_fixed) break;
@@ -595,13 +643,14 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
             int ns = s->ssp_s;
             if (integ == PF_RKL1 || integ == PF_RKL2) ns = stage_count(integ == PF_RKL1 ? 1 : 2, h, dte);
             int res, aux;
-            if ((rc = do_step<T>(s, integ, ns, h, false, &res, &aux))) return rc;
+            if ((rc = do_step<T>(s, integ, ns, h, false, &res, &aux, !fe))) return rc;
             s->cur = res;
             s->st.accepted++;
             s->trace.insert(s->trace.end(), {h, (double)ns, 0.0, 1.0});
             s->t = last ? t_end : s->t + h;
             s->st.last_dt = h;
         }
+        if (fe) add_interval(s, FAM_STAGE | FAM_FE, e_run, mark(s), (int)(s->st.stages - st_run));
         s->st.t = s->t;
         return PF_OK;
     }

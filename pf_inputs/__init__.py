@@ -122,6 +122,21 @@ def _grid_coords(shape_zyx, z0=0, z1=None):
     return zz, yy, xx
 
 
+def _parallel_slabs(fn, starts) -> None:
+    """Run fn over independent z slabs on a thread pool (numpy and the k-d tree
+    release the GIL); results are identical to a sequential loop."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    starts = list(starts)
+    workers = max(1, min(16, os.cpu_count() or 1, len(starts)))
+    if workers == 1:
+        for z0 in starts:
+            fn(z0)
+        return
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(fn, starts))
+
+
 def voronoi_fields(shape_zyx, seeds: np.ndarray, n_fields: int, W: float,
                    knear: int = 4, slab: int = 16) -> np.ndarray:
     """Periodic Voronoi grains smoothed by eq. profile.
@@ -141,11 +156,12 @@ def voronoi_fields(shape_zyx, seeds: np.ndarray, n_fields: int, W: float,
     k = min(knear, len(seeds))
     out = np.zeros((n_fields, nz, ny, nx))
     zstep = slab if dim == 3 else 1
-    for z0 in range(0, nz, zstep):
+
+    def one(z0):
         z1 = min(nz, z0 + zstep)
         zz, yy, xx = _grid_coords(shape_zyx, z0, z1)
         X = np.stack([xx.ravel(), yy.ravel()] + ([zz.ravel()] if dim == 3 else []), axis=1)
-        _, idx = tree.query(X, k=k, workers=-1)
+        _, idx = tree.query(X, k=k, workers=1)
         idx = idx.reshape(len(X), k)
         # minimum-image displacement from X to each of the k seeds
         disp = seeds[idx] - X[:, None, :]
@@ -171,8 +187,11 @@ def voronoi_fields(shape_zyx, seeds: np.ndarray, n_fields: int, W: float,
         plane = np.zeros((n_fields, len(X)))
         rows = np.arange(len(X))
         for j in range(k):
-            np.add.at(plane, (fld[:, j], rows), vals[:, j])
+            # rows are distinct within one j, so plain fancy-index accumulation is exact
+            plane[fld[:, j], rows] += vals[:, j]
         out[:, z0:z1] = plane.reshape(n_fields, z1 - z0, ny, nx)
+
+    _parallel_slabs(one, range(0, nz, zstep))
     return out
 
 
@@ -188,11 +207,12 @@ def add_spheres(phi_grains: np.ndarray, centers: np.ndarray, radii: np.ndarray, 
     from scipy.spatial import cKDTree
     tree = cKDTree(centers, boxsize=box)
     kq = min(8, len(centers))
-    for z0 in range(0, nz, zstep):
+
+    def one(z0):
         z1 = min(nz, z0 + zstep)
         zz, yy, xx = _grid_coords((nz, ny, nx), z0, z1)
         X = np.stack([xx.ravel(), yy.ravel()] + ([zz.ravel()] if dim == 3 else []), axis=1)
-        dist, idx = tree.query(X, k=kq, workers=-1)
+        dist, idx = tree.query(X, k=kq, workers=1)
         dist = dist.reshape(len(X), kq)
         idx = idx.reshape(len(X), kq)
         pore = np.max(profile(radii[idx] - dist, W), axis=1)
@@ -201,6 +221,8 @@ def add_spheres(phi_grains: np.ndarray, centers: np.ndarray, radii: np.ndarray, 
         scale = np.where(s > 0, (1.0 - pore) / np.where(s > 0, s, 1.0), 0.0)
         out[:nf, z0:z1] = (g * scale).reshape(nf, z1 - z0, ny, nx)
         out[nf, z0:z1] = pore.reshape(z1 - z0, ny, nx)
+
+    _parallel_slabs(one, range(0, nz, zstep))
     return out
 
 
