@@ -23,6 +23,8 @@ import argparse
 import hashlib
 import json
 import math
+
+import numpy as np
 import os
 import sys
 import time
@@ -86,24 +88,31 @@ def copy_calibration(mib: int, reps: int):
     print(json.dumps({"copy_calibration_bytes": 4 * n, "reps": reps}), flush=True)
 
 
-def copy_bandwidth(gib: int = 4, reps: int = 5) -> float:
-    """Streaming device-to-device copy of `gib` GiB (read + write counted), GB/s:
-    the practical HBM ceiling to set the stencil kernels against."""
+def copy_bandwidth(gib: int = 4, reps: int = 5) -> dict:
+    """Streaming references on `gib` GiB arrays, GB/s (all bytes read and
+    written): a device copy and a two-input elementwise add.  They set the
+    practical HBM ceiling the stencil kernels are compared against."""
     import torch
     n = gib * (1 << 30) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    c = torch.empty_like(a)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del a, b
+
+    def rate(fn, nbytes):
+        fn()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
+
+    out = {"copy": rate(lambda: b.copy_(a), 8 * n),
+           "add": rate(lambda: torch.add(a, b, out=c), 12 * n)}
+    del a, b, c
     torch.cuda.empty_cache()
-    return 2 * 4 * n / (ms / 1e3) / 1e9
+    return out
 
 
 def cpu_baseline(wl, integ: str, t_end: float, tol_kw: dict, dt_fixed: float, sample_note: str):
@@ -122,12 +131,109 @@ def cpu_baseline(wl, integ: str, t_end: float, tol_kw: dict, dt_fixed: float, sa
             f"{el:.1f} s, FP64, {cores} OpenMP threads"}
 
 
+def area_slope_error(u0, u, t, M, dx=1.0, gamma=1.0):
+    """Relative error of the mean area rate (A(t) - A(0))/t of the grain
+    (phase 1) against the curvature-flow law -2 pi M gamma (Sec. 5.2.1)."""
+    rate = (u[1].sum() - u0[1].sum()) * dx * dx / t
+    return abs(rate / (-2 * math.pi * M * gamma) - 1.0)
+
+
+def batch_bench(args):
+    """96 independent shrinking-grain instances (side 64..512 by seed, R in
+    [0.2, 0.4] side, M in [0.5, 2]): 2000 forward-Euler steps each at 0.9 dt_e,
+    as one fused launch per step replayed from a hipGraph in FP32, against the
+    plain FP64 form run instance by instance."""
+    import torch
+    import paper_2601_16522_amd as pf
+    import pf_inputs as pi
+    nsteps = 2000
+    wls = pi.batch_instances()
+    cells = sum(w.cells for w in wls)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    b = pf.Batch([w.param_dict() for w in wls], prec=args.prec)
+    b.set_stream(stream)
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
+    t_end = [nsteps * d for d in dts]
+    nb = b.autotune()[0] if not args.no_autotune else None
+    K = 50
+
+    def one():
+        for i, w in enumerate(wls):
+            b.init_fields(i, w.u0)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        b.run_to(t_end, dt=dts, graph_steps=K)
+        e1.record(stream)
+        stream.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    total, ev_ms = 0.0, 0.0
+    for k in range(args.steps):
+        el, ms = one()
+        total += el
+        ev_ms += ms
+        print(f"# batch step {k}: {el * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    err32 = [area_slope_error(w.u0, b.get_fields(i)[0], t_end[i], w.mob[0]) for i, w in enumerate(wls)]
+
+    # the plain FP64 form, instance by instance (one launch per step each)
+    t64 = 0.0
+    err64 = []
+    for i, w in enumerate(wls):
+        s = pf.Sim(w.param_dict(), prec="fp64")
+        s.set_stream(stream)
+        s.init_fields(w.u0)
+        stream.synchronize()
+        ts = time.perf_counter()
+        s.run_to("fe", t_end[i], dt_fixed=dts[i])
+        stream.synchronize()
+        t64 += time.perf_counter() - ts  # the runs only, not the uploads
+        err64.append(area_slope_error(w.u0, s.get_fields()[0], t_end[i], w.mob[0]))
+        s.close()
+    value = cells * nsteps / (total / args.steps) / 1e9
+    E = 4 if args.prec == "fp32" else 8
+    F = wls[0].F
+    bytes_per_launch = 2 * F * E * cells
+    avg_s = ev_ms / args.steps / nsteps / 1e3
+    achieved = bytes_per_launch / avg_s / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "Gcell-stage/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(wls)} 2D shrinking grains, {cells} cells, "
+                               f"{nsteps} FE steps each at 0.9 dt_e, one fused launch per step, "
+                               f"hipGraph of {K} steps",
+                   "cells": cells, "instances": len(wls), "persistent_blocks": nb,
+                   "time_to_solution_ms": round(total / args.steps * 1e3, 3),
+                   "fp64_per_instance_time_ms": round(t64 * 1e3, 3),
+                   "speedup_vs_fp64_per_instance": round(t64 / (total / args.steps), 2),
+                   "area_rate_rel_error_fp32_batch_mean": float(np.mean(err32)),
+                   "area_rate_rel_error_fp64_single_mean": float(np.mean(err64)),
+                   "area_rate_rel_error_max_abs_diff": float(np.max(np.abs(np.subtract(err32, err64))))},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"batch_euler_kernel, avg {avg_s * 1e6:.2f} us per step (HIP events "
+                               f"over graph replays), {bytes_per_launch} algorithmic B/launch"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="voronoi2d", choices=["voronoi2d", "pores3d", "gg3d"])
+    ap.add_argument("--workload", default="voronoi2d",
+                    choices=["voronoi2d", "pores3d", "gg3d", "batch"])
     ap.add_argument("--size", type=int, default=0)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -146,6 +252,10 @@ def main():
         return
 
     import paper_2601_16522_amd as pf
+
+    if args.workload == "batch":
+        batch_bench(args)
+        return
 
     t_gen = time.perf_counter()
     wl = make_workload(args.workload, args.size)
@@ -243,7 +353,7 @@ def main():
                      "kernel": f"rkl2_stage_kernel (RKL2 stages j >= 2), {n_rkl2} launches, "
                                f"avg {avg_s * 1e6:.2f} us (HIP events), "
                                f"{bytes_per_launch} algorithmic B/launch",
-                     "copy_ref_GBs": round(copy_bw, 1)},
+                     "stream_ref_GBs": {k: round(v, 1) for k, v in copy_bw.items()}},
     }
     if not args.no_cpu_baseline:
         note = f"full {wl.name} solve ({desc}) on the host CPU"

@@ -175,10 +175,11 @@ pf_status pf_get_trace(pf_sim *sim, double *buf, long long cap, long long *n);
 pf_status pf_get_state(pf_sim *sim, void *buf, size_t *len);
 pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
 
-/* Launch shape of the stencil kernels: tile width tx (32, 64 or 128 cells in
- * x; the block is 256 threads, 256/tx rows in y) and the number of z planes a
- * block marches through (3D only, >= 1).  pf_autotune times the candidates on
- * the current state and keeps the fastest. */
+/* Launch shape of the stencil kernels: tile width tx (64 cells in x: the
+ * block is 256 threads over 64 x 4 cells) and the number of z planes a block
+ * marches through (3D only, >= 1).  pf_autotune times the z extents 4..256 on
+ * the current state and keeps the fastest.  The launch shape never changes a
+ * result bit. */
 pf_status pf_set_tiling(pf_sim *sim, int tx, int zchunk);
 pf_status pf_get_tiling(pf_sim *sim, int *tx, int *zchunk);
 pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
@@ -190,6 +191,38 @@ pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
  * number of launches of a family since timing was enabled. */
 pf_status pf_set_timing(pf_sim *sim, int enable);
 pf_status pf_get_kernel_time(pf_sim *sim, int family, double *ms, long long *launches);
+
+/* ---------------------------------------------------------------------------
+ * Batch of independent 2D simulations.  All instances share dim = 2, n_phi,
+ * with_c and the precision; grid sizes and every other parameter may differ.
+ * A step of the batch is one fused launch over the tiles of every instance (a
+ * persistent grid walks a tile list whose entries name their instance; the
+ * per-instance parameters, state offsets and step sizes live in device
+ * tables); sequences of steps are replayed from a captured hipGraph.
+ * -------------------------------------------------------------------------*/
+typedef struct pf_batch pf_batch;
+
+pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out);
+pf_status pf_batch_destroy(pf_batch *b);
+/* A non-null HIP stream for the batch's launches (graph capture needs one; by
+ * default the batch owns a stream of its own). */
+pf_status pf_batch_set_stream(pf_batch *b, void *hip_stream);
+/* Instance i's state from host doubles [F*V_i] and its time. */
+pf_status pf_batch_init_fields(pf_batch *b, int i, const double *u, double t0);
+pf_status pf_batch_get_fields(pf_batch *b, int i, double *u, double *t);
+pf_status pf_batch_stable_dt(pf_batch *b, int i, double *dt_e);
+/* Forward-Euler steps of every instance to its t_end[i] (steps dt[i], or
+ * 0.9 dt_e of the instance when dt == NULL; the last step is clipped exactly
+ * as pf_run_to clips it, so each instance takes the steps of its own
+ * single-instance run).  graph_steps > 0 replays a graph of that many steps;
+ * 0 launches every step directly.  stats (optional) is [n]. */
+pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
+                          const double *dt, int graph_steps, pf_stats *stats);
+/* Times persistent grid sizes on one step (the state is only read) and keeps
+ * the fastest; pf_batch_set_blocks sets it directly (multiple of 8). */
+pf_status pf_batch_autotune(pf_batch *b, int *nblocks, double *best_ms);
+pf_status pf_batch_set_blocks(pf_batch *b, int nblocks);
+const char *pf_batch_last_error(const pf_batch *b);
 
 /* Values of N for which kernels are compiled; returns the count. */
 int pf_supported_nphi(int *out, int cap);

@@ -35,7 +35,10 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_stage_count", "pf_step", "pf_run_to", "pf_error_norm", "pf_conservation",
            "pf_diagnostics", "pf_get_trace", "pf_get_state", "pf_set_state", "pf_set_tiling",
            "pf_get_tiling", "pf_autotune", "pf_set_timing", "pf_get_kernel_time",
-           "pf_supported_nphi", "pf_last_error"]
+           "pf_supported_nphi", "pf_last_error", "pf_batch_create", "pf_batch_destroy",
+           "pf_batch_set_stream", "pf_batch_init_fields", "pf_batch_get_fields",
+           "pf_batch_stable_dt", "pf_batch_run_to", "pf_batch_autotune", "pf_batch_set_blocks",
+           "pf_batch_last_error"]
 
 
 class PFError(RuntimeError):
@@ -135,6 +138,23 @@ def lib():
         L.pf_supported_nphi.restype = C.c_int
         L.pf_last_error.argtypes = [vp]
         L.pf_last_error.restype = C.c_char_p
+        bsigs = {
+            "pf_batch_create": [C.POINTER(_Params), i, C.POINTER(vp)],
+            "pf_batch_destroy": [vp],
+            "pf_batch_set_stream": [vp, vp],
+            "pf_batch_init_fields": [vp, i, pd, d],
+            "pf_batch_get_fields": [vp, i, pd, pd],
+            "pf_batch_stable_dt": [vp, i, pd],
+            "pf_batch_run_to": [vp, i, pd, pd, i, C.POINTER(_Stats)],
+            "pf_batch_autotune": [vp, C.POINTER(i), pd],
+            "pf_batch_set_blocks": [vp, i],
+        }
+        for name, args in bsigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.pf_batch_last_error.argtypes = [vp]
+        L.pf_batch_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -154,6 +174,95 @@ def _tptr(t) -> C.c_void_p:
     if not (t.is_cuda and t.is_contiguous()):
         raise ValueError("expected a contiguous CUDA tensor")
     return C.c_void_p(t.data_ptr())
+
+
+def _cparams(p: dict, prec: str, ssp_stages: int, keep: list) -> _Params:
+    """pf_params for one parameter dict; the arrays it points to go into keep."""
+    N = int(p["n_phi"])
+    T = int(p["n_types"])
+    arrs = [(C.c_int * N)(*[int(v) for v in p["type_of"]]),
+            (C.c_double * (T * T))(*p["gamma"]), (C.c_double * (T * T))(*p["mob"]),
+            (C.c_double * T)(*p["k"]), (C.c_double * T)(*p["c0"]), (C.c_double * T)(*p["D"])]
+    keep.extend(arrs)
+    return _Params(int(p["dim"]), int(p["nx"]), int(p["ny"]), int(p.get("nz", 1)),
+                   float(p["dx"]), float(p["W"]), N, arrs[0], T, arrs[1], arrs[2], arrs[3],
+                   arrs[4], arrs[5], int(bool(p["with_c"])), PRECISIONS[prec], int(ssp_stages))
+
+
+class Batch:
+    """Handle on a batch of independent 2D simulations (pf_batch): one fused
+    launch advances every instance by a forward-Euler step."""
+
+    def __init__(self, params_list, prec: str = "fp32"):
+        self._L = lib()
+        self._keep = []
+        n = len(params_list)
+        arr = (_Params * n)(*[_cparams(p, prec, 5, self._keep) for p in params_list])
+        self.n = n
+        self.prec = prec
+        self.shapes = [(int(p["n_phi"]) + (1 if p["with_c"] else 0), 1, int(p["ny"]), int(p["nx"]))
+                       for p in params_list]
+        h = C.c_void_p()
+        rc = self._L.pf_batch_create(arr, n, C.byref(h))
+        if rc != 0:
+            raise PFError(rc, "pf_batch_create")
+        self._h = h
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise PFError(rc, self._L.pf_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._chk(self._L.pf_batch_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def init_fields(self, i: int, u: np.ndarray, t0: float = 0.0):
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+        if u.size != int(np.prod(self.shapes[i])):
+            raise ValueError("wrong state size for instance %d" % i)
+        self._chk(self._L.pf_batch_init_fields(self._h, i, _dp(u), t0))
+
+    def get_fields(self, i: int):
+        out = np.empty(self.shapes[i], dtype=np.float64)
+        t = C.c_double()
+        self._chk(self._L.pf_batch_get_fields(self._h, i, _dp(out.reshape(-1)), C.byref(t)))
+        return out, t.value
+
+    def stable_dt(self, i: int) -> float:
+        v = C.c_double()
+        self._chk(self._L.pf_batch_stable_dt(self._h, i, C.byref(v)))
+        return v.value
+
+    def run_to(self, t_end, dt=None, graph_steps: int = 0):
+        te = np.ascontiguousarray(t_end, dtype=np.float64)
+        if te.size != self.n:
+            raise ValueError("t_end needs one value per instance")
+        dtv = None if dt is None else np.ascontiguousarray(dt, dtype=np.float64)
+        if dtv is not None and dtv.size != self.n:
+            raise ValueError("dt needs one value per instance")
+        st = (_Stats * self.n)()
+        self._chk(self._L.pf_batch_run_to(self._h, PF_FEULER, _dp(te),
+                                          _dp(dtv) if dtv is not None else None,
+                                          int(graph_steps), st))
+        return [Stats(*[getattr(x, f) for f, _ in _Stats._fields_]) for x in st]
+
+    def autotune(self):
+        nb, ms = C.c_int(), C.c_double()
+        self._chk(self._L.pf_batch_autotune(self._h, C.byref(nb), C.byref(ms)))
+        return nb.value, ms.value
+
+    def set_blocks(self, nblocks: int):
+        self._chk(self._L.pf_batch_set_blocks(self._h, int(nblocks)))
 
 
 class Sim:

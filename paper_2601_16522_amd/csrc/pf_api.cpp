@@ -243,12 +243,26 @@ void fill_params(const pf_sim *s, DevParams<T> &P) {
         P.c0[a] = (T)s->c0[ta];
         P.ik[a] = (T)ik;
         P.Dk[a] = (T)(s->D[ta] * ik);
+        P.k2[a] = (T)(2.0 * s->k[ta]);
+        P.hik[a] = (T)(0.5 * ik);
         P.tphi[a] = ta;
     }
     for (int t = 0; t < s->T; ++t) {
+        const double ik = 1.0 / s->k[t];
         P.k2t[t] = (T)(2.0 * s->k[t]);
+        P.hikt[t] = (T)(0.5 * ik);
         P.c0t[t] = (T)s->c0[t];
+        P.ikt[t] = (T)ik;
+        P.Dkt[t] = (T)(s->D[t] * ik);
     }
+    int uni = 1;
+    for (int a = 0; a < s->N; ++a)
+        for (int b = 0; b < s->N; ++b) {
+            if (a == b) continue;
+            uni &= P.A[a * NMAX + b] == P.A[1] && P.B[a * NMAX + b] == P.B[1] &&
+                   P.L[a * NMAX + b] == P.L[1];
+        }
+    P.uniform = uni;
 }
 
 // Stable Euler step (Sec. 3.2, Gershgorin estimates of the two-phase system):
@@ -751,16 +765,49 @@ struct CkptHeader {
     pf_stats st;
 };
 
-}  // namespace
+// Times the RKL2 inner-stage kernel (the dominant launch of the multi-stage
+// integrators: one stencil vector and three plain vectors read, one written)
+// for every candidate z extent on the current state and keeps the fastest.
+template <typename T>
+pf_status autotune_t(pf_sim *s, int w, double &best, int &bzc) {
+    const int zcs3[7] = {4, 8, 16, 32, 64, 128, 256};
+    const int ncand = s->dim == 3 ? 7 : 1;
+    hipEvent_t e0, e1;
+    HIPCHK(s, hipEventCreate(&e0));
+    HIPCHK(s, hipEventCreate(&e1));
+    best = 1e300;
+    bzc = s->zchunk;
+    const T *u = bp<T>(s, s->cur);
+    for (int j = 0; j < ncand; ++j) {
+        s->zchunk = s->dim == 3 ? zcs3[j] : 1;
+        if (s->dim == 3 && s->zchunk > s->nz && j > 0) continue;
+        pf_status rc = PF_OK;
+        for (int r = 0; r < 6 && !rc; ++r) {
+            if (r == 1) hipEventRecord(e0, s->stream);
+            rc = stage<T>(s, K_RKL2, u, u, u, u, bp<T>(s, w), nullptr, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0);
+        }
+        if (rc) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return rc;
+        }
+        HIPCHK(s, hipEventRecord(e1, s->stream));
+        HIPCHK(s, hipEventSynchronize(e1));
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms / 5.0 < best) {
+            best = ms / 5.0;
+            bzc = s->zchunk;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return PF_OK;
+}
 
-// ===========================================================================
-// C-ABI
-// ===========================================================================
-extern "C" {
-
-pf_status pf_create(const pf_params *p, pf_sim **out) {
-    if (!p || !out) return PF_EINVAL;
-    *out = nullptr;
+// Validates a parameter set and fills the host-side description of a
+// simulation (no device memory).
+pf_status init_meta(pf_sim *s, const pf_params *p) {
     if (p->dim != 2 && p->dim != 3) return PF_EINVAL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || (p->dim == 2 && p->nz != 1)) return PF_EINVAL;
     if (p->n_phi < 1 || p->n_phi > NMAX || p->n_types < 1 || p->n_types > TMAX) return PF_EINVAL;
@@ -769,12 +816,16 @@ pf_status pf_create(const pf_params *p, pf_sim **out) {
         return PF_EINVAL;
     if (p->prec != PF_FP64 && p->prec != PF_FP32) return PF_EUNSUPPORTED;
     if (!nphi_supported(p->n_phi)) return PF_EUNSUPPORTED;
+    {
+        // the kernels address one field plane with 32-bit byte offsets
+        const unsigned long long cells = (unsigned long long)p->nx * p->ny * p->nz;
+        const unsigned long long esz = p->prec == PF_FP64 ? 8 : 4;
+        if (cells * esz > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
+    }
     for (int a = 0; a < p->n_phi; ++a)
         if (p->type_of[a] < 0 || p->type_of[a] >= p->n_types) return PF_EINVAL;
     for (int t = 0; t < p->n_types; ++t)
         if (!(p->k[t] > 0)) return PF_EINVAL;
-    pf_sim *s = new (std::nothrow) pf_sim();
-    if (!s) return PF_ENOMEM;
     s->dim = p->dim; s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
     s->N = p->n_phi; s->T = p->n_types; s->with_c = p->with_c ? 1 : 0;
     s->ssp_s = p->ssp_stages >= 2 ? p->ssp_stages : 5;
@@ -790,7 +841,26 @@ pf_status pf_create(const pf_params *p, pf_sim **out) {
     s->F = s->N + s->with_c;
     s->V = (long long)p->nx * p->ny * p->nz;
     s->esz = p->prec == PF_FP64 ? sizeof(double) : sizeof(float);
-    pf_status rc = PF_OK;
+    return PF_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+pf_status pf_create(const pf_params *p, pf_sim **out) {
+    if (!p || !out) return PF_EINVAL;
+    *out = nullptr;
+    pf_sim *s = new (std::nothrow) pf_sim();
+    if (!s) return PF_ENOMEM;
+    pf_status rc = init_meta(s, p);
+    if (rc) {
+        delete s;
+        return rc;
+    }
     if (p->prec == PF_FP64) {
         DevParams<double> P;
         fill_params(s, P);
@@ -1045,7 +1115,7 @@ pf_status pf_set_state(pf_sim *s, const void *buf, size_t len) {
 
 pf_status pf_set_tiling(pf_sim *s, int tx, int zchunk) {
     if (!s) return PF_EINVAL;
-    if (tx != 32 && tx != 64 && tx != 128) return fail(s, PF_EINVAL, "tx must be 32, 64 or 128");
+    if (tx != 64) return fail(s, PF_EINVAL, "tx must be 64 (the tile is 64 x 4 cells)");
     if (zchunk < 1) return fail(s, PF_EINVAL, "zchunk must be >= 1");
     s->tx = tx;
     s->zchunk = zchunk;
@@ -1064,42 +1134,16 @@ pf_status pf_autotune(pf_sim *s, int *tx_out, int *zc_out, double *best_ms) {
     if (pf_status rc = need_fields(s)) return rc;
     const int w = work_index(s, 0);
     if (pf_status rc = ensure_buf(s, w)) return rc;
-    const int txs[3] = {32, 64, 128};
-    const int zcs3[5] = {4, 8, 16, 32, 64};
-    const int nz_cands = s->dim == 3 ? 5 : 1;
-    hipEvent_t e0, e1;
-    HIPCHK(s, hipEventCreate(&e0));
-    HIPCHK(s, hipEventCreate(&e1));
-    double best = 1e300;
-    int btx = s->tx, bzc = s->zchunk;
     const bool was_timing = s->timing;
     s->timing = false;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < nz_cands; ++j) {
-            s->tx = txs[i];
-            s->zchunk = s->dim == 3 ? zcs3[j] : 1;
-            if (s->dim == 3 && s->zchunk > s->nz) continue;
-            pf_status rc = pf_rhs_device(s, s->buf[w]);  // warm-up
-            if (rc) { s->timing = was_timing; return rc; }
-            HIPCHK(s, hipEventRecord(e0, s->stream));
-            for (int r = 0; r < 5; ++r)
-                if ((rc = pf_rhs_device(s, s->buf[w]))) { s->timing = was_timing; return rc; }
-            HIPCHK(s, hipEventRecord(e1, s->stream));
-            HIPCHK(s, hipEventSynchronize(e1));
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms / 5.0 < best) {
-                best = ms / 5.0;
-                btx = s->tx;
-                bzc = s->zchunk;
-            }
-        }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    double best;
+    int bzc;
+    pf_status rc = s->prec == PF_FP64 ? autotune_t<double>(s, w, best, bzc)
+                                      : autotune_t<float>(s, w, best, bzc);
     s->timing = was_timing;
-    s->tx = btx;
+    if (rc) return rc;
     s->zchunk = bzc;
-    if (tx_out) *tx_out = btx;
+    if (tx_out) *tx_out = s->tx;
     if (zc_out) *zc_out = bzc;
     if (best_ms) *best_ms = best;
     return PF_OK;
@@ -1127,5 +1171,410 @@ pf_status pf_get_kernel_time(pf_sim *s, int family, double *ms, long long *launc
 int pf_supported_nphi(int *out, int cap) { return supported_nphi_list(out, cap); }
 
 const char *pf_last_error(const pf_sim *s) { return s ? s->err.c_str() : "null handle"; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batch of independent 2D simulations (one fused launch per step for all)
+// ===========================================================================
+
+struct pf_batch {
+    int n = 0, N = 0, F = 0, with_c = 0;
+    pf_precision prec = PF_FP32;
+    size_t esz = 4;
+    std::vector<pf_sim> meta;      // per-instance parameters (no device memory)
+    std::vector<long long> off;    // element offsets in the batch buffers
+    long long total = 0;           // elements per batch buffer
+    std::vector<int> ntx, nty, tile0;
+    int total_tiles = 0;
+    void *bufA = nullptr, *bufB = nullptr;
+    void *dparams = nullptr, *dinst = nullptr;
+    int *dtile = nullptr, *dstep = nullptr;
+    std::vector<double> t;
+    std::vector<int> have;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int nblocks = 2048;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_k = 0;
+    std::string err;
+};
+
+namespace {
+
+pf_status bfail(pf_batch *b, pf_status code, const char *fmt, ...) {
+    if (b) {
+        char m[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(m, sizeof m, fmt, ap);
+        va_end(ap);
+        b->err = m;
+    }
+    return code;
+}
+
+#define BHIPCHK(b, expr)                                                                \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return bfail((b), PF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+template <typename T>
+BatchArgs<T> batch_args(pf_batch *b, int offset) {
+    BatchArgs<T> B;
+    B.params = (const DevParams<T> *)b->dparams;
+    B.inst = (const BatchInst<T> *)b->dinst;
+    B.tile_inst = b->dtile;
+    B.bufA = (T *)b->bufA;
+    B.bufB = (T *)b->bufB;
+    B.step_base = b->dstep;
+    B.step_offset = offset;
+    B.total_tiles = b->total_tiles;
+    return B;
+}
+
+template <typename T>
+pf_status batch_setup_params(pf_batch *b) {
+    std::vector<DevParams<T>> P(b->n);
+    for (int i = 0; i < b->n; ++i) fill_params(&b->meta[i], P[i]);
+    BHIPCHK(b, hipMalloc(&b->dparams, sizeof(DevParams<T>) * b->n));
+    BHIPCHK(b, hipMemcpy(b->dparams, P.data(), sizeof(DevParams<T>) * b->n, hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMalloc(&b->dinst, sizeof(BatchInst<T>) * b->n));
+    return PF_OK;
+}
+
+// Step sizes of each instance for a run to t_end[i]: the same clipping rule as
+// pf_run_to (full steps of dt, the last one landing on t_end), so every
+// instance takes bit for bit the steps a single-instance run would take.
+template <typename T>
+pf_status batch_plan(pf_batch *b, const double *t_end, const double *dt, int &max_steps) {
+    std::vector<BatchInst<T>> I(b->n);
+    max_steps = 0;
+    for (int i = 0; i < b->n; ++i) {
+        const double h0 = dt ? dt[i] : 0.9 * stable_dt(&b->meta[i]);
+        if (!(h0 > 0.0)) return bfail(b, PF_EINVAL, "instance %d: dt must be > 0", i);
+        double t = b->t[i];
+        long long nst = 0;
+        double hlast = h0;
+        bool clipped = false;
+        for (;;) {
+            const double rem = t_end[i] - t;
+            if (rem <= 1e-12 * h0) break;
+            double h = h0;
+            bool last = false;
+            if (rem <= h * (1.0 + 1e-10)) {
+                h = rem;
+                last = true;
+            }
+            ++nst;
+            if (nst > 100000000) return bfail(b, PF_EINVAL, "instance %d: too many steps", i);
+            if (last) {
+                hlast = h;
+                clipped = true;
+            }
+            t = last ? t_end[i] : t + h;
+        }
+        I[i].off = b->off[i];
+        I[i].ntx = b->ntx[i];
+        I[i].nty = b->nty[i];
+        I[i].tile0 = b->tile0[i];
+        I[i].nsteps = (int)nst;
+        I[i].nfull = (int)(clipped ? nst - 1 : nst);
+        I[i].dt = (T)h0;
+        I[i].dt_last = (T)hlast;
+        max_steps = std::max(max_steps, (int)nst);
+    }
+    BHIPCHK(b, hipMemcpyAsync(b->dinst, I.data(), sizeof(BatchInst<T>) * b->n, hipMemcpyHostToDevice,
+                              b->stream));
+    return PF_OK;
+}
+
+template <typename T>
+pf_status batch_launch_steps(pf_batch *b, int k) {
+    for (int j = 0; j < k; ++j) {
+        hipError_t e = launch_batch_euler<T>(b->N, batch_args<T>(b, j), b->nblocks, b->stream);
+        if (e != hipSuccess) return bfail(b, PF_EHIP, "batch launch: %s", hipGetErrorString(e));
+    }
+    BHIPCHK(b, launch_batch_tick(b->dstep, k, b->stream));
+    return PF_OK;
+}
+
+// k steps (k batched launches and one counter update) captured once into a
+// hipGraph and replayed; the graph holds kernel nodes only.
+template <typename T>
+pf_status batch_graph(pf_batch *b, int k) {
+    if (b->gexec && b->graph_k == k) return PF_OK;
+    if (b->gexec) {
+        hipGraphExecDestroy(b->gexec);
+        hipGraphDestroy(b->graph);
+        b->gexec = nullptr;
+        b->graph = nullptr;
+    }
+    BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    pf_status rc = batch_launch_steps<T>(b, k);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return bfail(b, PF_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return bfail(b, PF_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    b->graph = g;
+    b->graph_k = k;
+    return PF_OK;
+}
+
+template <typename T>
+pf_status batch_run(pf_batch *b, const double *t_end, const double *dt, int graph_k,
+                    pf_stats *stats) {
+    int S = 0;
+    pf_status rc = batch_plan<T>(b, t_end, dt, S);
+    if (rc) return rc;
+    const int zero = 0;
+    BHIPCHK(b, hipMemcpyAsync(b->dstep, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    int done = 0;
+    if (graph_k > 0 && S >= graph_k) {
+        if ((rc = batch_graph<T>(b, graph_k))) return rc;
+        for (; done + graph_k <= S; done += graph_k) BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+    }
+    if (S - done > 0 && (rc = batch_launch_steps<T>(b, S - done))) return rc;
+    // an instance with an odd number of steps ends in buffer B: copy it back
+    std::vector<BatchInst<T>> I(b->n);
+    BHIPCHK(b, hipMemcpyAsync(I.data(), b->dinst, sizeof(BatchInst<T>) * b->n, hipMemcpyDeviceToHost,
+                              b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->n; ++i) {
+        const size_t bytes = (size_t)b->meta[i].F * b->meta[i].V * b->esz;
+        if (I[i].nsteps & 1)
+            BHIPCHK(b, hipMemcpyAsync((char *)b->bufA + b->off[i] * b->esz,
+                                      (char *)b->bufB + b->off[i] * b->esz, bytes,
+                                      hipMemcpyDeviceToDevice, b->stream));
+        if (I[i].nsteps > 0) b->t[i] = t_end[i];
+        if (stats) {
+            stats[i] = pf_stats{};
+            stats[i].rhs_evals = stats[i].stages = stats[i].accepted = I[i].nsteps;
+            stats[i].t = b->t[i];
+            stats[i].last_dt = I[i].nsteps ? (double)(I[i].nfull < I[i].nsteps ? I[i].dt_last : I[i].dt) : 0.0;
+        }
+    }
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    return PF_OK;
+}
+
+template <typename T>
+pf_status batch_autotune(pf_batch *b, int *best_blocks, double *best_ms) {
+    // one step of every instance from buffer A into buffer B (A, the state, is
+    // only read), timed for several persistent grid sizes
+    std::vector<double> t_end(b->n), dt(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        dt[i] = 0.9 * stable_dt(&b->meta[i]);
+        t_end[i] = b->t[i] + dt[i];
+    }
+    int S = 0;
+    pf_status rc = batch_plan<T>(b, t_end.data(), dt.data(), S);
+    if (rc) return rc;
+    const int cands[5] = {512, 1024, 2048, 4096, 8192};
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    double best = 1e300;
+    int bb = b->nblocks;
+    const int zero = 0;
+    for (int c : cands) {
+        const int nb = std::min(c, (b->total_tiles + 7) / 8 * 8);
+        BHIPCHK(b, hipMemcpyAsync(b->dstep, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+        hipError_t e = launch_batch_euler<T>(b->N, batch_args<T>(b, 0), nb, b->stream);
+        BHIPCHK(b, hipEventRecord(e0, b->stream));
+        for (int r = 0; r < 5 && e == hipSuccess; ++r)
+            e = launch_batch_euler<T>(b->N, batch_args<T>(b, 0), nb, b->stream);
+        if (e != hipSuccess) return bfail(b, PF_EHIP, "batch launch: %s", hipGetErrorString(e));
+        BHIPCHK(b, hipEventRecord(e1, b->stream));
+        BHIPCHK(b, hipEventSynchronize(e1));
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms / 5.0 < best) {
+            best = ms / 5.0;
+            bb = nb;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->nblocks = bb;
+    if (best_blocks) *best_blocks = bb;
+    if (best_ms) *best_ms = best;
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_batch_destroy(pf_batch *b) {
+    if (!b) return PF_EINVAL;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    void *ptrs[6] = {b->bufA, b->bufB, b->dparams, b->dinst, b->dtile, b->dstep};
+    for (void *q : ptrs)
+        if (q) hipFree(q);
+    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    delete b;
+    return PF_OK;
+}
+
+pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out) {
+    if (!per_inst || !out || n < 1) return PF_EINVAL;
+    *out = nullptr;
+    pf_batch *b = new (std::nothrow) pf_batch();
+    if (!b) return PF_ENOMEM;
+    b->n = n;
+    b->meta.resize(n);
+    pf_status rc = PF_OK;
+    for (int i = 0; i < n && !rc; ++i) {
+        rc = init_meta(&b->meta[i], &per_inst[i]);
+        if (!rc && (per_inst[i].dim != 2 || per_inst[i].n_phi != per_inst[0].n_phi ||
+                    per_inst[i].prec != per_inst[0].prec ||
+                    (per_inst[i].with_c != 0) != (per_inst[0].with_c != 0)))
+            rc = PF_EINVAL;  // instances share dim 2, N, precision and with_c
+    }
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    b->N = b->meta[0].N;
+    b->F = b->meta[0].F;
+    b->with_c = b->meta[0].with_c;
+    b->prec = b->meta[0].prec;
+    b->esz = b->meta[0].esz;
+    b->off.resize(n);
+    b->ntx.resize(n);
+    b->nty.resize(n);
+    b->tile0.resize(n);
+    b->t.assign(n, 0.0);
+    b->have.assign(n, 0);
+    std::vector<int> tile_inst;
+    for (int i = 0; i < n; ++i) {
+        b->off[i] = b->total;
+        b->total += (long long)b->meta[i].F * b->meta[i].V;
+        b->total = (b->total + 63) / 64 * 64;  // 256-byte aligned instance starts
+        b->ntx[i] = (b->meta[i].nx + TILE_X - 1) / TILE_X;
+        b->nty[i] = (b->meta[i].ny + TILE_Y - 1) / TILE_Y;
+        b->tile0[i] = b->total_tiles;
+        b->total_tiles += b->ntx[i] * b->nty[i];
+        tile_inst.insert(tile_inst.end(), (size_t)b->ntx[i] * b->nty[i], i);
+    }
+    if (hipMalloc(&b->bufA, b->total * b->esz) != hipSuccess ||
+        hipMalloc(&b->bufB, b->total * b->esz) != hipSuccess ||
+        hipMalloc(&b->dtile, sizeof(int) * tile_inst.size()) != hipSuccess ||
+        hipMalloc(&b->dstep, sizeof(int)) != hipSuccess) {
+        pf_batch_destroy(b);
+        return PF_ENOMEM;
+    }
+    if (hipMemcpy(b->dtile, tile_inst.data(), sizeof(int) * tile_inst.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(b->bufA, 0, b->total * b->esz) != hipSuccess) {
+        pf_batch_destroy(b);
+        return PF_EHIP;
+    }
+    rc = b->prec == PF_FP64 ? batch_setup_params<double>(b) : batch_setup_params<float>(b);
+    if (!rc && hipStreamCreate(&b->stream) != hipSuccess) rc = PF_EHIP;
+    if (rc) {
+        pf_batch_destroy(b);
+        return rc;
+    }
+    b->own_stream = true;
+    b->nblocks = std::min(2048, (b->total_tiles + 7) / 8 * 8);
+    *out = b;
+    return PF_OK;
+}
+
+pf_status pf_batch_set_stream(pf_batch *b, void *stream) {
+    if (!b || !stream) return PF_EINVAL;  // graph capture needs a real stream
+    if (b->own_stream) {
+        hipStreamSynchronize(b->stream);
+        hipStreamDestroy(b->stream);
+        b->own_stream = false;
+    }
+    b->stream = (hipStream_t)stream;
+    return PF_OK;
+}
+
+pf_status pf_batch_init_fields(pf_batch *b, int i, const double *u, double t0) {
+    if (!b || !u || i < 0 || i >= b->n) return PF_EINVAL;
+    const long long n = (long long)b->meta[i].F * b->meta[i].V;
+    if (b->prec == PF_FP64) {
+        BHIPCHK(b, hipMemcpyAsync((double *)b->bufA + b->off[i], u, n * sizeof(double),
+                                  hipMemcpyHostToDevice, b->stream));
+    } else {
+        std::vector<float> h(n);
+        for (long long k = 0; k < n; ++k) h[k] = (float)u[k];
+        BHIPCHK(b, hipMemcpyAsync((float *)b->bufA + b->off[i], h.data(), n * sizeof(float),
+                                  hipMemcpyHostToDevice, b->stream));
+    }
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->t[i] = t0;
+    b->have[i] = 1;
+    return PF_OK;
+}
+
+pf_status pf_batch_get_fields(pf_batch *b, int i, double *u, double *t) {
+    if (!b || i < 0 || i >= b->n) return PF_EINVAL;
+    if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
+    if (t) *t = b->t[i];
+    if (!u) return PF_OK;
+    const long long n = (long long)b->meta[i].F * b->meta[i].V;
+    if (b->prec == PF_FP64) {
+        BHIPCHK(b, hipMemcpyAsync(u, (double *)b->bufA + b->off[i], n * sizeof(double),
+                                  hipMemcpyDeviceToHost, b->stream));
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+    } else {
+        std::vector<float> h(n);
+        BHIPCHK(b, hipMemcpyAsync(h.data(), (float *)b->bufA + b->off[i], n * sizeof(float),
+                                  hipMemcpyDeviceToHost, b->stream));
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        for (long long k = 0; k < n; ++k) u[k] = (double)h[k];
+    }
+    return PF_OK;
+}
+
+pf_status pf_batch_stable_dt(pf_batch *b, int i, double *dte) {
+    if (!b || !dte || i < 0 || i >= b->n) return PF_EINVAL;
+    *dte = stable_dt(&b->meta[i]);
+    return PF_OK;
+}
+
+pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end, const double *dt,
+                          int graph_steps, pf_stats *stats) {
+    if (!b || !t_end || graph_steps < 0) return PF_EINVAL;
+    if (integ != PF_FEULER) return bfail(b, PF_EUNSUPPORTED, "the batch advances forward Euler steps");
+    for (int i = 0; i < b->n; ++i)
+        if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
+    return b->prec == PF_FP64 ? batch_run<double>(b, t_end, dt, graph_steps, stats)
+                              : batch_run<float>(b, t_end, dt, graph_steps, stats);
+}
+
+pf_status pf_batch_autotune(pf_batch *b, int *nblocks, double *best_ms) {
+    if (!b) return PF_EINVAL;
+    for (int i = 0; i < b->n; ++i)
+        if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
+    return b->prec == PF_FP64 ? batch_autotune<double>(b, nblocks, best_ms)
+                              : batch_autotune<float>(b, nblocks, best_ms);
+}
+
+pf_status pf_batch_set_blocks(pf_batch *b, int nblocks) {
+    if (!b || nblocks < 8) return PF_EINVAL;
+    b->nblocks = nblocks / 8 * 8;
+    return PF_OK;
+}
+
+const char *pf_batch_last_error(const pf_batch *b) { return b ? b->err.c_str() : "null handle"; }
 
 }  // extern "C"

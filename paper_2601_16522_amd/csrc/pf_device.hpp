@@ -73,6 +73,53 @@ __device__ __forceinline__ void load_point(const T *__restrict__ u, long long V,
     v[N] = withc ? u[N * V + idx] : T(0);
 }
 
+// Field f of a state vector addressed by a 32-bit byte offset through a
+// buffer resource: the descriptor (base of the field plane, plane size in
+// bytes) is uniform and lives in scalar registers, the per-lane offset is one
+// 32-bit VGPR.  An offset past the plane reads 0 and drops a store instead of
+// touching other memory.  The handle refuses grids whose plane exceeds 4 GiB.
+// 0x00020000 is the buffer descriptor's format word for the gfx9 family.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *u, long long V, int f) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(u + (long long)f * V), 0,
+                                             (int)(unsigned)(V * (long long)sizeof(T)), 0x00020000);
+}
+
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return __hiloint2double((int)v[1], (int)v[0]);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, double x) {
+    typedef unsigned u2 __attribute__((vector_size(8)));
+    u2 v;
+    v[0] = (unsigned)__double2loint(x);
+    v[1] = (unsigned)__double2hiint(x);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T ldf(const T *u, long long V, int f, unsigned boff) {
+    return buf_load(plane_rsrc(u, V, f), boff, T(0));
+}
+template <typename T>
+__device__ __forceinline__ void stf(T *u, long long V, int f, unsigned boff, T v) {
+    buf_store(plane_rsrc(u, V, f), boff, v);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_point32(const T *u, long long V, unsigned boff, bool withc,
+                                             T *v) {
+#pragma unroll
+    for (int f = 0; f < N; ++f) v[f] = ldf(u, V, f, boff);
+    v[N] = withc ? ldf(u, V, N, boff) : T(0);
+}
+
 // Deterministic block reduction of (sum, count) over a 256-thread block: a
 // fixed shuffle tree inside each wavefront, then the four wavefront results in
 // order.  Thread 0 returns the block totals.

@@ -8,6 +8,7 @@ namespace pf {
 
 constexpr int NMAX = 16;  // largest number of order parameters a kernel is built for
 constexpr int TMAX = 4;   // largest number of thermodynamic types
+constexpr int TILE_X = 64, TILE_Y = 4;  // block tile of the stencil kernels (256 threads)
 
 // Per-simulation constants, resident in device memory and read through the
 // scalar cache (every address is uniform across the wavefront).  Pair tables
@@ -23,9 +24,15 @@ struct DevParams {
     T c0[NMAX];    // c0 of the phase's type
     T ik[NMAX];    // 1/k of the phase's type
     T Dk[NMAX];    // D/k of the phase's type
+    T k2[NMAX];    // 2k of the phase's type
+    T hik[NMAX];   // 1/(2k) of the phase's type
     int tphi[NMAX];
+    int uniform;   // 1 when every pair (a != b) has the same A, B and L
     T k2t[TMAX];   // 2k per type (grand potential)
+    T hikt[TMAX];  // 1/(2k) per type
     T c0t[TMAX];   // c0 per type
+    T ikt[TMAX];   // 1/k per type
+    T Dkt[TMAX];   // D/k per type
 };
 
 // Stage kinds of the fused stencil kernel.  Each evaluates rhs(y1) at the
@@ -65,6 +72,30 @@ struct StageArgs {
     int ntiles;
 };
 
+// One instance of a batch of independent 2D simulations that share N, the
+// precision and with_c.
+template <typename T>
+struct BatchInst {
+    long long off;     // element offset of the instance's state in each batch buffer
+    int ntx, nty;      // tiles of the instance
+    int tile0;         // first global tile of the instance
+    int nsteps;        // steps of the current run (the last one possibly clipped)
+    int nfull;         // steps of size dt; step nfull (if < nsteps) uses dt_last
+    T dt, dt_last;
+};
+
+template <typename T>
+struct BatchArgs {
+    const DevParams<T> *params;  // [n]
+    const BatchInst<T> *inst;    // [n]
+    const int *tile_inst;        // [total_tiles] instance of each global tile
+    T *bufA;                     // state at even steps
+    T *bufB;                     // state at odd steps
+    const int *step_base;        // device step counter (advanced by batch_tick)
+    int step_offset;             // step = *step_base + step_offset
+    int total_tiles;
+};
+
 // Launchers (implemented in pf_kernels.hip).  Return hipSuccess or the launch
 // error; they never synchronise.
 template <typename T>
@@ -82,6 +113,9 @@ hipError_t launch_finalize_norm(const double *red, const long long *redn, int np
                                 double *out, hipStream_t stream);
 hipError_t launch_finalize_diag(const double *red, int nparts, double *out,
                                 hipStream_t stream);
+template <typename T>
+hipError_t launch_batch_euler(int nphi, const BatchArgs<T> &args, int nblocks, hipStream_t stream);
+hipError_t launch_batch_tick(int *step_base, int k, hipStream_t stream);
 
 bool nphi_supported(int nphi);
 int supported_nphi_list(int *out, int cap);

@@ -160,8 +160,17 @@ finalize_diag_kernel(const double *red, int n, double *out) {
                                                          hipStream_t);
 template <typename T, int N>
 hipError_t launch_stage_n(int dim, const StageArgs<T> &A, int nblocks, hipStream_t stream);
+template <typename T, int N>
+hipError_t launch_batch_euler_n(const BatchArgs<T> &B, int nblocks, hipStream_t stream);
 PF_NPHI_LIST(PF_DECL)
 #undef PF_DECL
+#define PF_DECLB(n)                                                                        \
+    extern template hipError_t launch_batch_euler_n<float, n>(const BatchArgs<float> &, int, \
+                                                              hipStream_t);                \
+    extern template hipError_t launch_batch_euler_n<double, n>(const BatchArgs<double> &,   \
+                                                               int, hipStream_t);
+PF_NPHI_LIST(PF_DECLB)
+#undef PF_DECLB
 
 bool nphi_supported(int nphi) {
     switch (nphi) {
@@ -191,6 +200,30 @@ hipError_t launch_stage(int dim, int nphi, const StageArgs<T> &args, int nblocks
     default: return hipErrorInvalidValue;
     }
 }
+
+template <typename T>
+hipError_t launch_batch_euler(int nphi, const BatchArgs<T> &args, int nblocks, hipStream_t stream) {
+    switch (nphi) {
+#define PF_CASE(n) case n: return launch_batch_euler_n<T, n>(args, nblocks, stream);
+        PF_NPHI_LIST(PF_CASE)
+#undef PF_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Advances the batch step counter by k after a run of k batched stages (one
+// thread, an ordinary vector store).
+__global__ void batch_tick_kernel(int *step_base, int k) {
+    if (threadIdx.x == 0) step_base[0] = step_base[0] + k;
+}
+
+hipError_t launch_batch_tick(int *step_base, int k, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_tick_kernel, dim3(1), dim3(64), 0, stream, step_base, k);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_euler<float>(int, const BatchArgs<float> &, int, hipStream_t);
+template hipError_t launch_batch_euler<double>(int, const BatchArgs<double> &, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_embed_est(const DevParams<T> *P, int nphi, int with_c, long long V,

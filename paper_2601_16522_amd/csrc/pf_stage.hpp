@@ -11,302 +11,466 @@
 // HBM.  The estimator kind evaluates the Sommeijer-type local error of an
 // adaptive step (Sec. 3.3) and reduces its weighted squares in FP64 per block.
 //
-// The path is a memory-bound stencil (a few flops per byte), so it uses no
-// matrix cores.  Decomposition: a block is 256 threads covering a tile of
-// tx x ty cells of the x-y plane; a wavefront spans 64 consecutive x cells
-// (tx = 64) or two half rows (tx = 32), so every load and store of a plane row
-// is coalesced.  In 3D a block marches through zchunk planes in z and keeps the
-// planes z-1, z, z+1 of its own cells in registers: each value is read from HBM
-// once per march plus the two halo planes.  x and y neighbours come from the
-// L1/L2 caches (rows of the same tile are loaded by the block's other
-// wavefronts; halo rows by the neighbouring tile, which the XCD-aware tile
-// order places on the same XCD).
+// The path is a memory-bound stencil, so it uses no matrix cores.
 //
-// Floating-point order: every sum is accumulated in a fixed order (phases
-// ascending; neighbours x-, x+, y-, y+, z-, z+) and the library is compiled
-// without contraction, so the double-precision kernels reproduce a sequential
-// left-to-right evaluation of the same formulas bit for bit.
+// Decomposition.  A block is 256 threads covering a tile of 64 x 4 cells of
+// the x-y plane (a wavefront covers one full row of 64 cells, so row loads and
+// stores are coalesced).  The tile's plane is staged in LDS
+// with a one-cell halo (phi planes, chemical potential mu and mobility Mc per
+// point): every thread computes mu and Mc of its own cell once, the halo
+// threads those of the halo cells, and the x/y neighbours of the stencil are
+// then LDS reads.  Halo and tile slots hold the periodically wrapped cells, so
+// ragged tiles need no special case.  In 3D a block marches through zchunk
+// planes in z and keeps planes z-1, z, z+1 of its own cell (and the halo cell
+// it loads) in registers, prefetching plane z+1 while plane z is computed;
+// every value is read from HBM once per march, plus the halo columns and the
+// two z halo planes.
+//
+// Arithmetic.  The double-precision kernels evaluate every formula in the
+// oracle's order (phases ascending; neighbours x-, x+, y-, y+, z-, z+; pair
+// sums over b != a) and the library is compiled without contraction, so they
+// reproduce a sequential left-to-right evaluation bit for bit.  The
+// single-precision kernels (the chosen form) use the same model with cheaper
+// algebra: fused multiply-adds, hardware reciprocals, mu and Mc from per-type
+// phase sums, and, when every pair shares one A, B and L (a flag computed on
+// the host), the O(N) forms
+//   delta_a = A (sum_b Lap phi_b - Lap phi_a) + B (sum_b phi_b - phi_a) + psi_a
+//   dphi_a/dt = L (mean of delta over the active phases - delta_a),
+// which equal the pairwise sums of eq. phieq exactly in real arithmetic.
 #pragma once
+
+#include <type_traits>
 
 #include "pf_device.hpp"
 
 namespace pf {
 
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T x) {
+    if constexpr (std::is_same<T, float>::value) return __builtin_amdgcn_rcpf(x);
+    else return T(1) / x;
+}
+
+// IEEE maxNum (a NaN operand is ignored), so max > 0 is "some value > 0"
+template <typename T>
+__device__ __forceinline__ T max_num(T a, T b) {
+    if constexpr (std::is_same<T, float>::value) return __builtin_fmaxf(a, b);
+    else return __builtin_fmax(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+    if constexpr (std::is_same<T, float>::value) return __builtin_fmaf(a, b, c);
+    else return a * b + c;
+}
+
+// mu and Mc at one point (eqs. cadef, mueq, gibbs-energy, ceq).  Exact order
+// for the reference (double) form; fused multiply-adds and a hardware
+// reciprocal for the fast form.
+template <typename T, int N, bool FAST>
+__device__ __forceinline__ void point_mu_mc(const DevParams<T> &P, const T *v, T &mu, T &mc) {
+    if constexpr (!FAST) {
+        mu_mc<T, N>(P, v, mu, mc);
+    } else {
+        T sc0 = T(0), sik = T(0), smc = T(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            sc0 = fma_t(v[a], P.c0[a], sc0);
+            sik = fma_t(v[a], P.ik[a], sik);
+            smc = fma_t(v[a], P.Dk[a], smc);
+        }
+        mu = (v[N] - sc0) * fast_rcp(sik);
+        mc = smc;
+    }
+}
+
+// The hardware dispatches workgroup b to XCD (b mod 8).  Each XCD gets a
+// contiguous range of logical tiles (x fastest, then y, then z chunk), so tiles
+// that share halo rows run on the same XCD and share its L2.  gridDim.x is a
+// multiple of 8.
+__device__ __forceinline__ int xcd_logical_block() {
+    const int b = blockIdx.x;
+    const int per = gridDim.x >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// One tile (logical index L) of one stage.  Every thread of the block calls
+// it with the same arguments (it synchronises the block).
 template <typename T, int DIM, int N, int KIND>
-__device__ __forceinline__ void stage_body(const StageArgs<T> &A) {
+__device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
+                                           T *__restrict__ pair) {
+    constexpr bool FAST = std::is_same<T, float>::value;
     const DevParams<T> &P = *A.P;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const long long V = P.V;
     const bool withc = P.with_c != 0;
     const T idx2 = P.idx2;
-
-    // The hardware dispatches workgroup b to XCD (b mod 8).  Each XCD gets a
-    // contiguous range of logical tiles (x fastest, then y, then z chunk), so
-    // tiles that share halo rows run on the same XCD and share its L2.
-    const int b = blockIdx.x;
-    const int per = gridDim.x >> 3;
-    const int L = (b & 7) * per + (b >> 3);
-    const bool tile_ok = L < A.ntiles;
-    const int tix = L % A.ntx;
-    const int rest = L / A.ntx;
-    const int tiy = rest % A.nty;
-    const int tiz = rest / A.nty;
-    const int lx = threadIdx.x % A.tx, ly = threadIdx.x / A.tx;
-    const int x = tix * A.tx + lx, y = tiy * A.ty + ly;
-    const bool active = tile_ok && x < nx && y < ny;
+    const bool tile_ok = L < A.ntiles;  // uniform over the block
 
     double acc = 0.0;
     long long cnt = 0;
 
-    if (active) {
-        const T *__restrict__ y1 = A.y1;
-        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    if (tile_ok) {
+        // pair constants A, B, L (N x N each) live in LDS for the whole block, so
+        // the pairwise sums read them without holding N^2 scalar registers
+        for (int i = threadIdx.x; i < 3 * N * N; i += blockDim.x) {
+            const int tab = i / (N * N), ab = i % (N * N);
+            const int a = ab / N, bb = ab % N;
+            const T *src = tab == 0 ? P.A : tab == 1 ? P.B : P.L;
+            pair[i] = src[a * NMAX + bb];
+        }
+        // the tile is fixed at 64 x 4 (one wavefront per row) so that every LDS
+        // plane offset is an instruction immediate
+        constexpr int TX = TILE_X, TY = TILE_Y;
+        constexpr int TXH = TX + 2, TYH = TY + 2;
+        constexpr int plane_sz = TXH * TYH;
+        const int tix = L % A.ntx;
+        const int rest = L / A.ntx;
+        const int tiy = rest % A.nty;
+        const int tiz = rest / A.nty;
+        const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+        const int gx = tix * TX + lx, gy = tiy * TY + ly;
+        const bool active = gx < nx && gy < ny;
+        // own slot holds the periodically wrapped cell
+        const int x = gx % nx, y = gy % ny;
         const long long nxy = (long long)nx * ny;
+        const long long col = (long long)y * nx + x;
+        const int own_slot = (ly + 1) * TXH + (lx + 1);
+
+        // halo cell of this thread (2 TX + 2 TY positions, no corners)
+        constexpr int nhalo = 2 * TX + 2 * TY;
+        const int h = threadIdx.x;
+        const bool has_halo = h < nhalo;
+        int hslot = 0;
+        long long hcol = 0;
+        if (has_halo) {
+            int hx, hy;
+            if (h < TX) { hx = h; hy = -1; }
+            else if (h < 2 * TX) { hx = h - TX; hy = TY; }
+            else if (h < 2 * TX + TY) { hx = -1; hy = h - 2 * TX; }
+            else { hx = TX; hy = h - 2 * TX - TY; }
+            hslot = (hy + 1) * TXH + (hx + 1);
+            const int hgx = ((tix * TX + hx) % nx + nx) % nx;
+            const int hgy = ((tiy * TY + hy) % ny + ny) % ny;
+            hcol = (long long)hgy * nx + hgx;
+        }
+
         const int z0 = DIM == 3 ? tiz * A.zchunk : 0;
         const int z1 = DIM == 3 ? min(z0 + A.zchunk, nz) : 1;
+        const T *__restrict__ y1 = A.y1;
 
-        T prv[N + 1], cur[N + 1], nxt[N + 1];
-        const long long col = (long long)y * nx + x;
+        T prv[N + 1], cur[N + 1], nxt[N + 1], hcur[N + 1], hnxt[N + 1];
+        T mu_p = T(0), mc_p = T(0), mu_c = T(0), mc_c = T(0), mu_n = T(0), mc_n = T(0);
         if (DIM == 3) {
             const int zm = z0 == 0 ? nz - 1 : z0 - 1;
-            load_point<T, N>(y1, V, zm * nxy + col, withc, prv);
+            load_point32<T, N>(y1, V, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
+            if (withc) point_mu_mc<T, N, FAST>(P, prv, mu_p, mc_p);
         }
-        load_point<T, N>(y1, V, (long long)z0 * nxy + col, withc, cur);
+        load_point32<T, N>(y1, V, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
+        if (withc) point_mu_mc<T, N, FAST>(P, cur, mu_c, mc_c);
+        if (has_halo)
+            load_point32<T, N>(y1, V, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
+                               hcur);
 
+        // byte offset of the column inside one z plane; the plane offset goes into
+        // the (scalar) buffer base, so no per-field descriptor is loop invariant
+        const unsigned idx = (unsigned)col * (unsigned)sizeof(T);
         for (int z = z0; z < z1; ++z) {
             const long long pz = (long long)z * nxy;
-            const long long idx = pz + col;
             if (DIM == 3) {
                 const int zp = z == nz - 1 ? 0 : z + 1;
-                load_point<T, N>(y1, V, (long long)zp * nxy + col, withc, nxt);
+                load_point32<T, N>(y1, V, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
+                                   withc, nxt);
+                if (has_halo && z + 1 < z1)
+                    load_point32<T, N>(y1, V, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
+                                       withc, hnxt);
             }
 
-            // ---- right-hand side at (x, y, z) -----------------------------
-            // activity: phase a takes part at the cell when phi_a > 0 at the cell
-            // or at one of its 2d neighbours (the n(phi, grad phi) filter and N_z
-            // of eq. phieq)
-            T mu0 = T(0), mc0 = T(0);
-            if (withc) mu_mc<T, N>(P, cur, mu0, mc0);
-            unsigned act = 0u;
-            T lap[N];
+            // ---- stage plane z in LDS ---------------------------------------
 #pragma unroll
-            for (int a = 0; a < N; ++a) {
-                lap[a] = T(0);
-                if (cur[a] > T(0)) act |= 1u << a;
+            for (int a = 0; a < N; ++a) lds[a * plane_sz + own_slot] = cur[a];
+            lds[N * plane_sz + own_slot] = mu_c;
+            lds[(N + 1) * plane_sz + own_slot] = mc_c;
+            if (has_halo) {
+                T hmu = T(0), hmc = T(0);
+                if (withc) point_mu_mc<T, N, FAST>(P, hcur, hmu, hmc);
+#pragma unroll
+                for (int a = 0; a < N; ++a) lds[a * plane_sz + hslot] = hcur[a];
+                lds[N * plane_sz + hslot] = hmu;
+                lds[(N + 1) * plane_sz + hslot] = hmc;
             }
-            T flux = T(0);
-#pragma unroll
-            for (int k = 0; k < 2 * DIM; ++k) {
-                T nb[N + 1];
-                if (k < 4) {
-                    long long o;
-                    if (k == 0) o = pz + (long long)y * nx + xm;
-                    else if (k == 1) o = pz + (long long)y * nx + xp;
-                    else if (k == 2) o = pz + (long long)ym * nx + x;
-                    else o = pz + (long long)yp * nx + x;
-                    load_point<T, N>(y1, V, o, withc, nb);
-                } else {
-#pragma unroll
-                    for (int f = 0; f <= N; ++f) nb[f] = (k == 4) ? prv[f] : nxt[f];
-                }
+            if (DIM == 3 && withc) point_mu_mc<T, N, FAST>(P, nxt, mu_n, mc_n);
+            __syncthreads();
+
+            if (active) {
+                // ---- right-hand side at (x, y, z) -------------------------------
+                // activity of phase a: phi_a > 0 at the cell or at one of its 2d
+                // neighbours (filter n and N_z of eq. phieq), as max > 0
+                const int nbs[4] = {own_slot - 1, own_slot + 1, own_slot - TXH, own_slot + TXH};
+                T lap[N], mx[N];
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
-                    lap[a] = lap[a] + nb[a];
-                    if (nb[a] > T(0)) act |= 1u << a;
+                    lap[a] = T(0);
+                    mx[a] = cur[a];
                 }
-                if (withc) {
+                T flux = T(0);
+#pragma unroll
+                for (int k = 0; k < 2 * DIM; ++k) {
                     T muk, mck;
-                    mu_mc<T, N>(P, nb, muk, mck);
-                    flux = flux + (T(0.5) * (mc0 + mck)) * (muk - mu0);
-                }
-            }
-            const int nzc = __popc(act);
+                    if (k < 4) {
 #pragma unroll
-            for (int a = 0; a < N; ++a) lap[a] = (lap[a] - T(2 * DIM) * cur[a]) * idx2;
-
-            // variational derivative delta_a = sum_{b != a} (A_ab Lap phi_b +
-            // B_ab phi_b) + psi_{type(a)}(mu)
-            T psi[TMAX];
-            if (withc) {
+                        for (int a = 0; a < N; ++a) {
+                            const T v = lds[a * plane_sz + nbs[k]];
+                            lap[a] = lap[a] + v;
+                            mx[a] = max_num(mx[a], v);
+                        }
+                        muk = lds[N * plane_sz + nbs[k]];
+                        mck = lds[(N + 1) * plane_sz + nbs[k]];
+                    } else {
+                        const T *nv = k == 4 ? prv : nxt;
 #pragma unroll
-                for (int t = 0; t < TMAX; ++t)
-                    psi[t] = (t < P.n_types) ? (-mu0 * mu0) / P.k2t[t] - mu0 * P.c0t[t] : T(0);
-            }
-            T delta[N];
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                T s = T(0);
-#pragma unroll
-                for (int bb = 0; bb < N; ++bb) {
-                    if (bb == a) continue;
-                    s = s + (P.A[a * NMAX + bb] * lap[bb] + P.B[a * NMAX + bb] * cur[bb]);
-                }
-                if (withc) {
-                    const int t = P.tphi[a];
-                    const T ps = t == 0 ? psi[0] : t == 1 ? psi[1] : t == 2 ? psi[2] : psi[3];
-                    s = s + ps;
-                }
-                delta[a] = s;
-            }
-            // dphi_a/dt = -(1/N_z) sum_{b active} L_ab (delta_a - delta_b)
-            T r[N + 1];
-            const T inz = T(1) / T(nzc > 0 ? nzc : 1);
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                T ra = T(0);
-                if (((act >> a) & 1u) && nzc >= 2) {
-                    T s = T(0);
-#pragma unroll
-                    for (int bb = 0; bb < N; ++bb) {
-                        if (bb == a || !((act >> bb) & 1u)) continue;
-                        s = s + P.L[a * NMAX + bb] * (delta[a] - delta[bb]);
-                    }
-                    ra = -s * inz;
-                }
-                r[a] = ra;
-            }
-            r[N] = withc ? flux * idx2 : T(0);
-
-            // ---- stage combination, projection, store --------------------
-            T *__restrict__ out = A.out;
-            T yv[N + 1];
-            if constexpr (KIND == K_RHS) {
-#pragma unroll
-                for (int f = 0; f < N; ++f) out[f * V + idx] = r[f];
-                if (withc) out[N * V + idx] = r[N];
-            } else if constexpr (KIND == K_EST) {
-                // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi entry
-                // whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves [0,1] has
-                // zero error; weights r max(|u^n|,|u^{n+1}|) + a; DoF count with
-                // the two-DoF rule for cells without nontrivial phi entries
-                const T *__restrict__ un = A.u0;
-                const T *__restrict__ r0 = A.r0;
-                int nt = 0;
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    const T u_n = un[a * V + idx];
-                    const T rs = r0[a * V + idx] + r[a];
-                    T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
-                    const T trial = u_n + A.hdt * rs;
-                    if (trial < T(0) || trial > T(1)) e = T(0);
-                    if (e != T(0)) {
-                        const T w = A.r_phi * tmax(tabs(u_n), tabs(cur[a])) + A.a_phi;
-                        const T q = e / w;
-                        acc += (double)q * (double)q;
-                        ++nt;
-                    }
-                }
-                cnt += nt > 0 ? nt : 2;
-                if (withc) {
-                    const T u_n = un[N * V + idx];
-                    const T rs = r0[N * V + idx] + r[N];
-                    const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
-                    const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
-                    const T q = e / w;
-                    acc += (double)q * (double)q;
-                    cnt += 1;
-                }
-            } else {
-                if constexpr (KIND == K_EULER || KIND == K_SSP104_S5 || KIND == K_RKL2_FIRST) {
-#pragma unroll
-                    for (int f = 0; f <= N; ++f) yv[f] = cur[f] + A.a * r[f];
-                } else if constexpr (KIND == K_SSP2_FINAL) {
-                    const T *__restrict__ u0 = A.u0;
-#pragma unroll
-                    for (int f = 0; f <= N; ++f) {
-                        const T u = (f < N || withc) ? u0[f * V + idx] : T(0);
-                        yv[f] = ((A.a * cur[f] + u) + A.b * r[f]) / A.c;
-                    }
-                } else if constexpr (KIND == K_SSP104_FINAL) {
-                    const T *__restrict__ u0 = A.u0;
-#pragma unroll
-                    for (int f = 0; f <= N; ++f) {
-                        const T u = (f < N || withc) ? u0[f * V + idx] : T(0);
-                        yv[f] = (u + A.a * cur[f]) + A.b * r[f];
-                    }
-                } else if constexpr (KIND == K_RKL1) {
-                    const T *__restrict__ y2 = A.y2;
-#pragma unroll
-                    for (int f = 0; f <= N; ++f) {
-                        const T v2 = (f < N || withc) ? y2[f * V + idx] : T(0);
-                        yv[f] = (A.a * cur[f] + A.b * v2) + A.c * r[f];
-                    }
-                } else {  // K_RKL2
-                    const T *__restrict__ u0 = A.u0;
-                    const T *__restrict__ y2 = A.y2;
-                    const T *__restrict__ r0 = A.r0;
-#pragma unroll
-                    for (int f = 0; f <= N; ++f) {
-                        const bool have = f < N || withc;
-                        const T u = have ? u0[f * V + idx] : T(0);
-                        const T v2 = have ? y2[f * V + idx] : T(0);
-                        const T q0 = have ? r0[f * V + idx] : T(0);
-                        yv[f] = ((A.a * u + A.b * cur[f]) + A.c * v2) + A.d * (A.e * r[f] + A.f * q0);
-                    }
-                }
-
-                if constexpr (KIND == K_RKL2_FIRST) {
-                    // First RKL2 stage: where S changes the cell, replace rhs(u^{n,0})
-                    // of the phi planes by (S(u^{n,1}) - u^{n,0}) / (mut_1 dt) (Sec. 3.2).
-                    T ys[N];
-#pragma unroll
-                    for (int a = 0; a < N; ++a) ys[a] = yv[a];
-                    simplex<T, N>(ys);
-                    bool changed = false;
-#pragma unroll
-                    for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
-                    T *__restrict__ o2 = A.out2;
-#pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        out[a * V + idx] = ys[a];
-                        o2[a * V + idx] = changed ? (ys[a] - cur[a]) / A.a : r[a];
+                        for (int a = 0; a < N; ++a) {
+                            lap[a] = lap[a] + nv[a];
+                            mx[a] = max_num(mx[a], nv[a]);
+                        }
+                        muk = k == 4 ? mu_p : mu_n;
+                        mck = k == 4 ? mc_p : mc_n;
                     }
                     if (withc) {
-                        out[N * V + idx] = yv[N];
-                        o2[N * V + idx] = r[N];
+                        if constexpr (FAST) flux = fma_t(T(0.5) * (mc_c + mck), muk - mu_c, flux);
+                        else flux = flux + (T(0.5) * (mc_c + mck)) * (muk - mu_c);
                     }
-                } else if constexpr (KIND == K_SSP104_S5) {
-                    // Fifth SSP(10)4 stage plus the two linear updates of the
-                    // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1).
-                    simplex<T, N>(yv);
-                    const T *__restrict__ q2 = A.u0;
-                    T *__restrict__ o2 = A.out2;
-                    T q1n[N + 1];
+                }
+                unsigned act = 0u;
 #pragma unroll
-                    for (int f = 0; f <= N; ++f) {
-                        const bool have = f < N || withc;
-                        const T q2v = have ? q2[f * V + idx] : T(0);
-                        const T q2n = A.b * q2v + A.c * yv[f];
-                        if (have) o2[f * V + idx] = q2n;
-                        q1n[f] = A.d * q2n - A.e * yv[f];
+                for (int a = 0; a < N; ++a)
+                    if (mx[a] > T(0)) act |= 1u << a;
+                const int nzc = __popc(act);
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    if constexpr (FAST) lap[a] = fma_t(T(-2 * DIM), cur[a], lap[a]) * idx2;
+                    else lap[a] = (lap[a] - T(2 * DIM) * cur[a]) * idx2;
+                }
+
+                // variational derivative delta_a = sum_{b != a} (A_ab Lap phi_b +
+                // B_ab phi_b) + psi_{type(a)}(mu)
+                // grand potential psi_a(mu) = -mu^2/(2k_a) - mu c0_a (Sec. 2)
+                T psi[N];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    if (!withc) psi[a] = T(0);
+                    else if constexpr (FAST) psi[a] = fma_t(-(mu_c * mu_c), P.hik[a], -(mu_c * P.c0[a]));
+                    else psi[a] = (-mu_c * mu_c) / P.k2[a] - mu_c * P.c0[a];
+                }
+                T delta[N];
+                T r[N + 1];
+                const T inz = T(1) / T(nzc > 0 ? nzc : 1);
+                if (FAST && P.uniform) {
+                    const T A0 = pair[1], B0 = pair[N * N + 1], L0 = pair[2 * N * N + 1];
+                    T slap = T(0), sp = T(0);
+#pragma unroll
+                    for (int a = 0; a < N; ++a) {
+                        slap += lap[a];
+                        sp += cur[a];
                     }
-                    simplex<T, N>(q1n);
+                    T dact = T(0);
 #pragma unroll
-                    for (int f = 0; f < N; ++f) out[f * V + idx] = q1n[f];
-                    if (withc) out[N * V + idx] = q1n[N];
+                    for (int a = 0; a < N; ++a) {
+                        T s = fma_t(A0, slap - lap[a], B0 * (sp - cur[a]));
+                        if (withc) s += psi[a];
+                        delta[a] = s;
+                        if ((act >> a) & 1u) dact += s;
+                    }
+                    const T mean = dact * inz;
+#pragma unroll
+                    for (int a = 0; a < N; ++a)
+                        r[a] = (((act >> a) & 1u) && nzc >= 2) ? L0 * (mean - delta[a]) : T(0);
                 } else {
-                    simplex<T, N>(yv);
 #pragma unroll
-                    for (int f = 0; f < N; ++f) out[f * V + idx] = yv[f];
-                    if (withc) out[N * V + idx] = yv[N];
-                    if constexpr (KIND == K_EULER) {
-                        if (A.out2 != nullptr) {
-                            T *__restrict__ o2 = A.out2;
+                    for (int a = 0; a < N; ++a) {
+                        T s = T(0);
 #pragma unroll
-                            for (int f = 0; f < N; ++f) o2[f * V + idx] = r[f];
-                            if (withc) o2[N * V + idx] = r[N];
+                        for (int bb = 0; bb < N; ++bb) {
+                            if (bb == a) continue;
+                            const T Aab = pair[a * N + bb], Bab = pair[N * N + a * N + bb];
+                            if constexpr (FAST) s = fma_t(Aab, lap[bb], fma_t(Bab, cur[bb], s));
+                            else s = s + (Aab * lap[bb] + Bab * cur[bb]);
+                        }
+                        if (withc) s = s + psi[a];
+                        delta[a] = s;
+                    }
+                    // dphi_a/dt = -(1/N_z) sum_{b active} L_ab (delta_a - delta_b)
+#pragma unroll
+                    for (int a = 0; a < N; ++a) {
+                        T ra = T(0);
+                        if (((act >> a) & 1u) && nzc >= 2) {
+                            T s = T(0);
+#pragma unroll
+                            for (int bb = 0; bb < N; ++bb) {
+                                if (bb == a || !((act >> bb) & 1u)) continue;
+                                const T Lab = pair[2 * N * N + a * N + bb];
+                                if constexpr (FAST) s = fma_t(Lab, delta[a] - delta[bb], s);
+                                else s = s + Lab * (delta[a] - delta[bb]);
+                            }
+                            ra = -s * inz;
+                        }
+                        r[a] = ra;
+                    }
+                }
+                r[N] = withc ? flux * idx2 : T(0);
+
+                // ---- stage combination, projection, store ----------------------
+                T *__restrict__ out = A.out;
+                T yv[N + 1];
+                if constexpr (KIND == K_RHS) {
+#pragma unroll
+                    for (int f = 0; f < N; ++f) stf(out + pz, V, f, idx, r[f]);
+                    if (withc) stf(out + pz, V, N, idx, r[N]);
+                } else if constexpr (KIND == K_EST) {
+                    // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
+                    // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
+                    // [0,1] has zero error; weights r max(|u^n|,|u^{n+1}|) + a; the
+                    // two-DoF rule for cells without nontrivial phi entries
+                    const T *__restrict__ un = A.u0;
+                    const T *__restrict__ r0 = A.r0;
+                    int nt = 0;
+#pragma unroll
+                    for (int a = 0; a < N; ++a) {
+                        const T u_n = ldf(un + pz, V, a, idx);
+                        const T rs = ldf(r0 + pz, V, a, idx) + r[a];
+                        T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
+                        const T trial = u_n + A.hdt * rs;
+                        if (trial < T(0) || trial > T(1)) e = T(0);
+                        if (e != T(0)) {
+                            const T w = A.r_phi * tmax(tabs(u_n), tabs(cur[a])) + A.a_phi;
+                            const T q = e / w;
+                            acc += (double)q * (double)q;
+                            ++nt;
+                        }
+                    }
+                    cnt += nt > 0 ? nt : 2;
+                    if (withc) {
+                        const T u_n = ldf(un + pz, V, N, idx);
+                        const T rs = ldf(r0 + pz, V, N, idx) + r[N];
+                        const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
+                        const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
+                        const T q = e / w;
+                        acc += (double)q * (double)q;
+                        cnt += 1;
+                    }
+                } else {
+                    if constexpr (KIND == K_EULER || KIND == K_SSP104_S5 || KIND == K_RKL2_FIRST) {
+#pragma unroll
+                        for (int f = 0; f <= N; ++f) {
+                            if constexpr (FAST) yv[f] = fma_t(A.a, r[f], cur[f]);
+                            else yv[f] = cur[f] + A.a * r[f];
+                        }
+                    } else if constexpr (KIND == K_SSP2_FINAL) {
+                        const T *__restrict__ u0 = A.u0;
+#pragma unroll
+                        for (int f = 0; f <= N; ++f) {
+                            const T u = (f < N || withc) ? ldf(u0 + pz, V, f, idx) : T(0);
+                            yv[f] = ((A.a * cur[f] + u) + A.b * r[f]) / A.c;
+                        }
+                    } else if constexpr (KIND == K_SSP104_FINAL) {
+                        const T *__restrict__ u0 = A.u0;
+#pragma unroll
+                        for (int f = 0; f <= N; ++f) {
+                            const T u = (f < N || withc) ? ldf(u0 + pz, V, f, idx) : T(0);
+                            yv[f] = (u + A.a * cur[f]) + A.b * r[f];
+                        }
+                    } else if constexpr (KIND == K_RKL1) {
+                        const T *__restrict__ y2 = A.y2;
+#pragma unroll
+                        for (int f = 0; f <= N; ++f) {
+                            const T v2 = (f < N || withc) ? ldf(y2 + pz, V, f, idx) : T(0);
+                            if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, v2, A.a * cur[f]));
+                            else yv[f] = (A.a * cur[f] + A.b * v2) + A.c * r[f];
+                        }
+                    } else {  // K_RKL2
+                        const T *__restrict__ u0 = A.u0;
+                        const T *__restrict__ y2 = A.y2;
+                        const T *__restrict__ r0 = A.r0;
+#pragma unroll
+                        for (int f = 0; f <= N; ++f) {
+                            const bool have = f < N || withc;
+                            const T u = have ? ldf(u0 + pz, V, f, idx) : T(0);
+                            const T v2 = have ? ldf(y2 + pz, V, f, idx) : T(0);
+                            const T q0 = have ? ldf(r0 + pz, V, f, idx) : T(0);
+                            if constexpr (FAST)
+                                yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
+                                              fma_t(A.c, v2, fma_t(A.b, cur[f], A.a * u)));
+                            else
+                                yv[f] = ((A.a * u + A.b * cur[f]) + A.c * v2) + A.d * (A.e * r[f] + A.f * q0);
+                        }
+                    }
+
+                    if constexpr (KIND == K_RKL2_FIRST) {
+                        // First RKL2 stage: where S changes the cell, replace rhs(u^{n,0}) of
+                        // the phi planes by (S(u^{n,1}) - u^{n,0}) / (mut_1 dt) (Sec. 3.2).
+                        T ys[N];
+#pragma unroll
+                        for (int a = 0; a < N; ++a) ys[a] = yv[a];
+                        simplex<T, N>(ys);
+                        bool changed = false;
+#pragma unroll
+                        for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
+                        T *__restrict__ o2 = A.out2;
+#pragma unroll
+                        for (int a = 0; a < N; ++a) {
+                            stf(out + pz, V, a, idx, ys[a]);
+                            stf(o2 + pz, V, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+                        }
+                        if (withc) {
+                            stf(out + pz, V, N, idx, yv[N]);
+                            stf(o2 + pz, V, N, idx, r[N]);
+                        }
+                    } else if constexpr (KIND == K_SSP104_S5) {
+                        // Fifth SSP(10)4 stage plus the two linear updates of the
+                        // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1).
+                        simplex<T, N>(yv);
+                        const T *__restrict__ q2 = A.u0;
+                        T *__restrict__ o2 = A.out2;
+                        T q1n[N + 1];
+#pragma unroll
+                        for (int f = 0; f <= N; ++f) {
+                            const bool have = f < N || withc;
+                            const T q2v = have ? ldf(q2 + pz, V, f, idx) : T(0);
+                            const T q2n = A.b * q2v + A.c * yv[f];
+                            if (have) stf(o2 + pz, V, f, idx, q2n);
+                            q1n[f] = A.d * q2n - A.e * yv[f];
+                        }
+                        simplex<T, N>(q1n);
+#pragma unroll
+                        for (int f = 0; f < N; ++f) stf(out + pz, V, f, idx, q1n[f]);
+                        if (withc) stf(out + pz, V, N, idx, q1n[N]);
+                    } else {
+                        simplex<T, N>(yv);
+#pragma unroll
+                        for (int f = 0; f < N; ++f) stf(out + pz, V, f, idx, yv[f]);
+                        if (withc) stf(out + pz, V, N, idx, yv[N]);
+                        if constexpr (KIND == K_EULER) {
+                            if (A.out2 != nullptr) {
+                                T *__restrict__ o2 = A.out2;
+#pragma unroll
+                                for (int f = 0; f < N; ++f) stf(o2 + pz, V, f, idx, r[f]);
+                                if (withc) stf(o2 + pz, V, N, idx, r[N]);
+                            }
                         }
                     }
                 }
             }
+            __syncthreads();  // plane z of LDS is read; the next plane may overwrite it
 
             if (DIM == 3) {
 #pragma unroll
                 for (int f = 0; f <= N; ++f) {
                     prv[f] = cur[f];
                     cur[f] = nxt[f];
+                    hcur[f] = hnxt[f];
                 }
+                mu_p = mu_c; mc_p = mc_c;
+                mu_c = mu_n; mc_c = mc_n;
             }
         }
     }
@@ -320,11 +484,27 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A) {
     }
 }
 
+// LDS per block: (N + 2) planes of (TILE_X + 2) x (TILE_Y + 2) values.
+template <typename T, int N>
+constexpr int lds_elems() { return (N + 2) * (TILE_X + 2) * (TILE_Y + 2); }
+
+// Occupancy hint: the single-precision 3D kernels with up to 9 order
+// parameters fit three wavefronts per SIMD (<= 168 VGPRs) without scratch;
+// larger instances keep the compiler's choice.
+template <typename T, int DIM, int N>
+constexpr int min_waves_per_eu() {
+    return (std::is_same<T, float>::value && DIM == 3 && N <= 9) ? 3 : 1;
+}
+
 // One named kernel per stage kind, so that profiles separate them.
 #define PF_STAGE_KERNEL(name, kind)                                                  \
     template <typename T, int DIM, int N>                                           \
-    __global__ void __launch_bounds__(256) name(const StageArgs<T> A) {             \
-        stage_body<T, DIM, N, kind>(A);                                             \
+    __global__ void __launch_bounds__(256)                                          \
+        __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, DIM, N>(), 8)))      \
+        name(const StageArgs<T> A) {                                                \
+        __shared__ T lds[lds_elems<T, N>()];                                        \
+        __shared__ T pair[3 * N * N];                                               \
+        stage_body<T, DIM, N, kind>(A, xcd_logical_block(), lds, pair);             \
     }
 PF_STAGE_KERNEL(rhs_kernel, K_RHS)
 PF_STAGE_KERNEL(euler_stage_kernel, K_EULER)
@@ -352,6 +532,44 @@ hipError_t launch_stage_dn(const StageArgs<T> &A, int nblocks, hipStream_t strea
     case K_EST: hipLaunchKernelGGL((estimator_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// Batched forward-Euler stage over many independent 2D instances: a
+// persistent grid walks the global tile list (tiles of all instances, one
+// instance after the other); each tile takes its instance's parameters, state
+// offset and step size from device tables, so one launch advances every
+// instance by one step.  An instance whose run is complete is skipped.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) {
+    __shared__ T lds[lds_elems<T, N>()];
+    __shared__ T pair[3 * N * N];
+    const int step = *B.step_base + B.step_offset;
+    for (int g = xcd_logical_block(); g < B.total_tiles; g += gridDim.x) {
+        const int i = B.tile_inst[g];
+        const BatchInst<T> &I = B.inst[i];
+        if (step >= I.nsteps) continue;  // uniform over the block
+        const bool even = (step & 1) == 0;
+        StageArgs<T> A = {};
+        A.P = B.params + i;
+        A.y1 = (even ? B.bufA : B.bufB) + I.off;
+        A.out = (even ? B.bufB : B.bufA) + I.off;
+        A.kind = K_EULER;
+        A.a = step < I.nfull ? I.dt : I.dt_last;
+        A.tx = TILE_X;
+        A.ty = TILE_Y;
+        A.zchunk = 1;
+        A.ntx = I.ntx;
+        A.nty = I.nty;
+        A.nzc = 1;
+        A.ntiles = I.ntx * I.nty;
+        stage_body<T, 2, N, K_EULER>(A, g - I.tile0, lds, pair);
+    }
+}
+
+template <typename T, int N>
+hipError_t launch_batch_euler_n(const BatchArgs<T> &B, int nblocks, hipStream_t stream) {
+    hipLaunchKernelGGL((batch_euler_kernel<T, N>), dim3(nblocks), dim3(256), 0, stream, B);
     return hipGetLastError();
 }
 

@@ -10,4 +10,6 @@
 namespace pf {
 template hipError_t launch_stage_n<float, PF_NPHI>(int, const StageArgs<float> &, int, hipStream_t);
 template hipError_t launch_stage_n<double, PF_NPHI>(int, const StageArgs<double> &, int, hipStream_t);
+template hipError_t launch_batch_euler_n<float, PF_NPHI>(const BatchArgs<float> &, int, hipStream_t);
+template hipError_t launch_batch_euler_n<double, PF_NPHI>(const BatchArgs<double> &, int, hipStream_t);
 }  // namespace pf

@@ -1,0 +1,109 @@
+"""Batched 2D instances (one fused launch per step, hipGraph replay) against
+single-instance runs and the FP64 oracle, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import pf_inputs as pi
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pf = pytest.importorskip("paper_2601_16522_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    pf.lib()
+
+
+def small_batch():
+    """Six two-phase instances of uneven (partly ragged) size, radius and mobility."""
+    out = []
+    shapes = [(64, 64), (70, 45), (96, 96), (33, 50), (128, 64), (40, 200)]
+    rng = np.random.default_rng(9)
+    for k, (nx, ny) in enumerate(shapes):
+        R = float(rng.uniform(0.2, 0.4)) * min(nx, ny)
+        M = float(rng.uniform(0.5, 2.0))
+        wl = pi.single_grain(n=nx, ny=ny, R=R, W=4.0, M=M, seed=30 + k)
+        out.append(wl)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_equals_single_runs_bitwise(prec):
+    wls = small_batch()
+    b = pf.Batch([w.param_dict() for w in wls], prec=prec)
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
+    # uneven step counts (odd and even) and clipped last steps
+    t_end = [dts[i] * (17 + 3 * i) + 0.3 * dts[i] * (i % 2) for i in range(len(wls))]
+    st = b.run_to(t_end, graph_steps=4)
+    for i, w in enumerate(wls):
+        u_b, t_b = b.get_fields(i)
+        s = pf.Sim(w.param_dict(), prec=prec)
+        s.init_fields(w.u0)
+        st1 = s.run_to("fe", t_end[i], dt_fixed=dts[i])
+        u_s, t_s = s.get_fields()
+        assert st[i].accepted == st1.accepted and t_b == t_s == t_end[i]
+        assert np.array_equal(u_b, u_s), (i, np.abs(u_b - u_s).max())
+
+
+def test_batch_graph_replays_equal_eager_runs():
+    """Replay one captured graph across several runs, with eager work and
+    synchronisation in between, and compare every run with direct launches."""
+    wls = small_batch()[:4]
+    g = pf.Batch([w.param_dict() for w in wls], prec="fp32")
+    e = pf.Batch([w.param_dict() for w in wls], prec="fp32")
+    for i, w in enumerate(wls):
+        g.init_fields(i, w.u0)
+        e.init_fields(i, w.u0)
+    dts = [0.9 * g.stable_dt(i) for i in range(len(wls))]
+    t = [0.0] * len(wls)
+    for rep in range(4):
+        t = [t[i] + 12 * dts[i] for i in range(len(wls))]
+        g.run_to(t, dt=dts, graph_steps=6)
+        e.run_to(t, dt=dts, graph_steps=0)
+        _ = torch.ones(1024, device="cuda").sum().item()  # unrelated eager work + sync
+        for i in range(len(wls)):
+            ug, _ = g.get_fields(i)
+            ue, _ = e.get_fields(i)
+            assert np.array_equal(ug, ue), (rep, i)
+
+
+def test_batch_fp64_matches_oracle():
+    wls = small_batch()[:3]
+    b = pf.Batch([w.param_dict() for w in wls], prec="fp64")
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
+    t_end = [40 * d for d in dts]
+    b.run_to(t_end, graph_steps=8)
+    for i, w in enumerate(wls):
+        P = oracle.Params(**w.param_dict())
+        ref, st, rc = oracle.run_to(P, oracle.FE, w.u0, t_end[i], dt_fixed=dts[i])
+        u, t = b.get_fields(i)
+        assert rc == 0 and np.abs(u - ref).max() <= 1e-10
+
+
+def test_batch_autotune_keeps_state():
+    wls = small_batch()[:3]
+    b = pf.Batch([w.param_dict() for w in wls], prec="fp32")
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    before = [b.get_fields(i)[0] for i in range(3)]
+    nb, ms = b.autotune()
+    assert nb % 8 == 0 and ms > 0
+    for i in range(3):
+        assert np.array_equal(b.get_fields(i)[0], before[i])
+
+
+def test_batch_rejects_mixed_instances():
+    a = pi.single_grain(n=32, R=8.0).param_dict()
+    c = dict(pi.voronoi_2d(n=40, n_grains=4, n_phi=3, dmin=5.0).param_dict())
+    with pytest.raises(pf.PFError):
+        pf.Batch([a, c])

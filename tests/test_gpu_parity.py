@@ -218,7 +218,7 @@ def test_tiling_does_not_change_results(prec):
     wl = pores_3d(n=40, nyz=(36, 21))
     dte = oracle.stable_dt(P_of(wl))
     outs = []
-    for tx, zc in ((64, 16), (32, 4), (128, 64), (64, 1)):
+    for tx, zc in ((64, 16), (64, 4), (64, 64), (64, 1), (64, 3), (64, 256)):
         sim = make(wl, prec=prec)
         sim.set_tiling(tx, zc)
         sim.step("rkl2", 12 * dte)
@@ -272,7 +272,7 @@ def test_error_paths():
         sim.run_to("fe", 1.0, tol=pf.Tol())
     assert e.value.code == -7
     with pytest.raises(pf.PFError) as e:
-        sim.set_tiling(48, 4)
+        sim.set_tiling(32, 4)
     assert e.value.code == -1
 
 
