@@ -62,6 +62,8 @@ struct pf_sim {
     int cur = 0;
     bool have_fields = false;
     void *dparams = nullptr;
+    KConsts<float> kf{};
+    KConsts<double> kd{};
     double *red = nullptr;
     long long *redn = nullptr;
     int red_cap = 0;
@@ -218,6 +220,25 @@ void collect_timing(pf_sim *s) {
 // ---------------------------------------------------------------------------
 // Constants (Sec. 2): A = 4 W gamma / pi, B = 4 gamma / (pi W), L = pi M / (4 W)
 // ---------------------------------------------------------------------------
+template <typename T>
+void fill_kconsts(const DevParams<T> &P, KConsts<T> &K) {
+    std::memset(&K, 0, sizeof K);
+    K.nx = P.nx; K.ny = P.ny; K.nz = P.nz;
+    K.with_c = P.with_c; K.n_types = P.n_types; K.uniform = P.uniform;
+    K.V = P.V; K.idx2 = P.idx2;
+    for (int a = 0; a < NMAX; ++a) {
+        K.c0[a] = P.c0[a]; K.ik[a] = P.ik[a]; K.Dk[a] = P.Dk[a];
+        K.hik[a] = P.hik[a]; K.k2[a] = P.k2[a];
+    }
+}
+
+template <typename T>
+const KConsts<T> &kconsts(const pf_sim *s);
+template <>
+const KConsts<float> &kconsts<float>(const pf_sim *s) { return s->kf; }
+template <>
+const KConsts<double> &kconsts<double>(const pf_sim *s) { return s->kd; }
+
 template <typename T>
 void fill_params(const pf_sim *s, DevParams<T> &P) {
     std::memset(&P, 0, sizeof P);
@@ -398,6 +419,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
                 unsigned fam) {
     StageArgs<T> A;
     std::memset(&A, 0, sizeof A);
+    A.K = kconsts<T>(s);
     A.P = (const DevParams<T> *)s->dparams;
     A.y1 = y1;
     A.y2 = y2;
@@ -405,6 +427,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     A.r0 = r0;
     A.out = out;
     A.out2 = out2;
+    set_field_bases(A, s->F, s->V);
     A.kind = kind;
     A.a = (T)a; A.b = (T)b; A.c = (T)c; A.d = (T)d; A.e = (T)e; A.f = (T)f;
     int ntx, nty, nzc, ntiles, nblocks;
@@ -435,10 +458,12 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
     if (kind == 0) {
         StageArgs<T> A;
         std::memset(&A, 0, sizeof A);
+        A.K = kconsts<T>(s);
         A.P = (const DevParams<T> *)s->dparams;
         A.y1 = unew;
         A.u0 = uold;
         A.r0 = aux;
+        set_field_bases(A, s->F, s->V);
         A.kind = K_EST;
         A.red = s->red;
         A.redn = s->redn;
@@ -864,11 +889,13 @@ pf_status pf_create(const pf_params *p, pf_sim **out) {
     if (p->prec == PF_FP64) {
         DevParams<double> P;
         fill_params(s, P);
+        fill_kconsts(P, s->kd);
         if (hipMalloc(&s->dparams, sizeof P) != hipSuccess) rc = PF_ENOMEM;
         else if (hipMemcpy(s->dparams, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess) rc = PF_EHIP;
     } else {
         DevParams<float> P;
         fill_params(s, P);
+        fill_kconsts(P, s->kf);
         if (hipMalloc(&s->dparams, sizeof P) != hipSuccess) rc = PF_ENOMEM;
         else if (hipMemcpy(s->dparams, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess) rc = PF_EHIP;
     }

@@ -24,8 +24,8 @@ __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
 // KKS chemical potential and diffusive mobility at one point (eqs. cadef,
 // mueq, gibbs-energy, ceq): mu = (c - sum phi_a c0_a) / (sum phi_a / k_a),
 // Mc = sum phi_a D_a / k_a.
-template <typename T, int N>
-__device__ __forceinline__ void mu_mc(const DevParams<T> &P, const T *v, T &mu, T &mc) {
+template <typename T, int N, typename C>
+__device__ __forceinline__ void mu_mc(const C &P, const T *v, T &mu, T &mc) {
     T sc0 = T(0), sik = T(0), smc = T(0);
 #pragma unroll
     for (int a = 0; a < N; ++a) {
@@ -73,51 +73,24 @@ __device__ __forceinline__ void load_point(const T *__restrict__ u, long long V,
     v[N] = withc ? u[N * V + idx] : T(0);
 }
 
-// Field f of a state vector addressed by a 32-bit byte offset through a
-// buffer resource: the descriptor (base of the field plane, plane size in
-// bytes) is uniform and lives in scalar registers, the per-lane offset is one
-// 32-bit VGPR.  An offset past the plane reads 0 and drops a store instead of
-// touching other memory.  The handle refuses grids whose plane exceeds 4 GiB.
-// 0x00020000 is the buffer descriptor's format word for the gfx9 family.
+// A field plane at a 32-bit byte offset: the plane base comes from the kernel
+// arguments (scalar registers), the per-lane offset is one 32-bit VGPR, so each
+// access is a single global load/store with a scalar base.  The handle refuses
+// grids whose plane exceeds 4 GiB.
 template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *u, long long V, int f) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(u + (long long)f * V), 0,
-                                             (int)(unsigned)(V * (long long)sizeof(T)), 0x00020000);
-}
-
-__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
-    return __hiloint2double((int)v[1], (int)v[0]);
-}
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, float x) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)off, 0, 0);
-}
-__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, double x) {
-    typedef unsigned u2 __attribute__((vector_size(8)));
-    u2 v;
-    v[0] = (unsigned)__double2loint(x);
-    v[1] = (unsigned)__double2hiint(x);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
-}
-
-template <typename T>
-__device__ __forceinline__ T ldf(const T *u, long long V, int f, unsigned boff) {
-    return buf_load(plane_rsrc(u, V, f), boff, T(0));
+__device__ __forceinline__ T ldp(const T *base, unsigned boff) {
+    return *(const T *)((const char *)base + boff);
 }
 template <typename T>
-__device__ __forceinline__ void stf(T *u, long long V, int f, unsigned boff, T v) {
-    buf_store(plane_rsrc(u, V, f), boff, v);
+__device__ __forceinline__ void stp(T *base, unsigned boff, T v) {
+    *(T *)((char *)base + boff) = v;
 }
 
 template <typename T, int N>
-__device__ __forceinline__ void load_point32(const T *u, long long V, unsigned boff, bool withc,
-                                             T *v) {
+__device__ __forceinline__ void load_point32(const T *const *fb, unsigned boff, bool withc, T *v) {
 #pragma unroll
-    for (int f = 0; f < N; ++f) v[f] = ldf(u, V, f, boff);
-    v[N] = withc ? ldf(u, V, N, boff) : T(0);
+    for (int f = 0; f < N; ++f) v[f] = ldp(fb[f], boff);
+    v[N] = withc ? ldp(fb[N], boff) : T(0);
 }
 
 // Deterministic block reduction of (sum, count) over a 256-thread block: a

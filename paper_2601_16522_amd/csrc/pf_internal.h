@@ -50,15 +50,32 @@ enum StageKind : int {
     K_EST = 8           // Sommeijer estimate of u^{n+1} = y1 against u^n = u0, R0 = r0
 };
 
+// Uniform per-simulation constants the stage kernels read: passed by value as
+// kernel arguments so that they live in scalar registers.
+template <typename T>
+struct KConsts {
+    int nx, ny, nz, with_c, n_types, uniform;
+    long long V;
+    T idx2;
+    T c0[NMAX], ik[NMAX], Dk[NMAX], hik[NMAX], k2[NMAX];
+};
+
+constexpr int FMAX = NMAX + 1;  // fields of a state vector: N phases + c
+
 template <typename T>
 struct StageArgs {
-    const DevParams<T> *P;
+    KConsts<T> K;
+    const DevParams<T> *P;  // pair tables (staged into LDS by each block)
     const T *y1;    // stencil input
     const T *y2;
     const T *u0;
     const T *r0;
     T *out;
     T *out2;
+    // base of every field plane of each vector (filled from the pointers above);
+    // an access is one of these scalar bases plus a 32-bit per-lane byte offset
+    const T *fy1[FMAX], *fy2[FMAX], *fu0[FMAX], *fr0[FMAX];
+    T *fout[FMAX], *fout2[FMAX];
     double *red;    // per-block partial sums (EST)
     long long *redn;
     int kind;
@@ -74,6 +91,19 @@ struct StageArgs {
 
 // One instance of a batch of independent 2D simulations that share N, the
 // precision and with_c.
+// Fills the per-field bases of a StageArgs from its vector pointers.
+template <typename T>
+__host__ __device__ inline void set_field_bases(StageArgs<T> &A, int F, long long V) {
+    for (int f = 0; f < F; ++f) {
+        A.fy1[f] = A.y1 ? A.y1 + f * V : nullptr;
+        A.fy2[f] = A.y2 ? A.y2 + f * V : nullptr;
+        A.fu0[f] = A.u0 ? A.u0 + f * V : nullptr;
+        A.fr0[f] = A.r0 ? A.r0 + f * V : nullptr;
+        A.fout[f] = A.out ? A.out + f * V : nullptr;
+        A.fout2[f] = A.out2 ? A.out2 + f * V : nullptr;
+    }
+}
+
 template <typename T>
 struct BatchInst {
     long long off;     // element offset of the instance's state in each batch buffer

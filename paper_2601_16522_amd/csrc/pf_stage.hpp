@@ -68,7 +68,7 @@ __device__ __forceinline__ T fma_t(T a, T b, T c) {
 // for the reference (double) form; fused multiply-adds and a hardware
 // reciprocal for the fast form.
 template <typename T, int N, bool FAST>
-__device__ __forceinline__ void point_mu_mc(const DevParams<T> &P, const T *v, T &mu, T &mc) {
+__device__ __forceinline__ void point_mu_mc(const KConsts<T> &P, const T *v, T &mu, T &mc) {
     if constexpr (!FAST) {
         mu_mc<T, N>(P, v, mu, mc);
     } else {
@@ -100,7 +100,7 @@ template <typename T, int DIM, int N, int KIND>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
                                            T *__restrict__ pair) {
     constexpr bool FAST = std::is_same<T, float>::value;
-    const DevParams<T> &P = *A.P;
+    const KConsts<T> &P = A.K;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const long long V = P.V;
     const bool withc = P.with_c != 0;
@@ -116,7 +116,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
         for (int i = threadIdx.x; i < 3 * N * N; i += blockDim.x) {
             const int tab = i / (N * N), ab = i % (N * N);
             const int a = ab / N, bb = ab % N;
-            const T *src = tab == 0 ? P.A : tab == 1 ? P.B : P.L;
+            const T *src = tab == 0 ? A.P->A : tab == 1 ? A.P->B : A.P->L;
             pair[i] = src[a * NMAX + bb];
         }
         // the tile is fixed at 64 x 4 (one wavefront per row) so that every LDS
@@ -157,32 +157,29 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
 
         const int z0 = DIM == 3 ? tiz * A.zchunk : 0;
         const int z1 = DIM == 3 ? min(z0 + A.zchunk, nz) : 1;
-        const T *__restrict__ y1 = A.y1;
 
         T prv[N + 1], cur[N + 1], nxt[N + 1], hcur[N + 1], hnxt[N + 1];
         T mu_p = T(0), mc_p = T(0), mu_c = T(0), mc_c = T(0), mu_n = T(0), mc_n = T(0);
         if (DIM == 3) {
             const int zm = z0 == 0 ? nz - 1 : z0 - 1;
-            load_point32<T, N>(y1, V, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
+            load_point32<T, N>(A.fy1, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
             if (withc) point_mu_mc<T, N, FAST>(P, prv, mu_p, mc_p);
         }
-        load_point32<T, N>(y1, V, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
+        load_point32<T, N>(A.fy1, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
         if (withc) point_mu_mc<T, N, FAST>(P, cur, mu_c, mc_c);
         if (has_halo)
-            load_point32<T, N>(y1, V, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
+            load_point32<T, N>(A.fy1, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
                                hcur);
 
-        // byte offset of the column inside one z plane; the plane offset goes into
-        // the (scalar) buffer base, so no per-field descriptor is loop invariant
-        const unsigned idx = (unsigned)col * (unsigned)sizeof(T);
         for (int z = z0; z < z1; ++z) {
             const long long pz = (long long)z * nxy;
+            const unsigned idx = (unsigned)(pz + col) * (unsigned)sizeof(T);  // byte offset in a plane
             if (DIM == 3) {
                 const int zp = z == nz - 1 ? 0 : z + 1;
-                load_point32<T, N>(y1, V, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
+                load_point32<T, N>(A.fy1, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
                                    withc, nxt);
                 if (has_halo && z + 1 < z1)
-                    load_point32<T, N>(y1, V, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
+                    load_point32<T, N>(A.fy1, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
                                        withc, hnxt);
             }
 
@@ -320,24 +317,21 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                 r[N] = withc ? flux * idx2 : T(0);
 
                 // ---- stage combination, projection, store ----------------------
-                T *__restrict__ out = A.out;
                 T yv[N + 1];
                 if constexpr (KIND == K_RHS) {
 #pragma unroll
-                    for (int f = 0; f < N; ++f) stf(out + pz, V, f, idx, r[f]);
-                    if (withc) stf(out + pz, V, N, idx, r[N]);
+                    for (int f = 0; f < N; ++f) stp(A.fout[f], idx, r[f]);
+                    if (withc) stp(A.fout[N], idx, r[N]);
                 } else if constexpr (KIND == K_EST) {
                     // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
                     // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
                     // [0,1] has zero error; weights r max(|u^n|,|u^{n+1}|) + a; the
                     // two-DoF rule for cells without nontrivial phi entries
-                    const T *__restrict__ un = A.u0;
-                    const T *__restrict__ r0 = A.r0;
                     int nt = 0;
 #pragma unroll
                     for (int a = 0; a < N; ++a) {
-                        const T u_n = ldf(un + pz, V, a, idx);
-                        const T rs = ldf(r0 + pz, V, a, idx) + r[a];
+                        const T u_n = ldp(A.fu0[a], idx);
+                        const T rs = ldp(A.fr0[a], idx) + r[a];
                         T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
                         const T trial = u_n + A.hdt * rs;
                         if (trial < T(0) || trial > T(1)) e = T(0);
@@ -350,8 +344,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     }
                     cnt += nt > 0 ? nt : 2;
                     if (withc) {
-                        const T u_n = ldf(un + pz, V, N, idx);
-                        const T rs = ldf(r0 + pz, V, N, idx) + r[N];
+                        const T u_n = ldp(A.fu0[N], idx);
+                        const T rs = ldp(A.fr0[N], idx) + r[N];
                         const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
                         const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
                         const T q = e / w;
@@ -366,37 +360,31 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                             else yv[f] = cur[f] + A.a * r[f];
                         }
                     } else if constexpr (KIND == K_SSP2_FINAL) {
-                        const T *__restrict__ u0 = A.u0;
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldf(u0 + pz, V, f, idx) : T(0);
+                            const T u = (f < N || withc) ? ldp(A.fu0[f], idx) : T(0);
                             yv[f] = ((A.a * cur[f] + u) + A.b * r[f]) / A.c;
                         }
                     } else if constexpr (KIND == K_SSP104_FINAL) {
-                        const T *__restrict__ u0 = A.u0;
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldf(u0 + pz, V, f, idx) : T(0);
+                            const T u = (f < N || withc) ? ldp(A.fu0[f], idx) : T(0);
                             yv[f] = (u + A.a * cur[f]) + A.b * r[f];
                         }
                     } else if constexpr (KIND == K_RKL1) {
-                        const T *__restrict__ y2 = A.y2;
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T v2 = (f < N || withc) ? ldf(y2 + pz, V, f, idx) : T(0);
+                            const T v2 = (f < N || withc) ? ldp(A.fy2[f], idx) : T(0);
                             if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, v2, A.a * cur[f]));
                             else yv[f] = (A.a * cur[f] + A.b * v2) + A.c * r[f];
                         }
                     } else {  // K_RKL2
-                        const T *__restrict__ u0 = A.u0;
-                        const T *__restrict__ y2 = A.y2;
-                        const T *__restrict__ r0 = A.r0;
-#pragma unroll
+    #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
-                            const T u = have ? ldf(u0 + pz, V, f, idx) : T(0);
-                            const T v2 = have ? ldf(y2 + pz, V, f, idx) : T(0);
-                            const T q0 = have ? ldf(r0 + pz, V, f, idx) : T(0);
+                            const T u = have ? ldp(A.fu0[f], idx) : T(0);
+                            const T v2 = have ? ldp(A.fy2[f], idx) : T(0);
+                            const T q0 = have ? ldp(A.fr0[f], idx) : T(0);
                             if constexpr (FAST)
                                 yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
                                               fma_t(A.c, v2, fma_t(A.b, cur[f], A.a * u)));
@@ -415,46 +403,42 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                         bool changed = false;
 #pragma unroll
                         for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
-                        T *__restrict__ o2 = A.out2;
 #pragma unroll
                         for (int a = 0; a < N; ++a) {
-                            stf(out + pz, V, a, idx, ys[a]);
-                            stf(o2 + pz, V, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+                            stp(A.fout[a], idx, ys[a]);
+                            stp(A.fout2[a], idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
                         }
                         if (withc) {
-                            stf(out + pz, V, N, idx, yv[N]);
-                            stf(o2 + pz, V, N, idx, r[N]);
+                            stp(A.fout[N], idx, yv[N]);
+                            stp(A.fout2[N], idx, r[N]);
                         }
                     } else if constexpr (KIND == K_SSP104_S5) {
                         // Fifth SSP(10)4 stage plus the two linear updates of the
                         // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1).
                         simplex<T, N>(yv);
-                        const T *__restrict__ q2 = A.u0;
-                        T *__restrict__ o2 = A.out2;
                         T q1n[N + 1];
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
-                            const T q2v = have ? ldf(q2 + pz, V, f, idx) : T(0);
+                            const T q2v = have ? ldp(A.fu0[f], idx) : T(0);
                             const T q2n = A.b * q2v + A.c * yv[f];
-                            if (have) stf(o2 + pz, V, f, idx, q2n);
+                            if (have) stp(A.fout2[f], idx, q2n);
                             q1n[f] = A.d * q2n - A.e * yv[f];
                         }
                         simplex<T, N>(q1n);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stf(out + pz, V, f, idx, q1n[f]);
-                        if (withc) stf(out + pz, V, N, idx, q1n[N]);
+                        for (int f = 0; f < N; ++f) stp(A.fout[f], idx, q1n[f]);
+                        if (withc) stp(A.fout[N], idx, q1n[N]);
                     } else {
                         simplex<T, N>(yv);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stf(out + pz, V, f, idx, yv[f]);
-                        if (withc) stf(out + pz, V, N, idx, yv[N]);
+                        for (int f = 0; f < N; ++f) stp(A.fout[f], idx, yv[f]);
+                        if (withc) stp(A.fout[N], idx, yv[N]);
                         if constexpr (KIND == K_EULER) {
                             if (A.out2 != nullptr) {
-                                T *__restrict__ o2 = A.out2;
-#pragma unroll
-                                for (int f = 0; f < N; ++f) stf(o2 + pz, V, f, idx, r[f]);
-                                if (withc) stf(o2 + pz, V, N, idx, r[N]);
+        #pragma unroll
+                                for (int f = 0; f < N; ++f) stp(A.fout2[f], idx, r[f]);
+                                if (withc) stp(A.fout2[N], idx, r[N]);
                             }
                         }
                     }
@@ -552,8 +536,20 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
         const bool even = (step & 1) == 0;
         StageArgs<T> A = {};
         A.P = B.params + i;
+        {
+            const DevParams<T> &Q = B.params[i];
+            A.K.nx = Q.nx; A.K.ny = Q.ny; A.K.nz = Q.nz;
+            A.K.with_c = Q.with_c; A.K.n_types = Q.n_types; A.K.uniform = Q.uniform;
+            A.K.V = Q.V; A.K.idx2 = Q.idx2;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                A.K.c0[a] = Q.c0[a]; A.K.ik[a] = Q.ik[a]; A.K.Dk[a] = Q.Dk[a];
+                A.K.hik[a] = Q.hik[a]; A.K.k2[a] = Q.k2[a];
+            }
+        }
         A.y1 = (even ? B.bufA : B.bufB) + I.off;
         A.out = (even ? B.bufB : B.bufA) + I.off;
+        set_field_bases(A, N + (A.K.with_c ? 1 : 0), A.K.V);
         A.kind = K_EULER;
         A.a = step < I.nfull ? I.dt : I.dt_last;
         A.tx = TILE_X;
