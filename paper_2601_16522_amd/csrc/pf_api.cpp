@@ -846,6 +846,10 @@ pf_status init_meta(pf_sim *s, const pf_params *p) {
         const unsigned long long cells = (unsigned long long)p->nx * p->ny * p->nz;
         const unsigned long long esz = p->prec == PF_FP64 ? 8 : 4;
         if (cells * esz > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
+        // and one vector spans at most four such groups of planes
+        const unsigned long long G = 0xFFFFFFFFull / (cells * esz);
+        const unsigned long long F = (unsigned long long)p->n_phi + (p->with_c ? 1 : 0);
+        if (F > 4 * G) return PF_EUNSUPPORTED;
     }
     for (int a = 0; a < p->n_phi; ++a)
         if (p->type_of[a] < 0 || p->type_of[a] >= p->n_types) return PF_EINVAL;

@@ -73,24 +73,64 @@ __device__ __forceinline__ void load_point(const T *__restrict__ u, long long V,
     v[N] = withc ? u[N * V + idx] : T(0);
 }
 
-// A field plane at a 32-bit byte offset: the plane base comes from the kernel
-// arguments (scalar registers), the per-lane offset is one 32-bit VGPR, so each
-// access is a single global load/store with a scalar base.  The handle refuses
-// grids whose plane exceeds 4 GiB.
-template <typename T>
-__device__ __forceinline__ T ldp(const T *base, unsigned boff) {
-    return *(const T *)((const char *)base + boff);
+// Field f of vector v at a 32-bit per-lane byte offset, through a buffer
+// resource: the descriptor (first plane of the field's group, group span in
+// bytes) and the plane offset inside the group are uniform (scalar registers);
+// fields of one group share one descriptor.  An offset past the group reads 0
+// and drops a store instead of touching other memory.  0x00020000 is the
+// buffer descriptor's format word for the gfx9 family.
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
+                                          float) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
 }
-template <typename T>
-__device__ __forceinline__ void stp(T *base, unsigned boff, T v) {
-    *(T *)((char *)base + boff) = v;
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
+                                           double) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0);
+    return __hiloint2double((int)v[1], (int)v[0]);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
+                                          float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)off, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
+                                          double x) {
+    typedef unsigned u2 __attribute__((vector_size(8)));
+    u2 v;
+    v[0] = (unsigned)__double2loint(x);
+    v[1] = (unsigned)__double2hiint(x);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, 0);
 }
 
-template <typename T, int N>
-__device__ __forceinline__ void load_point32(const T *const *fb, unsigned boff, bool withc, T *v) {
+template <typename S>
+__device__ __forceinline__ int field_group(const S &A, int f) {
+    const int G = A.G;
+    return f >= 3 * G ? 3 : f >= 2 * G ? 2 : f >= G ? 1 : 0;
+}
+
+template <typename T, typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const S &A, int v, int g) {
+    // G * plane_bytes < 4 GiB by construction (set_field_bases)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(A.gb[v][g]), 0,
+                                             (int)(unsigned)(A.G * (unsigned long long)A.plane_bytes),
+                                             0x00020000);
+}
+
+template <typename T, typename S>
+__device__ __forceinline__ T ldv(const S &A, int v, int f, unsigned boff) {
+    const int g = field_group(A, f);
+    return buf_load(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, T(0));
+}
+template <typename T, typename S>
+__device__ __forceinline__ void stv(const S &A, int v, int f, unsigned boff, T x) {
+    const int g = field_group(A, f);
+    buf_store(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, x);
+}
+
+template <typename T, int N, typename S>
+__device__ __forceinline__ void load_point32(const S &A, int v, unsigned boff, bool withc, T *x) {
 #pragma unroll
-    for (int f = 0; f < N; ++f) v[f] = ldp(fb[f], boff);
-    v[N] = withc ? ldp(fb[N], boff) : T(0);
+    for (int f = 0; f < N; ++f) x[f] = ldv<T>(A, v, f, boff);
+    x[N] = withc ? ldv<T>(A, v, N, boff) : T(0);
 }
 
 // Deterministic block reduction of (sum, count) over a 256-thread block: a

@@ -72,10 +72,14 @@ struct StageArgs {
     const T *r0;
     T *out;
     T *out2;
-    // base of every field plane of each vector (filled from the pointers above);
-    // an access is one of these scalar bases plus a 32-bit per-lane byte offset
-    const T *fy1[FMAX], *fy2[FMAX], *fu0[FMAX], *fr0[FMAX];
-    T *fout[FMAX], *fout2[FMAX];
+    // Buffer addressing of the six vectors above: the field planes of a vector
+    // are split into groups of G consecutive planes whose span fits a 32-bit
+    // byte range; gb[v][g] is the first plane of group g of vector v (y1, y2,
+    // u0, r0, out, out2).  Field f is read from group f / G at scalar offset
+    // (f mod G) * plane_bytes plus a 32-bit per-lane offset.
+    const T *gb[6][4];
+    int G;
+    unsigned plane_bytes;
     double *red;    // per-block partial sums (EST)
     long long *redn;
     int kind;
@@ -91,17 +95,20 @@ struct StageArgs {
 
 // One instance of a batch of independent 2D simulations that share N, the
 // precision and with_c.
-// Fills the per-field bases of a StageArgs from its vector pointers.
+// Fills the buffer-group bases of a StageArgs from its vector pointers.  The
+// caller guarantees V * sizeof(T) < 4 GiB and F <= 4 G.
 template <typename T>
 __host__ __device__ inline void set_field_bases(StageArgs<T> &A, int F, long long V) {
-    for (int f = 0; f < F; ++f) {
-        A.fy1[f] = A.y1 ? A.y1 + f * V : nullptr;
-        A.fy2[f] = A.y2 ? A.y2 + f * V : nullptr;
-        A.fu0[f] = A.u0 ? A.u0 + f * V : nullptr;
-        A.fr0[f] = A.r0 ? A.r0 + f * V : nullptr;
-        A.fout[f] = A.out ? A.out + f * V : nullptr;
-        A.fout2[f] = A.out2 ? A.out2 + f * V : nullptr;
-    }
+    const unsigned long long pb = (unsigned long long)V * sizeof(T);
+    int G = (int)(0xFFFFFFFFull / pb);
+    if (G > F) G = F;
+    if (G < 1) G = 1;
+    A.G = G;
+    A.plane_bytes = (unsigned)pb;
+    const T *vec[6] = {A.y1, A.y2, A.u0, A.r0, A.out, A.out2};
+    for (int v = 0; v < 6; ++v)
+        for (int g = 0; g < 4; ++g)
+            A.gb[v][g] = (vec[v] && g * G < F) ? vec[v] + (long long)g * G * V : vec[v];
 }
 
 template <typename T>

@@ -67,17 +67,20 @@ __device__ __forceinline__ T fma_t(T a, T b, T c) {
 // mu and Mc at one point (eqs. cadef, mueq, gibbs-energy, ceq).  Exact order
 // for the reference (double) form; fused multiply-adds and a hardware
 // reciprocal for the fast form.
+// kc: per-phase constants staged in LDS (rows c0, 1/k, D/k, 1/(2k)), read by
+// the fast form so that they hold no scalar registers across the z march.
 template <typename T, int N, bool FAST>
-__device__ __forceinline__ void point_mu_mc(const KConsts<T> &P, const T *v, T &mu, T &mc) {
+__device__ __forceinline__ void point_mu_mc(const KConsts<T> &P, const T *kc, const T *v, T &mu,
+                                            T &mc) {
     if constexpr (!FAST) {
         mu_mc<T, N>(P, v, mu, mc);
     } else {
         T sc0 = T(0), sik = T(0), smc = T(0);
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            sc0 = fma_t(v[a], P.c0[a], sc0);
-            sik = fma_t(v[a], P.ik[a], sik);
-            smc = fma_t(v[a], P.Dk[a], smc);
+            sc0 = fma_t(v[a], kc[a], sc0);
+            sik = fma_t(v[a], kc[N + a], sik);
+            smc = fma_t(v[a], kc[2 * N + a], smc);
         }
         mu = (v[N] - sc0) * fast_rcp(sik);
         mc = smc;
@@ -98,7 +101,7 @@ __device__ __forceinline__ int xcd_logical_block() {
 // it with the same arguments (it synchronises the block).
 template <typename T, int DIM, int N, int KIND>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
-                                           T *__restrict__ pair) {
+                                           T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
     const KConsts<T> &P = A.K;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -119,6 +122,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             const T *src = tab == 0 ? A.P->A : tab == 1 ? A.P->B : A.P->L;
             pair[i] = src[a * NMAX + bb];
         }
+        for (int i = threadIdx.x; i < 4 * N; i += blockDim.x) {
+            const int row = i / N, a = i % N;
+            const T *src = row == 0 ? A.P->c0 : row == 1 ? A.P->ik : row == 2 ? A.P->Dk : A.P->hik;
+            kc[i] = src[a];
+        }
+        __syncthreads();  // the tables are read from the first plane on
         // the tile is fixed at 64 x 4 (one wavefront per row) so that every LDS
         // plane offset is an instruction immediate
         constexpr int TX = TILE_X, TY = TILE_Y;
@@ -162,13 +171,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
         T mu_p = T(0), mc_p = T(0), mu_c = T(0), mc_c = T(0), mu_n = T(0), mc_n = T(0);
         if (DIM == 3) {
             const int zm = z0 == 0 ? nz - 1 : z0 - 1;
-            load_point32<T, N>(A.fy1, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
-            if (withc) point_mu_mc<T, N, FAST>(P, prv, mu_p, mc_p);
+            load_point32<T, N>(A, 0, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
+            if (withc) point_mu_mc<T, N, FAST>(P, kc, prv, mu_p, mc_p);
         }
-        load_point32<T, N>(A.fy1, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
-        if (withc) point_mu_mc<T, N, FAST>(P, cur, mu_c, mc_c);
+        load_point32<T, N>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
+        if (withc) point_mu_mc<T, N, FAST>(P, kc, cur, mu_c, mc_c);
         if (has_halo)
-            load_point32<T, N>(A.fy1, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
+            load_point32<T, N>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
                                hcur);
 
         for (int z = z0; z < z1; ++z) {
@@ -176,10 +185,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             const unsigned idx = (unsigned)(pz + col) * (unsigned)sizeof(T);  // byte offset in a plane
             if (DIM == 3) {
                 const int zp = z == nz - 1 ? 0 : z + 1;
-                load_point32<T, N>(A.fy1, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
+                load_point32<T, N>(A, 0, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
                                    withc, nxt);
                 if (has_halo && z + 1 < z1)
-                    load_point32<T, N>(A.fy1, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
+                    load_point32<T, N>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
                                        withc, hnxt);
             }
 
@@ -190,13 +199,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             lds[(N + 1) * plane_sz + own_slot] = mc_c;
             if (has_halo) {
                 T hmu = T(0), hmc = T(0);
-                if (withc) point_mu_mc<T, N, FAST>(P, hcur, hmu, hmc);
+                if (withc) point_mu_mc<T, N, FAST>(P, kc, hcur, hmu, hmc);
 #pragma unroll
                 for (int a = 0; a < N; ++a) lds[a * plane_sz + hslot] = hcur[a];
                 lds[N * plane_sz + hslot] = hmu;
                 lds[(N + 1) * plane_sz + hslot] = hmc;
             }
-            if (DIM == 3 && withc) point_mu_mc<T, N, FAST>(P, nxt, mu_n, mc_n);
+            if (DIM == 3 && withc) point_mu_mc<T, N, FAST>(P, kc, nxt, mu_n, mc_n);
             __syncthreads();
 
             if (active) {
@@ -256,7 +265,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
                     if (!withc) psi[a] = T(0);
-                    else if constexpr (FAST) psi[a] = fma_t(-(mu_c * mu_c), P.hik[a], -(mu_c * P.c0[a]));
+                    else if constexpr (FAST) psi[a] = fma_t(-(mu_c * mu_c), kc[3 * N + a], -(mu_c * kc[a]));
                     else psi[a] = (-mu_c * mu_c) / P.k2[a] - mu_c * P.c0[a];
                 }
                 T delta[N];
@@ -320,8 +329,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                 T yv[N + 1];
                 if constexpr (KIND == K_RHS) {
 #pragma unroll
-                    for (int f = 0; f < N; ++f) stp(A.fout[f], idx, r[f]);
-                    if (withc) stp(A.fout[N], idx, r[N]);
+                    for (int f = 0; f < N; ++f) stv<T>(A, 4, f, idx, r[f]);
+                    if (withc) stv<T>(A, 4, N, idx, r[N]);
                 } else if constexpr (KIND == K_EST) {
                     // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
                     // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
@@ -330,8 +339,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     int nt = 0;
 #pragma unroll
                     for (int a = 0; a < N; ++a) {
-                        const T u_n = ldp(A.fu0[a], idx);
-                        const T rs = ldp(A.fr0[a], idx) + r[a];
+                        const T u_n = ldv<T>(A, 2, a, idx);
+                        const T rs = ldv<T>(A, 3, a, idx) + r[a];
                         T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
                         const T trial = u_n + A.hdt * rs;
                         if (trial < T(0) || trial > T(1)) e = T(0);
@@ -344,8 +353,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     }
                     cnt += nt > 0 ? nt : 2;
                     if (withc) {
-                        const T u_n = ldp(A.fu0[N], idx);
-                        const T rs = ldp(A.fr0[N], idx) + r[N];
+                        const T u_n = ldv<T>(A, 2, N, idx);
+                        const T rs = ldv<T>(A, 3, N, idx) + r[N];
                         const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
                         const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
                         const T q = e / w;
@@ -362,19 +371,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     } else if constexpr (KIND == K_SSP2_FINAL) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldp(A.fu0[f], idx) : T(0);
+                            const T u = (f < N || withc) ? ldv<T>(A, 2, f, idx) : T(0);
                             yv[f] = ((A.a * cur[f] + u) + A.b * r[f]) / A.c;
                         }
                     } else if constexpr (KIND == K_SSP104_FINAL) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldp(A.fu0[f], idx) : T(0);
+                            const T u = (f < N || withc) ? ldv<T>(A, 2, f, idx) : T(0);
                             yv[f] = (u + A.a * cur[f]) + A.b * r[f];
                         }
                     } else if constexpr (KIND == K_RKL1) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T v2 = (f < N || withc) ? ldp(A.fy2[f], idx) : T(0);
+                            const T v2 = (f < N || withc) ? ldv<T>(A, 1, f, idx) : T(0);
                             if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, v2, A.a * cur[f]));
                             else yv[f] = (A.a * cur[f] + A.b * v2) + A.c * r[f];
                         }
@@ -382,9 +391,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
     #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
-                            const T u = have ? ldp(A.fu0[f], idx) : T(0);
-                            const T v2 = have ? ldp(A.fy2[f], idx) : T(0);
-                            const T q0 = have ? ldp(A.fr0[f], idx) : T(0);
+                            const T u = have ? ldv<T>(A, 2, f, idx) : T(0);
+                            const T v2 = have ? ldv<T>(A, 1, f, idx) : T(0);
+                            const T q0 = have ? ldv<T>(A, 3, f, idx) : T(0);
                             if constexpr (FAST)
                                 yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
                                               fma_t(A.c, v2, fma_t(A.b, cur[f], A.a * u)));
@@ -405,12 +414,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                         for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
 #pragma unroll
                         for (int a = 0; a < N; ++a) {
-                            stp(A.fout[a], idx, ys[a]);
-                            stp(A.fout2[a], idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+                            stv<T>(A, 4, a, idx, ys[a]);
+                            stv<T>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
                         }
                         if (withc) {
-                            stp(A.fout[N], idx, yv[N]);
-                            stp(A.fout2[N], idx, r[N]);
+                            stv<T>(A, 4, N, idx, yv[N]);
+                            stv<T>(A, 5, N, idx, r[N]);
                         }
                     } else if constexpr (KIND == K_SSP104_S5) {
                         // Fifth SSP(10)4 stage plus the two linear updates of the
@@ -420,25 +429,25 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
-                            const T q2v = have ? ldp(A.fu0[f], idx) : T(0);
+                            const T q2v = have ? ldv<T>(A, 2, f, idx) : T(0);
                             const T q2n = A.b * q2v + A.c * yv[f];
-                            if (have) stp(A.fout2[f], idx, q2n);
+                            if (have) stv<T>(A, 5, f, idx, q2n);
                             q1n[f] = A.d * q2n - A.e * yv[f];
                         }
                         simplex<T, N>(q1n);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stp(A.fout[f], idx, q1n[f]);
-                        if (withc) stp(A.fout[N], idx, q1n[N]);
+                        for (int f = 0; f < N; ++f) stv<T>(A, 4, f, idx, q1n[f]);
+                        if (withc) stv<T>(A, 4, N, idx, q1n[N]);
                     } else {
                         simplex<T, N>(yv);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stp(A.fout[f], idx, yv[f]);
-                        if (withc) stp(A.fout[N], idx, yv[N]);
+                        for (int f = 0; f < N; ++f) stv<T>(A, 4, f, idx, yv[f]);
+                        if (withc) stv<T>(A, 4, N, idx, yv[N]);
                         if constexpr (KIND == K_EULER) {
                             if (A.out2 != nullptr) {
         #pragma unroll
-                                for (int f = 0; f < N; ++f) stp(A.fout2[f], idx, r[f]);
-                                if (withc) stp(A.fout2[N], idx, r[N]);
+                                for (int f = 0; f < N; ++f) stv<T>(A, 5, f, idx, r[f]);
+                                if (withc) stv<T>(A, 5, N, idx, r[N]);
                             }
                         }
                     }
@@ -488,7 +497,8 @@ constexpr int min_waves_per_eu() {
         name(const StageArgs<T> A) {                                                \
         __shared__ T lds[lds_elems<T, N>()];                                        \
         __shared__ T pair[3 * N * N];                                               \
-        stage_body<T, DIM, N, kind>(A, xcd_logical_block(), lds, pair);             \
+        __shared__ T kc[4 * N];                                                     \
+        stage_body<T, DIM, N, kind>(A, xcd_logical_block(), lds, pair, kc);         \
     }
 PF_STAGE_KERNEL(rhs_kernel, K_RHS)
 PF_STAGE_KERNEL(euler_stage_kernel, K_EULER)
@@ -528,6 +538,7 @@ template <typename T, int N>
 __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) {
     __shared__ T lds[lds_elems<T, N>()];
     __shared__ T pair[3 * N * N];
+    __shared__ T kc[4 * N];
     const int step = *B.step_base + B.step_offset;
     for (int g = xcd_logical_block(); g < B.total_tiles; g += gridDim.x) {
         const int i = B.tile_inst[g];
@@ -559,7 +570,7 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
         A.nty = I.nty;
         A.nzc = 1;
         A.ntiles = I.ntx * I.nty;
-        stage_body<T, 2, N, K_EULER>(A, g - I.tile0, lds, pair);
+        stage_body<T, 2, N, K_EULER>(A, g - I.tile0, lds, pair, kc);
     }
 }
 
