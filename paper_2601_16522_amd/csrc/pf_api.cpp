@@ -1475,6 +1475,9 @@ pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out) {
                     per_inst[i].prec != per_inst[0].prec ||
                     (per_inst[i].with_c != 0) != (per_inst[0].with_c != 0)))
             rc = PF_EINVAL;  // instances share dim 2, N, precision and with_c
+        // the batch kernel addresses an instance's whole state as one buffer group
+        if (!rc && (unsigned long long)b->meta[i].F * b->meta[i].V * b->meta[i].esz > 0xFFFFFFFFull)
+            rc = PF_EUNSUPPORTED;
     }
     if (rc) {
         delete b;

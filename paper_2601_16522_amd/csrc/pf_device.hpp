@@ -101,8 +101,13 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
     __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, 0);
 }
 
-template <typename S>
+// Group of field f.  ONEG: the caller guarantees that all fields of a vector
+// fit one group (G >= F), so the group is 0 at compile time and the group base
+// is a constant index (needed where the StageArgs live in registers rather
+// than in the kernel arguments: a runtime index would spill them to scratch).
+template <bool ONEG, typename S>
 __device__ __forceinline__ int field_group(const S &A, int f) {
+    if constexpr (ONEG) return 0;
     const int G = A.G;
     return f >= 3 * G ? 3 : f >= 2 * G ? 2 : f >= G ? 1 : 0;
 }
@@ -115,22 +120,22 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const S &A, int v, 
                                              0x00020000);
 }
 
-template <typename T, typename S>
+template <typename T, bool ONEG = false, typename S>
 __device__ __forceinline__ T ldv(const S &A, int v, int f, unsigned boff) {
-    const int g = field_group(A, f);
+    const int g = field_group<ONEG>(A, f);
     return buf_load(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, T(0));
 }
-template <typename T, typename S>
+template <typename T, bool ONEG = false, typename S>
 __device__ __forceinline__ void stv(const S &A, int v, int f, unsigned boff, T x) {
-    const int g = field_group(A, f);
+    const int g = field_group<ONEG>(A, f);
     buf_store(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, x);
 }
 
-template <typename T, int N, typename S>
+template <typename T, int N, bool ONEG = false, typename S>
 __device__ __forceinline__ void load_point32(const S &A, int v, unsigned boff, bool withc, T *x) {
 #pragma unroll
-    for (int f = 0; f < N; ++f) x[f] = ldv<T>(A, v, f, boff);
-    x[N] = withc ? ldv<T>(A, v, N, boff) : T(0);
+    for (int f = 0; f < N; ++f) x[f] = ldv<T, ONEG>(A, v, f, boff);
+    x[N] = withc ? ldv<T, ONEG>(A, v, N, boff) : T(0);
 }
 
 // Deterministic block reduction of (sum, count) over a 256-thread block: a

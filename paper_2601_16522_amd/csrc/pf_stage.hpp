@@ -98,8 +98,9 @@ __device__ __forceinline__ int xcd_logical_block() {
 }
 
 // One tile (logical index L) of one stage.  Every thread of the block calls
-// it with the same arguments (it synchronises the block).
-template <typename T, int DIM, int N, int KIND>
+// it with the same arguments (it synchronises the block).  ONEG: every vector's
+// fields lie in buffer group 0 (see field_group).
+template <typename T, int DIM, int N, int KIND, bool ONEG = false>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
@@ -171,13 +172,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
         T mu_p = T(0), mc_p = T(0), mu_c = T(0), mc_c = T(0), mu_n = T(0), mc_n = T(0);
         if (DIM == 3) {
             const int zm = z0 == 0 ? nz - 1 : z0 - 1;
-            load_point32<T, N>(A, 0, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
+            load_point32<T, N, ONEG>(A, 0, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
             if (withc) point_mu_mc<T, N, FAST>(P, kc, prv, mu_p, mc_p);
         }
-        load_point32<T, N>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
+        load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
         if (withc) point_mu_mc<T, N, FAST>(P, kc, cur, mu_c, mc_c);
         if (has_halo)
-            load_point32<T, N>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
+            load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
                                hcur);
 
         for (int z = z0; z < z1; ++z) {
@@ -185,10 +186,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             const unsigned idx = (unsigned)(pz + col) * (unsigned)sizeof(T);  // byte offset in a plane
             if (DIM == 3) {
                 const int zp = z == nz - 1 ? 0 : z + 1;
-                load_point32<T, N>(A, 0, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
+                load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
                                    withc, nxt);
                 if (has_halo && z + 1 < z1)
-                    load_point32<T, N>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
+                    load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
                                        withc, hnxt);
             }
 
@@ -329,8 +330,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                 T yv[N + 1];
                 if constexpr (KIND == K_RHS) {
 #pragma unroll
-                    for (int f = 0; f < N; ++f) stv<T>(A, 4, f, idx, r[f]);
-                    if (withc) stv<T>(A, 4, N, idx, r[N]);
+                    for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 4, f, idx, r[f]);
+                    if (withc) stv<T, ONEG>(A, 4, N, idx, r[N]);
                 } else if constexpr (KIND == K_EST) {
                     // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
                     // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
@@ -339,8 +340,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     int nt = 0;
 #pragma unroll
                     for (int a = 0; a < N; ++a) {
-                        const T u_n = ldv<T>(A, 2, a, idx);
-                        const T rs = ldv<T>(A, 3, a, idx) + r[a];
+                        const T u_n = ldv<T, ONEG>(A, 2, a, idx);
+                        const T rs = ldv<T, ONEG>(A, 3, a, idx) + r[a];
                         T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
                         const T trial = u_n + A.hdt * rs;
                         if (trial < T(0) || trial > T(1)) e = T(0);
@@ -353,8 +354,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     }
                     cnt += nt > 0 ? nt : 2;
                     if (withc) {
-                        const T u_n = ldv<T>(A, 2, N, idx);
-                        const T rs = ldv<T>(A, 3, N, idx) + r[N];
+                        const T u_n = ldv<T, ONEG>(A, 2, N, idx);
+                        const T rs = ldv<T, ONEG>(A, 3, N, idx) + r[N];
                         const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
                         const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
                         const T q = e / w;
@@ -371,19 +372,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     } else if constexpr (KIND == K_SSP2_FINAL) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldv<T>(A, 2, f, idx) : T(0);
+                            const T u = (f < N || withc) ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
                             yv[f] = ((A.a * cur[f] + u) + A.b * r[f]) / A.c;
                         }
                     } else if constexpr (KIND == K_SSP104_FINAL) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldv<T>(A, 2, f, idx) : T(0);
+                            const T u = (f < N || withc) ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
                             yv[f] = (u + A.a * cur[f]) + A.b * r[f];
                         }
                     } else if constexpr (KIND == K_RKL1) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T v2 = (f < N || withc) ? ldv<T>(A, 1, f, idx) : T(0);
+                            const T v2 = (f < N || withc) ? ldv<T, ONEG>(A, 1, f, idx) : T(0);
                             if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, v2, A.a * cur[f]));
                             else yv[f] = (A.a * cur[f] + A.b * v2) + A.c * r[f];
                         }
@@ -391,9 +392,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
     #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
-                            const T u = have ? ldv<T>(A, 2, f, idx) : T(0);
-                            const T v2 = have ? ldv<T>(A, 1, f, idx) : T(0);
-                            const T q0 = have ? ldv<T>(A, 3, f, idx) : T(0);
+                            const T u = have ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
+                            const T v2 = have ? ldv<T, ONEG>(A, 1, f, idx) : T(0);
+                            const T q0 = have ? ldv<T, ONEG>(A, 3, f, idx) : T(0);
                             if constexpr (FAST)
                                 yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
                                               fma_t(A.c, v2, fma_t(A.b, cur[f], A.a * u)));
@@ -414,12 +415,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                         for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
 #pragma unroll
                         for (int a = 0; a < N; ++a) {
-                            stv<T>(A, 4, a, idx, ys[a]);
-                            stv<T>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+                            stv<T, ONEG>(A, 4, a, idx, ys[a]);
+                            stv<T, ONEG>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
                         }
                         if (withc) {
-                            stv<T>(A, 4, N, idx, yv[N]);
-                            stv<T>(A, 5, N, idx, r[N]);
+                            stv<T, ONEG>(A, 4, N, idx, yv[N]);
+                            stv<T, ONEG>(A, 5, N, idx, r[N]);
                         }
                     } else if constexpr (KIND == K_SSP104_S5) {
                         // Fifth SSP(10)4 stage plus the two linear updates of the
@@ -429,25 +430,25 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
-                            const T q2v = have ? ldv<T>(A, 2, f, idx) : T(0);
+                            const T q2v = have ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
                             const T q2n = A.b * q2v + A.c * yv[f];
-                            if (have) stv<T>(A, 5, f, idx, q2n);
+                            if (have) stv<T, ONEG>(A, 5, f, idx, q2n);
                             q1n[f] = A.d * q2n - A.e * yv[f];
                         }
                         simplex<T, N>(q1n);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T>(A, 4, f, idx, q1n[f]);
-                        if (withc) stv<T>(A, 4, N, idx, q1n[N]);
+                        for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 4, f, idx, q1n[f]);
+                        if (withc) stv<T, ONEG>(A, 4, N, idx, q1n[N]);
                     } else {
                         simplex<T, N>(yv);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T>(A, 4, f, idx, yv[f]);
-                        if (withc) stv<T>(A, 4, N, idx, yv[N]);
+                        for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 4, f, idx, yv[f]);
+                        if (withc) stv<T, ONEG>(A, 4, N, idx, yv[N]);
                         if constexpr (KIND == K_EULER) {
                             if (A.out2 != nullptr) {
         #pragma unroll
-                                for (int f = 0; f < N; ++f) stv<T>(A, 5, f, idx, r[f]);
-                                if (withc) stv<T>(A, 5, N, idx, r[N]);
+                                for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 5, f, idx, r[f]);
+                                if (withc) stv<T, ONEG>(A, 5, N, idx, r[N]);
                             }
                         }
                     }
@@ -560,7 +561,12 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
         }
         A.y1 = (even ? B.bufA : B.bufB) + I.off;
         A.out = (even ? B.bufB : B.bufA) + I.off;
-        set_field_bases(A, N + (A.K.with_c ? 1 : 0), A.K.V);
+        // one buffer group per vector: the host admits only instances whose
+        // state spans less than 4 GiB
+        A.G = N + (A.K.with_c ? 1 : 0);
+        A.plane_bytes = (unsigned)(A.K.V * (long long)sizeof(T));
+        A.gb[0][0] = A.y1;
+        A.gb[4][0] = A.out;
         A.kind = K_EULER;
         A.a = step < I.nfull ? I.dt : I.dt_last;
         A.tx = TILE_X;
@@ -570,7 +576,7 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
         A.nty = I.nty;
         A.nzc = 1;
         A.ntiles = I.ntx * I.nty;
-        stage_body<T, 2, N, K_EULER>(A, g - I.tile0, lds, pair, kc);
+        stage_body<T, 2, N, K_EULER, true>(A, g - I.tile0, lds, pair, kc);
     }
 }
 
