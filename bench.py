@@ -26,6 +26,7 @@ import math
 
 import numpy as np
 import os
+import subprocess
 import sys
 import time
 
@@ -42,7 +43,7 @@ def kernel_hash() -> str:
     """Hash of the device sources (any edit invalidates the stored counters)."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".h")):
+        if name.endswith((".hip", ".hpp", ".h")) and name != "stream_ref.hip":
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -88,31 +89,20 @@ def copy_calibration(mib: int, reps: int):
     print(json.dumps({"copy_calibration_bytes": 4 * n, "reps": reps}), flush=True)
 
 
-def copy_bandwidth(gib: int = 4, reps: int = 5) -> dict:
-    """Streaming references on `gib` GiB arrays, GB/s (all bytes read and
-    written): a device copy and a two-input elementwise add.  They set the
-    practical HBM ceiling the stencil kernels are compared against."""
-    import torch
-    n = gib * (1 << 30) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    c = torch.empty_like(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def rate(fn, nbytes):
-        fn()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
-
-    out = {"copy": rate(lambda: b.copy_(a), 8 * n),
-           "add": rate(lambda: torch.add(a, b, out=c), 12 * n)}
-    del a, b, c
-    torch.cuda.empty_cache()
-    return out
+def stream_reference(vector_bytes: int):
+    """Streaming references at the stage's own footprint: the committed
+    stream_ref program (built beside the library) run as a child process on
+    vectors of `vector_bytes` bytes.  Returns GB/s of its 4-read-1-write,
+    copy and read-only kernels, or None when the program is not built."""
+    exe = os.path.join(ROOT, "paper_2601_16522_amd", "stream_ref")
+    if not os.path.exists(exe):
+        return None
+    n = max(1024, vector_bytes // 4)
+    r = subprocess.run([exe, str(n), "10"], capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        print(f"# stream_ref failed: {r.stderr.strip()}", file=sys.stderr, flush=True)
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def cpu_baseline(wl, integ: str, t_end: float, tol_kw: dict, dt_fixed: float, sample_note: str):
@@ -158,7 +148,10 @@ def batch_bench(args):
     dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
     t_end = [nsteps * d for d in dts]
     nb = b.autotune()[0] if not args.no_autotune else None
-    K = 50
+    if args.blocks:
+        b.set_blocks(args.blocks)
+        nb = args.blocks
+    K = args.graph_steps
 
     def one():
         for i, w in enumerate(wls):
@@ -186,7 +179,7 @@ def batch_bench(args):
     # the plain FP64 form, instance by instance (one launch per step each)
     t64 = 0.0
     err64 = []
-    for i, w in enumerate(wls):
+    for i, w in enumerate(wls if not args.no_fp64_ref else []):
         s = pf.Sim(w.param_dict(), prec="fp64")
         s.set_stream(stream)
         s.init_fields(w.u0)
@@ -203,6 +196,8 @@ def batch_bench(args):
     bytes_per_launch = 2 * F * E * cells
     avg_s = ev_ms / args.steps / nsteps / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
+    traffic = measured_traffic(f"batch_euler/{len(wls)}inst/{args.prec}")
+    sref = stream_reference(F * E * cells)
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gcell-stage/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -211,19 +206,23 @@ def batch_bench(args):
         "data": "synthetic",
         "config": {"workload": f"batch of {len(wls)} 2D shrinking grains, {cells} cells, "
                                f"{nsteps} FE steps each at 0.9 dt_e, one fused launch per step, "
-                               f"hipGraph of {K} steps",
+                               + (f"hipGraph of {K} steps" if K > 0 else "direct launches"),
                    "cells": cells, "instances": len(wls), "persistent_blocks": nb,
                    "time_to_solution_ms": round(total / args.steps * 1e3, 3),
-                   "fp64_per_instance_time_ms": round(t64 * 1e3, 3),
-                   "speedup_vs_fp64_per_instance": round(t64 / (total / args.steps), 2),
-                   "area_rate_rel_error_fp32_batch_mean": float(np.mean(err32)),
-                   "area_rate_rel_error_fp64_single_mean": float(np.mean(err64)),
-                   "area_rate_rel_error_max_abs_diff": float(np.max(np.abs(np.subtract(err32, err64))))},
+                   "area_rate_rel_error_fp32_batch_mean": float(np.mean(err32))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": f"batch_euler_kernel, avg {avg_s * 1e6:.2f} us per step (HIP events "
-                               f"over graph replays), {bytes_per_launch} algorithmic B/launch"},
+                               f"over graph replays), {bytes_per_launch} algorithmic B/launch",
+                     "stream_ref_GBs": sref,
+                     "frac_of_stream_copy": round(achieved / sref["copy"], 4) if sref else None},
     }
+    if err64:
+        out["config"].update({
+            "fp64_per_instance_time_ms": round(t64 * 1e3, 3),
+            "speedup_vs_fp64_per_instance": round(t64 / (total / args.steps), 2),
+            "area_rate_rel_error_fp64_single_mean": float(np.mean(err64)),
+            "area_rate_rel_error_max_abs_diff": float(np.max(np.abs(np.subtract(err32, err64))))})
     print(json.dumps(out), flush=True)
 
 
@@ -238,7 +237,15 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--zchunk", type=int, default=0,
+                    help="z planes per block (3D); skips the tiling autotuner")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB")
+    ap.add_argument("--blocks", type=int, default=0,
+                    help="batch: persistent grid size (skips the block-count autotuner)")
+    ap.add_argument("--graph-steps", type=int, default=50,
+                    help="batch: steps per captured hipGraph (0: direct launches)")
+    ap.add_argument("--no-fp64-ref", action="store_true",
+                    help="batch: skip the FP64 instance-by-instance comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -284,7 +291,10 @@ def main():
 
     sim.init_fields_device(u0_dev)
     tiling = sim.get_tiling()
-    if not args.no_autotune:
+    if args.zchunk:
+        sim.set_tiling(tiling[0], args.zchunk)
+        tiling = sim.get_tiling()
+    elif not args.no_autotune:
         tiling = sim.autotune()[:2]
     print(f"# tiling tx={tiling[0]} zchunk={tiling[1]}", file=sys.stderr, flush=True)
 
@@ -317,9 +327,9 @@ def main():
     sim.set_timing(False)
     diag = sim.diagnostics()
 
-    copy_bw = copy_bandwidth()
-    value = wl.cells * rhs / total / 1e9
     E = 8 if args.prec == "fp64" else 4
+    sref = stream_reference(wl.F * E * wl.cells)
+    value = wl.cells * rhs / total / 1e9
     bytes_per_launch = 5 * wl.F * E * wl.cells      # Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j out
     avg_s = ms_rkl2 / max(n_rkl2, 1) / 1e3
     achieved = bytes_per_launch / avg_s / 1e9 if n_rkl2 else 0.0
@@ -353,7 +363,8 @@ def main():
                      "kernel": f"rkl2_stage_kernel (RKL2 stages j >= 2), {n_rkl2} launches, "
                                f"avg {avg_s * 1e6:.2f} us (HIP events), "
                                f"{bytes_per_launch} algorithmic B/launch",
-                     "stream_ref_GBs": {k: round(v, 1) for k, v in copy_bw.items()}},
+                     "stream_ref_GBs": sref,
+                     "frac_of_stream_4r1w": round(achieved / sref["4r1w"], 4) if sref else None},
     }
     if not args.no_cpu_baseline:
         note = f"full {wl.name} solve ({desc}) on the host CPU"

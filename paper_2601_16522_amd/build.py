@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpf.so")
+STREAM_REF = os.path.join(HERE, "stream_ref")
 NPHI = [2, 3, 4, 8, 9, 13]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -59,6 +60,12 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the streaming-bandwidth reference program (a measurement aid, not linked)
+    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, "stream_ref.hip"), "-o", STREAM_REF + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(STREAM_REF + ".tmp", STREAM_REF)
     return LIB
 
 

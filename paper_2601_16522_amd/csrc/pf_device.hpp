@@ -79,26 +79,32 @@ __device__ __forceinline__ void load_point(const T *__restrict__ u, long long V,
 // fields of one group share one descriptor.  An offset past the group reads 0
 // and drops a store instead of touching other memory.  0x00020000 is the
 // buffer descriptor's format word for the gfx9 family.
+// CP: cache-policy bits of the access (0: default; 2: non-temporal, for
+// streams that are touched once).
+template <int CP = 0>
 __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
                                           float) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, CP));
 }
+template <int CP = 0>
 __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
                                            double) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, CP);
     return __hiloint2double((int)v[1], (int)v[0]);
 }
+template <int CP = 0>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
                                           float x) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)off, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)off, (int)soff, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff,
                                           double x) {
     typedef unsigned u2 __attribute__((vector_size(8)));
     u2 v;
     v[0] = (unsigned)__double2loint(x);
     v[1] = (unsigned)__double2hiint(x);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, CP);
 }
 
 // Group of field f.  ONEG: the caller guarantees that all fields of a vector
@@ -120,15 +126,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const S &A, int v, 
                                              0x00020000);
 }
 
-template <typename T, bool ONEG = false, typename S>
+template <typename T, bool ONEG = false, int CP = 0, typename S>
 __device__ __forceinline__ T ldv(const S &A, int v, int f, unsigned boff) {
     const int g = field_group<ONEG>(A, f);
-    return buf_load(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, T(0));
+    return buf_load<CP>(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, T(0));
 }
-template <typename T, bool ONEG = false, typename S>
+template <typename T, bool ONEG = false, int CP = 0, typename S>
 __device__ __forceinline__ void stv(const S &A, int v, int f, unsigned boff, T x) {
     const int g = field_group<ONEG>(A, f);
-    buf_store(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, x);
+    buf_store<CP>(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, x);
 }
 
 template <typename T, int N, bool ONEG = false, typename S>

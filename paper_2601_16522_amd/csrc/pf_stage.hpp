@@ -97,13 +97,63 @@ __device__ __forceinline__ int xcd_logical_block() {
     return (b & 7) * per + (b >> 3);
 }
 
+// Pair constants A, B, L (N x N each) and the per-phase constants (rows c0,
+// 1/k, D/k, 1/(2k)) of one simulation into LDS: the pairwise sums and the
+// fast mu then read them without holding N^2 scalar registers.  The caller
+// synchronises before they are read.
+template <typename T, int N>
+__device__ __forceinline__ void stage_tables(const DevParams<T> *P, T *__restrict__ pair,
+                                             T *__restrict__ kc) {
+    for (int i = threadIdx.x; i < 3 * N * N; i += blockDim.x) {
+        const int tab = i / (N * N), ab = i % (N * N);
+        const int a = ab / N, bb = ab % N;
+        const T *src = tab == 0 ? P->A : tab == 1 ? P->B : P->L;
+        pair[i] = src[a * NMAX + bb];
+    }
+    for (int i = threadIdx.x; i < 4 * N; i += blockDim.x) {
+        const int row = i / N, a = i % N;
+        const T *src = row == 0 ? P->c0 : row == 1 ? P->ik : row == 2 ? P->Dk : P->hik;
+        kc[i] = src[a];
+    }
+}
+
+// Cache policy of the operand streams of a stage (the vectors other than the
+// stencil input, and the outputs): each of their values is touched once per
+// stage, while the stencil input is re-read as the halo of the neighbouring
+// tiles.
+template <int DIM> constexpr int operand_load_cp() { return DIM == 3 ? 2 : 0; }
+template <int DIM> constexpr int out_store_cp() { return DIM == 3 ? 2 : 0; }
+// Combination operands loaded with the stencil input, before the barrier.
+template <int DIM> constexpr bool early_operands() { return false; }
+
+// Operands of the stage combination at one cell: o0 from u0 (vector 2), o1
+// from y2 (vector 1), o2 from r0 (vector 3), as far as the stage kind uses them.
+template <typename T, int N, int KIND, bool ONEG, int OPERAND_CP, typename S>
+__device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool withc, T *o0, T *o1,
+                                              T *o2) {
+    constexpr bool U0 = KIND == K_SSP2_FINAL || KIND == K_SSP104_S5 || KIND == K_SSP104_FINAL ||
+                        KIND == K_RKL2 || KIND == K_EST;
+    constexpr bool Y2 = KIND == K_RKL1 || KIND == K_RKL2;
+    constexpr bool R0 = KIND == K_RKL2 || KIND == K_EST;
+#pragma unroll
+    for (int f = 0; f <= N; ++f) {
+        const bool have = f < N || withc;
+        if constexpr (U0) o0[f] = have ? ldv<T, ONEG, OPERAND_CP>(A, 2, f, idx) : T(0);
+        if constexpr (Y2) o1[f] = have ? ldv<T, ONEG, OPERAND_CP>(A, 1, f, idx) : T(0);
+        if constexpr (R0) o2[f] = have ? ldv<T, ONEG, OPERAND_CP>(A, 3, f, idx) : T(0);
+    }
+}
+
 // One tile (logical index L) of one stage.  Every thread of the block calls
 // it with the same arguments (it synchronises the block).  ONEG: every vector's
-// fields lie in buffer group 0 (see field_group).
-template <typename T, int DIM, int N, int KIND, bool ONEG = false>
+// fields lie in buffer group 0 (see field_group).  TABLES: stage the LDS
+// tables of A.P first (false: the caller has staged them).
+template <typename T, int DIM, int N, int KIND, bool ONEG = false, bool TABLES = true>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
+    constexpr bool EARLY = early_operands<DIM>();
+    constexpr int LCP = operand_load_cp<DIM>(), SCP = out_store_cp<DIM>();
     const KConsts<T> &P = A.K;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const long long V = P.V;
@@ -115,20 +165,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
     long long cnt = 0;
 
     if (tile_ok) {
-        // pair constants A, B, L (N x N each) live in LDS for the whole block, so
-        // the pairwise sums read them without holding N^2 scalar registers
-        for (int i = threadIdx.x; i < 3 * N * N; i += blockDim.x) {
-            const int tab = i / (N * N), ab = i % (N * N);
-            const int a = ab / N, bb = ab % N;
-            const T *src = tab == 0 ? A.P->A : tab == 1 ? A.P->B : A.P->L;
-            pair[i] = src[a * NMAX + bb];
+        if constexpr (TABLES) {
+            stage_tables<T, N>(A.P, pair, kc);
+            __syncthreads();  // the tables are read from the first plane on
         }
-        for (int i = threadIdx.x; i < 4 * N; i += blockDim.x) {
-            const int row = i / N, a = i % N;
-            const T *src = row == 0 ? A.P->c0 : row == 1 ? A.P->ik : row == 2 ? A.P->Dk : A.P->hik;
-            kc[i] = src[a];
-        }
-        __syncthreads();  // the tables are read from the first plane on
         // the tile is fixed at 64 x 4 (one wavefront per row) so that every LDS
         // plane offset is an instruction immediate
         constexpr int TX = TILE_X, TY = TILE_Y;
@@ -170,13 +210,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
 
         T prv[N + 1], cur[N + 1], nxt[N + 1], hcur[N + 1], hnxt[N + 1];
         T mu_p = T(0), mc_p = T(0), mu_c = T(0), mc_c = T(0), mu_n = T(0), mc_n = T(0);
+        // every load of the first plane is issued before the first use of one
         if (DIM == 3) {
             const int zm = z0 == 0 ? nz - 1 : z0 - 1;
             load_point32<T, N, ONEG>(A, 0, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
-            if (withc) point_mu_mc<T, N, FAST>(P, kc, prv, mu_p, mc_p);
         }
         load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
-        if (withc) point_mu_mc<T, N, FAST>(P, kc, cur, mu_c, mc_c);
         if (has_halo)
             load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
                                hcur);
@@ -191,6 +230,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                 if (has_halo && z + 1 < z1)
                     load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
                                        withc, hnxt);
+            }
+            T o0[N + 1], o1[N + 1], o2[N + 1];
+            if constexpr (EARLY) load_operands<T, N, KIND, ONEG, LCP>(A, idx, withc, o0, o1, o2);
+            if (z == z0 && withc) {  // later planes rotate their mu and Mc in
+                if (DIM == 3) point_mu_mc<T, N, FAST>(P, kc, prv, mu_p, mc_p);
+                point_mu_mc<T, N, FAST>(P, kc, cur, mu_c, mc_c);
             }
 
             // ---- stage plane z in LDS ---------------------------------------
@@ -327,11 +372,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                 r[N] = withc ? flux * idx2 : T(0);
 
                 // ---- stage combination, projection, store ----------------------
+                if constexpr (!EARLY) load_operands<T, N, KIND, ONEG, LCP>(A, idx, withc, o0, o1, o2);
                 T yv[N + 1];
                 if constexpr (KIND == K_RHS) {
 #pragma unroll
-                    for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 4, f, idx, r[f]);
-                    if (withc) stv<T, ONEG>(A, 4, N, idx, r[N]);
+                    for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 4, f, idx, r[f]);
+                    if (withc) stv<T, ONEG, SCP>(A, 4, N, idx, r[N]);
                 } else if constexpr (KIND == K_EST) {
                     // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
                     // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
@@ -340,8 +386,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     int nt = 0;
 #pragma unroll
                     for (int a = 0; a < N; ++a) {
-                        const T u_n = ldv<T, ONEG>(A, 2, a, idx);
-                        const T rs = ldv<T, ONEG>(A, 3, a, idx) + r[a];
+                        const T u_n = o0[a];
+                        const T rs = o2[a] + r[a];
                         T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
                         const T trial = u_n + A.hdt * rs;
                         if (trial < T(0) || trial > T(1)) e = T(0);
@@ -354,8 +400,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     }
                     cnt += nt > 0 ? nt : 2;
                     if (withc) {
-                        const T u_n = ldv<T, ONEG>(A, 2, N, idx);
-                        const T rs = ldv<T, ONEG>(A, 3, N, idx) + r[N];
+                        const T u_n = o0[N];
+                        const T rs = o2[N] + r[N];
                         const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
                         const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
                         const T q = e / w;
@@ -372,29 +418,23 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                     } else if constexpr (KIND == K_SSP2_FINAL) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
-                            yv[f] = ((A.a * cur[f] + u) + A.b * r[f]) / A.c;
+                            yv[f] = ((A.a * cur[f] + o0[f]) + A.b * r[f]) / A.c;
                         }
                     } else if constexpr (KIND == K_SSP104_FINAL) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T u = (f < N || withc) ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
-                            yv[f] = (u + A.a * cur[f]) + A.b * r[f];
+                            yv[f] = (o0[f] + A.a * cur[f]) + A.b * r[f];
                         }
                     } else if constexpr (KIND == K_RKL1) {
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const T v2 = (f < N || withc) ? ldv<T, ONEG>(A, 1, f, idx) : T(0);
-                            if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, v2, A.a * cur[f]));
-                            else yv[f] = (A.a * cur[f] + A.b * v2) + A.c * r[f];
+                            if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, o1[f], A.a * cur[f]));
+                            else yv[f] = (A.a * cur[f] + A.b * o1[f]) + A.c * r[f];
                         }
                     } else {  // K_RKL2
     #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            const bool have = f < N || withc;
-                            const T u = have ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
-                            const T v2 = have ? ldv<T, ONEG>(A, 1, f, idx) : T(0);
-                            const T q0 = have ? ldv<T, ONEG>(A, 3, f, idx) : T(0);
+                            const T u = o0[f], v2 = o1[f], q0 = o2[f];
                             if constexpr (FAST)
                                 yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
                                               fma_t(A.c, v2, fma_t(A.b, cur[f], A.a * u)));
@@ -415,12 +455,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                         for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
 #pragma unroll
                         for (int a = 0; a < N; ++a) {
-                            stv<T, ONEG>(A, 4, a, idx, ys[a]);
-                            stv<T, ONEG>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+                            stv<T, ONEG, SCP>(A, 4, a, idx, ys[a]);
+                            stv<T, ONEG, SCP>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
                         }
                         if (withc) {
-                            stv<T, ONEG>(A, 4, N, idx, yv[N]);
-                            stv<T, ONEG>(A, 5, N, idx, r[N]);
+                            stv<T, ONEG, SCP>(A, 4, N, idx, yv[N]);
+                            stv<T, ONEG, SCP>(A, 5, N, idx, r[N]);
                         }
                     } else if constexpr (KIND == K_SSP104_S5) {
                         // Fifth SSP(10)4 stage plus the two linear updates of the
@@ -430,25 +470,24 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
-                            const T q2v = have ? ldv<T, ONEG>(A, 2, f, idx) : T(0);
-                            const T q2n = A.b * q2v + A.c * yv[f];
-                            if (have) stv<T, ONEG>(A, 5, f, idx, q2n);
+                            const T q2n = A.b * o0[f] + A.c * yv[f];
+                            if (have) stv<T, ONEG, SCP>(A, 5, f, idx, q2n);
                             q1n[f] = A.d * q2n - A.e * yv[f];
                         }
                         simplex<T, N>(q1n);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 4, f, idx, q1n[f]);
-                        if (withc) stv<T, ONEG>(A, 4, N, idx, q1n[N]);
+                        for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 4, f, idx, q1n[f]);
+                        if (withc) stv<T, ONEG, SCP>(A, 4, N, idx, q1n[N]);
                     } else {
                         simplex<T, N>(yv);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 4, f, idx, yv[f]);
-                        if (withc) stv<T, ONEG>(A, 4, N, idx, yv[N]);
+                        for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 4, f, idx, yv[f]);
+                        if (withc) stv<T, ONEG, SCP>(A, 4, N, idx, yv[N]);
                         if constexpr (KIND == K_EULER) {
                             if (A.out2 != nullptr) {
         #pragma unroll
-                                for (int f = 0; f < N; ++f) stv<T, ONEG>(A, 5, f, idx, r[f]);
-                                if (withc) stv<T, ONEG>(A, 5, N, idx, r[N]);
+                                for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 5, f, idx, r[f]);
+                                if (withc) stv<T, ONEG, SCP>(A, 5, N, idx, r[N]);
                             }
                         }
                     }
@@ -531,9 +570,10 @@ hipError_t launch_stage_dn(const StageArgs<T> &A, int nblocks, hipStream_t strea
 }
 
 // Batched forward-Euler stage over many independent 2D instances: a
-// persistent grid walks the global tile list (tiles of all instances, one
-// instance after the other); each tile takes its instance's parameters, state
-// offset and step size from device tables, so one launch advances every
+// persistent grid splits the global tile list (tiles of all instances, one
+// instance after the other) into one contiguous range per block.  A block
+// loads an instance's constants, state offset and step size, and stages its
+// LDS tables, when its walk enters that instance, so one launch advances every
 // instance by one step.  An instance whose run is complete is skipped.
 template <typename T, int N>
 __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) {
@@ -541,14 +581,24 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
     __shared__ T pair[3 * N * N];
     __shared__ T kc[4 * N];
     const int step = *B.step_base + B.step_offset;
-    for (int g = xcd_logical_block(); g < B.total_tiles; g += gridDim.x) {
-        const int i = B.tile_inst[g];
-        const BatchInst<T> &I = B.inst[i];
-        if (step >= I.nsteps) continue;  // uniform over the block
-        const bool even = (step & 1) == 0;
-        StageArgs<T> A = {};
-        A.P = B.params + i;
-        {
+    const long long L = xcd_logical_block();
+    const int g0 = (int)(L * B.total_tiles / gridDim.x);
+    const int g1 = (int)((L + 1) * B.total_tiles / gridDim.x);
+    if (g0 >= g1) return;
+    int i = B.tile_inst[g0] - 1;
+    int tile0 = 0, end = g0;  // tiles [tile0, end) belong to instance i
+    StageArgs<T> A = {};
+    for (int g = g0; g < g1; ++g) {
+        if (g >= end) {  // uniform over the block: enter instance i + 1
+            ++i;
+            const BatchInst<T> &I = B.inst[i];
+            tile0 = I.tile0;
+            end = tile0 + I.ntx * I.nty;
+            if (step >= I.nsteps) {  // this instance's run is complete
+                g = end - 1;
+                continue;
+            }
+            const bool even = (step & 1) == 0;
             const DevParams<T> &Q = B.params[i];
             A.K.nx = Q.nx; A.K.ny = Q.ny; A.K.nz = Q.nz;
             A.K.with_c = Q.with_c; A.K.n_types = Q.n_types; A.K.uniform = Q.uniform;
@@ -558,25 +608,28 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
                 A.K.c0[a] = Q.c0[a]; A.K.ik[a] = Q.ik[a]; A.K.Dk[a] = Q.Dk[a];
                 A.K.hik[a] = Q.hik[a]; A.K.k2[a] = Q.k2[a];
             }
+            A.y1 = (even ? B.bufA : B.bufB) + I.off;
+            A.out = (even ? B.bufB : B.bufA) + I.off;
+            // one buffer group per vector: the host admits only instances whose
+            // state spans less than 4 GiB
+            A.G = N + (A.K.with_c ? 1 : 0);
+            A.plane_bytes = (unsigned)(A.K.V * (long long)sizeof(T));
+            A.gb[0][0] = A.y1;
+            A.gb[4][0] = A.out;
+            A.kind = K_EULER;
+            A.a = step < I.nfull ? I.dt : I.dt_last;
+            A.tx = TILE_X;
+            A.ty = TILE_Y;
+            A.zchunk = 1;
+            A.ntx = I.ntx;
+            A.nty = I.nty;
+            A.nzc = 1;
+            A.ntiles = I.ntx * I.nty;
+            // the previous tile's last barrier follows its last table read
+            stage_tables<T, N>(B.params + i, pair, kc);
+            __syncthreads();
         }
-        A.y1 = (even ? B.bufA : B.bufB) + I.off;
-        A.out = (even ? B.bufB : B.bufA) + I.off;
-        // one buffer group per vector: the host admits only instances whose
-        // state spans less than 4 GiB
-        A.G = N + (A.K.with_c ? 1 : 0);
-        A.plane_bytes = (unsigned)(A.K.V * (long long)sizeof(T));
-        A.gb[0][0] = A.y1;
-        A.gb[4][0] = A.out;
-        A.kind = K_EULER;
-        A.a = step < I.nfull ? I.dt : I.dt_last;
-        A.tx = TILE_X;
-        A.ty = TILE_Y;
-        A.zchunk = 1;
-        A.ntx = I.ntx;
-        A.nty = I.nty;
-        A.nzc = 1;
-        A.ntiles = I.ntx * I.nty;
-        stage_body<T, 2, N, K_EULER, true>(A, g - I.tile0, lds, pair, kc);
+        stage_body<T, 2, N, K_EULER, true, false>(A, g - tile0, lds, pair, kc);
     }
 }
 

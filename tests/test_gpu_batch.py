@@ -33,10 +33,14 @@ def small_batch():
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_batch_equals_single_runs_bitwise(prec):
+@pytest.mark.parametrize("prec,blocks", [("fp32", None), ("fp64", None), ("fp32", 8), ("fp64", 24)])
+def test_batch_equals_single_runs_bitwise(prec, blocks):
+    """blocks: persistent grid size; a small grid makes each block walk tiles of
+    several instances, entering and skipping (finished) instances mid-range."""
     wls = small_batch()
     b = pf.Batch([w.param_dict() for w in wls], prec=prec)
+    if blocks is not None:
+        b.set_blocks(blocks)
     for i, w in enumerate(wls):
         b.init_fields(i, w.u0)
     dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
