@@ -144,6 +144,42 @@ __device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool wit
     }
 }
 
+// v mod n for v in [-n, 2n) by one compare each way (no integer division);
+// other v (grids smaller than a tile) by the remainder.
+__device__ __forceinline__ int wrap_index(int v, int n) {
+    if (v < 0) v += n;
+    if (v >= n) v -= n;
+    if (v < 0 || v >= n) v = (v % n + n) % n;
+    return v;
+}
+
+// Plane offset (column) of the thread's own cell and of its halo cell in tile
+// (tix, tiy) of a TILE_X x TILE_Y tiling, both periodically wrapped.  The halo
+// cells are the 2 TILE_X + 2 TILE_Y edge neighbours of the tile (no corners),
+// one per thread h < 2 TILE_X + 2 TILE_Y; hslot is its LDS slot.
+__device__ __forceinline__ void tile_columns(int tix, int tiy, int nx, int ny, long long &col,
+                                             long long &hcol, int &hslot, bool &active) {
+    constexpr int TX = TILE_X, TY = TILE_Y, TXH = TILE_X + 2;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int gx = tix * TX + lx, gy = tiy * TY + ly;
+    active = gx < nx && gy < ny;
+    col = (long long)wrap_index(gy, ny) * nx + wrap_index(gx, nx);
+    const int h = threadIdx.x;
+    hslot = 0;
+    hcol = 0;
+    if (h < 2 * TX + 2 * TY) {
+        int hx, hy;
+        if (h < TX) { hx = h; hy = -1; }
+        else if (h < 2 * TX) { hx = h - TX; hy = TY; }
+        else if (h < 2 * TX + TY) { hx = -1; hy = h - 2 * TX; }
+        else { hx = TX; hy = h - 2 * TX - TY; }
+        hslot = (hy + 1) * TXH + (hx + 1);
+        const int hgx = wrap_index(tix * TX + hx, nx);
+        const int hgy = wrap_index(tiy * TY + hy, ny);
+        hcol = (long long)hgy * nx + hgx;
+    }
+}
+
 // One tile (logical index L) of one stage.  Every thread of the block calls
 // it with the same arguments (it synchronises the block).  ONEG: every vector's
 // fields lie in buffer group 0 (see field_group).  TABLES: stage the LDS
@@ -179,31 +215,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
         const int tiy = rest % A.nty;
         const int tiz = rest / A.nty;
         const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-        const int gx = tix * TX + lx, gy = tiy * TY + ly;
-        const bool active = gx < nx && gy < ny;
-        // own slot holds the periodically wrapped cell
-        const int x = gx % nx, y = gy % ny;
         const long long nxy = (long long)nx * ny;
-        const long long col = (long long)y * nx + x;
+        // own slot holds the periodically wrapped cell
         const int own_slot = (ly + 1) * TXH + (lx + 1);
-
-        // halo cell of this thread (2 TX + 2 TY positions, no corners)
-        constexpr int nhalo = 2 * TX + 2 * TY;
-        const int h = threadIdx.x;
-        const bool has_halo = h < nhalo;
-        int hslot = 0;
-        long long hcol = 0;
-        if (has_halo) {
-            int hx, hy;
-            if (h < TX) { hx = h; hy = -1; }
-            else if (h < 2 * TX) { hx = h - TX; hy = TY; }
-            else if (h < 2 * TX + TY) { hx = -1; hy = h - 2 * TX; }
-            else { hx = TX; hy = h - 2 * TX - TY; }
-            hslot = (hy + 1) * TXH + (hx + 1);
-            const int hgx = ((tix * TX + hx) % nx + nx) % nx;
-            const int hgy = ((tiy * TY + hy) % ny + ny) % ny;
-            hcol = (long long)hgy * nx + hgx;
-        }
+        const bool has_halo = threadIdx.x < 2 * TX + 2 * TY;
+        long long col, hcol;
+        int hslot;
+        bool active;
+        tile_columns(tix, tiy, nx, ny, col, hcol, hslot, active);
 
         const int z0 = DIM == 3 ? tiz * A.zchunk : 0;
         const int z1 = DIM == 3 ? min(z0 + A.zchunk, nz) : 1;
@@ -218,7 +237,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
         load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
         if (has_halo)
             load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
-                               hcur);
+                                     hcur);
 
         for (int z = z0; z < z1; ++z) {
             const long long pz = (long long)z * nxy;
