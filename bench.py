@@ -147,10 +147,13 @@ def batch_bench(args):
         b.init_fields(i, w.u0)
     dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
     t_end = [nsteps * d for d in dts]
-    nb = b.autotune()[0] if not args.no_autotune else None
+    if not args.no_autotune:
+        b.autotune()
     if args.blocks:
         b.set_blocks(args.blocks)
-        nb = args.blocks
+    if args.fusion:
+        b.set_fusion(args.fusion)
+    nb, depth = b.config()
     K = args.graph_steps
 
     def one():
@@ -193,10 +196,12 @@ def batch_bench(args):
     value = cells * nsteps / (total / args.steps) / 1e9
     E = 4 if args.prec == "fp32" else 8
     F = wls[0].F
+    # one launch reads the state once and writes it once, for `depth` steps
     bytes_per_launch = 2 * F * E * cells
-    avg_s = ev_ms / args.steps / nsteps / 1e3
+    launches = -(-nsteps // depth)
+    avg_s = ev_ms / args.steps / launches / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
-    traffic = measured_traffic(f"batch_euler/{len(wls)}inst/{args.prec}")
+    traffic = measured_traffic(f"batch_euler_d{depth}/{len(wls)}inst/{args.prec}")
     sref = stream_reference(F * E * cells)
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gcell-stage/s", "n_gpus": 1,
@@ -205,15 +210,19 @@ def batch_bench(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"batch of {len(wls)} 2D shrinking grains, {cells} cells, "
-                               f"{nsteps} FE steps each at 0.9 dt_e, one fused launch per step, "
-                               + (f"hipGraph of {K} steps" if K > 0 else "direct launches"),
+                               f"{nsteps} FE steps each at 0.9 dt_e, one fused launch per "
+                               f"{depth} step(s), "
+                               + (f"hipGraphs of {K} launches" if K > 0 else "direct launches"),
                    "cells": cells, "instances": len(wls), "persistent_blocks": nb,
+                   "fusion_depth": depth,
+                   "state_GBs_per_step": round(2 * F * E * cells / (avg_s / depth) / 1e9, 1),
                    "time_to_solution_ms": round(total / args.steps * 1e3, 3),
                    "area_rate_rel_error_fp32_batch_mean": float(np.mean(err32))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"batch_euler_kernel, avg {avg_s * 1e6:.2f} us per step (HIP events "
-                               f"over graph replays), {bytes_per_launch} algorithmic B/launch",
+                     "kernel": f"batch_euler_kernel (depth {depth}), avg {avg_s * 1e6:.2f} us per launch "
+                               f"of {depth} step(s) (HIP events over graph replays), "
+                               f"{bytes_per_launch} algorithmic B/launch",
                      "stream_ref_GBs": sref,
                      "frac_of_stream_copy": round(achieved / sref["copy"], 4) if sref else None},
     }
@@ -242,6 +251,8 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB")
     ap.add_argument("--blocks", type=int, default=0,
                     help="batch: persistent grid size (skips the block-count autotuner)")
+    ap.add_argument("--fusion", type=int, default=0, choices=[0, 1, 2],
+                    help="batch: steps per launch (0: the autotuner's choice)")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="batch: steps per captured hipGraph (0: direct launches)")
     ap.add_argument("--no-fp64-ref", action="store_true",

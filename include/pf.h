@@ -195,10 +195,15 @@ pf_status pf_get_kernel_time(pf_sim *sim, int family, double *ms, long long *lau
 /* ---------------------------------------------------------------------------
  * Batch of independent 2D simulations.  All instances share dim = 2, n_phi,
  * with_c and the precision; grid sizes and every other parameter may differ.
- * A step of the batch is one fused launch over the tiles of every instance (a
- * persistent grid walks a tile list whose entries name their instance; the
+ * Each instance's state must span less than 4 GiB (else PF_EUNSUPPORTED).
+ * A launch of the batch advances every instance by one forward-Euler step
+ * (Sec. 3.2), or by two (stage-fusion depth 2: a tile computes the first step
+ * on itself and a one-cell ring, the second on itself, in one pass over HBM);
+ * a persistent grid walks a tile list whose entries name their instance, the
  * per-instance parameters, state offsets and step sizes live in device
- * tables); sequences of steps are replayed from a captured hipGraph.
+ * tables, and sequences of launches are replayed from a captured hipGraph.
+ * Results do not depend on the depth or the grid size: every instance takes
+ * bit for bit the steps of its own single-instance run.
  * -------------------------------------------------------------------------*/
 typedef struct pf_batch pf_batch;
 
@@ -218,10 +223,17 @@ pf_status pf_batch_stable_dt(pf_batch *b, int i, double *dt_e);
  * 0 launches every step directly.  stats (optional) is [n]. */
 pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
                           const double *dt, int graph_steps, pf_stats *stats);
-/* Times persistent grid sizes on one step (the state is only read) and keeps
- * the fastest; pf_batch_set_blocks sets it directly (multiple of 8). */
+/* Times one launch for each persistent grid size (512..8192 blocks) and each
+ * fusion depth the instances allow (the state is only read) and keeps the
+ * fastest per step; best_ms is that time per step.  pf_batch_set_blocks sets
+ * the grid size directly (rounded down to a multiple of 8, >= 8);
+ * pf_batch_set_fusion the depth (1 or 2; PF_EUNSUPPORTED when depth 2 needs
+ * more LDS than a workgroup has: FP64 with n_phi > 4);  pf_batch_get_config
+ * reads both (either pointer may be NULL). */
 pf_status pf_batch_autotune(pf_batch *b, int *nblocks, double *best_ms);
 pf_status pf_batch_set_blocks(pf_batch *b, int nblocks);
+pf_status pf_batch_set_fusion(pf_batch *b, int depth);
+pf_status pf_batch_get_config(const pf_batch *b, int *nblocks, int *depth);
 const char *pf_batch_last_error(const pf_batch *b);
 
 /* Values of N for which kernels are compiled; returns the count. */

@@ -38,7 +38,7 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_supported_nphi", "pf_last_error", "pf_batch_create", "pf_batch_destroy",
            "pf_batch_set_stream", "pf_batch_init_fields", "pf_batch_get_fields",
            "pf_batch_stable_dt", "pf_batch_run_to", "pf_batch_autotune", "pf_batch_set_blocks",
-           "pf_batch_last_error"]
+           "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error"]
 
 
 class PFError(RuntimeError):
@@ -148,6 +148,8 @@ def lib():
             "pf_batch_run_to": [vp, i, pd, pd, i, C.POINTER(_Stats)],
             "pf_batch_autotune": [vp, C.POINTER(i), pd],
             "pf_batch_set_blocks": [vp, i],
+            "pf_batch_set_fusion": [vp, i],
+            "pf_batch_get_config": [vp, C.POINTER(i), C.POINTER(i)],
         }
         for name, args in bsigs.items():
             fn = getattr(L, name)
@@ -263,6 +265,16 @@ class Batch:
 
     def set_blocks(self, nblocks: int):
         self._chk(self._L.pf_batch_set_blocks(self._h, int(nblocks)))
+
+    def set_fusion(self, depth: int):
+        """Steps per batched launch (stage-fusion depth), 1 or 2."""
+        self._chk(self._L.pf_batch_set_fusion(self._h, int(depth)))
+
+    def config(self):
+        """(persistent grid size, fusion depth) used by the next run."""
+        nb, d = C.c_int(), C.c_int()
+        self._chk(self._L.pf_batch_get_config(self._h, C.byref(nb), C.byref(d)))
+        return nb.value, d.value
 
 
 class Sim:

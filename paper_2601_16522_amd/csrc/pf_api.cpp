@@ -1226,9 +1226,10 @@ struct pf_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int nblocks = 2048;
+    int depth = 1;                 // steps per batched launch (stage-fusion depth)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    int graph_k = 0;
+    int graph_k = 0, graph_depth = 0, graph_blocks = 0;
     std::string err;
 };
 
@@ -1254,7 +1255,7 @@ pf_status bfail(pf_batch *b, pf_status code, const char *fmt, ...) {
     } while (0)
 
 template <typename T>
-BatchArgs<T> batch_args(pf_batch *b, int offset) {
+BatchArgs<T> batch_args(pf_batch *b, int offset, int depth) {
     BatchArgs<T> B;
     B.params = (const DevParams<T> *)b->dparams;
     B.inst = (const BatchInst<T> *)b->dinst;
@@ -1264,7 +1265,12 @@ BatchArgs<T> batch_args(pf_batch *b, int offset) {
     B.step_base = b->dstep;
     B.step_offset = offset;
     B.total_tiles = b->total_tiles;
+    B.depth = depth;
     return B;
+}
+
+bool batch_depth_ok(const pf_batch *b, int depth) {
+    return depth == 1 || (depth == 2 && batch_depth2_fits((int)b->esz, b->N));
 }
 
 template <typename T>
@@ -1323,21 +1329,26 @@ pf_status batch_plan(pf_batch *b, const double *t_end, const double *dt, int &ma
     return PF_OK;
 }
 
+// k batched launches of b->depth steps each (launch j covers the steps from
+// the device counter + j * depth on) and one counter update by k * depth.
 template <typename T>
 pf_status batch_launch_steps(pf_batch *b, int k) {
+    const int d = b->depth;
     for (int j = 0; j < k; ++j) {
-        hipError_t e = launch_batch_euler<T>(b->N, batch_args<T>(b, j), b->nblocks, b->stream);
+        hipError_t e = launch_batch_euler<T>(b->N, batch_args<T>(b, j * d, d), b->nblocks, b->stream);
         if (e != hipSuccess) return bfail(b, PF_EHIP, "batch launch: %s", hipGetErrorString(e));
     }
-    BHIPCHK(b, launch_batch_tick(b->dstep, k, b->stream));
+    BHIPCHK(b, launch_batch_tick(b->dstep, k * d, b->stream));
     return PF_OK;
 }
 
-// k steps (k batched launches and one counter update) captured once into a
-// hipGraph and replayed; the graph holds kernel nodes only.
+// k launches (and one counter update) captured once into a hipGraph and
+// replayed; the graph holds kernel nodes only.  A change of k, of the fusion
+// depth or of the grid size re-captures it.
 template <typename T>
 pf_status batch_graph(pf_batch *b, int k) {
-    if (b->gexec && b->graph_k == k) return PF_OK;
+    if (b->gexec && b->graph_k == k && b->graph_depth == b->depth && b->graph_blocks == b->nblocks)
+        return PF_OK;
     if (b->gexec) {
         hipGraphExecDestroy(b->gexec);
         hipGraphDestroy(b->graph);
@@ -1360,6 +1371,8 @@ pf_status batch_graph(pf_batch *b, int k) {
     }
     b->graph = g;
     b->graph_k = k;
+    b->graph_depth = b->depth;
+    b->graph_blocks = b->nblocks;
     return PF_OK;
 }
 
@@ -1371,20 +1384,24 @@ pf_status batch_run(pf_batch *b, const double *t_end, const double *dt, int grap
     if (rc) return rc;
     const int zero = 0;
     BHIPCHK(b, hipMemcpyAsync(b->dstep, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    const int d = b->depth;
+    const int launches = (S + d - 1) / d;
     int done = 0;
-    if (graph_k > 0 && S >= graph_k) {
+    if (graph_k > 0 && launches >= graph_k) {
         if ((rc = batch_graph<T>(b, graph_k))) return rc;
-        for (; done + graph_k <= S; done += graph_k) BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+        for (; done + graph_k <= launches; done += graph_k)
+            BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
     }
-    if (S - done > 0 && (rc = batch_launch_steps<T>(b, S - done))) return rc;
-    // an instance with an odd number of steps ends in buffer B: copy it back
+    if (launches - done > 0 && (rc = batch_launch_steps<T>(b, launches - done))) return rc;
+    // an instance that took part in an odd number of launches ends in buffer B:
+    // copy it back
     std::vector<BatchInst<T>> I(b->n);
     BHIPCHK(b, hipMemcpyAsync(I.data(), b->dinst, sizeof(BatchInst<T>) * b->n, hipMemcpyDeviceToHost,
                               b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     for (int i = 0; i < b->n; ++i) {
         const size_t bytes = (size_t)b->meta[i].F * b->meta[i].V * b->esz;
-        if (I[i].nsteps & 1)
+        if (((I[i].nsteps + d - 1) / d) & 1)
             BHIPCHK(b, hipMemcpyAsync((char *)b->bufA + b->off[i] * b->esz,
                                       (char *)b->bufB + b->off[i] * b->esz, bytes,
                                       hipMemcpyDeviceToDevice, b->stream));
@@ -1400,14 +1417,15 @@ pf_status batch_run(pf_batch *b, const double *t_end, const double *dt, int grap
     return PF_OK;
 }
 
+// Picks the persistent grid size and the stage-fusion depth: one launch of
+// every supported depth (two steps of every instance planned, buffer A only
+// read) timed for several grid sizes; the fastest time per step wins.
 template <typename T>
 pf_status batch_autotune(pf_batch *b, int *best_blocks, double *best_ms) {
-    // one step of every instance from buffer A into buffer B (A, the state, is
-    // only read), timed for several persistent grid sizes
     std::vector<double> t_end(b->n), dt(b->n);
     for (int i = 0; i < b->n; ++i) {
         dt[i] = 0.9 * stable_dt(&b->meta[i]);
-        t_end[i] = b->t[i] + dt[i];
+        t_end[i] = b->t[i] + 2.0 * dt[i];
     }
     int S = 0;
     pf_status rc = batch_plan<T>(b, t_end.data(), dt.data(), S);
@@ -1417,28 +1435,34 @@ pf_status batch_autotune(pf_batch *b, int *best_blocks, double *best_ms) {
     BHIPCHK(b, hipEventCreate(&e0));
     BHIPCHK(b, hipEventCreate(&e1));
     double best = 1e300;
-    int bb = b->nblocks;
+    int bb = b->nblocks, bd = b->depth;
     const int zero = 0;
-    for (int c : cands) {
-        const int nb = std::min(c, (b->total_tiles + 7) / 8 * 8);
-        BHIPCHK(b, hipMemcpyAsync(b->dstep, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
-        hipError_t e = launch_batch_euler<T>(b->N, batch_args<T>(b, 0), nb, b->stream);
-        BHIPCHK(b, hipEventRecord(e0, b->stream));
-        for (int r = 0; r < 5 && e == hipSuccess; ++r)
-            e = launch_batch_euler<T>(b->N, batch_args<T>(b, 0), nb, b->stream);
-        if (e != hipSuccess) return bfail(b, PF_EHIP, "batch launch: %s", hipGetErrorString(e));
-        BHIPCHK(b, hipEventRecord(e1, b->stream));
-        BHIPCHK(b, hipEventSynchronize(e1));
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms / 5.0 < best) {
-            best = ms / 5.0;
-            bb = nb;
+    for (int d = 1; d <= 2; ++d) {
+        if (!batch_depth_ok(b, d)) continue;
+        for (int c : cands) {
+            const int nb = std::min(c, (b->total_tiles + 7) / 8 * 8);
+            BHIPCHK(b, hipMemcpyAsync(b->dstep, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+            hipError_t e = launch_batch_euler<T>(b->N, batch_args<T>(b, 0, d), nb, b->stream);
+            BHIPCHK(b, hipEventRecord(e0, b->stream));
+            for (int r = 0; r < 5 && e == hipSuccess; ++r)
+                e = launch_batch_euler<T>(b->N, batch_args<T>(b, 0, d), nb, b->stream);
+            if (e != hipSuccess) return bfail(b, PF_EHIP, "batch launch: %s", hipGetErrorString(e));
+            BHIPCHK(b, hipEventRecord(e1, b->stream));
+            BHIPCHK(b, hipEventSynchronize(e1));
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            const double per_step = ms / 5.0 / d;
+            if (per_step < best) {
+                best = per_step;
+                bb = nb;
+                bd = d;
+            }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     b->nblocks = bb;
+    b->depth = bd;
     if (best_blocks) *best_blocks = bb;
     if (best_ms) *best_ms = best;
     return PF_OK;
@@ -1606,6 +1630,22 @@ pf_status pf_batch_autotune(pf_batch *b, int *nblocks, double *best_ms) {
 pf_status pf_batch_set_blocks(pf_batch *b, int nblocks) {
     if (!b || nblocks < 8) return PF_EINVAL;
     b->nblocks = nblocks / 8 * 8;
+    return PF_OK;
+}
+
+pf_status pf_batch_set_fusion(pf_batch *b, int depth) {
+    if (!b || (depth != 1 && depth != 2)) return PF_EINVAL;
+    if (!batch_depth_ok(b, depth))
+        return bfail(b, PF_EUNSUPPORTED, "fusion depth %d needs more LDS than a workgroup has at N = %d",
+                     depth, b->N);
+    b->depth = depth;
+    return PF_OK;
+}
+
+pf_status pf_batch_get_config(const pf_batch *b, int *nblocks, int *depth) {
+    if (!b) return PF_EINVAL;
+    if (nblocks) *nblocks = b->nblocks;
+    if (depth) *depth = b->depth;
     return PF_OK;
 }
 

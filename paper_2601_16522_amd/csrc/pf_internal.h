@@ -121,6 +121,17 @@ struct BatchInst {
     T dt, dt_last;
 };
 
+// Stage-fusion depth 2 of the batched forward-Euler kernel: a tile computes
+// two steps in one pass from its input with a two-cell halo.  Its LDS holds
+// the input region (TILE_X + 4) x (TILE_Y + 4) and the first step on
+// (TILE_X + 2) x (TILE_Y + 2), N + 3 planes each (phi, mu, Mc, c), plus the
+// pair and per-phase tables; it must fit one workgroup's 64 KiB.
+constexpr int F2_IN_X = TILE_X + 4, F2_IN_Y = TILE_Y + 4, F2_IN = F2_IN_X * F2_IN_Y;
+constexpr int F2_MID_X = TILE_X + 2, F2_MID_Y = TILE_Y + 2, F2_MID = F2_MID_X * F2_MID_Y;
+constexpr bool batch_depth2_fits(int esz, int n) {
+    return esz * ((n + 3) * (F2_IN + F2_MID) + 3 * n * n + 4 * n) <= 65536;
+}
+
 template <typename T>
 struct BatchArgs {
     const DevParams<T> *params;  // [n]
@@ -131,6 +142,7 @@ struct BatchArgs {
     const int *step_base;        // device step counter (advanced by batch_tick)
     int step_offset;             // step = *step_base + step_offset
     int total_tiles;
+    int depth;                   // steps per launch (stage-fusion depth): 1 or 2
 };
 
 // Launchers (implemented in pf_kernels.hip).  Return hipSuccess or the launch

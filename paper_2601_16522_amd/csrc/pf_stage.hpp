@@ -180,6 +180,134 @@ __device__ __forceinline__ void tile_columns(int tix, int tiy, int nx, int ny, l
     }
 }
 
+// Right-hand side of eqs. phieq and ceq at one cell (the per-cell part of
+// every stage kind): x/y neighbours from an LDS plane tile holding the N phi
+// planes, then mu, then Mc, PLANE values apart, with rows ROW apart (own: the
+// cell's slot); in 3D the z neighbours come from registers (prv below, nxt
+// above).  cur: the cell's own N + 1 values, mu_c / mc_c its mu and Mc.
+template <typename T, int DIM, int N, bool FAST, int PLANE, int ROW>
+__device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restrict__ lds,
+                                          const T *__restrict__ pair, const T *__restrict__ kc,
+                                          const int own, const T *cur, const T mu_c, const T mc_c,
+                                          const T *prv, const T mu_p, const T mc_p, const T *nxt,
+                                          const T mu_n, const T mc_n, T *r) {
+    const bool withc = P.with_c != 0;
+    const T idx2 = P.idx2;
+    // activity of phase a: phi_a > 0 at the cell or at one of its 2d
+    // neighbours (filter n and N_z of eq. phieq), as max > 0
+    const int nbs[4] = {own - 1, own + 1, own - ROW, own + ROW};
+    T lap[N], mx[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        lap[a] = T(0);
+        mx[a] = cur[a];
+    }
+    T flux = T(0);
+#pragma unroll
+    for (int k = 0; k < 2 * DIM; ++k) {
+        T muk, mck;
+        if (k < 4) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const T v = lds[a * PLANE + nbs[k]];
+                lap[a] = lap[a] + v;
+                mx[a] = max_num(mx[a], v);
+            }
+            muk = lds[N * PLANE + nbs[k]];
+            mck = lds[(N + 1) * PLANE + nbs[k]];
+        } else {
+            const T *nv = k == 4 ? prv : nxt;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                lap[a] = lap[a] + nv[a];
+                mx[a] = max_num(mx[a], nv[a]);
+            }
+            muk = k == 4 ? mu_p : mu_n;
+            mck = k == 4 ? mc_p : mc_n;
+        }
+        if (withc) {
+            if constexpr (FAST) flux = fma_t(T(0.5) * (mc_c + mck), muk - mu_c, flux);
+            else flux = flux + (T(0.5) * (mc_c + mck)) * (muk - mu_c);
+        }
+    }
+    unsigned act = 0u;
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+        if (mx[a] > T(0)) act |= 1u << a;
+    const int nzc = __popc(act);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if constexpr (FAST) lap[a] = fma_t(T(-2 * DIM), cur[a], lap[a]) * idx2;
+        else lap[a] = (lap[a] - T(2 * DIM) * cur[a]) * idx2;
+    }
+
+    // variational derivative delta_a = sum_{b != a} (A_ab Lap phi_b +
+    // B_ab phi_b) + psi_{type(a)}(mu)
+    // grand potential psi_a(mu) = -mu^2/(2k_a) - mu c0_a (Sec. 2)
+    T psi[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (!withc) psi[a] = T(0);
+        else if constexpr (FAST) psi[a] = fma_t(-(mu_c * mu_c), kc[3 * N + a], -(mu_c * kc[a]));
+        else psi[a] = (-mu_c * mu_c) / P.k2[a] - mu_c * P.c0[a];
+    }
+    T delta[N];
+    const T inz = T(1) / T(nzc > 0 ? nzc : 1);
+    if (FAST && P.uniform) {
+        const T A0 = pair[1], B0 = pair[N * N + 1], L0 = pair[2 * N * N + 1];
+        T slap = T(0), sp = T(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            slap += lap[a];
+            sp += cur[a];
+        }
+        T dact = T(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            T s = fma_t(A0, slap - lap[a], B0 * (sp - cur[a]));
+            if (withc) s += psi[a];
+            delta[a] = s;
+            if ((act >> a) & 1u) dact += s;
+        }
+        const T mean = dact * inz;
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+            r[a] = (((act >> a) & 1u) && nzc >= 2) ? L0 * (mean - delta[a]) : T(0);
+    } else {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            T s = T(0);
+#pragma unroll
+            for (int bb = 0; bb < N; ++bb) {
+                if (bb == a) continue;
+                const T Aab = pair[a * N + bb], Bab = pair[N * N + a * N + bb];
+                if constexpr (FAST) s = fma_t(Aab, lap[bb], fma_t(Bab, cur[bb], s));
+                else s = s + (Aab * lap[bb] + Bab * cur[bb]);
+            }
+            if (withc) s = s + psi[a];
+            delta[a] = s;
+        }
+        // dphi_a/dt = -(1/N_z) sum_{b active} L_ab (delta_a - delta_b)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            T ra = T(0);
+            if (((act >> a) & 1u) && nzc >= 2) {
+                T s = T(0);
+#pragma unroll
+                for (int bb = 0; bb < N; ++bb) {
+                    if (bb == a || !((act >> bb) & 1u)) continue;
+                    const T Lab = pair[2 * N * N + a * N + bb];
+                    if constexpr (FAST) s = fma_t(Lab, delta[a] - delta[bb], s);
+                    else s = s + Lab * (delta[a] - delta[bb]);
+                }
+                ra = -s * inz;
+            }
+            r[a] = ra;
+        }
+    }
+    r[N] = withc ? flux * idx2 : T(0);
+}
+
 // One tile (logical index L) of one stage.  Every thread of the block calls
 // it with the same arguments (it synchronises the block).  ONEG: every vector's
 // fields lie in buffer group 0 (see field_group).  TABLES: stage the LDS
@@ -275,120 +403,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
 
             if (active) {
                 // ---- right-hand side at (x, y, z) -------------------------------
-                // activity of phase a: phi_a > 0 at the cell or at one of its 2d
-                // neighbours (filter n and N_z of eq. phieq), as max > 0
-                const int nbs[4] = {own_slot - 1, own_slot + 1, own_slot - TXH, own_slot + TXH};
-                T lap[N], mx[N];
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    lap[a] = T(0);
-                    mx[a] = cur[a];
-                }
-                T flux = T(0);
-#pragma unroll
-                for (int k = 0; k < 2 * DIM; ++k) {
-                    T muk, mck;
-                    if (k < 4) {
-#pragma unroll
-                        for (int a = 0; a < N; ++a) {
-                            const T v = lds[a * plane_sz + nbs[k]];
-                            lap[a] = lap[a] + v;
-                            mx[a] = max_num(mx[a], v);
-                        }
-                        muk = lds[N * plane_sz + nbs[k]];
-                        mck = lds[(N + 1) * plane_sz + nbs[k]];
-                    } else {
-                        const T *nv = k == 4 ? prv : nxt;
-#pragma unroll
-                        for (int a = 0; a < N; ++a) {
-                            lap[a] = lap[a] + nv[a];
-                            mx[a] = max_num(mx[a], nv[a]);
-                        }
-                        muk = k == 4 ? mu_p : mu_n;
-                        mck = k == 4 ? mc_p : mc_n;
-                    }
-                    if (withc) {
-                        if constexpr (FAST) flux = fma_t(T(0.5) * (mc_c + mck), muk - mu_c, flux);
-                        else flux = flux + (T(0.5) * (mc_c + mck)) * (muk - mu_c);
-                    }
-                }
-                unsigned act = 0u;
-#pragma unroll
-                for (int a = 0; a < N; ++a)
-                    if (mx[a] > T(0)) act |= 1u << a;
-                const int nzc = __popc(act);
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    if constexpr (FAST) lap[a] = fma_t(T(-2 * DIM), cur[a], lap[a]) * idx2;
-                    else lap[a] = (lap[a] - T(2 * DIM) * cur[a]) * idx2;
-                }
-
-                // variational derivative delta_a = sum_{b != a} (A_ab Lap phi_b +
-                // B_ab phi_b) + psi_{type(a)}(mu)
-                // grand potential psi_a(mu) = -mu^2/(2k_a) - mu c0_a (Sec. 2)
-                T psi[N];
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    if (!withc) psi[a] = T(0);
-                    else if constexpr (FAST) psi[a] = fma_t(-(mu_c * mu_c), kc[3 * N + a], -(mu_c * kc[a]));
-                    else psi[a] = (-mu_c * mu_c) / P.k2[a] - mu_c * P.c0[a];
-                }
-                T delta[N];
                 T r[N + 1];
-                const T inz = T(1) / T(nzc > 0 ? nzc : 1);
-                if (FAST && P.uniform) {
-                    const T A0 = pair[1], B0 = pair[N * N + 1], L0 = pair[2 * N * N + 1];
-                    T slap = T(0), sp = T(0);
-#pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        slap += lap[a];
-                        sp += cur[a];
-                    }
-                    T dact = T(0);
-#pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        T s = fma_t(A0, slap - lap[a], B0 * (sp - cur[a]));
-                        if (withc) s += psi[a];
-                        delta[a] = s;
-                        if ((act >> a) & 1u) dact += s;
-                    }
-                    const T mean = dact * inz;
-#pragma unroll
-                    for (int a = 0; a < N; ++a)
-                        r[a] = (((act >> a) & 1u) && nzc >= 2) ? L0 * (mean - delta[a]) : T(0);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        T s = T(0);
-#pragma unroll
-                        for (int bb = 0; bb < N; ++bb) {
-                            if (bb == a) continue;
-                            const T Aab = pair[a * N + bb], Bab = pair[N * N + a * N + bb];
-                            if constexpr (FAST) s = fma_t(Aab, lap[bb], fma_t(Bab, cur[bb], s));
-                            else s = s + (Aab * lap[bb] + Bab * cur[bb]);
-                        }
-                        if (withc) s = s + psi[a];
-                        delta[a] = s;
-                    }
-                    // dphi_a/dt = -(1/N_z) sum_{b active} L_ab (delta_a - delta_b)
-#pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        T ra = T(0);
-                        if (((act >> a) & 1u) && nzc >= 2) {
-                            T s = T(0);
-#pragma unroll
-                            for (int bb = 0; bb < N; ++bb) {
-                                if (bb == a || !((act >> bb) & 1u)) continue;
-                                const T Lab = pair[2 * N * N + a * N + bb];
-                                if constexpr (FAST) s = fma_t(Lab, delta[a] - delta[bb], s);
-                                else s = s + Lab * (delta[a] - delta[bb]);
-                            }
-                            ra = -s * inz;
-                        }
-                        r[a] = ra;
-                    }
-                }
-                r[N] = withc ? flux * idx2 : T(0);
+                rhs_point<T, DIM, N, FAST, plane_sz, TXH>(P, lds, pair, kc, own_slot, cur, mu_c, mc_c,
+                                                          prv, mu_p, mc_p, nxt, mu_n, mc_n, r);
 
                 // ---- stage combination, projection, store ----------------------
                 if constexpr (!EARLY) load_operands<T, N, KIND, ONEG, LCP>(A, idx, withc, o0, o1, o2);
@@ -588,15 +605,134 @@ hipError_t launch_stage_dn(const StageArgs<T> &A, int nblocks, hipStream_t strea
     return hipGetLastError();
 }
 
-// Batched forward-Euler stage over many independent 2D instances: a
-// persistent grid splits the global tile list (tiles of all instances, one
-// instance after the other) into one contiguous range per block.  A block
-// loads an instance's constants, state offset and step size, and stages its
-// LDS tables, when its walk enters that instance, so one launch advances every
-// instance by one step.  An instance whose run is complete is skipped.
+// One forward-Euler step at a cell whose neighbourhood is in an LDS plane
+// tile (N phi planes, mu, Mc, c; PLANE values apart, rows ROW apart): the same
+// arithmetic as the single-step kernel's K_EULER path.
+template <typename T, int N, bool FAST, int PLANE, int ROW>
+__device__ __forceinline__ void euler_point(const KConsts<T> &P, const T *__restrict__ lds,
+                                            const T *__restrict__ pair, const T *__restrict__ kc,
+                                            const int slot, const T dt, T *y) {
+    T cur[N + 1];
+#pragma unroll
+    for (int a = 0; a < N; ++a) cur[a] = lds[a * PLANE + slot];
+    cur[N] = lds[(N + 2) * PLANE + slot];
+    T r[N + 1];
+    rhs_point<T, 2, N, FAST, PLANE, ROW>(P, lds, pair, kc, slot, cur, lds[N * PLANE + slot],
+                                         lds[(N + 1) * PLANE + slot], nullptr, T(0), T(0), nullptr,
+                                         T(0), T(0), r);
+#pragma unroll
+    for (int f = 0; f <= N; ++f) {
+        if constexpr (FAST) y[f] = fma_t(dt, r[f], cur[f]);
+        else y[f] = cur[f] + dt * r[f];
+    }
+    simplex<T, N>(y);
+}
+
+// Two forward-Euler steps of one 2D tile in one pass (stage-fusion depth 2).
+// The tile's input with a two-cell halo (periodically wrapped) is staged in
+// LDS with mu and Mc; the first step is computed on the tile and a one-cell
+// ring around it and kept in LDS with its mu and Mc; the second step is
+// computed on the tile and stored.  Every value is computed with the
+// arithmetic of the single-step kernel, so the result equals two single steps
+// bit for bit.  two == false: one step (dt1) only, from the input region.
+// Buffers: the state is read from A.gb[0][0] and written to A.gb[4][0] (one
+// buffer group each).
 template <typename T, int N>
+__device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, T *__restrict__ in,
+                                            T *__restrict__ mid, const T *__restrict__ pair,
+                                            const T *__restrict__ kc, const T dt1, const T dt2,
+                                            const bool two) {
+    constexpr bool FAST = std::is_same<T, float>::value;
+    constexpr int SCP = out_store_cp<2>();
+    const KConsts<T> &P = A.K;
+    const int nx = P.nx, ny = P.ny;
+    const bool withc = P.with_c != 0;
+    const int tix = L % A.ntx, tiy = L / A.ntx;
+    const int x0 = tix * TILE_X - 2, y0 = tiy * TILE_Y - 2;  // corner of the input region
+
+    // input region: every load is issued before the first use of one
+    constexpr int NP0 = (F2_IN + 255) / 256;
+    T v[NP0][N + 1];
+#pragma unroll
+    for (int k = 0; k < NP0; ++k) {
+        const int p = threadIdx.x + 256 * k;
+        if (p < F2_IN) {
+            const int px = p % F2_IN_X, py = p / F2_IN_X;
+            const long long col = (long long)wrap_index(y0 + py, ny) * nx + wrap_index(x0 + px, nx);
+            load_point32<T, N, true>(A, 0, (unsigned)col * (unsigned)sizeof(T), withc, v[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NP0; ++k) {
+        const int p = threadIdx.x + 256 * k;
+        if (p < F2_IN) {
+            T mu = T(0), mc = T(0);
+            if (withc) point_mu_mc<T, N, FAST>(P, kc, v[k], mu, mc);
+#pragma unroll
+            for (int a = 0; a < N; ++a) in[a * F2_IN + p] = v[k][a];
+            in[N * F2_IN + p] = mu;
+            in[(N + 1) * F2_IN + p] = mc;
+            in[(N + 2) * F2_IN + p] = v[k][N];
+        }
+    }
+    __syncthreads();
+
+    const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
+    const int gx = tix * TILE_X + lx, gy = tiy * TILE_Y + ly;
+    const bool active = gx < nx && gy < ny;
+    const unsigned idx = (unsigned)((long long)gy * nx + gx) * (unsigned)sizeof(T);
+    T y[N + 1];
+    if (!two) {
+        euler_point<T, N, FAST, F2_IN, F2_IN_X>(P, in, pair, kc, (ly + 2) * F2_IN_X + (lx + 2), dt1, y);
+    } else {
+        // first step on the tile and its one-cell ring
+        constexpr int NP1 = (F2_MID + 255) / 256;
+#pragma unroll
+        for (int k = 0; k < NP1; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            if (q < F2_MID) {
+                const int qx = q % F2_MID_X, qy = q / F2_MID_X;
+                T w[N + 1];
+                euler_point<T, N, FAST, F2_IN, F2_IN_X>(P, in, pair, kc, (qy + 1) * F2_IN_X + (qx + 1),
+                                                        dt1, w);
+                T mu = T(0), mc = T(0);
+                if (withc) point_mu_mc<T, N, FAST>(P, kc, w, mu, mc);
+#pragma unroll
+                for (int a = 0; a < N; ++a) mid[a * F2_MID + q] = w[a];
+                mid[N * F2_MID + q] = mu;
+                mid[(N + 1) * F2_MID + q] = mc;
+                mid[(N + 2) * F2_MID + q] = w[N];
+            }
+        }
+        __syncthreads();
+        euler_point<T, N, FAST, F2_MID, F2_MID_X>(P, mid, pair, kc, (ly + 1) * F2_MID_X + (lx + 1), dt2,
+                                                  y);
+    }
+    if (active) {
+#pragma unroll
+        for (int f = 0; f < N; ++f) stv<T, true, SCP>(A, 4, f, idx, y[f]);
+        if (withc) stv<T, true, SCP>(A, 4, N, idx, y[N]);
+    }
+    __syncthreads();  // the LDS regions are read; the next tile may overwrite them
+}
+
+// LDS of the batched kernel for a fusion depth.
+template <typename T, int N, int DEPTH>
+constexpr int batch_lds_elems() {
+    return DEPTH == 1 ? lds_elems<T, N>() : (N + 3) * (F2_IN + F2_MID);
+}
+
+// Batched forward Euler over many independent 2D instances, DEPTH steps per
+// launch: a persistent grid splits the global tile list (tiles of all
+// instances, one instance after the other) into one contiguous range per
+// block.  A block loads an instance's constants, state offset and step sizes,
+// and stages its LDS tables, when its walk enters that instance, so one launch
+// advances every instance by DEPTH steps (fewer at the end of its run).  An
+// instance whose run is complete is skipped.  Launch j reads buffer A when j is
+// even and B when odd (j = first step / DEPTH).
+template <typename T, int N, int DEPTH>
 __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) {
-    __shared__ T lds[lds_elems<T, N>()];
+    __shared__ T lds[batch_lds_elems<T, N, DEPTH>()];
     __shared__ T pair[3 * N * N];
     __shared__ T kc[4 * N];
     const int step = *B.step_base + B.step_offset;
@@ -607,6 +743,8 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
     int i = B.tile_inst[g0] - 1;
     int tile0 = 0, end = g0;  // tiles [tile0, end) belong to instance i
     StageArgs<T> A = {};
+    T dt2 = T(0);
+    bool two = false;
     for (int g = g0; g < g1; ++g) {
         if (g >= end) {  // uniform over the block: enter instance i + 1
             ++i;
@@ -617,7 +755,7 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
                 g = end - 1;
                 continue;
             }
-            const bool even = (step & 1) == 0;
+            const bool even = ((step / DEPTH) & 1) == 0;
             const DevParams<T> &Q = B.params[i];
             A.K.nx = Q.nx; A.K.ny = Q.ny; A.K.nz = Q.nz;
             A.K.with_c = Q.with_c; A.K.n_types = Q.n_types; A.K.uniform = Q.uniform;
@@ -637,6 +775,8 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
             A.gb[4][0] = A.out;
             A.kind = K_EULER;
             A.a = step < I.nfull ? I.dt : I.dt_last;
+            dt2 = step + 1 < I.nfull ? I.dt : I.dt_last;
+            two = DEPTH == 2 && step + 1 < I.nsteps;
             A.tx = TILE_X;
             A.ty = TILE_Y;
             A.zchunk = 1;
@@ -648,13 +788,25 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
             stage_tables<T, N>(B.params + i, pair, kc);
             __syncthreads();
         }
-        stage_body<T, 2, N, K_EULER, true, false>(A, g - tile0, lds, pair, kc);
+        if constexpr (DEPTH == 1)
+            stage_body<T, 2, N, K_EULER, true, false>(A, g - tile0, lds, pair, kc);
+        else
+            euler2_tile<T, N>(A, g - tile0, lds, lds + (N + 3) * F2_IN, pair, kc, A.a, dt2, two);
     }
 }
 
 template <typename T, int N>
 hipError_t launch_batch_euler_n(const BatchArgs<T> &B, int nblocks, hipStream_t stream) {
-    hipLaunchKernelGGL((batch_euler_kernel<T, N>), dim3(nblocks), dim3(256), 0, stream, B);
+    if (B.depth == 1) {
+        hipLaunchKernelGGL((batch_euler_kernel<T, N, 1>), dim3(nblocks), dim3(256), 0, stream, B);
+    } else if (B.depth == 2) {
+        if constexpr (batch_depth2_fits(sizeof(T), N))
+            hipLaunchKernelGGL((batch_euler_kernel<T, N, 2>), dim3(nblocks), dim3(256), 0, stream, B);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

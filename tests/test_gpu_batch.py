@@ -33,14 +33,20 @@ def small_batch():
     return out
 
 
-@pytest.mark.parametrize("prec,blocks", [("fp32", None), ("fp64", None), ("fp32", 8), ("fp64", 24)])
-def test_batch_equals_single_runs_bitwise(prec, blocks):
+@pytest.mark.parametrize("prec,blocks,depth", [("fp32", None, 1), ("fp64", None, 1), ("fp32", 8, 1),
+                                                ("fp64", 24, 1), ("fp32", None, 2), ("fp64", None, 2),
+                                                ("fp32", 8, 2), ("fp64", 16, 2)])
+def test_batch_equals_single_runs_bitwise(prec, blocks, depth):
     """blocks: persistent grid size; a small grid makes each block walk tiles of
-    several instances, entering and skipping (finished) instances mid-range."""
+    several instances, entering and skipping (finished) instances mid-range.
+    depth: steps per launch; at depth 2 the odd step counts end with a launch
+    that takes one step."""
     wls = small_batch()
     b = pf.Batch([w.param_dict() for w in wls], prec=prec)
     if blocks is not None:
         b.set_blocks(blocks)
+    b.set_fusion(depth)
+    assert b.config()[1] == depth
     for i, w in enumerate(wls):
         b.init_fields(i, w.u0)
     dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
@@ -57,12 +63,15 @@ def test_batch_equals_single_runs_bitwise(prec, blocks):
         assert np.array_equal(u_b, u_s), (i, np.abs(u_b - u_s).max())
 
 
-def test_batch_graph_replays_equal_eager_runs():
+@pytest.mark.parametrize("depth", [1, 2])
+def test_batch_graph_replays_equal_eager_runs(depth):
     """Replay one captured graph across several runs, with eager work and
     synchronisation in between, and compare every run with direct launches."""
     wls = small_batch()[:4]
     g = pf.Batch([w.param_dict() for w in wls], prec="fp32")
     e = pf.Batch([w.param_dict() for w in wls], prec="fp32")
+    g.set_fusion(depth)
+    e.set_fusion(depth)
     for i, w in enumerate(wls):
         g.init_fields(i, w.u0)
         e.init_fields(i, w.u0)
@@ -102,8 +111,25 @@ def test_batch_autotune_keeps_state():
     before = [b.get_fields(i)[0] for i in range(3)]
     nb, ms = b.autotune()
     assert nb % 8 == 0 and ms > 0
+    assert b.config() == (nb, b.config()[1]) and b.config()[1] in (1, 2)
     for i in range(3):
         assert np.array_equal(b.get_fields(i)[0], before[i])
+
+
+def test_batch_fusion_depth_limits():
+    """Depth 2 needs (N + 3) LDS planes of the two regions per workgroup: FP64
+    with 8 phases does not fit and is refused; bad depths are refused."""
+    wl = pi.voronoi_2d(n=64, n_grains=8, n_phi=8, dmin=5.0)
+    b = pf.Batch([wl.param_dict()], prec="fp64")
+    with pytest.raises(pf.PFError) as e:
+        b.set_fusion(2)
+    assert e.value.code == -7
+    assert b.config()[1] == 1
+    b32 = pf.Batch([wl.param_dict()], prec="fp32")
+    b32.set_fusion(2)
+    with pytest.raises(pf.PFError):
+        b32.set_fusion(3)
+    assert b32.config()[1] == 2
 
 
 def test_batch_rejects_mixed_instances():
