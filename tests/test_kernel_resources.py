@@ -56,5 +56,7 @@ def test_stage_kernels_do_not_spill(tmp_path):
         assert len(names) >= 9 * 2 * 2 + 2, (n, sorted(kernels))
         for k in names:
             assert kernels[k].get("ScratchSize [bytes/lane]", 0) == 0, (n, k, kernels[k])
+        # batch kernels: depth 1 in both precisions, depth 2 where its LDS fits
+        # (FP32 for every N, FP64 only up to N = 4)
         batch = [k for k in names if "batch_euler_kernel" in k]
-        assert len(batch) == 2, batch
+        assert len(batch) == 3, batch
