@@ -74,6 +74,7 @@ def lib():
         L = C.CDLL(_LIB)
         P, D, I, LL = C.POINTER(_Params), C.POINTER(C.c_double), C.c_int, C.c_longlong
         L.pfo_rhs.argtypes = [P, D, D]
+        L.pfo_rhs_at.argtypes = [P, D, C.POINTER(C.c_longlong), LL, D]
         L.pfo_delta.argtypes = [P, D, D]
         L.pfo_mu.argtypes = [P, D, D, D]
         L.pfo_simplex.argtypes = [P, D, C.POINTER(C.c_ubyte)]
@@ -191,6 +192,18 @@ def rhs(P: Params, u) -> np.ndarray:
     r = np.zeros_like(u)
     lib().pfo_rhs(C.byref(P._c()), _dp(u), _dp(r))
     return r
+
+
+def rhs_at(P: Params, u, cells) -> np.ndarray:
+    """The right-hand side at the listed cells (flat indices into a plane),
+    shape (len(cells), F): the per-cell formula of rhs()."""
+    u = _state(P, u)
+    idx = np.ascontiguousarray(cells, dtype=np.int64)
+    assert idx.ndim == 1 and (idx >= 0).all() and (idx < P.nx * P.ny * P.nz).all()
+    out = np.zeros((idx.size, P.F))
+    lib().pfo_rhs_at(C.byref(P._c()), _dp(u), idx.ctypes.data_as(C.POINTER(C.c_longlong)),
+                     idx.size, _dp(out))
+    return out
 
 
 def delta(P: Params, u) -> np.ndarray:

@@ -202,6 +202,44 @@ void pfo_delta(const pfo_params *P, const double *u, double *delta_out) {
  * for active a when N_z >= 2, otherwise 0.
  *   rc_i = (1/dx^2) sum_nb w_ij (mu_j - mu_i),  w_ij = (Mc_i + Mc_j)/2.
  * ------------------------------------------------------------------------- */
+static void cell_rhs(const pfo_params *P, const double *u, long long V, long long i,
+                     const double *mu, const double *mc, double *ri /* F values */) {
+    int N = P->n_phi;
+    long long nb[6];
+    int nnb = neighbours(P, i, nb);
+    int act[PFO_MAXN];
+    int nz = 0;
+    for (int a = 0; a < N; ++a) {
+        const double *pa = u + (long long)a * V;
+        int on = pa[i] > 0.0;
+        for (int k = 0; k < nnb; ++k) on = on || (pa[nb[k]] > 0.0);
+        act[a] = on;
+        nz += on;
+    }
+    double lap[PFO_MAXN], delta[PFO_MAXN];
+    cell_delta(P, u, V, i, mu, lap, delta);
+    for (int a = 0; a < N; ++a) {
+        double ra = 0.0;
+        if (act[a] && nz >= 2) {
+            double s = 0.0;
+            for (int b = 0; b < N; ++b) {
+                if (b == a || !act[b]) continue;
+                s = s + pair_L(P, a, b) * (delta[a] - delta[b]);
+            }
+            ra = -s * (1.0 / (double)nz);
+        }
+        ri[a] = ra;
+    }
+    if (P->with_c) {
+        double s = 0.0;
+        for (int k = 0; k < nnb; ++k) {
+            double w = 0.5 * (mc[i] + mc[nb[k]]);
+            s = s + w * (mu[nb[k]] - mu[i]);
+        }
+        ri[N] = s * (1.0 / (P->dx * P->dx));
+    }
+}
+
 void pfo_rhs(const pfo_params *P, const double *u, double *r) {
     long long V = ncells(P);
     int N = P->n_phi;
@@ -210,39 +248,30 @@ void pfo_rhs(const pfo_params *P, const double *u, double *r) {
     if (P->with_c) pfo_mu(P, u, mu, mc);
 #pragma omp parallel for schedule(static)
     for (long long i = 0; i < V; ++i) {
-        long long nb[6];
-        int nnb = neighbours(P, i, nb);
-        int act[PFO_MAXN];
-        int nz = 0;
-        for (int a = 0; a < N; ++a) {
-            const double *pa = u + (long long)a * V;
-            int on = pa[i] > 0.0;
-            for (int k = 0; k < nnb; ++k) on = on || (pa[nb[k]] > 0.0);
-            act[a] = on;
-            nz += on;
-        }
-        double lap[PFO_MAXN], delta[PFO_MAXN];
-        cell_delta(P, u, V, i, mu, lap, delta);
-        for (int a = 0; a < N; ++a) {
-            double ra = 0.0;
-            if (act[a] && nz >= 2) {
-                double s = 0.0;
-                for (int b = 0; b < N; ++b) {
-                    if (b == a || !act[b]) continue;
-                    s = s + pair_L(P, a, b) * (delta[a] - delta[b]);
-                }
-                ra = -s * (1.0 / (double)nz);
-            }
-            r[(long long)a * V + i] = ra;
-        }
-        if (P->with_c) {
-            double s = 0.0;
-            for (int k = 0; k < nnb; ++k) {
-                double w = 0.5 * (mc[i] + mc[nb[k]]);
-                s = s + w * (mu[nb[k]] - mu[i]);
-            }
-            r[(long long)N * V + i] = s * (1.0 / (P->dx * P->dx));
-        }
+        double ri[PFO_MAXN + 1];
+        cell_rhs(P, u, V, i, mu, mc, ri);
+        for (int a = 0; a < N; ++a) r[(long long)a * V + i] = ri[a];
+        if (P->with_c) r[(long long)N * V + i] = ri[N];
+    }
+    free(mu);
+    free(mc);
+}
+
+/* The right-hand side at n listed cells only (the same per-cell formula as
+ * pfo_rhs; mu and Mc are formed over the whole grid): out[k * F + f] is field
+ * f at cell cells[k].  For checking a large grid at sampled cells. */
+void pfo_rhs_at(const pfo_params *P, const double *u, const long long *cells, long long n,
+                double *out) {
+    long long V = ncells(P);
+    int F = P->n_phi + (P->with_c ? 1 : 0);
+    double *mu = (double *)calloc((size_t)V, sizeof(double));
+    double *mc = (double *)calloc((size_t)V, sizeof(double));
+    if (P->with_c) pfo_mu(P, u, mu, mc);
+#pragma omp parallel for schedule(static)
+    for (long long k = 0; k < n; ++k) {
+        double ri[PFO_MAXN + 1];
+        cell_rhs(P, u, V, cells[k], mu, mc, ri);
+        for (int f = 0; f < F; ++f) out[k * F + f] = ri[f];
     }
     free(mu);
     free(mc);

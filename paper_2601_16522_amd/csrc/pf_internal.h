@@ -44,9 +44,10 @@ enum StageKind : int {
     K_SSP2_FINAL = 2,   // out = S(((a y1 + u0) + b r) / c)
     K_SSP104_S5 = 3,    // y = S(y1 + a r); out2 = b u0 + c y; out = S(d out2 - e y)
     K_SSP104_FINAL = 4, // out = S((u0 + a y1) + b r)
-    K_RKL1 = 5,         // out = S((a y1 + b y2) + c r)
+    K_RKL1 = 5,         // out = S((a y1 + b y2) + c r); FP32: S(y1 + b (y2 - y1) + c r), a + b = 1
     K_RKL2_FIRST = 6,   // y* = y1 + a r; out = S(y*); out2 = R0 (corrected where S acted)
-    K_RKL2 = 7,         // out = S(((a u0 + b y1) + c y2) + d ((e r) + (f r0)))
+    K_RKL2 = 7,         // out = S(((a u0 + b y1) + c y2) + d ((e r) + (f r0)));
+                        // FP32: u0 + b (y1 - u0) + c (y2 - u0) for the first three terms
     K_EST = 8           // Sommeijer estimate of u^{n+1} = y1 against u^n = u0, R0 = r0
 };
 

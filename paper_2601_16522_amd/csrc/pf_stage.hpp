@@ -462,18 +462,23 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                             yv[f] = (o0[f] + A.a * cur[f]) + A.b * r[f];
                         }
                     } else if constexpr (KIND == K_RKL1) {
+                        // the fast form uses mu_j + nu_j = 1: Y_{j-1} + nu_j (Y_{j-2} -
+                        // Y_{j-1}), so rounded coefficients cannot change the total of c
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
-                            if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, o1[f], A.a * cur[f]));
+                            if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, o1[f] - cur[f], cur[f]));
                             else yv[f] = (A.a * cur[f] + A.b * o1[f]) + A.c * r[f];
                         }
                     } else {  // K_RKL2
     #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const T u = o0[f], v2 = o1[f], q0 = o2[f];
+                            // the fast form: u + mu_j (Y_{j-1} - u) + nu_j (Y_{j-2} - u), the
+                            // same combination, whose weights sum to 1 exactly whatever the
+                            // rounding of mu_j and nu_j (the total of c is kept)
                             if constexpr (FAST)
                                 yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
-                                              fma_t(A.c, v2, fma_t(A.b, cur[f], A.a * u)));
+                                              fma_t(A.c, v2 - u, fma_t(A.b, cur[f] - u, u)));
                             else
                                 yv[f] = ((A.a * u + A.b * cur[f]) + A.c * v2) + A.d * (A.e * r[f] + A.f * q0);
                         }

@@ -1,0 +1,173 @@
+"""Parity of the measured workloads at their full sizes, through the C-ABI.
+
+* 128^2 single grain (FE, 2000 steps at 0.9 dt_e): FP64 and FP32 against the
+  oracle, element by element.
+* 256^3 grains + pores (N = 13) and 512^3 grain growth + pores (N = 9): the
+  right-hand side against the oracle at sampled cells (the oracle evaluates
+  the same per-cell formula there), FP64 on the state and FP32 on the
+  FP32-rounded state; then one FP32 RKL2 step at 100 dt_e (21 stages) in the
+  autotuned launch shape that bench.py times, checked by properties that hold
+  at any size (phi in [0, 1], sum of phi, conservation of c) and by the launch
+  shape changing no bit.
+* The 96-instance batch (FE, 2000 steps each): FP32 in the autotuned launch
+  configuration against single-instance runs, bit for bit, on a sample of
+  instances; FP64 against the oracle on the smallest instances.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pf_inputs as pi
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pf = pytest.importorskip("paper_2601_16522_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+    pf.lib()
+
+
+def fp32_rounded(u):
+    return np.asarray(u, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_single_grain_2000_fe_steps(prec, tol):
+    wl = pi.single_grain()
+    P = oracle.Params(**wl.param_dict())
+    dt = 0.9 * oracle.stable_dt(P)
+    t_end = 2000 * dt
+    u0 = wl.u0 if prec == "fp64" else fp32_rounded(wl.u0)
+    ref, st, rc = oracle.run_to(P, oracle.FE, u0, t_end, dt_fixed=dt)
+    assert rc == 0 and st.accepted == 2000
+    sim = pf.Sim(wl.param_dict(), prec=prec)
+    sim.init_fields(wl.u0)
+    s = sim.run_to("fe", t_end, dt_fixed=dt)
+    u, t = sim.get_fields()
+    assert s.accepted == 2000 and t == t_end
+    d = np.abs(u - ref)
+    print(f"\nsingle grain 128^2 {prec} 2000 FE: max |dphi| {d[:2].max():.3e}, max |dc| {d[2].max():.3e}",
+          flush=True)
+    assert d[:2].max() <= tol and d[2].max() <= tol
+
+
+def _sample_cells(V, n, seed):
+    return np.sort(np.random.default_rng(seed).choice(V, size=n, replace=False))
+
+
+def _check_rhs_sampled(wl, prec, cells, tol):
+    """GPU RHS of the state against the oracle's at `cells`; error relative to
+    the largest sampled magnitude of each field."""
+    P = oracle.Params(**wl.param_dict())
+    u = wl.u0 if prec == "fp64" else fp32_rounded(wl.u0)
+    ref = oracle.rhs_at(P, u, cells)
+    sim = pf.Sim(wl.param_dict(), prec=prec)
+    sim.init_fields(wl.u0)
+    r = sim.rhs().reshape(wl.F, -1)[:, cells].T
+    sim.close()
+    scale = np.maximum(np.abs(ref).max(axis=0), 1e-300)
+    err = (np.abs(r - ref) / scale).max(axis=0)
+    print(f"\n{wl.name} {prec} RHS at {cells.size} cells: max error / field scale {err.max():.3e}",
+          flush=True)
+    assert err.max() <= tol, err
+
+
+def _check_rkl2_step_properties(wl):
+    """One FP32 RKL2 step at 100 dt_e in the autotuned tiling, then the same
+    step in another z extent: identical bits, phi in [0, 1], sum phi = 1,
+    sum c conserved."""
+    sim = pf.Sim(wl.param_dict(), prec="fp32")
+    sim.init_fields(wl.u0)
+    c0 = sim.conservation()
+    tx, zc, _ = sim.autotune()
+    dt = 100 * sim.stable_dt()
+    st = sim.step("rkl2", dt)
+    assert st.stages == 21
+    d = sim.diagnostics()
+    c1 = d["sum_c"]
+    print(f"\n{wl.name} FP32 RKL2 step (zchunk {zc}): phi in [{d['min_phi']:.3e}, {d['max_phi']:.6f}], "
+          f"max |sum phi - 1| {d['max_sum_dev']:.3e}, sum c {c0:.9e} -> {c1:.9e} "
+          f"(rel {abs(c1 - c0) / abs(c0):.2e})", flush=True)
+    assert d["nonfinite"] == 0
+    assert d["min_phi"] >= 0.0 and d["max_phi"] <= 1.0
+    assert d["max_sum_dev"] <= 1e-6
+    assert abs(c1 - c0) <= 1e-7 * abs(c0)
+    a = torch.empty(wl.F * wl.cells, dtype=torch.float32, device="cuda")
+    sim.get_fields_device(a)
+    sim.close()
+    other = pf.Sim(wl.param_dict(), prec="fp32")
+    other.init_fields(wl.u0)
+    other.set_tiling(tx, 16 if zc != 16 else 64)
+    other.step("rkl2", dt)
+    b = torch.empty_like(a)
+    other.get_fields_device(b)
+    other.close()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def pores256():
+    return pi.grains_pores_3d(n=256, n_grains=12, n_grain_fields=12, n_pores=40, r_range=(4.0, 10.0))
+
+
+@pytest.fixture(scope="module")
+def gg512():
+    return pi.grain_growth_pores_3d(n=512)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-4)])
+def test_pores256_rhs_sampled(pores256, prec, tol):
+    _check_rhs_sampled(pores256, prec, _sample_cells(pores256.cells, 20000, 11), tol)
+
+
+def test_pores256_rkl2_step_properties(pores256):
+    _check_rkl2_step_properties(pores256)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-4)])
+def test_gg512_rhs_sampled(gg512, prec, tol):
+    _check_rhs_sampled(gg512, prec, _sample_cells(gg512.cells, 20000, 12), tol)
+
+
+def test_gg512_rkl2_step_properties(gg512):
+    _check_rkl2_step_properties(gg512)
+
+
+def test_batch96_full_size():
+    wls = pi.batch_instances()
+    b = pf.Batch([w.param_dict() for w in wls], prec="fp32")
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    b.autotune()
+    nb, depth = b.config()
+    dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
+    t_end = [2000 * d for d in dts]
+    st = b.run_to(t_end, dt=dts, graph_steps=50)
+    assert all(s.accepted == 2000 for s in st)
+    sizes = [w.nx for w in wls]
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 17, 42, 95})
+    for i in sample:
+        s = pf.Sim(wls[i].param_dict(), prec="fp32")
+        s.init_fields(wls[i].u0)
+        s.run_to("fe", t_end[i], dt_fixed=dts[i])
+        assert np.array_equal(b.get_fields(i)[0], s.get_fields()[0]), (i, nb, depth)
+        s.close()
+    # FP64 batch against the oracle on the two smallest instances
+    b64 = pf.Batch([w.param_dict() for w in wls], prec="fp64")
+    for i, w in enumerate(wls):
+        b64.init_fields(i, w.u0)
+    b64.run_to(t_end, dt=dts, graph_steps=50)
+    for i in np.argsort(sizes)[:2]:
+        P = oracle.Params(**wls[i].param_dict())
+        ref, _, rc = oracle.run_to(P, oracle.FE, wls[i].u0, t_end[i], dt_fixed=dts[i])
+        assert rc == 0
+        assert np.abs(b64.get_fields(int(i))[0] - ref).max() <= 1e-10

@@ -308,18 +308,21 @@ def test_cfg2_full_size_one_rkl2_step_fp64_and_fp32():
     sim32.step("rkl2", dt)
     u32, _ = sim32.get_fields()
     d = np.abs(u32[:8] - ref[:8])
-    # Values off by more than 1e-4 must sit at triple junctions: there a phase
-    # of value ~0 decides its activity (phi > 0) differently in FP32 and FP64,
-    # which switches a term of the right-hand side on or off.  Junction cells:
-    # three or more phases above 1e-6 in the FP64 result.
+    # Values off by more than 1e-4 come from activity decisions (phi > 0, R1)
+    # taken differently in FP32 and FP64 where a third phase has a vanishing
+    # tail: switching it on or off changes N_z and the pairwise terms of eq.
+    # phieq.  Such cells have three or more phases > 0 (in either result); a
+    # change at stage j reaches at most s - j cells by the end of the step, so
+    # every such value lies within s = 21 cells of one.
     from scipy import ndimage
-    junction = ((ref[:8] > 1e-6).sum(axis=0) >= 3).reshape(wl.ny, wl.nx)
-    dist = ndimage.distance_transform_edt(~junction)
+    tails = (((ref[:8] > 0).sum(axis=0) >= 3) | ((u32[:8] > 0).sum(axis=0) >= 3)).reshape(wl.ny, wl.nx)
+    dist = ndimage.distance_transform_edt(~tails)
     bad = (d > 1e-4).any(axis=0).reshape(wl.ny, wl.nx)
     far = float(dist[bad].max()) if bad.any() else 0.0
     print(f"\ncfg2 FP32 vs oracle: max {d.max():.3e} rms {math.sqrt((d**2).mean()):.3e} "
           f"count>1e-4 {(d > 1e-4).sum()} of {d.size}; cells {bad.sum()}, farthest from a "
-          f"triple junction {far:.2f} cells", flush=True)
+          f"three-phase cell {far:.2f} cells", flush=True)
     assert math.sqrt((d ** 2).mean()) <= 1e-5
     assert d.max() <= 1e-2
-    assert far <= 3.0
+    assert (d > 1e-4).sum() <= 1e-5 * d.size
+    assert far <= s

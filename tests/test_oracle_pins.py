@@ -102,6 +102,16 @@ def test_phase_rates_sum_to_zero():
     assert np.abs(r[:N]).max() > 1e-3
 
 
+def test_rhs_at_sampled_cells_equals_rhs():
+    """The sampled form (used to check grids too large for a full oracle pass)
+    is the same per-cell formula: equal bits, 3D with two types."""
+    wl = pi.grains_pores_3d(n=16, n_grains=5, n_grain_fields=5, n_pores=3, r_range=(2.0, 3.0))
+    P = oracle.Params(**wl.param_dict())
+    r = oracle.rhs(P, wl.u0).reshape(P.F, -1)
+    cells = np.random.default_rng(1).choice(r.shape[1], size=300, replace=False)
+    assert np.array_equal(oracle.rhs_at(P, wl.u0, cells), r[:, cells].T)
+
+
 # -----------------------------------------------------------------------------
 # Closed forms of the model
 # -----------------------------------------------------------------------------
