@@ -105,7 +105,12 @@ typedef struct {
     double t, last_dt, last_err;
 } pf_stats;
 
-/* Handle life cycle. */
+/* Handle life cycle.  pf_create returns PF_EINVAL for inconsistent parameters
+ * and PF_EUNSUPPORTED for an n_phi this build has no kernels for
+ * (pf_supported_nphi) or a grid too large to address: the kernels split a
+ * state vector's N + 1 planes into 1, 2 or 4 groups of ceil((N + 1) / groups)
+ * planes, each group spanning less than 4 GiB (FP32 512^3 with N = 9 needs
+ * two, FP64 four). */
 pf_status pf_create(const pf_params *p, pf_sim **out);
 pf_status pf_destroy(pf_sim *sim);
 

@@ -1,8 +1,9 @@
 """Build libpf.so (gfx950 HIP kernels + host engine + C-ABI) in-tree with hipcc.
 
 The fused stage kernels are instantiated once per supported number of order
-parameters (pf_stage_inst.hip with -DPF_NPHI=n); those objects compile in
-parallel and are linked with the reduction kernels and the host engine.
+parameters and number of buffer groups (pf_stage_inst.hip with -DPF_NPHI=n
+-DPF_NG=g); those objects compile in parallel and are linked with the
+reduction kernels and the host engine.
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpf.so")
 STREAM_REF = os.path.join(HERE, "stream_ref")
 NPHI = [2, 3, 4, 8, 9, 13]
+NGROUPS = [1, 2, 4]  # buffer groups per state vector (kernels are compiled per count)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -31,8 +33,8 @@ FLAGS = [
 
 
 def _units():
-    units = [(os.path.join(CSRC, "pf_stage_inst.hip"), os.path.join(OBJ, f"stage_n{n}.o"),
-              [f"-DPF_NPHI={n}"]) for n in NPHI]
+    units = [(os.path.join(CSRC, "pf_stage_inst.hip"), os.path.join(OBJ, f"stage_n{n}_g{g}.o"),
+              [f"-DPF_NPHI={n}", f"-DPF_NG={g}"]) for n in NPHI for g in NGROUPS]
     units.append((os.path.join(CSRC, "pf_kernels.hip"), os.path.join(OBJ, "kernels.o"), []))
     units.append((os.path.join(CSRC, "pf_api.cpp"), os.path.join(OBJ, "api.o"), []))
     return units

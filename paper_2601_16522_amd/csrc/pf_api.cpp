@@ -427,7 +427,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     A.r0 = r0;
     A.out = out;
     A.out2 = out2;
-    set_field_bases(A, s->F, s->V);
+    set_field_bases(A, s->N, s->V);
     A.kind = kind;
     A.a = (T)a; A.b = (T)b; A.c = (T)c; A.d = (T)d; A.e = (T)e; A.f = (T)f;
     int ntx, nty, nzc, ntiles, nblocks;
@@ -463,7 +463,7 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
         A.y1 = unew;
         A.u0 = uold;
         A.r0 = aux;
-        set_field_bases(A, s->F, s->V);
+        set_field_bases(A, s->N, s->V);
         A.kind = K_EST;
         A.red = s->red;
         A.redn = s->redn;
@@ -842,14 +842,11 @@ pf_status init_meta(pf_sim *s, const pf_params *p) {
     if (p->prec != PF_FP64 && p->prec != PF_FP32) return PF_EUNSUPPORTED;
     if (!nphi_supported(p->n_phi)) return PF_EUNSUPPORTED;
     {
-        // the kernels address one field plane with 32-bit byte offsets
-        const unsigned long long cells = (unsigned long long)p->nx * p->ny * p->nz;
-        const unsigned long long esz = p->prec == PF_FP64 ? 8 : 4;
-        if (cells * esz > 0xFFFFFFFFull) return PF_EUNSUPPORTED;
-        // and one vector spans at most four such groups of planes
-        const unsigned long long G = 0xFFFFFFFFull / (cells * esz);
-        const unsigned long long F = (unsigned long long)p->n_phi + (p->with_c ? 1 : 0);
-        if (F > 4 * G) return PF_EUNSUPPORTED;
+        // the kernels address a vector's planes in at most four groups of
+        // ceil((N + 1) / groups) planes, each within a 32-bit byte range
+        const long long cells = (long long)p->nx * p->ny * p->nz;
+        if (field_groups_needed(p->n_phi, cells, p->prec == PF_FP64 ? 8 : 4) == 0)
+            return PF_EUNSUPPORTED;
     }
     for (int a = 0; a < p->n_phi; ++a)
         if (p->type_of[a] < 0 || p->type_of[a] >= p->n_types) return PF_EINVAL;

@@ -107,41 +107,32 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
     __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, CP);
 }
 
-// Group of field f.  ONEG: the caller guarantees that all fields of a vector
-// fit one group (G >= F), so the group is 0 at compile time and the group base
-// is a constant index (needed where the StageArgs live in registers rather
-// than in the kernel arguments: a runtime index would spill them to scratch).
-template <bool ONEG, typename S>
-__device__ __forceinline__ int field_group(const S &A, int f) {
-    if constexpr (ONEG) return 0;
-    const int G = A.G;
-    return f >= 3 * G ? 3 : f >= 2 * G ? 2 : f >= G ? 1 : 0;
-}
-
-template <typename T, typename S>
+// Buffer resource of group g of vector v: GS planes from its base.
+// GS * plane_bytes < 2^32 by construction (set_field_bases).
+template <typename T, int GS, typename S>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const S &A, int v, int g) {
-    // G * plane_bytes < 4 GiB by construction (set_field_bases)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(A.gb[v][g]), 0,
-                                             (int)(unsigned)(A.G * (unsigned long long)A.plane_bytes),
-                                             0x00020000);
+                                             (int)((unsigned)GS * A.plane_bytes), 0x00020000);
 }
 
-template <typename T, bool ONEG = false, int CP = 0, typename S>
+// Field f of vector v at per-lane byte offset boff, with GS planes per buffer
+// group: group f / GS and plane f mod GS are constants wherever f is.
+template <typename T, int GS, int CP = 0, typename S>
 __device__ __forceinline__ T ldv(const S &A, int v, int f, unsigned boff) {
-    const int g = field_group<ONEG>(A, f);
-    return buf_load<CP>(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, T(0));
+    const int g = f / GS;
+    return buf_load<CP>(group_rsrc<T, GS>(A, v, g), boff, (unsigned)(f - g * GS) * A.plane_bytes, T(0));
 }
-template <typename T, bool ONEG = false, int CP = 0, typename S>
+template <typename T, int GS, int CP = 0, typename S>
 __device__ __forceinline__ void stv(const S &A, int v, int f, unsigned boff, T x) {
-    const int g = field_group<ONEG>(A, f);
-    buf_store<CP>(group_rsrc<T>(A, v, g), boff, (unsigned)(f - g * A.G) * A.plane_bytes, x);
+    const int g = f / GS;
+    buf_store<CP>(group_rsrc<T, GS>(A, v, g), boff, (unsigned)(f - g * GS) * A.plane_bytes, x);
 }
 
-template <typename T, int N, bool ONEG = false, typename S>
+template <typename T, int N, int GS, typename S>
 __device__ __forceinline__ void load_point32(const S &A, int v, unsigned boff, bool withc, T *x) {
 #pragma unroll
-    for (int f = 0; f < N; ++f) x[f] = ldv<T, ONEG>(A, v, f, boff);
-    x[N] = withc ? ldv<T, ONEG>(A, v, N, boff) : T(0);
+    for (int f = 0; f < N; ++f) x[f] = ldv<T, GS>(A, v, f, boff);
+    x[N] = withc ? ldv<T, GS>(A, v, N, boff) : T(0);
 }
 
 // Deterministic block reduction of (sum, count) over a 256-thread block: a

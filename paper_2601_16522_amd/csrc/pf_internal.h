@@ -73,13 +73,15 @@ struct StageArgs {
     const T *r0;
     T *out;
     T *out2;
-    // Buffer addressing of the six vectors above: the field planes of a vector
-    // are split into groups of G consecutive planes whose span fits a 32-bit
-    // byte range; gb[v][g] is the first plane of group g of vector v (y1, y2,
-    // u0, r0, out, out2).  Field f is read from group f / G at scalar offset
-    // (f mod G) * plane_bytes plus a 32-bit per-lane offset.
+    // Buffer addressing of the six vectors above: the N + 1 field planes of a
+    // vector are split into ng groups (1, 2 or 4) of GS = ceil((N + 1) / ng)
+    // consecutive planes whose span fits a 32-bit byte range; gb[v][g] is the
+    // first plane of group g of vector v (y1, y2, u0, r0, out, out2).  Field f
+    // is read from group f / GS at scalar offset (f mod GS) * plane_bytes plus a
+    // 32-bit per-lane offset; kernels are compiled per ng, so both are
+    // constants.
     const T *gb[6][4];
-    int G;
+    int ng;
     unsigned plane_bytes;
     double *red;    // per-block partial sums (EST)
     long long *redn;
@@ -94,24 +96,34 @@ struct StageArgs {
     int ntiles;
 };
 
-// One instance of a batch of independent 2D simulations that share N, the
-// precision and with_c.
+// Planes per buffer group for N order parameters (+ c) split into ng groups.
+constexpr int group_planes(int n, int ng) { return (n + 1 + ng - 1) / ng; }
+
+// The smallest group count (1, 2 or 4) whose groups span at most 2^32 - 1
+// bytes for planes of V values of esz bytes, or 0 when even four do not.
+inline int field_groups_needed(int n, long long V, int esz) {
+    const unsigned long long pb = (unsigned long long)V * esz;
+    for (int ng = 1; ng <= 4; ng *= 2)
+        if ((unsigned long long)group_planes(n, ng) * pb <= 0xFFFFFFFFull) return ng;
+    return 0;
+}
+
 // Fills the buffer-group bases of a StageArgs from its vector pointers.  The
-// caller guarantees V * sizeof(T) < 4 GiB and F <= 4 G.
+// caller guarantees field_groups_needed(n, V, sizeof(T)) > 0.
 template <typename T>
-__host__ __device__ inline void set_field_bases(StageArgs<T> &A, int F, long long V) {
-    const unsigned long long pb = (unsigned long long)V * sizeof(T);
-    int G = (int)(0xFFFFFFFFull / pb);
-    if (G > F) G = F;
-    if (G < 1) G = 1;
-    A.G = G;
-    A.plane_bytes = (unsigned)pb;
+inline void set_field_bases(StageArgs<T> &A, int n, long long V) {
+    const int ng = field_groups_needed(n, V, (int)sizeof(T));
+    const int GS = group_planes(n, ng);
+    A.ng = ng;
+    A.plane_bytes = (unsigned)((unsigned long long)V * sizeof(T));
     const T *vec[6] = {A.y1, A.y2, A.u0, A.r0, A.out, A.out2};
     for (int v = 0; v < 6; ++v)
         for (int g = 0; g < 4; ++g)
-            A.gb[v][g] = (vec[v] && g * G < F) ? vec[v] + (long long)g * G * V : vec[v];
+            A.gb[v][g] = (vec[v] && g < ng) ? vec[v] + (long long)g * GS * V : vec[v];
 }
 
+// One instance of a batch of independent 2D simulations that share N, the
+// precision and with_c.
 template <typename T>
 struct BatchInst {
     long long off;     // element offset of the instance's state in each batch buffer

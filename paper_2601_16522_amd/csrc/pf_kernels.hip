@@ -152,18 +152,20 @@ finalize_diag_kernel(const double *red, int n, double *out) {
 
 #define PF_NPHI_LIST(X) X(2) X(3) X(4) X(8) X(9) X(13)
 
-// defined in pf_stage_inst.hip, one object per N
-#define PF_DECL(n)                                                                         \
-    extern template hipError_t launch_stage_n<float, n>(int, const StageArgs<float> &, int, \
-                                                        hipStream_t);                      \
-    extern template hipError_t launch_stage_n<double, n>(int, const StageArgs<double> &, int, \
-                                                         hipStream_t);
-template <typename T, int N>
+// defined in pf_stage_inst.hip, one object per (N, number of buffer groups)
+#define PF_DECLG(n, g)                                                                       \
+    extern template hipError_t launch_stage_n<float, n, g>(int, const StageArgs<float> &, int, \
+                                                           hipStream_t);                      \
+    extern template hipError_t launch_stage_n<double, n, g>(int, const StageArgs<double> &,    \
+                                                            int, hipStream_t);
+#define PF_DECL(n) PF_DECLG(n, 1) PF_DECLG(n, 2) PF_DECLG(n, 4)
+template <typename T, int N, int NG>
 hipError_t launch_stage_n(int dim, const StageArgs<T> &A, int nblocks, hipStream_t stream);
 template <typename T, int N>
 hipError_t launch_batch_euler_n(const BatchArgs<T> &B, int nblocks, hipStream_t stream);
 PF_NPHI_LIST(PF_DECL)
 #undef PF_DECL
+#undef PF_DECLG
 #define PF_DECLB(n)                                                                        \
     extern template hipError_t launch_batch_euler_n<float, n>(const BatchArgs<float> &, int, \
                                                               hipStream_t);                \
@@ -194,7 +196,14 @@ template <typename T>
 hipError_t launch_stage(int dim, int nphi, const StageArgs<T> &args, int nblocks,
                         hipStream_t stream) {
     switch (nphi) {
-#define PF_CASE(n) case n: return launch_stage_n<T, n>(dim, args, nblocks, stream);
+#define PF_CASE(n)                                                                  \
+    case n:                                                                         \
+        switch (args.ng) {                                                          \
+        case 1: return launch_stage_n<T, n, 1>(dim, args, nblocks, stream);         \
+        case 2: return launch_stage_n<T, n, 2>(dim, args, nblocks, stream);         \
+        case 4: return launch_stage_n<T, n, 4>(dim, args, nblocks, stream);         \
+        default: return hipErrorInvalidValue;                                       \
+        }
         PF_NPHI_LIST(PF_CASE)
 #undef PF_CASE
     default: return hipErrorInvalidValue;

