@@ -143,6 +143,38 @@ pf_status pf_stable_dt(pf_sim *sim, double *dt_e);
  * stability interval scaled by the 0.9 safety factor (eq. sts-limit). */
 pf_status pf_stage_count(pf_sim *sim, pf_integrator integ, double dt, int *s);
 
+/* ---------------------------------------------------------------------------
+ * Host-side helpers: the engine's own scalar computations, callable without a
+ * handle or a device (no device memory, no launches).
+ * -------------------------------------------------------------------------*/
+/* pf_stable_dt of a parameter set (same validation as pf_create). */
+pf_status pf_params_stable_dt(const pf_params *p, double *dt_e);
+/* pf_stage_count for PF_RKL1 / PF_RKL2 given dt_e; PF_EINVAL for other
+ * integrators or non-positive dt, dt_e. */
+pf_status pf_rkl_stage_count(pf_integrator integ, double dt, double dt_e, int *s);
+
+/* Step-size controller of Sec. 3.3 (PID form with gains 1.25, 0.5, -0.6, 0.25,
+ * 0 on errors scaled by the bias b, limiter 1 + 5 atan((F - 1) / 5), bias
+ * raised to sqrt(b) (at most 0.98) on acceptance and lowered to b^2 (at least
+ * 0.1) on rejection; a step is accepted when err < 1, a non-finite err is a
+ * rejection with factor 0).  pf_controller_update takes the error norm of a
+ * step of size h of a method of order `order`, sets *accept and the proposed
+ * next step *h_next, and advances the state as pf_run_to does. */
+typedef struct {
+    double b;     /* bias */
+    int nhist;    /* accepted steps in the history (0..2) */
+    double E1, E2, h1, h2; /* last two accepted scaled errors and steps */
+} pf_controller;
+pf_status pf_controller_init(pf_controller *c);
+pf_status pf_controller_update(pf_controller *c, int order, double err, double h, int *accept,
+                               double *h_next);
+
+/* Exact output times (Sec. 5 opening): the step from t towards t_end has size
+ * h unless the remainder is at most h (1 + 1e-10), in which case it is the
+ * remainder and *last = 1.  Returns 1 with *h_use set, 0 when t_end is reached
+ * (remainder at most 1e-12 h), -1 for invalid arguments. */
+int pf_clip_step(double t, double t_end, double h, double *h_use, int *last);
+
 /* One step of size dt (RKL stage count from pf_stage_count).  stats may be
  * NULL; otherwise it is overwritten with this call's counters. */
 pf_status pf_step(pf_sim *sim, pf_integrator integ, double dt, pf_stats *stats);

@@ -38,7 +38,9 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_supported_nphi", "pf_last_error", "pf_batch_create", "pf_batch_destroy",
            "pf_batch_set_stream", "pf_batch_init_fields", "pf_batch_get_fields",
            "pf_batch_stable_dt", "pf_batch_run_to", "pf_batch_autotune", "pf_batch_set_blocks",
-           "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error"]
+           "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error",
+           "pf_params_stable_dt", "pf_rkl_stage_count", "pf_controller_init",
+           "pf_controller_update", "pf_clip_step"]
 
 
 class PFError(RuntimeError):
@@ -69,6 +71,11 @@ class _Stats(C.Structure):
 
 
 @dataclass
+class _Controller(C.Structure):
+    _fields_ = [("b", C.c_double), ("nhist", C.c_int), ("E1", C.c_double), ("E2", C.c_double),
+                ("h1", C.c_double), ("h2", C.c_double)]
+
+
 class Tol:
     r_phi: float = 1e-4
     a_phi: float = 1e-2
@@ -157,6 +164,17 @@ def lib():
             fn.restype = C.c_int
         L.pf_batch_last_error.argtypes = [vp]
         L.pf_batch_last_error.restype = C.c_char_p
+        hsigs = {
+            "pf_params_stable_dt": [C.POINTER(_Params), pd],
+            "pf_rkl_stage_count": [i, d, d, C.POINTER(i)],
+            "pf_controller_init": [C.POINTER(_Controller)],
+            "pf_controller_update": [C.POINTER(_Controller), i, d, d, C.POINTER(i), pd],
+            "pf_clip_step": [d, d, d, pd, C.POINTER(i)],
+        }
+        for name, args in hsigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
         _lib = L
     return _lib
 
@@ -165,6 +183,59 @@ def supported_nphi():
     out = (C.c_int * 64)()
     n = lib().pf_supported_nphi(out, 64)
     return [out[i] for i in range(min(n, 64))]
+
+
+# ---------------------------------------------------------------------------
+# Host-side helpers (no handle, no device)
+# ---------------------------------------------------------------------------
+
+def _hchk(code: int, what: str):
+    if code != 0:
+        raise PFError(code, what)
+
+
+def params_stable_dt(params: dict) -> float:
+    """dt_e of a parameter set (pf_params_stable_dt)."""
+    keep = []
+    cp = _cparams(params, "fp64", 0, keep)
+    v = C.c_double()
+    _hchk(lib().pf_params_stable_dt(C.byref(cp), C.byref(v)), "pf_params_stable_dt")
+    return v.value
+
+
+def rkl_stage_count(integ: str, dt: float, dt_e: float) -> int:
+    """RKL stage count for dt (pf_rkl_stage_count); integ is "rkl1" or "rkl2"."""
+    v = C.c_int()
+    _hchk(lib().pf_rkl_stage_count(INTEGRATORS[integ], dt, dt_e, C.byref(v)), "pf_rkl_stage_count")
+    return v.value
+
+
+class Controller:
+    """The engine's step-size controller (pf_controller_*)."""
+
+    def __init__(self):
+        self._c = _Controller()
+        _hchk(lib().pf_controller_init(C.byref(self._c)), "pf_controller_init")
+
+    def update(self, order: int, err: float, h: float):
+        """Returns (accepted, proposed next step)."""
+        acc, hn = C.c_int(), C.c_double()
+        _hchk(lib().pf_controller_update(C.byref(self._c), order, err, h, C.byref(acc),
+                                         C.byref(hn)), "pf_controller_update")
+        return bool(acc.value), hn.value
+
+    @property
+    def bias(self) -> float:
+        return self._c.b
+
+
+def clip_step(t: float, t_end: float, h: float):
+    """(step size, is last) of the next step towards t_end, or None when t_end is reached."""
+    hu, last = C.c_double(), C.c_int()
+    r = lib().pf_clip_step(t, t_end, h, C.byref(hu), C.byref(last))
+    if r < 0:
+        raise PFError(-1, "pf_clip_step: invalid arguments")
+    return (hu.value, bool(last.value)) if r == 1 else None
 
 
 def _dp(a: np.ndarray):

@@ -26,11 +26,15 @@ namespace {
 constexpr int NBUF = 7;
 constexpr double PI = 3.14159265358979323846;
 
-struct Ctrl {
-    double b = 0.9;
-    int nhist = 0;
-    double E1 = 0, E2 = 0, h1 = 0, h2 = 0;
-};
+// Controller state (pf_controller of the C-ABI): bias b, accepted-history
+// length and the last two accepted scaled errors and steps.
+inline pf_controller ctrl_initial() {
+    pf_controller c;
+    c.b = 0.9;
+    c.nhist = 0;
+    c.E1 = c.E2 = c.h1 = c.h2 = 0.0;
+    return c;
+}
 
 struct Pending {
     unsigned mask;
@@ -70,7 +74,7 @@ struct pf_sim {
     double *dres = nullptr;
     double *hres = nullptr;  // pinned
     double t = 0.0;
-    Ctrl ctrl;
+    pf_controller ctrl = ctrl_initial();
     double dt_next = 0.0;   // controller proposal carried between pf_run_to calls
     std::vector<double> trace;
     std::string err;
@@ -315,6 +319,17 @@ double stable_dt(const pf_sim *s) {
     return 2.0 / lam;
 }
 
+// Exact output times (Sec. 5): the step from t towards t_end has size h unless
+// the remainder is at most h (1 + 1e-10); then it is the remainder and the
+// last one.  A remainder at most 1e-12 h means t_end is reached (false).
+bool clip_step(double t, double t_end, double h, double &h_use, bool &last) {
+    const double rem = t_end - t;
+    if (rem <= 1e-12 * h) return false;
+    last = rem <= h * (1.0 + 1e-10);
+    h_use = last ? rem : h;
+    return true;
+}
+
 // Smallest odd stage count inside the exact RKL stability bound times 0.9.
 int stage_count(int order, double dt, double dte) {
     if (!(dt > 0.0) || !(dte > 0.0)) return -1;
@@ -370,7 +385,7 @@ int method_order(int integ) {
 }
 
 // PID controller of Sec. 3.3 (Soederlind), bias b in [0.1, 0.98].
-double ctrl_update(Ctrl &c, int order, double e, double h, bool &accept) {
+double ctrl_update(pf_controller &c, int order, double e, double h, bool &accept) {
     const double k1 = 1.25, k2 = 0.5, k3 = -0.6, k4 = 0.25, k5 = 0.0;
     const double p1 = order + 1.0;
     const bool finite = std::isfinite(e);
@@ -671,14 +686,9 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
         hipEvent_t e_run = fe ? mark(s) : nullptr;
         const long long st_run = s->st.stages;
         for (;;) {
-            const double rem = t_end - s->t;
-            if (rem <= 1e-12 * dt_fixed) break;
-            double h = dt_fixed;
-            bool last = false;
-            if (rem <= h * (1.0 + 1e-10)) {
-                h = rem;
-                last = true;
-            }
+            double h;
+            bool last;
+            if (!clip_step(s->t, t_end, dt_fixed, h, last)) break;
             int ns = s->ssp_s;
             if (integ == PF_RKL1 || integ == PF_RKL2) ns = stage_count(integ == PF_RKL1 ? 1 : 2, h, dte);
             int res, aux;
@@ -704,14 +714,9 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
     double dt = tol->dt0 > 0.0 ? tol->dt0 : (s->dt_next > 0.0 ? s->dt_next : 0.9 * dte);
     int nonfinite = 0;
     for (;;) {
-        const double rem = t_end - s->t;
-        double h = std::min(dt, dtmax);
-        if (rem <= 1e-12 * h) break;
-        bool last = false;
-        if (rem <= h * (1.0 + 1e-10)) {
-            h = rem;
-            last = true;
-        }
+        double h;
+        bool last;
+        if (!clip_step(s->t, t_end, std::min(dt, dtmax), h, last)) break;
         if (!last && h < 1e-12 * dte) return fail(s, PF_EDTMIN, "adaptive step underflow (dt = %g)", h);
         int ns = s->ssp_s;
         if (integ != PF_SSP_S2) ns = stage_count(order, h, dte);
@@ -944,7 +949,7 @@ pf_status pf_init_fields(pf_sim *s, const double *phi, const double *c, double t
     if (rc) return rc;
     s->t = t0;
     s->have_fields = true;
-    s->ctrl = Ctrl();
+    s->ctrl = ctrl_initial();
     s->dt_next = 0.0;
     return PF_OK;
 }
@@ -955,7 +960,7 @@ pf_status pf_init_fields_device(pf_sim *s, const void *state, double t0) {
                              s->stream));
     s->t = t0;
     s->have_fields = true;
-    s->ctrl = Ctrl();
+    s->ctrl = ctrl_initial();
     s->dt_next = 0.0;
     return PF_OK;
 }
@@ -1198,6 +1203,47 @@ pf_status pf_get_kernel_time(pf_sim *s, int family, double *ms, long long *launc
 
 int pf_supported_nphi(int *out, int cap) { return supported_nphi_list(out, cap); }
 
+pf_status pf_params_stable_dt(const pf_params *p, double *dt_e) {
+    if (!p || !dt_e) return PF_EINVAL;
+    pf_sim meta;
+    if (pf_status rc = init_meta(&meta, p)) return rc;
+    *dt_e = stable_dt(&meta);
+    return PF_OK;
+}
+
+pf_status pf_rkl_stage_count(pf_integrator integ, double dt, double dt_e, int *ns) {
+    if (!ns || (integ != PF_RKL1 && integ != PF_RKL2)) return PF_EINVAL;
+    const int v = stage_count(integ == PF_RKL1 ? 1 : 2, dt, dt_e);
+    if (v < 0) return PF_EINVAL;
+    *ns = v;
+    return PF_OK;
+}
+
+pf_status pf_controller_init(pf_controller *c) {
+    if (!c) return PF_EINVAL;
+    *c = ctrl_initial();
+    return PF_OK;
+}
+
+pf_status pf_controller_update(pf_controller *c, int order, double err, double h, int *accept,
+                               double *h_next) {
+    if (!c || !accept || !h_next || order < 1 || !(h > 0.0)) return PF_EINVAL;
+    bool acc = false;
+    *h_next = ctrl_update(*c, order, err, h, acc);
+    *accept = acc ? 1 : 0;
+    return PF_OK;
+}
+
+int pf_clip_step(double t, double t_end, double h, double *h_use, int *last) {
+    if (!h_use || !last || !(h > 0.0)) return -1;
+    bool l = false;
+    double hu = 0.0;
+    if (!clip_step(t, t_end, h, hu, l)) return 0;
+    *h_use = hu;
+    *last = l ? 1 : 0;
+    return 1;
+}
+
 const char *pf_last_error(const pf_sim *s) { return s ? s->err.c_str() : "null handle"; }
 
 }  // extern "C"
@@ -1295,14 +1341,9 @@ pf_status batch_plan(pf_batch *b, const double *t_end, const double *dt, int &ma
         double hlast = h0;
         bool clipped = false;
         for (;;) {
-            const double rem = t_end[i] - t;
-            if (rem <= 1e-12 * h0) break;
-            double h = h0;
-            bool last = false;
-            if (rem <= h * (1.0 + 1e-10)) {
-                h = rem;
-                last = true;
-            }
+            double h;
+            bool last;
+            if (!clip_step(t, t_end[i], h0, h, last)) break;
             ++nst;
             if (nst > 100000000) return bfail(b, PF_EINVAL, "instance %d: too many steps", i);
             if (last) {
