@@ -132,7 +132,8 @@ def batch_bench(args):
     """96 independent shrinking-grain instances (side 64..512 by seed, R in
     [0.2, 0.4] side, M in [0.5, 2]): 2000 forward-Euler steps each at 0.9 dt_e,
     as one fused launch per step replayed from a hipGraph in FP32, against the
-    plain FP64 form run instance by instance."""
+    plain FP64 form run instance by instance; then the same end times with
+    batched RKL2 steps of --rkl2-dte dt_e."""
     import torch
     import paper_2601_16522_amd as pf
     import pf_inputs as pi
@@ -179,6 +180,21 @@ def batch_bench(args):
         print(f"# batch step {k}: {el * 1e3:.2f} ms", file=sys.stderr, flush=True)
     err32 = [area_slope_error(w.u0, b.get_fields(i)[0], t_end[i], w.mob[0]) for i, w in enumerate(wls)]
 
+    # the same end times with batched RKL2 steps of args.rkl2_dte dt_e (eq. sts)
+    dts_rkl2 = [args.rkl2_dte / 0.9 * d for d in dts]
+    rkl2_ms, rkl2_rhs = [], 0
+    for k in range(max(args.steps, 1) + 1):
+        for i, w in enumerate(wls):
+            b.init_fields(i, w.u0)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        st_r = b.run_to(t_end, dt=dts_rkl2, graph_steps=10, integ="rkl2")
+        stream.synchronize()
+        if k > 0:  # the first run captures the graph
+            rkl2_ms.append((time.perf_counter() - t0) * 1e3)
+        rkl2_rhs = sum(x.rhs_evals for x in st_r)
+    err_rkl2 = [area_slope_error(w.u0, b.get_fields(i)[0], t_end[i], w.mob[0]) for i, w in enumerate(wls)]
+
     # the plain FP64 form, instance by instance (one launch per step each)
     t64 = 0.0
     err64 = []
@@ -217,7 +233,11 @@ def batch_bench(args):
                    "fusion_depth": depth,
                    "state_GBs_per_step": round(2 * F * E * cells / (avg_s / depth) / 1e9, 1),
                    "time_to_solution_ms": round(total / args.steps * 1e3, 3),
-                   "area_rate_rel_error_fp32_batch_mean": float(np.mean(err32))},
+                   "area_rate_rel_error_fp32_batch_mean": float(np.mean(err32)),
+                   "rkl2_batch": {"step_dt_e": args.rkl2_dte, "rhs_evals": int(rkl2_rhs),
+                                  "time_to_solution_ms": round(float(np.mean(rkl2_ms)), 3),
+                                  "speedup_vs_fe_batch": round(total / args.steps * 1e3 / float(np.mean(rkl2_ms)), 2),
+                                  "area_rate_rel_error_mean": float(np.mean(err_rkl2))}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": f"batch_euler_kernel (depth {depth}), avg {avg_s * 1e6:.2f} us per launch "
@@ -251,6 +271,8 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB")
     ap.add_argument("--blocks", type=int, default=0,
                     help="batch: persistent grid size (skips the block-count autotuner)")
+    ap.add_argument("--rkl2-dte", type=float, default=50.0,
+                    help="batch: RKL2 step in units of dt_e for the RKL2 comparison")
     ap.add_argument("--fusion", type=int, default=0, choices=[0, 1, 2],
                     help="batch: steps per launch (0: the autotuner's choice)")
     ap.add_argument("--graph-steps", type=int, default=50,

@@ -253,11 +253,16 @@ pf_status pf_batch_set_stream(pf_batch *b, void *hip_stream);
 pf_status pf_batch_init_fields(pf_batch *b, int i, const double *u, double t0);
 pf_status pf_batch_get_fields(pf_batch *b, int i, double *u, double *t);
 pf_status pf_batch_stable_dt(pf_batch *b, int i, double *dt_e);
-/* Forward-Euler steps of every instance to its t_end[i] (steps dt[i], or
- * 0.9 dt_e of the instance when dt == NULL; the last step is clipped exactly
- * as pf_run_to clips it, so each instance takes the steps of its own
- * single-instance run).  graph_steps > 0 replays a graph of that many steps;
- * 0 launches every step directly.  stats (optional) is [n]. */
+/* Fixed steps of every instance to its t_end[i] (steps dt[i], or 0.9 dt_e of
+ * the instance when dt == NULL; the last step is clipped exactly as pf_run_to
+ * clips it, so each instance takes the steps of its own single-instance run).
+ * integ: PF_FEULER, or PF_RKL2 (eq. sts; each instance with its own stage
+ * count per step, eq. sts-limit, and its coefficients from a device table; a
+ * step is one launch per stage over all instances whose step has that stage;
+ * the RKL2 ring, R0 and the table are allocated on the first RKL2 run and
+ * kept); others return PF_EUNSUPPORTED.  graph_steps > 0 replays a graph of
+ * that many launches (forward Euler) or steps (RKL2); 0 launches directly.
+ * stats (optional) is [n]. */
 pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
                           const double *dt, int graph_steps, pf_stats *stats);
 /* Times one launch for each persistent grid size (512..8192 blocks) and each

@@ -316,7 +316,9 @@ class Batch:
         self._chk(self._L.pf_batch_stable_dt(self._h, i, C.byref(v)))
         return v.value
 
-    def run_to(self, t_end, dt=None, graph_steps: int = 0):
+    def run_to(self, t_end, dt=None, graph_steps: int = 0, integ: str = "fe"):
+        """Fixed steps of every instance to its t_end (integ "fe" or "rkl2");
+        dt per instance or None (0.9 dt_e each)."""
         te = np.ascontiguousarray(t_end, dtype=np.float64)
         if te.size != self.n:
             raise ValueError("t_end needs one value per instance")
@@ -324,7 +326,7 @@ class Batch:
         if dtv is not None and dtv.size != self.n:
             raise ValueError("dt needs one value per instance")
         st = (_Stats * self.n)()
-        self._chk(self._L.pf_batch_run_to(self._h, PF_FEULER, _dp(te),
+        self._chk(self._L.pf_batch_run_to(self._h, INTEGRATORS[integ], _dp(te),
                                           _dp(dtv) if dtv is not None else None,
                                           int(graph_steps), st))
         return [Stats(*[getattr(x, f) for f, _ in _Stats._fields_]) for x in st]

@@ -1262,6 +1262,13 @@ struct pf_batch {
     std::vector<int> ntx, nty, tile0;
     int total_tiles = 0;
     void *bufA = nullptr, *bufB = nullptr;
+    // RKL2 runs: ring slots (bufB is the first), the slot-0 store and R0,
+    // allocated on the first RKL2 run; the stage coefficient table
+    void *bufQ2 = nullptr, *bufS0 = nullptr, *bufR0 = nullptr;
+    void *dcoef = nullptr;
+    size_t coef_bytes = 0;
+    int coef_stride = 0;  // stages + 1 of the longest step
+    int integ = PF_FEULER;  // integrator of the current run
     void *dparams = nullptr, *dinst = nullptr;
     int *dtile = nullptr, *dstep = nullptr;
     std::vector<double> t;
@@ -1272,7 +1279,7 @@ struct pf_batch {
     int depth = 1;                 // steps per batched launch (stage-fusion depth)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    int graph_k = 0, graph_depth = 0, graph_blocks = 0;
+    int graph_k = 0, graph_depth = 0, graph_blocks = 0, graph_integ = -1, graph_stages = 0;
     std::string err;
 };
 
@@ -1309,6 +1316,39 @@ BatchArgs<T> batch_args(pf_batch *b, int offset, int depth) {
     B.step_offset = offset;
     B.total_tiles = b->total_tiles;
     B.depth = depth;
+    B.kind = K_EULER;
+    B.stage = 0;
+    for (int v = 0; v < 6; ++v) B.role[v] = nullptr;
+    B.state = (T *)b->bufA;
+    B.coef = (const T *)b->dcoef;
+    B.coef_stride = b->coef_stride;
+    return B;
+}
+
+// Arguments of stage j (1..) of an RKL2 step of the batch (step offset k): the
+// buffer roles of the single-instance scheme (u^{n,0} = state A, R0, and the
+// ring of three stage slots whose slot 0 is u^{n,0} until stage 3 overwrites
+// it from a store of its own).
+template <typename T>
+BatchArgs<T> batch_rkl2_args(pf_batch *b, int k, int j) {
+    BatchArgs<T> B = batch_args<T>(b, k, 1);
+    T *U = (T *)b->bufA, *W0 = (T *)b->bufB, *W1 = (T *)b->bufQ2, *S0 = (T *)b->bufS0,
+      *R0 = (T *)b->bufR0;
+    B.stage = j;
+    if (j == 1) {
+        B.kind = K_RKL2_FIRST;
+        B.role[0] = U;
+        B.role[4] = W0;
+        B.role[5] = R0;
+        return B;
+    }
+    T *slot[3] = {j >= 3 ? S0 : U, W0, W1};
+    B.kind = K_RKL2;
+    B.role[0] = slot[(j - 1) % 3];
+    B.role[1] = slot[(j - 2) % 3];
+    B.role[2] = U;
+    B.role[3] = R0;
+    B.role[4] = slot[j % 3];
     return B;
 }
 
@@ -1330,11 +1370,16 @@ pf_status batch_setup_params(pf_batch *b) {
 // pf_run_to (full steps of dt, the last one landing on t_end), so every
 // instance takes bit for bit the steps a single-instance run would take.
 template <typename T>
-pf_status batch_plan(pf_batch *b, const double *t_end, const double *dt, int &max_steps) {
+pf_status batch_plan(pf_batch *b, const double *t_end, const double *dt, int &max_steps,
+                     int &max_stages) {
     std::vector<BatchInst<T>> I(b->n);
+    std::vector<double> hfull(b->n), hclip(b->n);  // step sizes in double
     max_steps = 0;
+    max_stages = 1;
+    const bool rkl2 = b->integ == PF_RKL2;
     for (int i = 0; i < b->n; ++i) {
-        const double h0 = dt ? dt[i] : 0.9 * stable_dt(&b->meta[i]);
+        const double dte = stable_dt(&b->meta[i]);
+        const double h0 = dt ? dt[i] : 0.9 * dte;
         if (!(h0 > 0.0)) return bfail(b, PF_EINVAL, "instance %d: dt must be > 0", i);
         double t = b->t[i];
         long long nst = 0;
@@ -1360,20 +1405,69 @@ pf_status batch_plan(pf_batch *b, const double *t_end, const double *dt, int &ma
         I[i].nfull = (int)(clipped ? nst - 1 : nst);
         I[i].dt = (T)h0;
         I[i].dt_last = (T)hlast;
+        hfull[i] = h0;
+        hclip[i] = hlast;
+        I[i].s_full = rkl2 ? stage_count(2, h0, dte) : 1;
+        I[i].s_last = rkl2 ? stage_count(2, hlast, dte) : 1;
+        if (I[i].s_full < 0 || I[i].s_last < 0) return bfail(b, PF_EINVAL, "instance %d: bad dt", i);
         max_steps = std::max(max_steps, (int)nst);
+        if (nst > 0) max_stages = std::max(max_stages, std::max(I[i].s_full, I[i].s_last));
+    }
+    if (rkl2) {
+        // coefficients exactly as the single-instance step passes them
+        b->coef_stride = max_stages + 1;
+        std::vector<T> cf((size_t)b->n * 2 * b->coef_stride * 6, T(0));
+        for (int i = 0; i < b->n; ++i)
+            for (int c = 0; c < 2; ++c) {
+                const int ns = c ? I[i].s_last : I[i].s_full;
+                const double hd = c ? hclip[i] : hfull[i];
+                for (int j = 1; j <= ns; ++j) {
+                    double mu, nu, mut, gam;
+                    rkl_coeffs(2, ns, j, mu, nu, mut, gam);
+                    T *e = &cf[((size_t)(2 * i + c) * b->coef_stride + j) * 6];
+                    if (j == 1) {
+                        e[0] = (T)(mut * hd);
+                    } else {
+                        e[0] = (T)((1.0 - mu) - nu);
+                        e[1] = (T)mu;
+                        e[2] = (T)nu;
+                        e[3] = (T)hd;
+                        e[4] = (T)mut;
+                        e[5] = (T)gam;
+                    }
+                }
+            }
+        const size_t bytes = cf.size() * sizeof(T);
+        if (bytes > b->coef_bytes) {
+            if (b->dcoef) hipFree(b->dcoef);
+            b->dcoef = nullptr;
+            b->coef_bytes = 0;
+            BHIPCHK(b, hipMalloc(&b->dcoef, bytes));
+            b->coef_bytes = bytes;
+        }
+        BHIPCHK(b, hipMemcpyAsync(b->dcoef, cf.data(), bytes, hipMemcpyHostToDevice, b->stream));
+        BHIPCHK(b, hipStreamSynchronize(b->stream));  // cf is a local
     }
     BHIPCHK(b, hipMemcpyAsync(b->dinst, I.data(), sizeof(BatchInst<T>) * b->n, hipMemcpyHostToDevice,
                               b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));  // I is a local
     return PF_OK;
 }
 
-// k batched launches of b->depth steps each (launch j covers the steps from
-// the device counter + j * depth on) and one counter update by k * depth.
+// k batched launches (forward Euler: b->depth steps each, launch j covering the
+// steps from the device counter + j * depth on; RKL2: one step of `stages`
+// stage launches each) and one counter update by the steps taken.
 template <typename T>
-pf_status batch_launch_steps(pf_batch *b, int k) {
-    const int d = b->depth;
+pf_status batch_launch_steps(pf_batch *b, int k, int stages) {
+    const int d = b->integ == PF_RKL2 ? 1 : b->depth;
     for (int j = 0; j < k; ++j) {
-        hipError_t e = launch_batch_euler<T>(b->N, batch_args<T>(b, j * d, d), b->nblocks, b->stream);
+        hipError_t e = hipSuccess;
+        if (b->integ == PF_RKL2) {
+            for (int st = 1; st <= stages && e == hipSuccess; ++st)
+                e = launch_batch_euler<T>(b->N, batch_rkl2_args<T>(b, j, st), b->nblocks, b->stream);
+        } else {
+            e = launch_batch_euler<T>(b->N, batch_args<T>(b, j * d, d), b->nblocks, b->stream);
+        }
         if (e != hipSuccess) return bfail(b, PF_EHIP, "batch launch: %s", hipGetErrorString(e));
     }
     BHIPCHK(b, launch_batch_tick(b->dstep, k * d, b->stream));
@@ -1382,10 +1476,12 @@ pf_status batch_launch_steps(pf_batch *b, int k) {
 
 // k launches (and one counter update) captured once into a hipGraph and
 // replayed; the graph holds kernel nodes only.  A change of k, of the fusion
-// depth or of the grid size re-captures it.
+// depth, of the grid size, of the integrator or of the stage count re-captures
+// it (the buffers and the coefficient table it refers to stay allocated).
 template <typename T>
-pf_status batch_graph(pf_batch *b, int k) {
-    if (b->gexec && b->graph_k == k && b->graph_depth == b->depth && b->graph_blocks == b->nblocks)
+pf_status batch_graph(pf_batch *b, int k, int stages) {
+    if (b->gexec && b->graph_k == k && b->graph_depth == b->depth && b->graph_blocks == b->nblocks &&
+        b->graph_integ == b->integ && b->graph_stages == stages)
         return PF_OK;
     if (b->gexec) {
         hipGraphExecDestroy(b->gexec);
@@ -1394,7 +1490,7 @@ pf_status batch_graph(pf_batch *b, int k) {
         b->graph = nullptr;
     }
     BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    pf_status rc = batch_launch_steps<T>(b, k);
+    pf_status rc = batch_launch_steps<T>(b, k, stages);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc) {
@@ -1411,42 +1507,65 @@ pf_status batch_graph(pf_batch *b, int k) {
     b->graph_k = k;
     b->graph_depth = b->depth;
     b->graph_blocks = b->nblocks;
+    b->graph_integ = b->integ;
+    b->graph_stages = stages;
     return PF_OK;
 }
 
 template <typename T>
-pf_status batch_run(pf_batch *b, const double *t_end, const double *dt, int graph_k,
+pf_status batch_rkl2_buffers(pf_batch *b) {
+    void **bufs[3] = {&b->bufQ2, &b->bufS0, &b->bufR0};
+    for (void **q : bufs)
+        if (!*q) {
+            if (hipMalloc(q, b->total * b->esz) != hipSuccess) {
+                *q = nullptr;
+                return bfail(b, PF_ENOMEM, "batch RKL2 buffers");
+            }
+            BHIPCHK(b, hipMemset(*q, 0, b->total * b->esz));
+        }
+    return PF_OK;
+}
+
+template <typename T>
+pf_status batch_run(pf_batch *b, int integ, const double *t_end, const double *dt, int graph_k,
                     pf_stats *stats) {
-    int S = 0;
-    pf_status rc = batch_plan<T>(b, t_end, dt, S);
+    pf_status rc;
+    if (integ == PF_RKL2 && (rc = batch_rkl2_buffers<T>(b))) return rc;
+    b->integ = integ;
+    int S = 0, stages = 1;
+    rc = batch_plan<T>(b, t_end, dt, S, stages);
     if (rc) return rc;
     const int zero = 0;
     BHIPCHK(b, hipMemcpyAsync(b->dstep, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
-    const int d = b->depth;
+    const bool rkl2 = integ == PF_RKL2;
+    const int d = rkl2 ? 1 : b->depth;
     const int launches = (S + d - 1) / d;
     int done = 0;
     if (graph_k > 0 && launches >= graph_k) {
-        if ((rc = batch_graph<T>(b, graph_k))) return rc;
+        if ((rc = batch_graph<T>(b, graph_k, stages))) return rc;
         for (; done + graph_k <= launches; done += graph_k)
             BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
     }
-    if (launches - done > 0 && (rc = batch_launch_steps<T>(b, launches - done))) return rc;
-    // an instance that took part in an odd number of launches ends in buffer B:
-    // copy it back
+    if (launches - done > 0 && (rc = batch_launch_steps<T>(b, launches - done, stages))) return rc;
+    // forward Euler: an instance that took part in an odd number of launches
+    // ends in buffer B, copied back; RKL2 steps end in the state buffer
     std::vector<BatchInst<T>> I(b->n);
     BHIPCHK(b, hipMemcpyAsync(I.data(), b->dinst, sizeof(BatchInst<T>) * b->n, hipMemcpyDeviceToHost,
                               b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     for (int i = 0; i < b->n; ++i) {
         const size_t bytes = (size_t)b->meta[i].F * b->meta[i].V * b->esz;
-        if (((I[i].nsteps + d - 1) / d) & 1)
+        if (!rkl2 && (((I[i].nsteps + d - 1) / d) & 1))
             BHIPCHK(b, hipMemcpyAsync((char *)b->bufA + b->off[i] * b->esz,
                                       (char *)b->bufB + b->off[i] * b->esz, bytes,
                                       hipMemcpyDeviceToDevice, b->stream));
         if (I[i].nsteps > 0) b->t[i] = t_end[i];
         if (stats) {
+            const long long nf = I[i].nfull, nc = I[i].nsteps - I[i].nfull;
             stats[i] = pf_stats{};
-            stats[i].rhs_evals = stats[i].stages = stats[i].accepted = I[i].nsteps;
+            stats[i].accepted = I[i].nsteps;
+            stats[i].rhs_evals = stats[i].stages =
+                rkl2 ? nf * I[i].s_full + nc * I[i].s_last : I[i].nsteps;
             stats[i].t = b->t[i];
             stats[i].last_dt = I[i].nsteps ? (double)(I[i].nfull < I[i].nsteps ? I[i].dt_last : I[i].dt) : 0.0;
         }
@@ -1465,8 +1584,9 @@ pf_status batch_autotune(pf_batch *b, int *best_blocks, double *best_ms) {
         dt[i] = 0.9 * stable_dt(&b->meta[i]);
         t_end[i] = b->t[i] + 2.0 * dt[i];
     }
-    int S = 0;
-    pf_status rc = batch_plan<T>(b, t_end.data(), dt.data(), S);
+    int S = 0, stages = 1;
+    b->integ = PF_FEULER;
+    pf_status rc = batch_plan<T>(b, t_end.data(), dt.data(), S, stages);
     if (rc) return rc;
     const int cands[5] = {512, 1024, 2048, 4096, 8192};
     hipEvent_t e0, e1;
@@ -1515,7 +1635,8 @@ pf_status pf_batch_destroy(pf_batch *b) {
     if (b->stream) hipStreamSynchronize(b->stream);
     if (b->gexec) hipGraphExecDestroy(b->gexec);
     if (b->graph) hipGraphDestroy(b->graph);
-    void *ptrs[6] = {b->bufA, b->bufB, b->dparams, b->dinst, b->dtile, b->dstep};
+    void *ptrs[10] = {b->bufA, b->bufB, b->dparams, b->dinst, b->dtile, b->dstep,
+                      b->bufQ2, b->bufS0, b->bufR0, b->dcoef};
     for (void *q : ptrs)
         if (q) hipFree(q);
     if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
@@ -1650,11 +1771,12 @@ pf_status pf_batch_stable_dt(pf_batch *b, int i, double *dte) {
 pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end, const double *dt,
                           int graph_steps, pf_stats *stats) {
     if (!b || !t_end || graph_steps < 0) return PF_EINVAL;
-    if (integ != PF_FEULER) return bfail(b, PF_EUNSUPPORTED, "the batch advances forward Euler steps");
+    if (integ != PF_FEULER && integ != PF_RKL2)
+        return bfail(b, PF_EUNSUPPORTED, "the batch advances forward Euler or RKL2 steps");
     for (int i = 0; i < b->n; ++i)
         if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
-    return b->prec == PF_FP64 ? batch_run<double>(b, t_end, dt, graph_steps, stats)
-                              : batch_run<float>(b, t_end, dt, graph_steps, stats);
+    return b->prec == PF_FP64 ? batch_run<double>(b, integ, t_end, dt, graph_steps, stats)
+                              : batch_run<float>(b, integ, t_end, dt, graph_steps, stats);
 }
 
 pf_status pf_batch_autotune(pf_batch *b, int *nblocks, double *best_ms) {

@@ -131,6 +131,7 @@ struct BatchInst {
     int tile0;         // first global tile of the instance
     int nsteps;        // steps of the current run (the last one possibly clipped)
     int nfull;         // steps of size dt; step nfull (if < nsteps) uses dt_last
+    int s_full, s_last;  // RKL stage counts of a full and of the clipped step
     T dt, dt_last;
 };
 
@@ -156,6 +157,17 @@ struct BatchArgs {
     int step_offset;             // step = *step_base + step_offset
     int total_tiles;
     int depth;                   // steps per launch (stage-fusion depth): 1 or 2
+    // multi-stage (RKL2) launches: stage index j of the step, the base pointers
+    // of the stage's vectors by role (y1, y2, u0, r0, out, out2; null when
+    // unused), the state vector (an instance's last stage writes its result
+    // there), and the stage coefficients a..f per (instance, full / clipped
+    // step, stage): coef[((2 i + clipped) * coef_stride + j) * 6 + 0..5]
+    int kind;                    // K_EULER (forward Euler), K_RKL2_FIRST or K_RKL2
+    int stage;
+    const T *role[6];
+    T *state;
+    const T *coef;
+    int coef_stride;
 };
 
 // Launchers (implemented in pf_kernels.hip).  Return hipSuccess or the launch

@@ -763,19 +763,24 @@ constexpr int batch_lds_elems() {
     return DEPTH == 1 ? lds_elems<T, N>() : (N + 3) * (F2_IN + F2_MID);
 }
 
-// Batched forward Euler over many independent 2D instances, DEPTH steps per
-// launch: a persistent grid splits the global tile list (tiles of all
-// instances, one instance after the other) into one contiguous range per
-// block.  A block loads an instance's constants, state offset and step sizes,
-// and stages its LDS tables, when its walk enters that instance, so one launch
-// advances every instance by DEPTH steps (fewer at the end of its run).  An
-// instance whose run is complete is skipped.  Launch j reads buffer A when j is
-// even and B when odd (j = first step / DEPTH).
-template <typename T, int N, int DEPTH>
-__global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) {
+// Batched stages over many independent 2D instances.  A persistent grid splits
+// the global tile list (tiles of all instances, one instance after the other)
+// into one contiguous range per block.  A block loads an instance's constants,
+// state offset and step data, and stages its LDS tables, when its walk enters
+// that instance; an instance whose run (or whose step's stages) is complete is
+// skipped.
+// KIND == K_EULER: forward Euler, DEPTH steps per launch; launch j reads buffer
+// A when j is even and B when odd (j = first step / DEPTH).
+// KIND == K_RKL2_FIRST / K_RKL2: stage B.stage of one RKL2 step (eq. sts) of
+// every instance, with the instance's stage count and coefficients for a full
+// or for its clipped last step; the vectors come by role, and an instance's
+// last stage writes the state vector.
+template <typename T, int N, int KIND, int DEPTH>
+__global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
     __shared__ T lds[batch_lds_elems<T, N, DEPTH>()];
     __shared__ T pair[3 * N * N];
     __shared__ T kc[4 * N];
+    constexpr bool RKL = KIND != K_EULER;
     const int step = *B.step_base + B.step_offset;
     const long long L = xcd_logical_block();
     const int g0 = (int)(L * B.total_tiles / gridDim.x);
@@ -792,11 +797,11 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
             const BatchInst<T> &I = B.inst[i];
             tile0 = I.tile0;
             end = tile0 + I.ntx * I.nty;
-            if (step >= I.nsteps) {  // this instance's run is complete
-                g = end - 1;
+            const bool clipped = step >= I.nfull;
+            if (step >= I.nsteps || (RKL && B.stage > (clipped ? I.s_last : I.s_full))) {
+                g = end - 1;  // nothing to do for this instance
                 continue;
             }
-            const bool even = ((step / DEPTH) & 1) == 0;
             const DevParams<T> &Q = B.params[i];
             A.K.nx = Q.nx; A.K.ny = Q.ny; A.K.nz = Q.nz;
             A.K.with_c = Q.with_c; A.K.n_types = Q.n_types; A.K.uniform = Q.uniform;
@@ -806,18 +811,37 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
                 A.K.c0[a] = Q.c0[a]; A.K.ik[a] = Q.ik[a]; A.K.Dk[a] = Q.Dk[a];
                 A.K.hik[a] = Q.hik[a]; A.K.k2[a] = Q.k2[a];
             }
-            A.y1 = (even ? B.bufA : B.bufB) + I.off;
-            A.out = (even ? B.bufB : B.bufA) + I.off;
+            if constexpr (!RKL) {
+                const bool even = ((step / DEPTH) & 1) == 0;
+                A.y1 = (even ? B.bufA : B.bufB) + I.off;
+                A.out = (even ? B.bufB : B.bufA) + I.off;
+                A.a = step < I.nfull ? I.dt : I.dt_last;
+                dt2 = step + 1 < I.nfull ? I.dt : I.dt_last;
+                two = DEPTH == 2 && step + 1 < I.nsteps;
+            } else {
+                const int si = clipped ? I.s_last : I.s_full;
+                const T *cf = B.coef + ((size_t)(2 * i + (clipped ? 1 : 0)) * B.coef_stride + B.stage) * 6;
+                A.a = cf[0]; A.b = cf[1]; A.c = cf[2]; A.d = cf[3]; A.e = cf[4]; A.f = cf[5];
+                const T *r[6];
+#pragma unroll
+                for (int v = 0; v < 6; ++v) r[v] = B.role[v] ? B.role[v] + I.off : nullptr;
+                A.y1 = r[0]; A.y2 = r[1]; A.u0 = r[2]; A.r0 = r[3];
+                // the step's last stage writes the instance's state (it reads the
+                // state only at its own cell, as u0, before writing it)
+                A.out = B.stage == si ? B.state + I.off : const_cast<T *>(r[4]);
+                A.out2 = const_cast<T *>(r[5]);
+                A.gb[1][0] = A.y2;
+                A.gb[2][0] = A.u0;
+                A.gb[3][0] = A.r0;
+                A.gb[5][0] = A.out2;
+            }
             // one buffer group per vector: the host admits only instances whose
             // state spans less than 4 GiB
             A.ng = 1;
             A.plane_bytes = (unsigned)(A.K.V * (long long)sizeof(T));
             A.gb[0][0] = A.y1;
             A.gb[4][0] = A.out;
-            A.kind = K_EULER;
-            A.a = step < I.nfull ? I.dt : I.dt_last;
-            dt2 = step + 1 < I.nfull ? I.dt : I.dt_last;
-            two = DEPTH == 2 && step + 1 < I.nsteps;
+            A.kind = KIND;
             A.tx = TILE_X;
             A.ty = TILE_Y;
             A.zchunk = 1;
@@ -829,20 +853,27 @@ __global__ void __launch_bounds__(256) batch_euler_kernel(const BatchArgs<T> B) 
             stage_tables<T, N>(B.params + i, pair, kc);
             __syncthreads();
         }
-        if constexpr (DEPTH == 1)
-            stage_body<T, 2, N, K_EULER, N + 1, false>(A, g - tile0, lds, pair, kc);
-        else
+        if constexpr (KIND == K_EULER && DEPTH == 2)
             euler2_tile<T, N>(A, g - tile0, lds, lds + (N + 3) * F2_IN, pair, kc, A.a, dt2, two);
+        else
+            stage_body<T, 2, N, KIND, N + 1, false>(A, g - tile0, lds, pair, kc);
     }
 }
 
 template <typename T, int N>
 hipError_t launch_batch_euler_n(const BatchArgs<T> &B, int nblocks, hipStream_t stream) {
-    if (B.depth == 1) {
-        hipLaunchKernelGGL((batch_euler_kernel<T, N, 1>), dim3(nblocks), dim3(256), 0, stream, B);
+    const dim3 grid(nblocks), block(256);
+    if (B.kind == K_RKL2_FIRST) {
+        hipLaunchKernelGGL((batch_kernel<T, N, K_RKL2_FIRST, 1>), grid, block, 0, stream, B);
+    } else if (B.kind == K_RKL2) {
+        hipLaunchKernelGGL((batch_kernel<T, N, K_RKL2, 1>), grid, block, 0, stream, B);
+    } else if (B.kind != K_EULER) {
+        return hipErrorInvalidValue;
+    } else if (B.depth == 1) {
+        hipLaunchKernelGGL((batch_kernel<T, N, K_EULER, 1>), grid, block, 0, stream, B);
     } else if (B.depth == 2) {
         if constexpr (batch_depth2_fits(sizeof(T), N))
-            hipLaunchKernelGGL((batch_euler_kernel<T, N, 2>), dim3(nblocks), dim3(256), 0, stream, B);
+            hipLaunchKernelGGL((batch_kernel<T, N, K_EULER, 2>), grid, block, 0, stream, B);
         else
             return hipErrorInvalidValue;
     } else {

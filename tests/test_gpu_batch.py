@@ -137,3 +137,55 @@ def test_batch_rejects_mixed_instances():
     c = dict(pi.voronoi_2d(n=40, n_grains=4, n_phi=3, dmin=5.0).param_dict())
     with pytest.raises(pf.PFError):
         pf.Batch([a, c])
+
+
+@pytest.mark.parametrize("prec,blocks,graph", [("fp32", None, 2), ("fp64", None, 0), ("fp32", 8, 3),
+                                               ("fp64", 16, 2)])
+def test_batch_rkl2_equals_single_runs_bitwise(prec, blocks, graph):
+    """RKL2 steps of 20 dt_e (eq. sts; 11 stages) with uneven step counts and
+    clipped last steps whose stage count differs: every instance equals its
+    single-instance run bit for bit, stage counts included."""
+    wls = small_batch()
+    b = pf.Batch([w.param_dict() for w in wls], prec=prec)
+    if blocks is not None:
+        b.set_blocks(blocks)
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    dts = [20.0 * b.stable_dt(i) for i in range(len(wls))]
+    t_end = [dts[i] * (2 + i) + 0.15 * dts[i] * (i % 2) for i in range(len(wls))]
+    st = b.run_to(t_end, dt=dts, graph_steps=graph, integ="rkl2")
+    for i, w in enumerate(wls):
+        u_b, t_b = b.get_fields(i)
+        s = pf.Sim(w.param_dict(), prec=prec)
+        s.init_fields(w.u0)
+        st1 = s.run_to("rkl2", t_end[i], dt_fixed=dts[i])
+        u_s, t_s = s.get_fields()
+        assert (st[i].accepted, st[i].rhs_evals) == (st1.accepted, st1.rhs_evals), i
+        assert t_b == t_s == t_end[i]
+        assert np.array_equal(u_b, u_s), (i, np.abs(u_b - u_s).max())
+        s.close()
+    # a second run continues from the reached state (ring and table reused)
+    t2 = [t + 2.5 * d for t, d in zip(t_end, dts)]
+    b.run_to(t2, dt=dts, graph_steps=graph, integ="rkl2")
+    for i, w in enumerate(wls[:2]):
+        s = pf.Sim(w.param_dict(), prec=prec)
+        s.init_fields(w.u0)
+        s.run_to("rkl2", t_end[i], dt_fixed=dts[i])
+        s.run_to("rkl2", t2[i], dt_fixed=dts[i])
+        assert np.array_equal(b.get_fields(i)[0], s.get_fields()[0]), i
+        s.close()
+
+
+def test_batch_rkl2_fp64_matches_oracle():
+    wls = small_batch()[:3]
+    b = pf.Batch([w.param_dict() for w in wls], prec="fp64")
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    dts = [25.0 * b.stable_dt(i) for i in range(len(wls))]
+    t_end = [3.4 * d for d in dts]
+    b.run_to(t_end, dt=dts, graph_steps=2, integ="rkl2")
+    for i, w in enumerate(wls):
+        P = oracle.Params(**w.param_dict())
+        ref, st, rc = oracle.run_to(P, oracle.RKL2, w.u0, t_end[i], dt_fixed=dts[i])
+        assert rc == 0
+        assert np.abs(b.get_fields(i)[0] - ref).max() <= 1e-10, i

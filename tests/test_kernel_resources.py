@@ -63,7 +63,8 @@ def test_stage_kernels_do_not_spill(tmp_path):
             assert r.get("VGPRs Spill", 0) == 0, (n, g, k, r)
             if "IfLi" in k:  # single precision: no SGPR spills either
                 assert r.get("SGPRs Spill", 0) == 0, (n, g, k, r)
-        # batch kernels (built with one group): depth 1 in both precisions,
-        # depth 2 where its LDS fits (FP32 for every N, FP64 only up to N = 4)
-        batch = [k for k in names if "batch_euler_kernel" in k]
-        assert len(batch) == (3 if g == 1 else 0), (n, g, batch)
+        # batch kernels (built with one group), per precision: forward Euler at
+        # depth 1, the two RKL2 stage kinds, and forward Euler at depth 2 where
+        # its LDS fits (FP32 for every N, FP64 only up to N = 4)
+        batch = [k for k in names if "batch_kernel" in k]
+        assert len(batch) == (7 if g == 1 else 0), (n, g, batch)
