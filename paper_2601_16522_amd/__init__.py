@@ -70,12 +70,12 @@ class _Stats(C.Structure):
                 ("t", C.c_double), ("last_dt", C.c_double), ("last_err", C.c_double)]
 
 
-@dataclass
 class _Controller(C.Structure):
     _fields_ = [("b", C.c_double), ("nhist", C.c_int), ("E1", C.c_double), ("E2", C.c_double),
                 ("h1", C.c_double), ("h2", C.c_double)]
 
 
+@dataclass
 class Tol:
     r_phi: float = 1e-4
     a_phi: float = 1e-2

@@ -161,6 +161,46 @@ def test_adaptive_run_fp64_matches_oracle_trace(integ):
     check_fp64(wl, u, ref, integ)
 
 
+@pytest.mark.parametrize("integ,tolv,tmul", [("rkl2", 1e-5, 1000.0), ("ssp2", 1e-4, 60.0)])
+def test_adaptive_3d_pores_fp64_matches_oracle_trace(integ, tolv, tmul):
+    """The sintering geometry (12 grains on 12 fields plus a pore phase of a
+    second type, c = phi_pore; mobile-pore parameters) at 32^3: adaptive RKL2
+    (Sommeijer estimate) and adaptive SSP(3)2 (embedded estimate) against the
+    oracle's trace, then FP32 on the same run by properties."""
+    wl = pi.grains_pores_3d(n=32, n_grains=12, n_grain_fields=12, n_pores=6, r_range=(2.0, 4.0),
+                            dmin=5.0)
+    P = P_of(wl)
+    t_end = tmul * oracle.stable_dt(P)
+    tol = dict(r_phi=tolv, a_phi=tolv, r_c=tolv, a_c=tolv)
+    ref, st_ref, rc = oracle.run_to(P, INTEG[integ], wl.u0, t_end, tol=oracle.Tol(**tol), s=3)
+    assert rc == 0 and st_ref.accepted > 10
+    sim = make(wl, ssp=3)
+    st = sim.run_to(integ, t_end, tol=pf.Tol(**tol))
+    tr = sim.trace()
+    assert tr.shape == st_ref.trace.shape, (tr.shape, st_ref.trace.shape)
+    assert np.array_equal(tr[:, 1], st_ref.trace[:, 1]) and np.array_equal(tr[:, 3], st_ref.trace[:, 3])
+    rel_dt = np.abs(tr[:, 0] / st_ref.trace[:, 0] - 1).max()
+    rel_e = np.abs(tr[:, 2] - st_ref.trace[:, 2]).max() / max(np.abs(st_ref.trace[:, 2]).max(), 1e-300)
+    print(f"\n3D pores {integ}: {len(tr)} attempts, max rel diff dt {rel_dt:.2e}, e {rel_e:.2e}", flush=True)
+    assert rel_dt <= 1e-9 and rel_e <= 1e-8, (rel_dt, rel_e)
+    u, t = sim.get_fields()
+    assert t == t_end
+    check_fp64(wl, u, ref, integ)
+    # FP32 stencil and stages, FP64 step control and sums: reaches t_end with
+    # the pore phase's c conserved and phi on the simplex
+    s32 = make(wl, prec="fp32", ssp=3)
+    c0 = s32.conservation()
+    st32 = s32.run_to(integ, t_end, tol=pf.Tol(**tol))
+    d = s32.diagnostics()
+    u32, t32 = s32.get_fields()
+    print(f"3D pores {integ} FP32: {st32.accepted} accepted / {st32.rejected} rejected (FP64 "
+          f"{st_ref.accepted}), max |dphi| vs oracle {np.abs(u32[:-1] - ref[:-1]).max():.2e}", flush=True)
+    assert t32 == t_end and d["nonfinite"] == 0
+    assert abs(d["sum_c"] - c0) <= 1e-6 * abs(c0)
+    assert d["max_sum_dev"] <= 1e-6 and d["min_phi"] >= 0.0 and d["max_phi"] <= 1.0
+    assert abs(st32.accepted - st_ref.accepted) <= max(2, st_ref.accepted // 10)
+
+
 def test_adaptive_with_outputs_carries_controller():
     wl = pi.single_grain(n=48, R=15.0)
     P = P_of(wl)

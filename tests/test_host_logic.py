@@ -95,3 +95,12 @@ def test_clip_step_matches_oracle_run():
             t = t_end if last else t + h
         assert len(steps) == st.accepted, (n_full, frac)
         assert np.array_equal(np.asarray(steps), st.trace[:, 0]), (n_full, frac)
+
+
+def test_tolerance_marshalling():
+    """pf.Tol keyword construction and its C struct (every adaptive call uses it)."""
+    t = pf.Tol(r_phi=1e-5, a_phi=2e-5, r_c=3e-5, a_c=4e-5, dt_max_over_dte=50.0, dt0=1e-3)
+    c = t._c()
+    assert (c.r_phi, c.a_phi, c.r_c, c.a_c, c.dt_max_over_dte, c.dt0) == (1e-5, 2e-5, 3e-5, 4e-5, 50.0, 1e-3)
+    d = pf.Tol()
+    assert (d.r_phi, d.a_phi, d.r_c, d.a_c) == (1e-4, 1e-2, 1e-4, 1e-4)
