@@ -240,7 +240,7 @@ def batch_bench(args):
                                   "area_rate_rel_error_mean": float(np.mean(err_rkl2))}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"batch_euler_kernel (depth {depth}), avg {avg_s * 1e6:.2f} us per launch "
+                     "kernel": f"batch_kernel (forward Euler, depth {depth}), avg {avg_s * 1e6:.2f} us per launch "
                                f"of {depth} step(s) (HIP events over graph replays), "
                                f"{bytes_per_launch} algorithmic B/launch",
                      "stream_ref_GBs": sref,
