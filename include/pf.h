@@ -227,6 +227,10 @@ pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
  * pf_get_kernel_time synchronises the stream and returns the total ms and the
  * number of launches of a family since timing was enabled. */
 pf_status pf_set_timing(pf_sim *sim, int enable);
+/* The same for a subset of the families (bit f = family f; 0 disables):
+ * events are recorded only around the selected families' launches, so that a
+ * timed run carries no event between the launches of the others. */
+pf_status pf_set_timing_families(pf_sim *sim, unsigned families);
 pf_status pf_get_kernel_time(pf_sim *sim, int family, double *ms, long long *launches);
 
 /* ---------------------------------------------------------------------------

@@ -40,7 +40,7 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_batch_stable_dt", "pf_batch_run_to", "pf_batch_autotune", "pf_batch_set_blocks",
            "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error",
            "pf_params_stable_dt", "pf_rkl_stage_count", "pf_controller_init",
-           "pf_controller_update", "pf_clip_step"]
+           "pf_controller_update", "pf_clip_step", "pf_set_timing_families"]
 
 
 class PFError(RuntimeError):
@@ -135,6 +135,7 @@ def lib():
             "pf_get_tiling": [vp, C.POINTER(i), C.POINTER(i)],
             "pf_autotune": [vp, C.POINTER(i), C.POINTER(i), pd],
             "pf_set_timing": [vp, i],
+            "pf_set_timing_families": [vp, C.c_uint],
             "pf_get_kernel_time": [vp, i, pd, C.POINTER(ll)],
         }
         for name, args in sigs.items():
@@ -522,8 +523,13 @@ class Sim:
         self._chk(self._L.pf_autotune(self._h, C.byref(a), C.byref(b), C.byref(ms)))
         return a.value, b.value, ms.value
 
-    def set_timing(self, on: bool):
-        self._chk(self._L.pf_set_timing(self._h, int(bool(on))))
+    def set_timing(self, on: bool, families=None):
+        """Kernel timing on/off; families: iterable of FAM_* to record only those."""
+        if families is None:
+            self._chk(self._L.pf_set_timing(self._h, int(bool(on))))
+        else:
+            mask = sum(1 << f for f in families) if on else 0
+            self._chk(self._L.pf_set_timing_families(self._h, mask))
 
     def kernel_time(self, family: int):
         ms, n = C.c_double(), C.c_longlong()

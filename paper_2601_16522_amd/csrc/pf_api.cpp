@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -24,6 +25,7 @@ using namespace pf;
 namespace {
 
 constexpr int NBUF = 7;
+constexpr int RES_DIAG = 0, RES_NORM = 8, RES_LEN = 16;
 constexpr double PI = 3.14159265358979323846;
 
 // Controller state (pf_controller of the C-ABI): bias b, accepted-history
@@ -71,8 +73,11 @@ struct pf_sim {
     double *red = nullptr;
     long long *redn = nullptr;
     int red_cap = 0;
-    double *dres = nullptr;
-    double *hres = nullptr;  // pinned
+    // pinned, coherent host memory for scalar results: [RES_DIAG, +5) the
+    // diagnostics, [RES_NORM, +4) the error norm (sum, count, norm, sequence)
+    double *hres = nullptr;
+    double *hres_dev = nullptr;  // the same memory as the device addresses it
+    double res_seq = 0.0;        // sequence number of the last norm result
     double t = 0.0;
     pf_controller ctrl = ctrl_initial();
     double dt_next = 0.0;   // controller proposal carried between pf_run_to calls
@@ -80,6 +85,7 @@ struct pf_sim {
     std::string err;
     int tx = 64, zchunk = 16;
     bool timing = false;
+    unsigned timing_mask = 0;  // families recorded while timing
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     double fam_ms[5] = {0, 0, 0, 0, 0};
@@ -170,8 +176,10 @@ hipEvent_t get_event(pf_sim *s) {
 // family (the inner stages of a step, the stages of a fixed-step run, one
 // estimator launch), not around every launch, so that the events add no gap
 // between the kernels they measure.
-hipEvent_t mark(pf_sim *s) {
-    if (!s->timing) return nullptr;
+// fam: the families whose intervals the event bounds; it is recorded only when
+// one of them is enabled.
+hipEvent_t mark(pf_sim *s, unsigned fam) {
+    if (!s->timing || !(s->timing_mask & fam)) return nullptr;
     hipEvent_t e = get_event(s);
     hipEventRecord(e, s->stream);
     return e;
@@ -186,7 +194,7 @@ void begin_timed(pf_sim *s, unsigned mask, Pending &p) {
     p.mask = mask;
     p.count = 1;
     p.e0 = p.e1 = nullptr;
-    if (!s->timing) return;
+    if (!s->timing || !(s->timing_mask & mask)) return;
     p.e0 = get_event(s);
     p.e1 = get_event(s);
     hipEventRecord(p.e0, s->stream);
@@ -461,6 +469,28 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
 }
 
 // Sommeijer-type estimate (kind 0) or embedded estimate (kind 1) -> norm on host.
+// Waits for the norm kernel's result: it writes the result and then sequence
+// number seq into the coherent host buffer, which is polled here (cheaper than
+// a stream synchronisation for one scalar per adaptive step).  The stream is
+// queried every few thousand polls, so a stream that drains or fails without
+// the number ends the wait with an error instead of a hang.
+pf_status wait_result(pf_sim *s, double seq) {
+    volatile const double *flag = s->hres + RES_NORM + 3;
+    for (unsigned long it = 1;; ++it) {
+        if (*flag == seq) break;
+        if ((it & 4095u) == 0) {
+            const hipError_t q = hipStreamQuery(s->stream);
+            if (q == hipSuccess) {
+                if (*flag == seq) break;
+                return fail(s, PF_EHIP, "norm result missing after the stream drained");
+            }
+            if (q != hipErrorNotReady) return fail(s, PF_EHIP, "stream: %s", hipGetErrorString(q));
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return PF_OK;
+}
+
 template <typename T>
 pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *unew, const T *aux,
                      const pf_tol &tol, double *norm, long long *ndof) {
@@ -502,12 +532,13 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
         end_timed(s, p);
     }
     begin_timed(s, FAM_RED, p);
-    HIPCHK(s, launch_finalize_norm(s->red, s->redn, nred, s->dres, s->stream));
+    s->res_seq += 1.0;
+    HIPCHK(s, launch_finalize_norm(s->red, s->redn, nred, s->hres_dev + RES_NORM, s->res_seq,
+                                   s->stream));
     end_timed(s, p);
-    HIPCHK(s, hipMemcpyAsync(s->hres, s->dres, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
-    *norm = s->hres[2];
-    if (ndof) *ndof = (long long)s->hres[1];
+    if (pf_status rc = wait_result(s, s->res_seq)) return rc;
+    *norm = s->hres[RES_NORM + 2];
+    if (ndof) *ndof = (long long)s->hres[RES_NORM + 1];
     s->st.rhs_evals += kind == 0 ? 1 : 0;
     return PF_OK;
 }
@@ -530,10 +561,11 @@ template <typename T>
 pf_status do_step(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *res, int *aux,
                   bool timed = true) {
     const long long st0 = s->st.stages;
-    hipEvent_t e0 = timed ? mark(s) : nullptr, ei = nullptr;
+    const unsigned fam = FAM_STAGE | (integ == PF_FEULER ? FAM_FE : 0u);
+    hipEvent_t e0 = timed ? mark(s, fam) : nullptr, ei = nullptr;
     pf_status rc = do_step_impl<T>(s, integ, nst, dt, want_aux, res, aux, timed ? &ei : nullptr);
     if (rc || !timed) return rc;
-    hipEvent_t e1 = mark(s);
+    hipEvent_t e1 = mark(s, fam | (integ == PF_RKL2 ? FAM_RKL2 : 0u));
     const int n = (int)(s->st.stages - st0);
     add_interval(s, FAM_STAGE | (integ == PF_FEULER ? FAM_FE : 0u), e0, e1, n);
     if (integ == PF_RKL2) add_interval(s, FAM_RKL2, ei, e1, n - 1);
@@ -650,7 +682,7 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
         if (rc) return rc;
         s->st.rhs_evals++;
         s->st.stages++;
-        if (e_inner) *e_inner = mark(s);
+        if (e_inner) *e_inner = mark(s, FAM_RKL2);
         for (int j = 2; j <= ns; ++j) {
             const int jc = j % 3, jp = (j - 1) % 3, jpp = (j - 2) % 3;
             if (jc == 0) slot[0] = slot0_store;
@@ -683,7 +715,7 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
     if (!tol) {
         if (!(dt_fixed > 0.0)) return fail(s, PF_EINVAL, "dt_fixed must be > 0");
         const bool fe = integ == PF_FEULER;
-        hipEvent_t e_run = fe ? mark(s) : nullptr;
+        hipEvent_t e_run = fe ? mark(s, FAM_STAGE | FAM_FE) : nullptr;
         const long long st_run = s->st.stages;
         for (;;) {
             double h;
@@ -699,7 +731,8 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
             s->t = last ? t_end : s->t + h;
             s->st.last_dt = h;
         }
-        if (fe) add_interval(s, FAM_STAGE | FAM_FE, e_run, mark(s), (int)(s->st.stages - st_run));
+        if (fe) add_interval(s, FAM_STAGE | FAM_FE, e_run, mark(s, FAM_STAGE | FAM_FE),
+                             (int)(s->st.stages - st_run));
         s->st.t = s->t;
         return PF_OK;
     }
@@ -905,8 +938,13 @@ pf_status pf_create(const pf_params *p, pf_sim **out) {
         if (hipMalloc(&s->dparams, sizeof P) != hipSuccess) rc = PF_ENOMEM;
         else if (hipMemcpy(s->dparams, &P, sizeof P, hipMemcpyHostToDevice) != hipSuccess) rc = PF_EHIP;
     }
-    if (!rc && hipMalloc(&s->dres, 8 * sizeof(double)) != hipSuccess) rc = PF_ENOMEM;
-    if (!rc && hipHostMalloc(&s->hres, 8 * sizeof(double)) != hipSuccess) rc = PF_ENOMEM;
+    // the reduction kernels write their scalar results straight into this
+    // memory, so reading them back needs no copy command
+    if (!rc && hipHostMalloc(&s->hres, RES_LEN * sizeof(double),
+                             hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        rc = PF_ENOMEM;
+    if (!rc) std::memset(s->hres, 0, RES_LEN * sizeof(double));
+    if (!rc && hipHostGetDevicePointer((void **)&s->hres_dev, s->hres, 0) != hipSuccess) rc = PF_EHIP;
     if (!rc) rc = ensure_buf(s, 0);
     if (rc) {
         pf_destroy(s);
@@ -925,7 +963,6 @@ pf_status pf_destroy(pf_sim *s) {
     if (s->dparams) hipFree(s->dparams);
     if (s->red) hipFree(s->red);
     if (s->redn) hipFree(s->redn);
-    if (s->dres) hipFree(s->dres);
     if (s->hres) hipHostFree(s->hres);
     for (auto &p : s->pending) {
         hipEventDestroy(p.e0);
@@ -1079,11 +1116,10 @@ pf_status pf_diagnostics(pf_sim *s, double out[5]) {
                        : launch_diag<float>((const float *)s->buf[s->cur], s->N, s->with_c, s->V,
                                             s->red, nb, s->stream);
     if (e != hipSuccess) return fail(s, PF_EHIP, "diag launch: %s", hipGetErrorString(e));
-    HIPCHK(s, launch_finalize_diag(s->red, nb, s->dres, s->stream));
+    HIPCHK(s, launch_finalize_diag(s->red, nb, s->hres_dev + RES_DIAG, s->stream));
     end_timed(s, p);
-    HIPCHK(s, hipMemcpyAsync(s->hres, s->dres, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    for (int k = 0; k < 5; ++k) out[k] = s->hres[k];
+    for (int k = 0; k < 5; ++k) out[k] = s->hres[RES_DIAG + k];
     return PF_OK;
 }
 
@@ -1182,15 +1218,20 @@ pf_status pf_autotune(pf_sim *s, int *tx_out, int *zc_out, double *best_ms) {
     return PF_OK;
 }
 
-pf_status pf_set_timing(pf_sim *s, int enable) {
+pf_status pf_set_timing_families(pf_sim *s, unsigned families) {
     if (!s) return PF_EINVAL;
     collect_timing(s);
-    s->timing = enable != 0;
+    s->timing = families != 0;
+    s->timing_mask = families & 31u;
     for (int f = 0; f < 5; ++f) {
         s->fam_ms[f] = 0.0;
         s->fam_n[f] = 0;
     }
     return PF_OK;
+}
+
+pf_status pf_set_timing(pf_sim *s, int enable) {
+    return pf_set_timing_families(s, enable ? 31u : 0u);
 }
 
 pf_status pf_get_kernel_time(pf_sim *s, int family, double *ms, long long *launches) {

@@ -184,7 +184,7 @@ template <typename T>
 hipError_t launch_diag(const T *u, int nphi, int with_c, long long V, double *red,
                        int nblocks, hipStream_t stream);
 hipError_t launch_finalize_norm(const double *red, const long long *redn, int nparts,
-                                double *out, hipStream_t stream);
+                                double *out, double seq, hipStream_t stream);
 hipError_t launch_finalize_diag(const double *red, int nparts, double *out,
                                 hipStream_t stream);
 template <typename T>

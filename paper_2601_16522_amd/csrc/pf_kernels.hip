@@ -100,8 +100,11 @@ diag_kernel(const T *__restrict__ u, int nphi, int withc, long long V, double *r
 }
 
 // Final reductions: one 256-thread block, fixed strided order then the tree.
+// The norm kernel writes (sum, count, norm) and then, after a system-scope
+// fence, the sequence number seq into out[3]: out is coherent host memory that
+// the host polls.
 __global__ void __launch_bounds__(256)
-finalize_norm_kernel(const double *red, const long long *redn, int n, double *out) {
+finalize_norm_kernel(const double *red, const long long *redn, int n, double *out, double seq) {
     double acc = 0.0;
     long long cnt = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -113,6 +116,8 @@ finalize_norm_kernel(const double *red, const long long *redn, int n, double *ou
         out[0] = acc;
         out[1] = (double)cnt;
         out[2] = cnt > 0 ? sqrt(acc / (double)cnt) : 0.0;
+        __threadfence_system();
+        *(volatile double *)(out + 3) = seq;
     }
 }
 
@@ -253,9 +258,9 @@ hipError_t launch_diag(const T *u, int nphi, int with_c, long long V, double *re
 }
 
 hipError_t launch_finalize_norm(const double *red, const long long *redn, int nparts,
-                                double *out, hipStream_t stream) {
+                                double *out, double seq, hipStream_t stream) {
     hipLaunchKernelGGL(finalize_norm_kernel, dim3(1), dim3(256), 0, stream, red, redn, nparts,
-                       out);
+                       out, seq);
     return hipGetLastError();
 }
 
