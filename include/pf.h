@@ -273,8 +273,9 @@ pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
  * fusion depth the instances allow (the state is only read) and keeps the
  * fastest per step; best_ms is that time per step.  pf_batch_set_blocks sets
  * the grid size directly (rounded down to a multiple of 8, >= 8);
- * pf_batch_set_fusion the depth (1 or 2; PF_EUNSUPPORTED when depth 2 needs
- * more LDS than a workgroup has: FP64 with n_phi > 4);  pf_batch_get_config
+ * pf_batch_set_fusion the depth (1 or 2; depth 2 is built for n_phi <= 4,
+ * where its LDS fits one workgroup in either precision, and returns
+ * PF_EUNSUPPORTED otherwise);  pf_batch_get_config
  * reads both (either pointer may be NULL). */
 pf_status pf_batch_autotune(pf_batch *b, int *nblocks, double *best_ms);
 pf_status pf_batch_set_blocks(pf_batch *b, int nblocks);

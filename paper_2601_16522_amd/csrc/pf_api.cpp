@@ -138,7 +138,7 @@ int work_index(const pf_sim *s, int k) {
 }
 
 void tiles(const pf_sim *s, int &ntx, int &nty, int &nzc, int &ntiles, int &nblocks) {
-    const int tx = s->tx, ty = 256 / s->tx;
+    const int tx = s->tx, ty = tile_rows(s->dim);
     ntx = (s->nx + tx - 1) / tx;
     nty = (s->ny + ty - 1) / ty;
     nzc = s->dim == 3 ? (s->nz + s->zchunk - 1) / s->zchunk : 1;
@@ -456,7 +456,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     int ntx, nty, nzc, ntiles, nblocks;
     tiles(s, ntx, nty, nzc, ntiles, nblocks);
     A.tx = s->tx;
-    A.ty = 256 / s->tx;
+    A.ty = tile_rows(s->dim);
     A.zchunk = s->zchunk;
     A.ntx = ntx;
     A.nty = nty;
@@ -516,7 +516,7 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
         A.r_c = (T)tol.r_c; A.a_c = (T)tol.a_c;
         A.dt6 = (T)(6.0 * dt);
         A.hdt = (T)(dt / 2.0);
-        A.tx = s->tx; A.ty = 256 / s->tx; A.zchunk = s->zchunk;
+        A.tx = s->tx; A.ty = tile_rows(s->dim); A.zchunk = s->zchunk;
         A.ntx = ntx; A.nty = nty; A.nzc = nzc; A.ntiles = ntiles;
         begin_timed(s, FAM_EST, p);
         hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
@@ -1724,7 +1724,7 @@ pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out) {
         b->total += (long long)b->meta[i].F * b->meta[i].V;
         b->total = (b->total + 63) / 64 * 64;  // 256-byte aligned instance starts
         b->ntx[i] = (b->meta[i].nx + TILE_X - 1) / TILE_X;
-        b->nty[i] = (b->meta[i].ny + TILE_Y - 1) / TILE_Y;
+        b->nty[i] = (b->meta[i].ny + tile_rows(2) - 1) / tile_rows(2);
         b->tile0[i] = b->total_tiles;
         b->total_tiles += b->ntx[i] * b->nty[i];
         tile_inst.insert(tile_inst.end(), (size_t)b->ntx[i] * b->nty[i], i);

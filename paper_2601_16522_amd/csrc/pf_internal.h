@@ -8,7 +8,16 @@ namespace pf {
 
 constexpr int NMAX = 16;  // largest number of order parameters a kernel is built for
 constexpr int TMAX = 4;   // largest number of thermodynamic types
-constexpr int TILE_X = 64, TILE_Y = 4;  // block tile of the stencil kernels (256 threads)
+constexpr int TILE_X = 64, TILE_Y = 4;  // 256 threads: one wavefront per row of 64 cells
+// Cells per thread in y of a 2D tile: the tile is 64 x (4 ROWS2D) cells, each
+// thread computing ROWS2D cells of one column.  Two rows halve the barriers
+// and the halo share per cell but measured slower on the two-phase batch and
+// double the registers of the eight-phase kernels, so one row is built.  A 3D
+// tile is 64 x 4 cells marched in z.
+constexpr int ROWS2D = 1;
+constexpr int tile_rows(int dim) { return dim == 2 ? TILE_Y * ROWS2D : TILE_Y; }
+// Largest number of order parameters built with stage-fusion depth 2.
+constexpr int DEPTH2_MAX_N = 4;
 
 // Per-simulation constants, resident in device memory and read through the
 // scalar cache (every address is uniform across the wavefront).  Pair tables
@@ -90,7 +99,7 @@ struct StageArgs {
     // estimator
     T r_phi, a_phi, r_c, a_c, dt6, hdt;
     // tiling
-    int tx, ty;      // tile (tx lanes in x, ty rows in y), tx*ty == blockDim.x
+    int tx, ty;      // tile of tx columns and ty rows (tile_rows(dim)), one block of 256 threads
     int zchunk;      // z planes per block (3D)
     int ntx, nty, nzc;
     int ntiles;
@@ -137,13 +146,16 @@ struct BatchInst {
 
 // Stage-fusion depth 2 of the batched forward-Euler kernel: a tile computes
 // two steps in one pass from its input with a two-cell halo.  Its LDS holds
-// the input region (TILE_X + 4) x (TILE_Y + 4) and the first step on
-// (TILE_X + 2) x (TILE_Y + 2), N + 3 planes each (phi, mu, Mc, c), plus the
-// pair and per-phase tables; it must fit one workgroup's 64 KiB.
-constexpr int F2_IN_X = TILE_X + 4, F2_IN_Y = TILE_Y + 4, F2_IN = F2_IN_X * F2_IN_Y;
-constexpr int F2_MID_X = TILE_X + 2, F2_MID_Y = TILE_Y + 2, F2_MID = F2_MID_X * F2_MID_Y;
+// the input region (TILE_X + 4) x (tile rows + 4) and the first step on
+// (TILE_X + 2) x (tile rows + 2), N + 3 planes each (phi, mu, Mc, c), plus the
+// pair and per-phase tables; it must fit one workgroup's 64 KiB.  Depth 2 is
+// built for few-field instances only (N <= DEPTH2_MAX_N): a thread holds
+// N + 1 values of up to three region cells at once, which above that leaves
+// one wave per SIMD.
+constexpr int F2_IN_X = TILE_X + 4, F2_IN = F2_IN_X * (tile_rows(2) + 4);
+constexpr int F2_MID_X = TILE_X + 2, F2_MID = F2_MID_X * (tile_rows(2) + 2);
 constexpr bool batch_depth2_fits(int esz, int n) {
-    return esz * ((n + 3) * (F2_IN + F2_MID) + 3 * n * n + 4 * n) <= 65536;
+    return n <= DEPTH2_MAX_N && esz * ((n + 3) * (F2_IN + F2_MID) + 3 * n * n + 4 * n) <= 65536;
 }
 
 template <typename T>

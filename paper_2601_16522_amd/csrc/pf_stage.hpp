@@ -24,19 +24,31 @@
 // planes in z and keeps planes z-1, z, z+1 of its own cell (and the halo cell
 // it loads) in registers, prefetching plane z+1 while plane z is computed;
 // every value is read from HBM once per march, plus the halo columns and the
-// two z halo planes.
+// two z halo planes.  Workgroups map to tiles XCD by XCD, so that neighbouring
+// tiles share one L2; in 3D the vectors other than the stencil input are
+// streamed non-temporally, which keeps the stencil input's lines in L2 for the
+// neighbours' halos.
+//
+// Addressing.  Every field plane is reached through a buffer resource of its
+// vector's plane group (1, 2 or 4 groups, a compile-time parameter) and a
+// 32-bit per-lane offset, so bases and descriptors stay in scalar registers.
 //
 // Arithmetic.  The double-precision kernels evaluate every formula in the
 // oracle's order (phases ascending; neighbours x-, x+, y-, y+, z-, z+; pair
 // sums over b != a) and the library is compiled without contraction, so they
 // reproduce a sequential left-to-right evaluation bit for bit.  The
 // single-precision kernels (the chosen form) use the same model with cheaper
-// algebra: fused multiply-adds, hardware reciprocals, mu and Mc from per-type
-// phase sums, and, when every pair shares one A, B and L (a flag computed on
-// the host), the O(N) forms
+// algebra: fused multiply-adds, hardware reciprocals (mu, 1/N_z, and the
+// normalisation of S), per-phase sums with constants staged in LDS, the RKL
+// combinations in a difference form whose weights sum to one whatever the
+// rounding of the coefficients (so the total of c is kept), and, when every
+// pair shares one A, B and L (a flag computed on the host), the O(N) forms
 //   delta_a = A (sum_b Lap phi_b - Lap phi_a) + B (sum_b phi_b - phi_a) + psi_a
 //   dphi_a/dt = L (mean of delta over the active phases - delta_a),
 // which equal the pairwise sums of eq. phieq exactly in real arithmetic.
+//
+// The batched kernel at the end runs the same stage bodies over the tiles of
+// many independent 2D simulations in one persistent launch.
 #pragma once
 
 #include <type_traits>
@@ -157,8 +169,6 @@ __device__ __forceinline__ void stage_tables(const DevParams<T> *P, T *__restric
 // tiles.
 template <int DIM> constexpr int operand_load_cp() { return DIM == 3 ? 2 : 0; }
 template <int DIM> constexpr int out_store_cp() { return DIM == 3 ? 2 : 0; }
-// Combination operands loaded with the stencil input, before the barrier.
-template <int DIM> constexpr bool early_operands() { return false; }
 
 // Operands of the stage combination at one cell: o0 from u0 (vector 2), o1
 // from y2 (vector 1), o2 from r0 (vector 3), as far as the stage kind uses them.
@@ -178,6 +188,17 @@ __device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool wit
     }
 }
 
+// f(0), f(1), ..., f(R - 1) as straight-line code.  A loop, even one of a
+// single trip, changes how the enclosing loop's invariants are hoisted and
+// can cost the stage kernels a wavefront of occupancy.
+template <int R, typename F>
+__device__ __forceinline__ void unrolled(F &&f) {
+    if constexpr (R > 0) {
+        unrolled<R - 1>(f);
+        f(R - 1);
+    }
+}
+
 // v mod n for v in [-n, 2n) by one compare each way (no integer division);
 // other v (grids smaller than a tile) by the remainder.
 __device__ __forceinline__ int wrap_index(int v, int n) {
@@ -187,31 +208,30 @@ __device__ __forceinline__ int wrap_index(int v, int n) {
     return v;
 }
 
-// Plane offset (column) of the thread's own cell and of its halo cell in tile
-// (tix, tiy) of a TILE_X x TILE_Y tiling, both periodically wrapped.  The halo
-// cells are the 2 TILE_X + 2 TILE_Y edge neighbours of the tile (no corners),
-// one per thread h < 2 TILE_X + 2 TILE_Y; hslot is its LDS slot.
-__device__ __forceinline__ void tile_columns(int tix, int tiy, int nx, int ny, long long &col,
-                                             long long &hcol, int &hslot, bool &active) {
-    constexpr int TX = TILE_X, TY = TILE_Y, TXH = TILE_X + 2;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int gx = tix * TX + lx, gy = tiy * TY + ly;
+// Plane offset (column) of the cell (tix * TILE_X + lx, tiy * TY + ly),
+// periodically wrapped; active: the cell lies inside the grid (ragged tiles).
+__device__ __forceinline__ void own_column(int tix, int tiy, int TY, int lx, int ly, int nx, int ny,
+                                           long long &col, bool &active) {
+    const int gx = tix * TILE_X + lx, gy = tiy * TY + ly;
     active = gx < nx && gy < ny;
     col = (long long)wrap_index(gy, ny) * nx + wrap_index(gx, nx);
-    const int h = threadIdx.x;
-    hslot = 0;
-    hcol = 0;
-    if (h < 2 * TX + 2 * TY) {
-        int hx, hy;
-        if (h < TX) { hx = h; hy = -1; }
-        else if (h < 2 * TX) { hx = h - TX; hy = TY; }
-        else if (h < 2 * TX + TY) { hx = -1; hy = h - 2 * TX; }
-        else { hx = TX; hy = h - 2 * TX - TY; }
-        hslot = (hy + 1) * TXH + (hx + 1);
-        const int hgx = wrap_index(tix * TX + hx, nx);
-        const int hgy = wrap_index(tiy * TY + hy, ny);
-        hcol = (long long)hgy * nx + hgx;
-    }
+}
+
+// Halo cell h (0 <= h < 2 TILE_X + 2 TY) of tile (tix, tiy) of height TY: the
+// edge neighbours of the tile without corners, periodically wrapped; hslot is
+// its slot in an LDS plane of (TILE_X + 2) x (TY + 2).
+__device__ __forceinline__ void halo_column(int tix, int tiy, int TY, int h, int nx, int ny,
+                                            long long &hcol, int &hslot) {
+    constexpr int TX = TILE_X, TXH = TILE_X + 2;
+    int hx, hy;
+    if (h < TX) { hx = h; hy = -1; }
+    else if (h < 2 * TX) { hx = h - TX; hy = TY; }
+    else if (h < 2 * TX + TY) { hx = -1; hy = h - 2 * TX; }
+    else { hx = TX; hy = h - 2 * TX - TY; }
+    hslot = (hy + 1) * TXH + (hx + 1);
+    const int hgx = wrap_index(tix * TX + hx, nx);
+    const int hgy = wrap_index(tiy * TY + hy, ny);
+    hcol = (long long)hgy * nx + hgx;
 }
 
 // Right-hand side of eqs. phieq and ceq at one cell (the per-cell part of
@@ -342,21 +362,162 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
     r[N] = withc ? flux * idx2 : T(0);
 }
 
+// Stage combination, projection and store at one cell (byte offset idx in a
+// plane) from its own values cur, its right-hand side r and the operands
+// o0 (u0), o1 (y2), o2 (r0) of the stage kind; the estimator kind adds its
+// weighted squares to acc and its degrees of freedom to cnt.
+template <typename T, int N, int KIND, int GS, int SCP, bool FAST>
+__device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsigned idx,
+                                             const bool withc, const T *cur, const T *r,
+                                             const T *o0, const T *o1, const T *o2, double &acc,
+                                             long long &cnt) {
+    T yv[N + 1];
+    if constexpr (KIND == K_RHS) {
+#pragma unroll
+        for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, r[f]);
+        if (withc) stv<T, GS, SCP>(A, 4, N, idx, r[N]);
+    } else if constexpr (KIND == K_EST) {
+        // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
+        // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
+        // [0,1] has zero error; weights r max(|u^n|,|u^{n+1}|) + a; the
+        // two-DoF rule for cells without nontrivial phi entries
+        int nt = 0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const T u_n = o0[a];
+            const T rs = o2[a] + r[a];
+            T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
+            const T trial = u_n + A.hdt * rs;
+            if (trial < T(0) || trial > T(1)) e = T(0);
+            if (e != T(0)) {
+                const T w = A.r_phi * tmax(tabs(u_n), tabs(cur[a])) + A.a_phi;
+                const T q = e / w;
+                acc += (double)q * (double)q;
+                ++nt;
+            }
+        }
+        cnt += nt > 0 ? nt : 2;
+        if (withc) {
+            const T u_n = o0[N];
+            const T rs = o2[N] + r[N];
+            const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
+            const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
+            const T q = e / w;
+            acc += (double)q * (double)q;
+            cnt += 1;
+        }
+    } else {
+        if constexpr (KIND == K_EULER || KIND == K_SSP104_S5 || KIND == K_RKL2_FIRST) {
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                if constexpr (FAST) yv[f] = fma_t(A.a, r[f], cur[f]);
+                else yv[f] = cur[f] + A.a * r[f];
+            }
+        } else if constexpr (KIND == K_SSP2_FINAL) {
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                yv[f] = ((A.a * cur[f] + o0[f]) + A.b * r[f]) / A.c;
+            }
+        } else if constexpr (KIND == K_SSP104_FINAL) {
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                yv[f] = (o0[f] + A.a * cur[f]) + A.b * r[f];
+            }
+        } else if constexpr (KIND == K_RKL1) {
+            // the fast form uses mu_j + nu_j = 1: Y_{j-1} + nu_j (Y_{j-2} -
+            // Y_{j-1}), so rounded coefficients cannot change the total of c
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, o1[f] - cur[f], cur[f]));
+                else yv[f] = (A.a * cur[f] + A.b * o1[f]) + A.c * r[f];
+            }
+        } else {  // K_RKL2
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                const T u = o0[f], v2 = o1[f], q0 = o2[f];
+                // the fast form: u + mu_j (Y_{j-1} - u) + nu_j (Y_{j-2} - u), the
+                // same combination, whose weights sum to 1 exactly whatever the
+                // rounding of mu_j and nu_j (the total of c is kept)
+                if constexpr (FAST)
+                    yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
+                                  fma_t(A.c, v2 - u, fma_t(A.b, cur[f] - u, u)));
+                else
+                    yv[f] = ((A.a * u + A.b * cur[f]) + A.c * v2) + A.d * (A.e * r[f] + A.f * q0);
+            }
+        }
+
+        if constexpr (KIND == K_RKL2_FIRST) {
+            // First RKL2 stage: where S changes the cell, replace rhs(u^{n,0}) of
+            // the phi planes by (S(u^{n,1}) - u^{n,0}) / (mut_1 dt) (Sec. 3.2).
+            T ys[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) ys[a] = yv[a];
+            project<T, N, FAST>(ys);
+            bool changed = false;
+#pragma unroll
+            for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                stv<T, GS, SCP>(A, 4, a, idx, ys[a]);
+                stv<T, GS, SCP>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+            }
+            if (withc) {
+                stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
+                stv<T, GS, SCP>(A, 5, N, idx, r[N]);
+            }
+        } else if constexpr (KIND == K_SSP104_S5) {
+            // Fifth SSP(10)4 stage plus the two linear updates of the
+            // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1).
+            project<T, N, FAST>(yv);
+            T q1n[N + 1];
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                const bool have = f < N || withc;
+                const T q2n = A.b * o0[f] + A.c * yv[f];
+                if (have) stv<T, GS, SCP>(A, 5, f, idx, q2n);
+                q1n[f] = A.d * q2n - A.e * yv[f];
+            }
+            project<T, N, FAST>(q1n);
+#pragma unroll
+            for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, q1n[f]);
+            if (withc) stv<T, GS, SCP>(A, 4, N, idx, q1n[N]);
+        } else {
+            project<T, N, FAST>(yv);
+#pragma unroll
+            for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, yv[f]);
+            if (withc) stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
+            if constexpr (KIND == K_EULER) {
+                if (A.out2 != nullptr) {
+#pragma unroll
+                    for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 5, f, idx, r[f]);
+                    if (withc) stv<T, GS, SCP>(A, 5, N, idx, r[N]);
+                }
+            }
+        }
+    }
+}
+
 // One tile (logical index L) of one stage.  Every thread of the block calls
 // it with the same arguments (it synchronises the block).  GS: planes per
 // buffer group of the vectors (see set_field_bases).  TABLES: stage the LDS
 // tables of A.P first (false: the caller has staged them).
+// The tile is 64 x TY cells, TY = tile_rows(DIM); thread (lx, ly) computes the
+// R = TY / 4 cells (lx, ly + 4 k) of its column (3D: R = 1, marched in z).
 template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
-    constexpr bool EARLY = early_operands<DIM>();
     constexpr int LCP = operand_load_cp<DIM>(), SCP = out_store_cp<DIM>();
+    // the tile shape is fixed at compile time (one wavefront per row) so that
+    // every LDS plane offset is an instruction immediate
+    constexpr int TX = TILE_X, TY = tile_rows(DIM), R = TY / TILE_Y;
+    constexpr int TXH = TX + 2, TYH = TY + 2;
+    constexpr int plane_sz = TXH * TYH;
+    static_assert(DIM == 2 || R == 1, "3D tiles march one row set in z");
+    static_assert(2 * TX + 2 * TY <= 256, "one halo cell per thread");
     const KConsts<T> &P = A.K;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const long long V = P.V;
     const bool withc = P.with_c != 0;
-    const T idx2 = P.idx2;
     const bool tile_ok = L < A.ntiles;  // uniform over the block
 
     double acc = 0.0;
@@ -367,63 +528,73 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             stage_tables<T, N>(A.P, pair, kc);
             __syncthreads();  // the tables are read from the first plane on
         }
-        // the tile is fixed at 64 x 4 (one wavefront per row) so that every LDS
-        // plane offset is an instruction immediate
-        constexpr int TX = TILE_X, TY = TILE_Y;
-        constexpr int TXH = TX + 2, TYH = TY + 2;
-        constexpr int plane_sz = TXH * TYH;
         const int tix = L % A.ntx;
         const int rest = L / A.ntx;
         const int tiy = rest % A.nty;
         const int tiz = rest / A.nty;
         const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
         const long long nxy = (long long)nx * ny;
-        // own slot holds the periodically wrapped cell
-        const int own_slot = (ly + 1) * TXH + (lx + 1);
+        // own slots hold the periodically wrapped cells
+        int own_slot[R];
+        long long col[R];
+        bool active[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            own_slot[k] = (ly + TILE_Y * k + 1) * TXH + (lx + 1);
+            own_column(tix, tiy, TY, lx, ly + TILE_Y * k, nx, ny, col[k], active[k]);
+        }
         const bool has_halo = threadIdx.x < 2 * TX + 2 * TY;
-        long long col, hcol;
-        int hslot;
-        bool active;
-        tile_columns(tix, tiy, nx, ny, col, hcol, hslot, active);
+        long long hcol = 0;
+        int hslot = 0;
+        if (has_halo) halo_column(tix, tiy, TY, threadIdx.x, nx, ny, hcol, hslot);
 
         const int z0 = DIM == 3 ? tiz * A.zchunk : 0;
         const int z1 = DIM == 3 ? min(z0 + A.zchunk, nz) : 1;
 
-        T prv[N + 1], cur[N + 1], nxt[N + 1], hcur[N + 1], hnxt[N + 1];
-        T mu_p = T(0), mc_p = T(0), mu_c = T(0), mc_c = T(0), mu_n = T(0), mc_n = T(0);
+        T prv[N + 1], cur[R][N + 1], nxt[N + 1], hcur[N + 1], hnxt[N + 1];
+        T mu_p = T(0), mc_p = T(0), mu_n = T(0), mc_n = T(0);
+        T mu_c[R], mc_c[R];
         // every load of the first plane is issued before the first use of one
         if (DIM == 3) {
             const int zm = z0 == 0 ? nz - 1 : z0 - 1;
-            load_point32<T, N, GS>(A, 0, (unsigned)(zm * nxy + col) * (unsigned)sizeof(T), withc, prv);
+            load_point32<T, N, GS>(A, 0, (unsigned)(zm * nxy + col[0]) * (unsigned)sizeof(T), withc, prv);
         }
-        load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + col) * (unsigned)sizeof(T), withc, cur);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + col[k]) * (unsigned)sizeof(T), withc,
+                                   cur[k]);
         if (has_halo)
             load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
-                                     hcur);
+                                   hcur);
 
         for (int z = z0; z < z1; ++z) {
             const long long pz = (long long)z * nxy;
-            const unsigned idx = (unsigned)(pz + col) * (unsigned)sizeof(T);  // byte offset in a plane
             if (DIM == 3) {
                 const int zp = z == nz - 1 ? 0 : z + 1;
-                load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + col) * (unsigned)sizeof(T),
-                                   withc, nxt);
+                load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + col[0]) * (unsigned)sizeof(T),
+                                       withc, nxt);
                 if (has_halo && z + 1 < z1)
                     load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
-                                       withc, hnxt);
+                                           withc, hnxt);
             }
-            T o0[N + 1], o1[N + 1], o2[N + 1];
-            if constexpr (EARLY) load_operands<T, N, KIND, GS, LCP>(A, idx, withc, o0, o1, o2);
-            if (z == z0 && withc) {  // later planes rotate their mu and Mc in
-                if (DIM == 3) point_mu_mc<T, N, FAST>(P, kc, prv, mu_p, mc_p);
-                point_mu_mc<T, N, FAST>(P, kc, cur, mu_c, mc_c);
+            if (z == z0) {  // later planes rotate their mu and Mc in
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    mu_c[k] = T(0);
+                    mc_c[k] = T(0);
+                    if (withc) point_mu_mc<T, N, FAST>(P, kc, cur[k], mu_c[k], mc_c[k]);
+                }
+                if (DIM == 3 && withc) point_mu_mc<T, N, FAST>(P, kc, prv, mu_p, mc_p);
             }
 
             // ---- stage plane z in LDS ---------------------------------------
 #pragma unroll
-            for (int a = 0; a < N; ++a) lds[a * plane_sz + own_slot] = cur[a];
-            lds[N * plane_sz + own_slot] = mu_c;
-            lds[(N + 1) * plane_sz + own_slot] = mc_c;
+            for (int k = 0; k < R; ++k) {
+#pragma unroll
+                for (int a = 0; a < N; ++a) lds[a * plane_sz + own_slot[k]] = cur[k][a];
+                lds[N * plane_sz + own_slot[k]] = mu_c[k];
+                lds[(N + 1) * plane_sz + own_slot[k]] = mc_c[k];
+            }
             if (has_halo) {
                 T hmu = T(0), hmc = T(0);
                 if (withc) point_mu_mc<T, N, FAST>(P, kc, hcur, hmu, hmc);
@@ -435,150 +606,29 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             if (DIM == 3 && withc) point_mu_mc<T, N, FAST>(P, kc, nxt, mu_n, mc_n);
             __syncthreads();
 
-            if (active) {
-                // ---- right-hand side at (x, y, z) -------------------------------
+            unrolled<R>([&](const int k) __attribute__((always_inline)) {
+                if (!active[k]) return;
+                const unsigned idx = (unsigned)(pz + col[k]) * (unsigned)sizeof(T);  // byte offset
+                // ---- right-hand side at the cell --------------------------------
                 T r[N + 1];
-                rhs_point<T, DIM, N, FAST, plane_sz, TXH>(P, lds, pair, kc, own_slot, cur, mu_c, mc_c,
+                rhs_point<T, DIM, N, FAST, plane_sz, TXH>(P, lds, pair, kc, own_slot[k], cur[k], mu_c[k], mc_c[k],
                                                           prv, mu_p, mc_p, nxt, mu_n, mc_n, r);
-
-                // ---- stage combination, projection, store ----------------------
-                if constexpr (!EARLY) load_operands<T, N, KIND, GS, LCP>(A, idx, withc, o0, o1, o2);
-                T yv[N + 1];
-                if constexpr (KIND == K_RHS) {
-#pragma unroll
-                    for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, r[f]);
-                    if (withc) stv<T, GS, SCP>(A, 4, N, idx, r[N]);
-                } else if constexpr (KIND == K_EST) {
-                    // e = (12 (u^n - u^{n+1}) + 6 dt (R0 + rhs(u^{n+1}))) / 15; a phi
-                    // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
-                    // [0,1] has zero error; weights r max(|u^n|,|u^{n+1}|) + a; the
-                    // two-DoF rule for cells without nontrivial phi entries
-                    int nt = 0;
-#pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        const T u_n = o0[a];
-                        const T rs = o2[a] + r[a];
-                        T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
-                        const T trial = u_n + A.hdt * rs;
-                        if (trial < T(0) || trial > T(1)) e = T(0);
-                        if (e != T(0)) {
-                            const T w = A.r_phi * tmax(tabs(u_n), tabs(cur[a])) + A.a_phi;
-                            const T q = e / w;
-                            acc += (double)q * (double)q;
-                            ++nt;
-                        }
-                    }
-                    cnt += nt > 0 ? nt : 2;
-                    if (withc) {
-                        const T u_n = o0[N];
-                        const T rs = o2[N] + r[N];
-                        const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
-                        const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
-                        const T q = e / w;
-                        acc += (double)q * (double)q;
-                        cnt += 1;
-                    }
-                } else {
-                    if constexpr (KIND == K_EULER || KIND == K_SSP104_S5 || KIND == K_RKL2_FIRST) {
-#pragma unroll
-                        for (int f = 0; f <= N; ++f) {
-                            if constexpr (FAST) yv[f] = fma_t(A.a, r[f], cur[f]);
-                            else yv[f] = cur[f] + A.a * r[f];
-                        }
-                    } else if constexpr (KIND == K_SSP2_FINAL) {
-#pragma unroll
-                        for (int f = 0; f <= N; ++f) {
-                            yv[f] = ((A.a * cur[f] + o0[f]) + A.b * r[f]) / A.c;
-                        }
-                    } else if constexpr (KIND == K_SSP104_FINAL) {
-#pragma unroll
-                        for (int f = 0; f <= N; ++f) {
-                            yv[f] = (o0[f] + A.a * cur[f]) + A.b * r[f];
-                        }
-                    } else if constexpr (KIND == K_RKL1) {
-                        // the fast form uses mu_j + nu_j = 1: Y_{j-1} + nu_j (Y_{j-2} -
-                        // Y_{j-1}), so rounded coefficients cannot change the total of c
-#pragma unroll
-                        for (int f = 0; f <= N; ++f) {
-                            if constexpr (FAST) yv[f] = fma_t(A.c, r[f], fma_t(A.b, o1[f] - cur[f], cur[f]));
-                            else yv[f] = (A.a * cur[f] + A.b * o1[f]) + A.c * r[f];
-                        }
-                    } else {  // K_RKL2
-    #pragma unroll
-                        for (int f = 0; f <= N; ++f) {
-                            const T u = o0[f], v2 = o1[f], q0 = o2[f];
-                            // the fast form: u + mu_j (Y_{j-1} - u) + nu_j (Y_{j-2} - u), the
-                            // same combination, whose weights sum to 1 exactly whatever the
-                            // rounding of mu_j and nu_j (the total of c is kept)
-                            if constexpr (FAST)
-                                yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
-                                              fma_t(A.c, v2 - u, fma_t(A.b, cur[f] - u, u)));
-                            else
-                                yv[f] = ((A.a * u + A.b * cur[f]) + A.c * v2) + A.d * (A.e * r[f] + A.f * q0);
-                        }
-                    }
-
-                    if constexpr (KIND == K_RKL2_FIRST) {
-                        // First RKL2 stage: where S changes the cell, replace rhs(u^{n,0}) of
-                        // the phi planes by (S(u^{n,1}) - u^{n,0}) / (mut_1 dt) (Sec. 3.2).
-                        T ys[N];
-#pragma unroll
-                        for (int a = 0; a < N; ++a) ys[a] = yv[a];
-                        project<T, N, FAST>(ys);
-                        bool changed = false;
-#pragma unroll
-                        for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
-#pragma unroll
-                        for (int a = 0; a < N; ++a) {
-                            stv<T, GS, SCP>(A, 4, a, idx, ys[a]);
-                            stv<T, GS, SCP>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
-                        }
-                        if (withc) {
-                            stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
-                            stv<T, GS, SCP>(A, 5, N, idx, r[N]);
-                        }
-                    } else if constexpr (KIND == K_SSP104_S5) {
-                        // Fifth SSP(10)4 stage plus the two linear updates of the
-                        // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1).
-                        project<T, N, FAST>(yv);
-                        T q1n[N + 1];
-#pragma unroll
-                        for (int f = 0; f <= N; ++f) {
-                            const bool have = f < N || withc;
-                            const T q2n = A.b * o0[f] + A.c * yv[f];
-                            if (have) stv<T, GS, SCP>(A, 5, f, idx, q2n);
-                            q1n[f] = A.d * q2n - A.e * yv[f];
-                        }
-                        project<T, N, FAST>(q1n);
-#pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, q1n[f]);
-                        if (withc) stv<T, GS, SCP>(A, 4, N, idx, q1n[N]);
-                    } else {
-                        project<T, N, FAST>(yv);
-#pragma unroll
-                        for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, yv[f]);
-                        if (withc) stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
-                        if constexpr (KIND == K_EULER) {
-                            if (A.out2 != nullptr) {
-        #pragma unroll
-                                for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 5, f, idx, r[f]);
-                                if (withc) stv<T, GS, SCP>(A, 5, N, idx, r[N]);
-                            }
-                        }
-                    }
-                }
-            }
+                // ---- stage combination, projection, store -----------------------
+                T o0[N + 1], o1[N + 1], o2[N + 1];
+                load_operands<T, N, KIND, GS, LCP>(A, idx, withc, o0, o1, o2);
+                cell_combine<T, N, KIND, GS, SCP, FAST>(A, idx, withc, cur[k], r, o0, o1, o2, acc, cnt);
+            });
             __syncthreads();  // plane z of LDS is read; the next plane may overwrite it
 
             if (DIM == 3) {
 #pragma unroll
                 for (int f = 0; f <= N; ++f) {
-                    prv[f] = cur[f];
-                    cur[f] = nxt[f];
+                    prv[f] = cur[0][f];
+                    cur[0][f] = nxt[f];
                     hcur[f] = hnxt[f];
                 }
-                mu_p = mu_c; mc_p = mc_c;
-                mu_c = mu_n; mc_c = mc_n;
+                mu_p = mu_c[0]; mc_p = mc_c[0];
+                mu_c[0] = mu_n; mc_c[0] = mc_n;
             }
         }
     }
@@ -592,16 +642,17 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
     }
 }
 
-// LDS per block: (N + 2) planes of (TILE_X + 2) x (TILE_Y + 2) values.
-template <typename T, int N>
-constexpr int lds_elems() { return (N + 2) * (TILE_X + 2) * (TILE_Y + 2); }
+// LDS per block: (N + 2) planes of (TILE_X + 2) x (tile rows + 2) values.
+template <typename T, int N, int DIM>
+constexpr int lds_elems() { return (N + 2) * (TILE_X + 2) * (tile_rows(DIM) + 2); }
 
 // Occupancy hint: the single-precision 3D kernels with up to 9 order
 // parameters fit three wavefronts per SIMD (<= 168 VGPRs) without scratch;
 // larger instances keep the compiler's choice.
+constexpr int MIN_WAVES_2D = 1;
 template <typename T, int DIM, int N>
 constexpr int min_waves_per_eu() {
-    return (std::is_same<T, float>::value && DIM == 3 && N <= 9) ? 3 : 1;
+    return DIM == 2 ? MIN_WAVES_2D : (std::is_same<T, float>::value && N <= 9) ? 3 : 1;
 }
 
 // One named kernel per stage kind, so that profiles separate them; NG is the
@@ -611,7 +662,7 @@ constexpr int min_waves_per_eu() {
     __global__ void __launch_bounds__(256)                                                 \
         __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, DIM, N>(), 8)))             \
         name(const StageArgs<T> A) {                                                       \
-        __shared__ T lds[lds_elems<T, N>()];                                               \
+        __shared__ T lds[lds_elems<T, N, DIM>()];                                          \
         __shared__ T pair[3 * N * N];                                                      \
         __shared__ T kc[4 * N];                                                            \
         stage_body<T, DIM, N, kind, group_planes(N, NG)>(A, xcd_logical_block(), lds, pair, \
@@ -688,8 +739,9 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, 
     const KConsts<T> &P = A.K;
     const int nx = P.nx, ny = P.ny;
     const bool withc = P.with_c != 0;
+    constexpr int TY = tile_rows(2), R = TY / TILE_Y;  // tile height, cells per thread
     const int tix = L % A.ntx, tiy = L / A.ntx;
-    const int x0 = tix * TILE_X - 2, y0 = tiy * TILE_Y - 2;  // corner of the input region
+    const int x0 = tix * TILE_X - 2, y0 = tiy * TY - 2;  // corner of the input region
 
     // input region: every load is issued before the first use of one
     constexpr int NP0 = (F2_IN + 255) / 256;
@@ -718,13 +770,14 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, 
     }
     __syncthreads();
 
+    // the thread's output cells (lx, ly + 4 k) of the tile
     const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
-    const int gx = tix * TILE_X + lx, gy = tiy * TILE_Y + ly;
-    const bool active = gx < nx && gy < ny;
-    const unsigned idx = (unsigned)((long long)gy * nx + gx) * (unsigned)sizeof(T);
-    T y[N + 1];
+    T y[R][N + 1];
     if (!two) {
-        euler_point<T, N, FAST, F2_IN, F2_IN_X>(P, in, pair, kc, (ly + 2) * F2_IN_X + (lx + 2), dt1, y);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            euler_point<T, N, FAST, F2_IN, F2_IN_X>(P, in, pair, kc,
+                                                    (ly + TILE_Y * k + 2) * F2_IN_X + (lx + 2), dt1, y[k]);
     } else {
         // first step on the tile and its one-cell ring
         constexpr int NP1 = (F2_MID + 255) / 256;
@@ -746,13 +799,20 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, 
             }
         }
         __syncthreads();
-        euler_point<T, N, FAST, F2_MID, F2_MID_X>(P, mid, pair, kc, (ly + 1) * F2_MID_X + (lx + 1), dt2,
-                                                  y);
-    }
-    if (active) {
 #pragma unroll
-        for (int f = 0; f < N; ++f) stv<T, N + 1, SCP>(A, 4, f, idx, y[f]);
-        if (withc) stv<T, N + 1, SCP>(A, 4, N, idx, y[N]);
+        for (int k = 0; k < R; ++k)
+            euler_point<T, N, FAST, F2_MID, F2_MID_X>(P, mid, pair, kc,
+                                                      (ly + TILE_Y * k + 1) * F2_MID_X + (lx + 1), dt2, y[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int gx = tix * TILE_X + lx, gy = tiy * TY + ly + TILE_Y * k;
+        if (gx < nx && gy < ny) {
+            const unsigned idx = (unsigned)((long long)gy * nx + gx) * (unsigned)sizeof(T);
+#pragma unroll
+            for (int f = 0; f < N; ++f) stv<T, N + 1, SCP>(A, 4, f, idx, y[k][f]);
+            if (withc) stv<T, N + 1, SCP>(A, 4, N, idx, y[k][N]);
+        }
     }
     __syncthreads();  // the LDS regions are read; the next tile may overwrite them
 }
@@ -760,7 +820,7 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, 
 // LDS of the batched kernel for a fusion depth.
 template <typename T, int N, int DEPTH>
 constexpr int batch_lds_elems() {
-    return DEPTH == 1 ? lds_elems<T, N>() : (N + 3) * (F2_IN + F2_MID);
+    return DEPTH == 1 ? lds_elems<T, N, 2>() : (N + 3) * (F2_IN + F2_MID);
 }
 
 // Batched stages over many independent 2D instances.  A persistent grid splits
@@ -843,7 +903,7 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
             A.gb[4][0] = A.out;
             A.kind = KIND;
             A.tx = TILE_X;
-            A.ty = TILE_Y;
+            A.ty = tile_rows(2);
             A.zchunk = 1;
             A.ntx = I.ntx;
             A.nty = I.nty;

@@ -117,19 +117,26 @@ def test_batch_autotune_keeps_state():
 
 
 def test_batch_fusion_depth_limits():
-    """Depth 2 needs (N + 3) LDS planes of the two regions per workgroup: FP64
-    with 8 phases does not fit and is refused; bad depths are refused."""
-    wl = pi.voronoi_2d(n=64, n_grains=8, n_phi=8, dmin=5.0)
-    b = pf.Batch([wl.param_dict()], prec="fp64")
-    with pytest.raises(pf.PFError) as e:
+    """Depth 2 is built for N <= 4, where (N + 3) LDS planes of the two
+    regions fit one workgroup: N = 2 and 4 take it in both precisions; N = 8
+    and 9 are refused; bad depths are refused."""
+    def batch(n_phi, prec):
+        wl = pi.voronoi_2d(n=64, n_grains=2 * n_phi, n_phi=n_phi, dmin=5.0)
+        return pf.Batch([wl.param_dict()], prec=prec)
+    for n_phi, prec in [(9, "fp32"), (8, "fp64"), (8, "fp32")]:
+        b = batch(n_phi, prec)
+        with pytest.raises(pf.PFError) as e:
+            b.set_fusion(2)
+        assert e.value.code == -7, (n_phi, prec)
+        assert b.config()[1] == 1
+        b.close()
+    for n_phi, prec in [(4, "fp32"), (4, "fp64"), (2, "fp64")]:
+        b = batch(n_phi, prec)
         b.set_fusion(2)
-    assert e.value.code == -7
-    assert b.config()[1] == 1
-    b32 = pf.Batch([wl.param_dict()], prec="fp32")
-    b32.set_fusion(2)
-    with pytest.raises(pf.PFError):
-        b32.set_fusion(3)
-    assert b32.config()[1] == 2
+        with pytest.raises(pf.PFError):
+            b.set_fusion(3)
+        assert b.config()[1] == 2, (n_phi, prec)
+        b.close()
 
 
 def test_batch_rejects_mixed_instances():

@@ -65,6 +65,17 @@ def test_stage_kernels_do_not_spill(tmp_path):
                 assert r.get("SGPRs Spill", 0) == 0, (n, g, k, r)
         # batch kernels (built with one group), per precision: forward Euler at
         # depth 1, the two RKL2 stage kinds, and forward Euler at depth 2 where
-        # its LDS fits (FP32 for every N, FP64 only up to N = 4)
+        # its LDS fits one workgroup
         batch = [k for k in names if "batch_kernel" in k]
-        assert len(batch) == (7 if g == 1 else 0), (n, g, batch)
+        expect = 6 + sum(_depth2_fits(esz, n) for esz in (4, 8))
+        assert len(batch) == (expect if g == 1 else 0), (n, g, batch)
+
+
+def _depth2_fits(esz, n):
+    """The LDS rule of the fused two-step batch kernel (pf_internal.h)."""
+    txt = open(os.path.join(ROOT, "paper_2601_16522_amd", "csrc", "pf_internal.h")).read()
+    if n > int(re.search(r"constexpr int DEPTH2_MAX_N = (\d+);", txt).group(1)):
+        return False
+    ty = 4 * int(re.search(r"constexpr int ROWS2D = (\d+);", txt).group(1))
+    f2 = 68 * (ty + 4) + 66 * (ty + 2)
+    return esz * ((n + 3) * f2 + 3 * n * n + 4 * n) <= 65536
