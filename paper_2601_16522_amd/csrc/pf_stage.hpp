@@ -87,9 +87,10 @@ __device__ __forceinline__ void point_mu_mc(const KConsts<T> &P, const T *kc, co
     if constexpr (!FAST) {
         mu_mc<T, N>(P, v, mu, mc);
     } else {
-        T sc0 = T(0), sik = T(0), smc = T(0);
+        // the sums start from their first term (no added zero)
+        T sc0 = v[0] * kc[0], sik = v[0] * kc[N], smc = v[0] * kc[2 * N];
 #pragma unroll
-        for (int a = 0; a < N; ++a) {
+        for (int a = 1; a < N; ++a) {
             sc0 = fma_t(v[a], kc[a], sc0);
             sik = fma_t(v[a], kc[N + a], sik);
             smc = fma_t(v[a], kc[2 * N + a], smc);
@@ -122,9 +123,9 @@ __device__ __forceinline__ void project(T *p) {
 #pragma unroll
             for (int a = 0; a < N; ++a) p[a] = (a == m) ? T(1) : T(0);
         }
-        T sum = T(0);
+        T sum = p[0];
 #pragma unroll
-        for (int a = 0; a < N; ++a) sum = sum + p[a];
+        for (int a = 1; a < N; ++a) sum = sum + p[a];
         if (sum > T(0)) {
             const T inv = fast_rcp(sum);
 #pragma unroll
@@ -199,27 +200,45 @@ __device__ __forceinline__ void unrolled(F &&f) {
     }
 }
 
-// v mod n for v in [-n, 2n) by one compare each way (no integer division);
-// other v (grids smaller than a tile) by the remainder.
+// v mod n.  GENERAL == false: v in [-n, 2n), by one compare each way (no
+// integer division); GENERAL: any v (grids smaller than a tile).
+template <bool GENERAL>
 __device__ __forceinline__ int wrap_index(int v, int n) {
     if (v < 0) v += n;
     if (v >= n) v -= n;
-    if (v < 0 || v >= n) v = (v % n + n) % n;
+    if constexpr (GENERAL)
+        if (v < 0 || v >= n) v = (v % n + n) % n;
     return v;
+}
+
+// Whether every index a tile touches, up to two cells beyond the tiles of an
+// nt-tile extent of length n (tile length t), lies in [-n, 2n) (uniform over
+// the grid, so the caller branches on it once).
+__device__ __forceinline__ bool wrap_fits(int nt, int t, int n) { return nt * t + 2 < 2 * n; }
+
+// Tile L of an ntx x nty x (z chunks) tiling, x fastest.
+struct TileIdx {
+    int L, tix, tiy, tiz;
+};
+__device__ __forceinline__ TileIdx tile_index(int L, int ntx, int nty) {
+    const int rest = L / ntx;
+    return {L, L - rest * ntx, rest % nty, rest / nty};
 }
 
 // Plane offset (column) of the cell (tix * TILE_X + lx, tiy * TY + ly),
 // periodically wrapped; active: the cell lies inside the grid (ragged tiles).
+template <bool GENERAL>
 __device__ __forceinline__ void own_column(int tix, int tiy, int TY, int lx, int ly, int nx, int ny,
                                            long long &col, bool &active) {
     const int gx = tix * TILE_X + lx, gy = tiy * TY + ly;
     active = gx < nx && gy < ny;
-    col = (long long)wrap_index(gy, ny) * nx + wrap_index(gx, nx);
+    col = (long long)wrap_index<GENERAL>(gy, ny) * nx + wrap_index<GENERAL>(gx, nx);
 }
 
 // Halo cell h (0 <= h < 2 TILE_X + 2 TY) of tile (tix, tiy) of height TY: the
 // edge neighbours of the tile without corners, periodically wrapped; hslot is
 // its slot in an LDS plane of (TILE_X + 2) x (TY + 2).
+template <bool GENERAL>
 __device__ __forceinline__ void halo_column(int tix, int tiy, int TY, int h, int nx, int ny,
                                             long long &hcol, int &hslot) {
     constexpr int TX = TILE_X, TXH = TILE_X + 2;
@@ -229,8 +248,8 @@ __device__ __forceinline__ void halo_column(int tix, int tiy, int TY, int h, int
     else if (h < 2 * TX + TY) { hx = -1; hy = h - 2 * TX; }
     else { hx = TX; hy = h - 2 * TX - TY; }
     hslot = (hy + 1) * TXH + (hx + 1);
-    const int hgx = wrap_index(tix * TX + hx, nx);
-    const int hgy = wrap_index(tiy * TY + hy, ny);
+    const int hgx = wrap_index<GENERAL>(tix * TX + hx, nx);
+    const int hgy = wrap_index<GENERAL>(tiy * TY + hy, ny);
     hcol = (long long)hgy * nx + hgx;
 }
 
@@ -250,6 +269,9 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
     // activity of phase a: phi_a > 0 at the cell or at one of its 2d
     // neighbours (filter n and N_z of eq. phieq), as max > 0
     const int nbs[4] = {own - 1, own + 1, own - ROW, own + ROW};
+    // the fast form starts its sums from the first term (no added zero) and
+    // sums 2 Mc_face (mu_k - mu) for the flux, halved once at the end; without
+    // c, mu and Mc are zero on every point, so the flux is zero unguarded
     T lap[N], mx[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
@@ -264,7 +286,7 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 const T v = lds[a * PLANE + nbs[k]];
-                lap[a] = lap[a] + v;
+                lap[a] = (FAST && k == 0) ? v : lap[a] + v;
                 mx[a] = max_num(mx[a], v);
             }
             muk = lds[N * PLANE + nbs[k]];
@@ -279,9 +301,10 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
             muk = k == 4 ? mu_p : mu_n;
             mck = k == 4 ? mc_p : mc_n;
         }
-        if (withc) {
-            if constexpr (FAST) flux = fma_t(T(0.5) * (mc_c + mck), muk - mu_c, flux);
-            else flux = flux + (T(0.5) * (mc_c + mck)) * (muk - mu_c);
+        if constexpr (FAST) {
+            flux = k == 0 ? (mc_c + mck) * (muk - mu_c) : fma_t(mc_c + mck, muk - mu_c, flux);
+        } else if (withc) {
+            flux = flux + (T(0.5) * (mc_c + mck)) * (muk - mu_c);
         }
     }
     unsigned act = 0u;
@@ -298,28 +321,28 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
     // variational derivative delta_a = sum_{b != a} (A_ab Lap phi_b +
     // B_ab phi_b) + psi_{type(a)}(mu)
     // grand potential psi_a(mu) = -mu^2/(2k_a) - mu c0_a (Sec. 2)
+    // (the fast form needs no guard: without c, mu = 0 gives psi = -0)
     T psi[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-        if (!withc) psi[a] = T(0);
-        else if constexpr (FAST) psi[a] = fma_t(-(mu_c * mu_c), kc[3 * N + a], -(mu_c * kc[a]));
+        if constexpr (FAST) psi[a] = fma_t(-(mu_c * mu_c), kc[3 * N + a], -(mu_c * kc[a]));
+        else if (!withc) psi[a] = T(0);
         else psi[a] = (-mu_c * mu_c) / P.k2[a] - mu_c * P.c0[a];
     }
     T delta[N];
     const T inz = FAST ? fast_rcp(T(nzc > 0 ? nzc : 1)) : T(1) / T(nzc > 0 ? nzc : 1);
     if (FAST && P.uniform) {
         const T A0 = pair[1], B0 = pair[N * N + 1], L0 = pair[2 * N * N + 1];
-        T slap = T(0), sp = T(0);
+        T slap = lap[0], sp = cur[0];
 #pragma unroll
-        for (int a = 0; a < N; ++a) {
+        for (int a = 1; a < N; ++a) {
             slap += lap[a];
             sp += cur[a];
         }
         T dact = T(0);
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            T s = fma_t(A0, slap - lap[a], B0 * (sp - cur[a]));
-            if (withc) s += psi[a];
+            const T s = fma_t(A0, slap - lap[a], B0 * (sp - cur[a])) + psi[a];
             delta[a] = s;
             if ((act >> a) & 1u) dact += s;
         }
@@ -359,7 +382,8 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
             r[a] = ra;
         }
     }
-    r[N] = withc ? flux * idx2 : T(0);
+    if constexpr (FAST) r[N] = flux * (T(0.5) * idx2);
+    else r[N] = withc ? flux * idx2 : T(0);
 }
 
 // Stage combination, projection and store at one cell (byte offset idx in a
@@ -500,11 +524,12 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
 // One tile (logical index L) of one stage.  Every thread of the block calls
 // it with the same arguments (it synchronises the block).  GS: planes per
 // buffer group of the vectors (see set_field_bases).  TABLES: stage the LDS
-// tables of A.P first (false: the caller has staged them).
+// tables of A.P first (false: the caller has staged them).  t: the tile's
+// index and coordinates (tile_index, or kept by a caller that walks tiles).
 // The tile is 64 x TY cells, TY = tile_rows(DIM); thread (lx, ly) computes the
 // R = TY / 4 cells (lx, ly + 4 k) of its column (3D: R = 1, marched in z).
 template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true>
-__device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T *__restrict__ lds,
+__device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx t, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
     constexpr int LCP = operand_load_cp<DIM>(), SCP = out_store_cp<DIM>();
@@ -518,7 +543,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
     const KConsts<T> &P = A.K;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const bool withc = P.with_c != 0;
-    const bool tile_ok = L < A.ntiles;  // uniform over the block
+    const bool tile_ok = t.L < A.ntiles;  // uniform over the block
 
     double acc = 0.0;
     long long cnt = 0;
@@ -528,25 +553,29 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
             stage_tables<T, N>(A.P, pair, kc);
             __syncthreads();  // the tables are read from the first plane on
         }
-        const int tix = L % A.ntx;
-        const int rest = L / A.ntx;
-        const int tiy = rest % A.nty;
-        const int tiz = rest / A.nty;
+        const int tix = t.tix, tiy = t.tiy, tiz = t.tiz;
         const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
         const long long nxy = (long long)nx * ny;
         // own slots hold the periodically wrapped cells
         int own_slot[R];
         long long col[R];
         bool active[R];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            own_slot[k] = (ly + TILE_Y * k + 1) * TXH + (lx + 1);
-            own_column(tix, tiy, TY, lx, ly + TILE_Y * k, nx, ny, col[k], active[k]);
-        }
         const bool has_halo = threadIdx.x < 2 * TX + 2 * TY;
         long long hcol = 0;
         int hslot = 0;
-        if (has_halo) halo_column(tix, tiy, TY, threadIdx.x, nx, ny, hcol, hslot);
+        auto columns = [&](auto general) __attribute__((always_inline)) {
+            constexpr bool G = decltype(general)::value;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                own_slot[k] = (ly + TILE_Y * k + 1) * TXH + (lx + 1);
+                own_column<G>(tix, tiy, TY, lx, ly + TILE_Y * k, nx, ny, col[k], active[k]);
+            }
+            if (has_halo) halo_column<G>(tix, tiy, TY, threadIdx.x, nx, ny, hcol, hslot);
+        };
+        if (wrap_fits(A.ntx, TX, nx) && wrap_fits(A.nty, TY, ny))
+            columns(std::false_type{});
+        else
+            columns(std::true_type{});
 
         const int z0 = DIM == 3 ? tiz * A.zchunk : 0;
         const int z1 = DIM == 3 ? min(z0 + A.zchunk, nz) : 1;
@@ -636,8 +665,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const int L, T
     if constexpr (KIND == K_EST) {
         block_sum(acc, cnt);
         if (threadIdx.x == 0 && tile_ok) {
-            A.red[L] = acc;
-            A.redn[L] = cnt;
+            A.red[t.L] = acc;
+            A.redn[t.L] = cnt;
         }
     }
 }
@@ -665,8 +694,8 @@ constexpr int min_waves_per_eu() {
         __shared__ T lds[lds_elems<T, N, DIM>()];                                          \
         __shared__ T pair[3 * N * N];                                                      \
         __shared__ T kc[4 * N];                                                            \
-        stage_body<T, DIM, N, kind, group_planes(N, NG)>(A, xcd_logical_block(), lds, pair, \
-                                                         kc);                              \
+        stage_body<T, DIM, N, kind, group_planes(N, NG)>(                                  \
+            A, tile_index(xcd_logical_block(), A.ntx, A.nty), lds, pair, kc);              \
     }
 PF_STAGE_KERNEL(rhs_kernel, K_RHS)
 PF_STAGE_KERNEL(euler_stage_kernel, K_EULER)
@@ -730,7 +759,7 @@ __device__ __forceinline__ void euler_point(const KConsts<T> &P, const T *__rest
 // Buffers: the state is read from A.gb[0][0] and written to A.gb[4][0] (one
 // buffer group each).
 template <typename T, int N>
-__device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, T *__restrict__ in,
+__device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const TileIdx t, T *__restrict__ in,
                                             T *__restrict__ mid, const T *__restrict__ pair,
                                             const T *__restrict__ kc, const T dt1, const T dt2,
                                             const bool two) {
@@ -740,21 +769,29 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const int L, 
     const int nx = P.nx, ny = P.ny;
     const bool withc = P.with_c != 0;
     constexpr int TY = tile_rows(2), R = TY / TILE_Y;  // tile height, cells per thread
-    const int tix = L % A.ntx, tiy = L / A.ntx;
+    const int tix = t.tix, tiy = t.tiy;
     const int x0 = tix * TILE_X - 2, y0 = tiy * TY - 2;  // corner of the input region
+    const bool fits = wrap_fits(A.ntx, TILE_X, nx) && wrap_fits(A.nty, TY, ny);
 
     // input region: every load is issued before the first use of one
     constexpr int NP0 = (F2_IN + 255) / 256;
     T v[NP0][N + 1];
+    auto load_region = [&](auto general) __attribute__((always_inline)) {
+        constexpr bool G = decltype(general)::value;
 #pragma unroll
-    for (int k = 0; k < NP0; ++k) {
-        const int p = threadIdx.x + 256 * k;
-        if (p < F2_IN) {
-            const int px = p % F2_IN_X, py = p / F2_IN_X;
-            const long long col = (long long)wrap_index(y0 + py, ny) * nx + wrap_index(x0 + px, nx);
-            load_point32<T, N, N + 1>(A, 0, (unsigned)col * (unsigned)sizeof(T), withc, v[k]);
+        for (int k = 0; k < NP0; ++k) {
+            const int p = threadIdx.x + 256 * k;
+            if (p < F2_IN) {
+                const int px = p % F2_IN_X, py = p / F2_IN_X;
+                const long long col = (long long)wrap_index<G>(y0 + py, ny) * nx + wrap_index<G>(x0 + px, nx);
+                load_point32<T, N, N + 1>(A, 0, (unsigned)col * (unsigned)sizeof(T), withc, v[k]);
+            }
         }
-    }
+    };
+    if (fits)
+        load_region(std::false_type{});
+    else
+        load_region(std::true_type{});
 #pragma unroll
     for (int k = 0; k < NP0; ++k) {
         const int p = threadIdx.x + 256 * k;
@@ -849,6 +886,7 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
     int i = B.tile_inst[g0] - 1;
     int tile0 = 0, end = g0;  // tiles [tile0, end) belong to instance i
     StageArgs<T> A = {};
+    TileIdx t = {0, 0, 0, 0};
     T dt2 = T(0);
     bool two = false;
     for (int g = g0; g < g1; ++g) {
@@ -909,14 +947,20 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
             A.nty = I.nty;
             A.nzc = 1;
             A.ntiles = I.ntx * I.nty;
+            t = tile_index(g - tile0, A.ntx, A.nty);  // later tiles step in x, then y
             // the previous tile's last barrier follows its last table read
             stage_tables<T, N>(B.params + i, pair, kc);
             __syncthreads();
         }
         if constexpr (KIND == K_EULER && DEPTH == 2)
-            euler2_tile<T, N>(A, g - tile0, lds, lds + (N + 3) * F2_IN, pair, kc, A.a, dt2, two);
+            euler2_tile<T, N>(A, t, lds, lds + (N + 3) * F2_IN, pair, kc, A.a, dt2, two);
         else
-            stage_body<T, 2, N, KIND, N + 1, false>(A, g - tile0, lds, pair, kc);
+            stage_body<T, 2, N, KIND, N + 1, false>(A, t, lds, pair, kc);
+        ++t.L;
+        if (++t.tix == A.ntx) {
+            t.tix = 0;
+            ++t.tiy;
+        }
     }
 }
 
