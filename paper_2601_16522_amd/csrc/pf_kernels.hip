@@ -107,6 +107,9 @@ __global__ void __launch_bounds__(256)
 finalize_norm_kernel(const double *red, const long long *redn, int n, double *out, double seq) {
     double acc = 0.0;
     long long cnt = 0;
+    // unrolled so that the loads of several partials are in flight at once;
+    // each thread still adds its partials in index order
+#pragma unroll 16
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         acc += red[i];
         cnt += redn[i];

@@ -405,17 +405,27 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
         // entry whose trial value u^n + dt/2 (R0 + rhs(u^{n+1})) leaves
         // [0,1] has zero error; weights r max(|u^n|,|u^{n+1}|) + a; the
         // two-DoF rule for cells without nontrivial phi entries
+        // (the fast form multiplies by 1/15 and by a hardware reciprocal of
+        // the weight: a control quantity, where an ulp does not matter)
+        const auto quot = [](T x, T y) __attribute__((always_inline)) {
+            if constexpr (FAST) return x * fast_rcp(y);
+            else return x / y;
+        };
+        const auto est = [&](T u_n, T u_1, T rs) __attribute__((always_inline)) {
+            if constexpr (FAST) return (T(12) * (u_n - u_1) + A.dt6 * rs) * T(1.0 / 15.0);
+            else return (T(12) * (u_n - u_1) + A.dt6 * rs) / T(15);
+        };
         int nt = 0;
 #pragma unroll
         for (int a = 0; a < N; ++a) {
             const T u_n = o0[a];
             const T rs = o2[a] + r[a];
-            T e = (T(12) * (u_n - cur[a]) + A.dt6 * rs) / T(15);
+            T e = est(u_n, cur[a], rs);
             const T trial = u_n + A.hdt * rs;
             if (trial < T(0) || trial > T(1)) e = T(0);
             if (e != T(0)) {
                 const T w = A.r_phi * tmax(tabs(u_n), tabs(cur[a])) + A.a_phi;
-                const T q = e / w;
+                const T q = quot(e, w);
                 acc += (double)q * (double)q;
                 ++nt;
             }
@@ -424,9 +434,9 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
         if (withc) {
             const T u_n = o0[N];
             const T rs = o2[N] + r[N];
-            const T e = (T(12) * (u_n - cur[N]) + A.dt6 * rs) / T(15);
+            const T e = est(u_n, cur[N], rs);
             const T w = A.r_c * tmax(tabs(u_n), tabs(cur[N])) + A.a_c;
-            const T q = e / w;
+            const T q = quot(e, w);
             acc += (double)q * (double)q;
             cnt += 1;
         }
@@ -480,10 +490,18 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
             bool changed = false;
 #pragma unroll
             for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
+            // (the fast form multiplies by a hardware reciprocal of mut_1 dt)
+            T inv_a = T(0);
+            if constexpr (FAST) inv_a = fast_rcp(A.a);
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 stv<T, GS, SCP>(A, 4, a, idx, ys[a]);
-                stv<T, GS, SCP>(A, 5, a, idx, changed ? (ys[a] - cur[a]) / A.a : r[a]);
+                T ra = r[a];
+                if (changed) {
+                    if constexpr (FAST) ra = (ys[a] - cur[a]) * inv_a;
+                    else ra = (ys[a] - cur[a]) / A.a;
+                }
+                stv<T, GS, SCP>(A, 5, a, idx, ra);
             }
             if (withc) {
                 stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
