@@ -269,6 +269,25 @@ pf_status pf_batch_stable_dt(pf_batch *b, int i, double *dt_e);
  * stats (optional) is [n]. */
 pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
                           const double *dt, int graph_steps, pf_stats *stats);
+/* Adaptive RKL2 steps of every instance to its t_end[i] (Sec. 3.3): each
+ * instance runs the loop of pf_run_to with tol (Sommeijer estimate of eq.
+ * sts with the phi filter, the weighted norm with its degree-of-freedom rule,
+ * the PID controller with bias and limiter, exact t_end), with a controller of
+ * its own that starts fresh (first step tol->dt0, or 0.9 dt_e of the instance
+ * when tol->dt0 <= 0), so every instance takes bit for bit the steps of a fresh
+ * single-instance pf_run_to(PF_RKL2, t_end[i], tol).  A batch step runs the
+ * stages, the estimate and the norms of all instances still running in
+ * batched launches and returns the norms to the host once; rejected instances
+ * keep their state.  integ must be PF_RKL2 (else PF_EUNSUPPORTED).  Errors:
+ * PF_EINVAL for negative tolerances, a field kind with zero weight or t_end[i]
+ * before the instance's time; PF_EDTMIN on a step underflow; PF_ENONFINITE
+ * after three non-finite norms of one instance in a row (the instances keep
+ * their last accepted states).  Allocates the adaptive work buffers (the new
+ * state, per-tile partials, norms) on the first call.  stats (optional) is [n]:
+ * accepted and rejected steps, stages, RHS evaluations (estimate included),
+ * last step, last norm and t of each instance. */
+pf_status pf_batch_run_adaptive(pf_batch *b, pf_integrator integ, const double *t_end,
+                                const pf_tol *tol, pf_stats *stats);
 /* Times one launch for each persistent grid size (512..8192 blocks) and each
  * fusion depth the instances allow (the state is only read) and keeps the
  * fastest per step; best_ms is that time per step.  pf_batch_set_blocks sets

@@ -37,7 +37,7 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_get_tiling", "pf_autotune", "pf_set_timing", "pf_get_kernel_time",
            "pf_supported_nphi", "pf_last_error", "pf_batch_create", "pf_batch_destroy",
            "pf_batch_set_stream", "pf_batch_init_fields", "pf_batch_get_fields",
-           "pf_batch_stable_dt", "pf_batch_run_to", "pf_batch_autotune", "pf_batch_set_blocks",
+           "pf_batch_stable_dt", "pf_batch_run_to", "pf_batch_run_adaptive", "pf_batch_autotune", "pf_batch_set_blocks",
            "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error",
            "pf_params_stable_dt", "pf_rkl_stage_count", "pf_controller_init",
            "pf_controller_update", "pf_clip_step", "pf_set_timing_families"]
@@ -154,6 +154,7 @@ def lib():
             "pf_batch_get_fields": [vp, i, pd, pd],
             "pf_batch_stable_dt": [vp, i, pd],
             "pf_batch_run_to": [vp, i, pd, pd, i, C.POINTER(_Stats)],
+            "pf_batch_run_adaptive": [vp, i, pd, C.POINTER(_Tol), C.POINTER(_Stats)],
             "pf_batch_autotune": [vp, C.POINTER(i), pd],
             "pf_batch_set_blocks": [vp, i],
             "pf_batch_set_fusion": [vp, i],
@@ -330,6 +331,17 @@ class Batch:
         self._chk(self._L.pf_batch_run_to(self._h, INTEGRATORS[integ], _dp(te),
                                           _dp(dtv) if dtv is not None else None,
                                           int(graph_steps), st))
+        return [Stats(*[getattr(x, f) for f, _ in _Stats._fields_]) for x in st]
+
+    def run_adaptive(self, t_end, tol: "Tol", integ: str = "rkl2"):
+        """Adaptive steps of every instance to its t_end, each with a fresh
+        controller of its own (pf_batch_run_adaptive)."""
+        te = np.ascontiguousarray(t_end, dtype=np.float64)
+        if te.size != self.n:
+            raise ValueError("t_end needs one value per instance")
+        st = (_Stats * self.n)()
+        ctol = tol._c()
+        self._chk(self._L.pf_batch_run_adaptive(self._h, INTEGRATORS[integ], _dp(te), C.byref(ctol), st))
         return [Stats(*[getattr(x, f) for f, _ in _Stats._fields_]) for x in st]
 
     def autotune(self):

@@ -1321,6 +1321,16 @@ struct pf_batch {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_k = 0, graph_depth = 0, graph_blocks = 0, graph_integ = -1, graph_stages = 0;
+    // adaptive runs (allocated on the first): the new state, per-tile error
+    // partials, per-instance control words (tile0, tiles, active, accepted),
+    // state offsets and lengths, norms, and the host-visible copy of the norms
+    // followed by their sequence number
+    void *bufY = nullptr;
+    double *dred = nullptr, *dnorm = nullptr;
+    long long *dredn = nullptr, *dlen = nullptr;
+    int *dctl = nullptr;
+    double *hnorm = nullptr, *hnorm_dev = nullptr;
+    double norm_seq = 0.0;
     std::string err;
 };
 
@@ -1568,6 +1578,221 @@ pf_status batch_rkl2_buffers(pf_batch *b) {
 }
 
 template <typename T>
+pf_status batch_adaptive_buffers(pf_batch *b) {
+    if (b->hnorm) return PF_OK;
+    const int n = b->n;
+    if (hipMalloc(&b->bufY, b->total * b->esz) != hipSuccess ||
+        hipMalloc((void **)&b->dred, sizeof(double) * b->total_tiles) != hipSuccess ||
+        hipMalloc((void **)&b->dredn, sizeof(long long) * b->total_tiles) != hipSuccess ||
+        hipMalloc((void **)&b->dnorm, sizeof(double) * 3 * n) != hipSuccess ||
+        hipMalloc((void **)&b->dctl, sizeof(int) * 4 * n) != hipSuccess ||
+        hipMalloc((void **)&b->dlen, sizeof(long long) * 2 * n) != hipSuccess)
+        return bfail(b, PF_ENOMEM, "batch adaptive buffers");
+    BHIPCHK(b, hipMemset(b->bufY, 0, b->total * b->esz));
+    std::vector<long long> ol(2 * n);
+    for (int i = 0; i < n; ++i) {
+        ol[i] = b->off[i];
+        ol[n + i] = (long long)b->meta[i].F * b->meta[i].V;
+    }
+    BHIPCHK(b, hipMemcpy(b->dlen, ol.data(), sizeof(long long) * 2 * n, hipMemcpyHostToDevice));
+    void *h = nullptr;
+    if (hipHostMalloc(&h, sizeof(double) * (3 * n + 1), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return bfail(b, PF_ENOMEM, "batch norm buffer");
+    b->hnorm = (double *)h;
+    for (int k = 0; k <= 3 * n; ++k) b->hnorm[k] = 0.0;
+    BHIPCHK(b, hipHostGetDevicePointer((void **)&b->hnorm_dev, h, 0));
+    return PF_OK;
+}
+
+// Polls the host-visible norm buffer for sequence number seq (see wait_result).
+pf_status batch_wait_norms(pf_batch *b, double seq) {
+    volatile const double *flag = b->hnorm + 3 * b->n;
+    for (unsigned long it = 1;; ++it) {
+        if (*flag == seq) break;
+        if ((it & 4095u) == 0) {
+            const hipError_t q = hipStreamQuery(b->stream);
+            if (q == hipSuccess) {
+                if (*flag == seq) break;
+                return bfail(b, PF_EHIP, "norm results missing after the stream drained");
+            }
+            if (q != hipErrorNotReady) return bfail(b, PF_EHIP, "stream: %s", hipGetErrorString(q));
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return PF_OK;
+}
+
+// Adaptive RKL2 steps of every instance to its t_end (Sec. 3.3): each instance
+// runs the single-instance adaptive loop of run_to_t with its own controller,
+// step and stage count.  One batch step launches the stages of all instances
+// still running (each with its own coefficients; the last stage writes the new
+// state into bufY), the estimate, the per-instance norms and their copy to the
+// host; the host updates every controller, and a copy kernel moves the new
+// state of the accepted instances into the state buffer.  A rejected instance
+// keeps its state and retries with the controller's smaller step.
+template <typename T>
+pf_status batch_run_adaptive(pf_batch *b, const double *t_end, const pf_tol &tol, pf_stats *stats) {
+    pf_status rc;
+    if ((rc = batch_rkl2_buffers<T>(b)) || (rc = batch_adaptive_buffers<T>(b))) return rc;
+    if (b->gexec) {  // the coefficient table may move; a cached graph would refer to it
+        hipGraphExecDestroy(b->gexec);
+        hipGraphDestroy(b->graph);
+        b->gexec = nullptr;
+        b->graph = nullptr;
+    }
+    const int n = b->n;
+    const double ratio = tol.dt_max_over_dte > 0.0 ? tol.dt_max_over_dte : 200.0;
+    std::vector<double> dte(n), dt(n), h(n);
+    std::vector<pf_controller> ctrl(n, ctrl_initial());
+    std::vector<pf_stats> st(n, pf_stats{});
+    std::vector<int> nonfinite(n, 0), done(n, 0), ns(n, 0), ctl(4 * n);
+    std::vector<char> last(n, 0);
+    std::vector<BatchInst<T>> I(n);
+    std::vector<T> cf;
+    long long max_len = 1;
+    for (int i = 0; i < n; ++i) {
+        dte[i] = stable_dt(&b->meta[i]);
+        dt[i] = tol.dt0 > 0.0 ? tol.dt0 : 0.9 * dte[i];
+        max_len = std::max(max_len, (long long)b->meta[i].F * b->meta[i].V);
+    }
+    const int zero = 0;
+    BHIPCHK(b, hipMemcpyAsync(b->dstep, &zero, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    pf_status fail_rc = PF_OK;
+    while (!fail_rc) {
+        int active = 0, max_s = 1;
+        for (int i = 0; i < n; ++i) {
+            BatchInst<T> &q = I[i];
+            q = BatchInst<T>{};
+            q.off = b->off[i];
+            q.ntx = b->ntx[i];
+            q.nty = b->nty[i];
+            q.tile0 = b->tile0[i];
+            ctl[4 * i] = b->tile0[i];
+            ctl[4 * i + 1] = b->ntx[i] * b->nty[i];
+            ctl[4 * i + 2] = ctl[4 * i + 3] = 0;
+            if (done[i]) continue;
+            bool li;
+            if (!clip_step(b->t[i], t_end[i], std::min(dt[i], ratio * dte[i]), h[i], li)) {
+                done[i] = 1;
+                continue;
+            }
+            if (!li && h[i] < 1e-12 * dte[i])
+                return bfail(b, PF_EDTMIN, "instance %d: adaptive step underflow (dt = %g)", i, h[i]);
+            last[i] = li;
+            ns[i] = stage_count(2, h[i], dte[i]);
+            if (ns[i] < 1) return bfail(b, PF_EINVAL, "instance %d: bad step %g", i, h[i]);
+            q.nsteps = q.nfull = 1;
+            q.s_full = q.s_last = ns[i];
+            q.dt = q.dt_last = (T)h[i];
+            q.dt6 = (T)(6.0 * h[i]);
+            q.hdt = (T)(h[i] / 2.0);
+            ctl[4 * i + 2] = 1;
+            ++active;
+            max_s = std::max(max_s, ns[i]);
+        }
+        if (!active) break;
+        // coefficients of every running instance's step, as the single-instance
+        // step passes them (row 2 i: a full step)
+        b->coef_stride = max_s + 1;
+        cf.assign((size_t)n * 2 * b->coef_stride * 6, T(0));
+        for (int i = 0; i < n; ++i) {
+            if (!ctl[4 * i + 2]) continue;
+            for (int j = 1; j <= ns[i]; ++j) {
+                double mu, nu, mut, gam;
+                rkl_coeffs(2, ns[i], j, mu, nu, mut, gam);
+                T *e = &cf[((size_t)(2 * i) * b->coef_stride + j) * 6];
+                if (j == 1) {
+                    e[0] = (T)(mut * h[i]);
+                } else {
+                    e[0] = (T)((1.0 - mu) - nu);
+                    e[1] = (T)mu;
+                    e[2] = (T)nu;
+                    e[3] = (T)h[i];
+                    e[4] = (T)mut;
+                    e[5] = (T)gam;
+                }
+            }
+        }
+        const size_t bytes = cf.size() * sizeof(T);
+        if (bytes > b->coef_bytes) {
+            BHIPCHK(b, hipStreamSynchronize(b->stream));
+            if (b->dcoef) hipFree(b->dcoef);
+            b->dcoef = nullptr;
+            b->coef_bytes = 0;
+            BHIPCHK(b, hipMalloc(&b->dcoef, bytes));
+            b->coef_bytes = bytes;
+        }
+        BHIPCHK(b, hipMemcpyAsync(b->dcoef, cf.data(), bytes, hipMemcpyHostToDevice, b->stream));
+        BHIPCHK(b, hipMemcpyAsync(b->dinst, I.data(), sizeof(BatchInst<T>) * n, hipMemcpyHostToDevice,
+                                  b->stream));
+        BHIPCHK(b, hipMemcpyAsync(b->dctl, ctl.data(), sizeof(int) * 4 * n, hipMemcpyHostToDevice,
+                                  b->stream));
+        hipError_t e = hipSuccess;
+        for (int j = 1; j <= max_s && e == hipSuccess; ++j) {
+            BatchArgs<T> B = batch_rkl2_args<T>(b, 0, j);
+            B.state = (T *)b->bufY;
+            e = launch_batch_euler<T>(b->N, B, b->nblocks, b->stream);
+        }
+        if (e == hipSuccess) {
+            BatchArgs<T> B = batch_args<T>(b, 0, 1);
+            B.kind = K_EST;
+            B.role[0] = (const T *)b->bufY;
+            B.role[2] = (const T *)b->bufA;
+            B.role[3] = (const T *)b->bufR0;
+            B.red = b->dred;
+            B.redn = b->dredn;
+            B.r_phi = (T)tol.r_phi; B.a_phi = (T)tol.a_phi;
+            B.r_c = (T)tol.r_c; B.a_c = (T)tol.a_c;
+            e = launch_batch_euler<T>(b->N, B, b->nblocks, b->stream);
+        }
+        if (e == hipSuccess) e = launch_finalize_norm_batch(b->dred, b->dredn, b->dctl, n, b->dnorm, b->stream);
+        b->norm_seq += 1.0;
+        if (e == hipSuccess) e = launch_publish(b->dnorm, 3 * n, b->hnorm_dev, b->norm_seq, b->stream);
+        if (e != hipSuccess) return bfail(b, PF_EHIP, "batch adaptive step: %s", hipGetErrorString(e));
+        if ((rc = batch_wait_norms(b, b->norm_seq))) return rc;
+        int accepted = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!ctl[4 * i + 2]) continue;
+            const double err = b->hnorm[3 * i + 2];
+            bool acc;
+            const double hn = ctrl_update(ctrl[i], 2, err, h[i], acc);
+            st[i].rhs_evals += ns[i] + 1;
+            st[i].stages += ns[i];
+            st[i].last_err = err;
+            if (acc) {
+                ctl[4 * i + 3] = 1;
+                ++accepted;
+                b->t[i] = last[i] ? t_end[i] : b->t[i] + h[i];
+                st[i].accepted++;
+                st[i].last_dt = h[i];
+                nonfinite[i] = 0;
+            } else {
+                st[i].rejected++;
+                if (!std::isfinite(err) && ++nonfinite[i] >= 3 && !fail_rc)
+                    fail_rc = bfail(b, PF_ENONFINITE, "instance %d: non-finite error norm three times in a row", i);
+            }
+            dt[i] = hn;
+        }
+        if (accepted) {
+            BHIPCHK(b, hipMemcpyAsync(b->dctl, ctl.data(), sizeof(int) * 4 * n, hipMemcpyHostToDevice,
+                                      b->stream));
+            e = launch_batch_accept<T>((const T *)b->bufY, (T *)b->bufA, b->dlen, b->dlen + n, b->dctl, n,
+                                       max_len, b->stream);
+            if (e != hipSuccess) return bfail(b, PF_EHIP, "batch accept: %s", hipGetErrorString(e));
+        }
+        // the host tables are rewritten next step: their copies must be done
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+    }
+    if (stats)
+        for (int i = 0; i < n; ++i) {
+            stats[i] = st[i];
+            stats[i].t = b->t[i];
+        }
+    return fail_rc;
+}
+
+template <typename T>
 pf_status batch_run(pf_batch *b, int integ, const double *t_end, const double *dt, int graph_k,
                     pf_stats *stats) {
     pf_status rc;
@@ -1676,10 +1901,12 @@ pf_status pf_batch_destroy(pf_batch *b) {
     if (b->stream) hipStreamSynchronize(b->stream);
     if (b->gexec) hipGraphExecDestroy(b->gexec);
     if (b->graph) hipGraphDestroy(b->graph);
-    void *ptrs[10] = {b->bufA, b->bufB, b->dparams, b->dinst, b->dtile, b->dstep,
-                      b->bufQ2, b->bufS0, b->bufR0, b->dcoef};
+    void *ptrs[16] = {b->bufA, b->bufB, b->dparams, b->dinst, b->dtile, b->dstep,
+                      b->bufQ2, b->bufS0, b->bufR0, b->dcoef, b->bufY, b->dred,
+                      b->dredn, b->dnorm, b->dctl, b->dlen};
     for (void *q : ptrs)
         if (q) hipFree(q);
+    if (b->hnorm) hipHostFree(b->hnorm);
     if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
     delete b;
     return PF_OK;
@@ -1818,6 +2045,21 @@ pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
         if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
     return b->prec == PF_FP64 ? batch_run<double>(b, integ, t_end, dt, graph_steps, stats)
                               : batch_run<float>(b, integ, t_end, dt, graph_steps, stats);
+}
+
+pf_status pf_batch_run_adaptive(pf_batch *b, pf_integrator integ, const double *t_end,
+                                const pf_tol *tol, pf_stats *stats) {
+    if (!b || !t_end || !tol) return PF_EINVAL;
+    if (integ != PF_RKL2) return bfail(b, PF_EUNSUPPORTED, "adaptive batches take RKL2 steps");
+    if (!(tol->r_phi >= 0.0 && tol->a_phi >= 0.0 && tol->r_c >= 0.0 && tol->a_c >= 0.0) ||
+        !(tol->a_phi > 0.0 || tol->r_phi > 0.0) || !(tol->a_c > 0.0 || tol->r_c > 0.0))
+        return bfail(b, PF_EINVAL, "tolerances must be >= 0 with a nonzero weight per field kind");
+    for (int i = 0; i < b->n; ++i) {
+        if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
+        if (!(t_end[i] >= b->t[i])) return bfail(b, PF_EINVAL, "instance %d: t_end before t", i);
+    }
+    return b->prec == PF_FP64 ? batch_run_adaptive<double>(b, t_end, *tol, stats)
+                              : batch_run_adaptive<float>(b, t_end, *tol, stats);
 }
 
 pf_status pf_batch_autotune(pf_batch *b, int *nblocks, double *best_ms) {

@@ -142,6 +142,7 @@ struct BatchInst {
     int nfull;         // steps of size dt; step nfull (if < nsteps) uses dt_last
     int s_full, s_last;  // RKL stage counts of a full and of the clipped step
     T dt, dt_last;
+    T dt6, hdt;        // 6 dt and dt / 2 of the step (error estimate), rounded from double
 };
 
 // Stage-fusion depth 2 of the batched forward-Euler kernel: a tile computes
@@ -174,12 +175,17 @@ struct BatchArgs {
     // unused), the state vector (an instance's last stage writes its result
     // there), and the stage coefficients a..f per (instance, full / clipped
     // step, stage): coef[((2 i + clipped) * coef_stride + j) * 6 + 0..5]
-    int kind;                    // K_EULER (forward Euler), K_RKL2_FIRST or K_RKL2
+    int kind;                    // K_EULER, K_RKL2_FIRST, K_RKL2 or K_EST
     int stage;
     const T *role[6];
     T *state;
     const T *coef;
     int coef_stride;
+    // error-estimate launches (K_EST, roles y1 = u^{n+1}, u0 = u^n, r0 = R0):
+    // per-tile partials at the global tile index, the norm's tolerances
+    double *red;
+    long long *redn;
+    T r_phi, a_phi, r_c, a_c;
 };
 
 // Launchers (implemented in pf_kernels.hip).  Return hipSuccess or the launch
@@ -199,6 +205,19 @@ hipError_t launch_finalize_norm(const double *red, const long long *redn, int np
                                 double *out, double seq, hipStream_t stream);
 hipError_t launch_finalize_diag(const double *red, int nparts, double *out,
                                 hipStream_t stream);
+// Batched adaptive steps: per-instance norms from per-tile partials (ctl holds
+// tile0, tile count, active flag and accept flag per instance; one block per
+// instance, each in the single-instance finalisation's order) into out[3 i ..];
+// the copy of out[0 .. 3 n) to host-visible memory followed by the sequence
+// number seq at host_out[3 n]; the copy of each accepted instance's new state
+// (len[i] elements at off[i]) from src to dst.
+hipError_t launch_finalize_norm_batch(const double *red, const long long *redn, const int *ctl, int n,
+                                      double *out, hipStream_t stream);
+hipError_t launch_publish(const double *src, int count, double *host_out, double seq,
+                          hipStream_t stream);
+template <typename T>
+hipError_t launch_batch_accept(const T *src, T *dst, const long long *off, const long long *len,
+                               const int *ctl, int n, long long max_len, hipStream_t stream);
 template <typename T>
 hipError_t launch_batch_euler(int nphi, const BatchArgs<T> &args, int nblocks, hipStream_t stream);
 hipError_t launch_batch_tick(int *step_base, int k, hipStream_t stream);

@@ -1,6 +1,8 @@
 // pf_kernels.hip -- reduction and diagnostic kernels, and the dispatch of the
 // fused stage kernels (pf_stage.hpp) over the compiled numbers of order
 // parameters.
+#include <algorithm>
+
 #include "pf_device.hpp"
 
 namespace pf {
@@ -154,6 +156,59 @@ finalize_diag_kernel(const double *red, int n, double *out) {
         for (int k = 0; k < 5; ++k) out[k] = sh[0][k];
 }
 
+// Norms of a batched adaptive step, one block per instance: its per-tile
+// partials red[tile0 .. tile0 + ntiles) summed exactly as finalize_norm_kernel
+// sums a single instance's (thread-strided in index order, then block_sum), so
+// an instance's norm equals the one its single-instance run computes.
+__global__ void __launch_bounds__(256)
+finalize_norm_batch_kernel(const double *red, const long long *redn, const int *ctl, double *out) {
+    const int i = blockIdx.x;
+    const int *c = ctl + 4 * i;  // tile0, ntiles, active, accept
+    double acc = 0.0;
+    long long cnt = 0;
+    if (c[2]) {
+        const double *r = red + c[0];
+        const long long *rn = redn + c[0];
+        const int n = c[1];
+#pragma unroll 16
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            acc += r[k];
+            cnt += rn[k];
+        }
+    }
+    block_sum(acc, cnt);
+    if (threadIdx.x == 0) {
+        out[3 * i] = acc;
+        out[3 * i + 1] = (double)cnt;
+        out[3 * i + 2] = cnt > 0 ? sqrt(acc / (double)cnt) : 0.0;
+    }
+}
+
+// src[0 .. count) to host-visible memory, then the sequence number after it
+// once every value is visible to the host.
+__global__ void __launch_bounds__(256)
+publish_kernel(const double *src, int count, double *host_out, double seq) {
+    for (int k = threadIdx.x; k < count; k += blockDim.x) host_out[k] = src[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        *(volatile double *)(host_out + count) = seq;
+    }
+}
+
+// The new state of each accepted instance (blockIdx.y), len[i] elements from
+// off[i], grid-strided over blockIdx.x.
+template <typename T>
+__global__ void __launch_bounds__(256)
+batch_accept_kernel(const T *src, T *dst, const long long *off, const long long *len, const int *ctl) {
+    const int i = blockIdx.y;
+    if (!ctl[4 * i + 3]) return;
+    const long long o = off[i], n = len[i];
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        dst[o + k] = src[o + k];
+}
+
 // ------------------------------------------------------------------------
 // Dispatch over the compiled (dim, N) instances
 // ------------------------------------------------------------------------
@@ -266,6 +321,35 @@ hipError_t launch_finalize_norm(const double *red, const long long *redn, int np
                        out, seq);
     return hipGetLastError();
 }
+
+hipError_t launch_finalize_norm_batch(const double *red, const long long *redn, const int *ctl, int n,
+                                      double *out, hipStream_t stream) {
+    if (n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(finalize_norm_batch_kernel, dim3(n), dim3(256), 0, stream, red, redn, ctl, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish(const double *src, int count, double *host_out, double seq,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(256), 0, stream, src, count, host_out, seq);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_accept(const T *src, T *dst, const long long *off, const long long *len,
+                               const int *ctl, int n, long long max_len, hipStream_t stream) {
+    if (n < 1 || n > 65535 || max_len < 1) return hipErrorInvalidValue;
+    const long long bx = std::min<long long>((max_len + 1023) / 1024, 4096);
+    hipLaunchKernelGGL((batch_accept_kernel<T>), dim3((unsigned)bx, (unsigned)n), dim3(256), 0, stream,
+                       src, dst, off, len, ctl);
+    return hipGetLastError();
+}
+template hipError_t launch_batch_accept<float>(const float *, float *, const long long *,
+                                               const long long *, const int *, int, long long,
+                                               hipStream_t);
+template hipError_t launch_batch_accept<double>(const double *, double *, const long long *,
+                                                const long long *, const int *, int, long long,
+                                                hipStream_t);
 
 hipError_t launch_finalize_diag(const double *red, int nparts, double *out,
                                 hipStream_t stream) {

@@ -890,12 +890,15 @@ constexpr int batch_lds_elems() {
 // every instance, with the instance's stage count and coefficients for a full
 // or for its clipped last step; the vectors come by role, and an instance's
 // last stage writes the state vector.
+// KIND == K_EST: the error estimate of every instance's step (Sec. 3.3) from
+// the roles u^{n+1}, u^n and R0, one partial sum per tile at the tile's global
+// index.
 template <typename T, int N, int KIND, int DEPTH>
 __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
     __shared__ T lds[batch_lds_elems<T, N, DEPTH>()];
     __shared__ T pair[3 * N * N];
     __shared__ T kc[4 * N];
-    constexpr bool RKL = KIND != K_EULER;
+    constexpr bool RKL = KIND == K_RKL2_FIRST || KIND == K_RKL2;
     const int step = *B.step_base + B.step_offset;
     const long long L = xcd_logical_block();
     const int g0 = (int)(L * B.total_tiles / gridDim.x);
@@ -905,6 +908,10 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
     int tile0 = 0, end = g0;  // tiles [tile0, end) belong to instance i
     StageArgs<T> A = {};
     TileIdx t = {0, 0, 0, 0};
+    if constexpr (KIND == K_EST) {  // the norm's tolerances, the same for every instance
+        A.r_phi = B.r_phi; A.a_phi = B.a_phi;
+        A.r_c = B.r_c; A.a_c = B.a_c;
+    }
     T dt2 = T(0);
     bool two = false;
     for (int g = g0; g < g1; ++g) {
@@ -927,7 +934,19 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
                 A.K.c0[a] = Q.c0[a]; A.K.ik[a] = Q.ik[a]; A.K.Dk[a] = Q.Dk[a];
                 A.K.hik[a] = Q.hik[a]; A.K.k2[a] = Q.k2[a];
             }
-            if constexpr (!RKL) {
+            if constexpr (KIND == K_EST) {
+                const T *r[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) r[v] = B.role[v] ? B.role[v] + I.off : nullptr;
+                A.y1 = r[0]; A.u0 = r[2]; A.r0 = r[3];
+                A.out = nullptr;
+                A.gb[2][0] = A.u0;
+                A.gb[3][0] = A.r0;
+                A.dt6 = I.dt6;
+                A.hdt = I.hdt;
+                A.red = B.red + I.tile0;
+                A.redn = B.redn + I.tile0;
+            } else if constexpr (!RKL) {
                 const bool even = ((step / DEPTH) & 1) == 0;
                 A.y1 = (even ? B.bufA : B.bufB) + I.off;
                 A.out = (even ? B.bufB : B.bufA) + I.off;
@@ -985,7 +1004,9 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
 template <typename T, int N>
 hipError_t launch_batch_euler_n(const BatchArgs<T> &B, int nblocks, hipStream_t stream) {
     const dim3 grid(nblocks), block(256);
-    if (B.kind == K_RKL2_FIRST) {
+    if (B.kind == K_EST) {
+        hipLaunchKernelGGL((batch_kernel<T, N, K_EST, 1>), grid, block, 0, stream, B);
+    } else if (B.kind == K_RKL2_FIRST) {
         hipLaunchKernelGGL((batch_kernel<T, N, K_RKL2_FIRST, 1>), grid, block, 0, stream, B);
     } else if (B.kind == K_RKL2) {
         hipLaunchKernelGGL((batch_kernel<T, N, K_RKL2, 1>), grid, block, 0, stream, B);

@@ -139,6 +139,76 @@ def test_batch_fusion_depth_limits():
         b.close()
 
 
+@pytest.mark.parametrize("prec,dt0", [("fp32", 0.0), ("fp64", 0.0), ("fp32", 30.0), ("fp64", 30.0)])
+def test_batch_adaptive_equals_single_runs_bitwise(prec, dt0):
+    """Adaptive RKL2 of six uneven instances in one batch against fresh
+    single-instance adaptive runs (pf_run_to with the same tolerances): the
+    same accepted and rejected steps, stages, RHS evaluations, end time and
+    last norm, and the same fields bit for bit.  dt0 = 30 starts every
+    instance at 120-240 dt_e, which forces rejections."""
+    wls = small_batch()
+    tol = pf.Tol(r_phi=1e-4, a_phi=1e-3, r_c=1e-4, a_c=1e-4, dt0=dt0)
+    b = pf.Batch([w.param_dict() for w in wls], prec=prec)
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    t_end = [40.0 + 7.5 * i for i in range(len(wls))]
+    st = b.run_adaptive(t_end, tol)
+    rejected = 0
+    for i, w in enumerate(wls):
+        s = pf.Sim(w.param_dict(), prec=prec)
+        s.init_fields(w.u0)
+        ss = s.run_to("rkl2", t_end[i], tol=tol)
+        u, t = s.get_fields()
+        ub, tb = b.get_fields(i)
+        got = (st[i].accepted, st[i].rejected, st[i].stages, st[i].rhs_evals, st[i].last_err)
+        assert got == (ss.accepted, ss.rejected, ss.stages, ss.rhs_evals, ss.last_err), (i, got, ss)
+        assert tb == t == t_end[i]
+        assert np.array_equal(ub, u), i
+        rejected += ss.rejected
+        s.close()
+    print(f"\nbatch adaptive {prec} dt0={dt0}: accepted {[x.accepted for x in st]}, "
+          f"rejected {[x.rejected for x in st]}", flush=True)
+    if dt0 > 0:
+        assert rejected > 0
+    b.close()
+
+
+def test_batch_adaptive_fp64_matches_oracle():
+    """One instance of the adaptive batch against the oracle's adaptive RKL2
+    run: the same accepted and rejected steps, fields to 1e-10."""
+    wls = small_batch()[:3]
+    tol = dict(r_phi=1e-4, a_phi=1e-3, r_c=1e-4, a_c=1e-4)
+    b = pf.Batch([w.param_dict() for w in wls], prec="fp64")
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    t_end = [30.0, 45.0, 25.0]
+    st = b.run_adaptive(t_end, pf.Tol(**tol))
+    for i in (1, 2):
+        P = oracle.Params(**wls[i].param_dict())
+        ref, st_ref, rc = oracle.run_to(P, oracle.RKL2, wls[i].u0, t_end[i], tol=oracle.Tol(**tol))
+        assert rc == 0
+        assert (st[i].accepted, st[i].rejected) == (st_ref.accepted, st_ref.rejected), i
+        u, _ = b.get_fields(i)
+        assert np.abs(u - ref).max() <= 1e-10, i
+    b.close()
+
+
+def test_batch_adaptive_rejects_bad_calls():
+    wls = small_batch()[:2]
+    b = pf.Batch([w.param_dict() for w in wls], prec="fp32")
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    with pytest.raises(pf.PFError) as e:
+        b.run_adaptive([1.0, 1.0], pf.Tol(), integ="fe")
+    assert e.value.code == -7
+    with pytest.raises(pf.PFError) as e:
+        b.run_adaptive([1.0, 1.0], pf.Tol(r_phi=0.0, a_phi=0.0))
+    assert e.value.code == -1
+    st = b.run_adaptive([0.0, 0.0], pf.Tol())  # nothing to do
+    assert all(x.accepted == 0 and x.rejected == 0 for x in st)
+    b.close()
+
+
 def test_batch_rejects_mixed_instances():
     a = pi.single_grain(n=32, R=8.0).param_dict()
     c = dict(pi.voronoi_2d(n=40, n_grains=4, n_phi=3, dmin=5.0).param_dict())
