@@ -133,7 +133,8 @@ def batch_bench(args):
     [0.2, 0.4] side, M in [0.5, 2]): 2000 forward-Euler steps each at 0.9 dt_e,
     as one fused launch per step replayed from a hipGraph in FP32, against the
     plain FP64 form run instance by instance; then the same end times with
-    batched RKL2 steps of --rkl2-dte dt_e."""
+    batched RKL2 steps of --rkl2-dte dt_e, and with adaptive batched RKL2
+    (a controller per instance, the cfg2 tolerances)."""
     import torch
     import paper_2601_16522_amd as pf
     import pf_inputs as pi
@@ -195,6 +196,20 @@ def batch_bench(args):
         rkl2_rhs = sum(x.rhs_evals for x in st_r)
     err_rkl2 = [area_slope_error(w.u0, b.get_fields(i)[0], t_end[i], w.mob[0]) for i, w in enumerate(wls)]
 
+    # the same end times with adaptive RKL2, one controller per instance (Sec. 3.3)
+    tol = pf.Tol(r_phi=1e-4, a_phi=1e-2, r_c=1e-4, a_c=1e-4)
+    ad_ms, st_a = [], []
+    for k in range(max(args.steps, 1) + 1):
+        for i, w in enumerate(wls):
+            b.init_fields(i, w.u0)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        st_a = b.run_adaptive(t_end, tol)
+        stream.synchronize()
+        if k > 0:  # the first run allocates the adaptive buffers
+            ad_ms.append((time.perf_counter() - t0) * 1e3)
+    err_ad = [area_slope_error(w.u0, b.get_fields(i)[0], t_end[i], w.mob[0]) for i, w in enumerate(wls)]
+
     # the plain FP64 form, instance by instance (one launch per step each)
     t64 = 0.0
     err64 = []
@@ -237,7 +252,16 @@ def batch_bench(args):
                    "rkl2_batch": {"step_dt_e": args.rkl2_dte, "rhs_evals": int(rkl2_rhs),
                                   "time_to_solution_ms": round(float(np.mean(rkl2_ms)), 3),
                                   "speedup_vs_fe_batch": round(total / args.steps * 1e3 / float(np.mean(rkl2_ms)), 2),
-                                  "area_rate_rel_error_mean": float(np.mean(err_rkl2))}},
+                                  "area_rate_rel_error_mean": float(np.mean(err_rkl2))},
+                   "rkl2_adaptive_batch": {
+                       "tol": {"r_phi": tol.r_phi, "a_phi": tol.a_phi, "r_c": tol.r_c, "a_c": tol.a_c},
+                       "accepted": int(sum(x.accepted for x in st_a)),
+                       "rejected": int(sum(x.rejected for x in st_a)),
+                       "rhs_evals": int(sum(x.rhs_evals for x in st_a)),
+                       "batch_steps": int(max(x.accepted + x.rejected for x in st_a)),
+                       "time_to_solution_ms": round(float(np.mean(ad_ms)), 3),
+                       "speedup_vs_fe_batch": round(total / args.steps * 1e3 / float(np.mean(ad_ms)), 2),
+                       "area_rate_rel_error_mean": float(np.mean(err_ad))}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": f"batch_kernel (forward Euler, depth {depth}), avg {avg_s * 1e6:.2f} us per launch "
