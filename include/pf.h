@@ -278,7 +278,8 @@ pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
  * single-instance pf_run_to(PF_RKL2, t_end[i], tol).  A batch step runs the
  * stages, the estimate and the norms of all instances still running in
  * batched launches and returns the norms to the host once; rejected instances
- * keep their state.  integ must be PF_RKL2 (else PF_EUNSUPPORTED).  Errors:
+ * keep their state.  integ must be PF_RKL2 and the batch may hold at most
+ * 65535 instances (else PF_EUNSUPPORTED).  Errors:
  * PF_EINVAL for negative tolerances, a field kind with zero weight or t_end[i]
  * before the instance's time; PF_EDTMIN on a step underflow; PF_ENONFINITE
  * after three non-finite norms of one instance in a row (the instances keep

@@ -2051,6 +2051,7 @@ pf_status pf_batch_run_adaptive(pf_batch *b, pf_integrator integ, const double *
                                 const pf_tol *tol, pf_stats *stats) {
     if (!b || !t_end || !tol) return PF_EINVAL;
     if (integ != PF_RKL2) return bfail(b, PF_EUNSUPPORTED, "adaptive batches take RKL2 steps");
+    if (b->n > 65535) return bfail(b, PF_EUNSUPPORTED, "adaptive batches hold at most 65535 instances");
     if (!(tol->r_phi >= 0.0 && tol->a_phi >= 0.0 && tol->r_c >= 0.0 && tol->a_c >= 0.0) ||
         !(tol->a_phi > 0.0 || tol->r_phi > 0.0) || !(tol->a_c > 0.0 || tol->r_c > 0.0))
         return bfail(b, PF_EINVAL, "tolerances must be >= 0 with a nonzero weight per field kind");

