@@ -214,9 +214,11 @@ pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
 
 /* Launch shape of the stencil kernels: tile width tx (64 cells in x: the
  * block is 256 threads over 64 x 4 cells) and the number of z planes a block
- * marches through (3D only, >= 1).  pf_autotune times the z extents 4..256 on
- * the current state and keeps the fastest.  The launch shape never changes a
- * result bit. */
+ * marches through (3D only, >= 1).  pf_autotune times the RKL2 inner stage at
+ * the z extents 4..256 (inputs: the current state and copies of it in three
+ * work buffers, which it allocates if the handle has not yet; the state is only
+ * read), in two interleaved passes keeping each extent's faster time, and
+ * keeps the fastest extent.  The launch shape never changes a result bit. */
 pf_status pf_set_tiling(pf_sim *sim, int tx, int zchunk);
 pf_status pf_get_tiling(pf_sim *sim, int *tx, int *zchunk);
 pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
