@@ -14,8 +14,10 @@ Prints one JSON line (metric of the project: Gcell-stage/s, i.e. cells x RHS
 evaluations per second, with the time to solution and the HBM roofline of the
 dominant kernel, the RKL2 inner stage).
 
-Other modes: --workload pores3d (3D grains + pores, fixed RKL2 steps) for the
-3D kernel, --copy-calib for the rocprofv3 counter calibration copy kernel.
+Other modes: --workload pores3d|gg3d (3D grains + pores, two fixed RKL2 steps;
+with --adaptive, pores3d runs adaptive RKL2 to t_end = 1e-3), --workload batch
+(96 uneven 2D instances), --copy-calib for the rocprofv3 counter calibration
+copy kernel.
 """
 from __future__ import annotations
 
@@ -301,6 +303,9 @@ def main():
                     help="batch: steps per launch (0: the autotuner's choice)")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="batch: steps per captured hipGraph (0: direct launches)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="pores3d: adaptive RKL2 to t_end = 1e-3 with r = a = 1e-4 (the 256^3 "
+                         "sintering run) instead of two fixed steps")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="batch: skip the FP64 instance-by-instance comparison")
     args = ap.parse_args()
@@ -340,6 +345,13 @@ def main():
         tol_kw = dict(r_phi=1e-4, a_phi=1e-2, r_c=1e-4, a_c=1e-4)
         tol = pf.Tol(**tol_kw)
         desc = "adaptive RKL2 t=0..100, a_phi=1e-2, r=a_c=1e-4"
+    elif args.adaptive and args.workload == "pores3d":
+        integ, t_end, dt_fixed = "rkl2", 1e-3, 0.0
+        tol_kw = dict(r_phi=1e-4, a_phi=1e-4, r_c=1e-4, a_c=1e-4)
+        tol = pf.Tol(**tol_kw)
+        desc = "adaptive RKL2 t=0..1e-3, r=a=1e-4"
+    elif args.adaptive:
+        raise SystemExit("--adaptive applies to --workload pores3d")
     else:
         integ, tol_kw, tol = "rkl2", None, None
         dt_fixed = 100.0 * dte
@@ -432,7 +444,9 @@ def main():
     if not args.no_cpu_baseline:
         note = f"full {wl.name} solve ({desc}) on the host CPU"
         if args.workload != "voronoi2d":
-            note = f"one fixed RKL2 step of {wl.name}"
+            note = f"one fixed RKL2 step of {wl.name} at 100 dt_e"
+            dt_fixed = 100.0 * dte
+            integ, tol_kw = "rkl2", None
             t_end_cpu = dt_fixed
         else:
             t_end_cpu = t_end
