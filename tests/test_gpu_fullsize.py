@@ -9,6 +9,8 @@
   autotuned launch shape that bench.py times, checked by properties that hold
   at any size (phi in [0, 1], sum of phi, conservation of c) and by the launch
   shape changing no bit.
+* 256^3 grains + pores, adaptive RKL2 to t = 2e-4 in FP64 and FP32: end time,
+  simplex, conservation, and the two precisions against each other.
 * The 96-instance batch (FE, 2000 steps each): FP32 in the autotuned launch
   configuration against single-instance runs, bit for bit, on a sample of
   instances; FP64 against the oracle on the smallest instances.
@@ -131,6 +133,41 @@ def test_pores256_rhs_sampled(pores256, prec, tol):
 
 def test_pores256_rkl2_step_properties(pores256):
     _check_rkl2_step_properties(pores256)
+
+
+def test_pores256_adaptive_rkl2(pores256):
+    """The 256^3 sintering workload as bench.py --adaptive runs it (adaptive
+    RKL2, r = a = 1e-4), to t = 2e-4 (720 dt_e) in both precisions: each ends
+    exactly at t_end with phi on the simplex and sum c conserved; the FP32 run
+    takes the FP64 run's accepted steps (to within 10%) and matches its fields
+    to RMS 1e-5 and max 1e-2 (single-precision activity decisions near
+    three-phase cells move a few values by more than 1e-4, as on the 2D
+    Voronoi workload)."""
+    tol = pf.Tol(r_phi=1e-4, a_phi=1e-4, r_c=1e-4, a_c=1e-4)
+    t_end = 2e-4
+    res = {}
+    for prec in ("fp64", "fp32"):
+        sim = pf.Sim(pores256.param_dict(), prec=prec)
+        sim.init_fields(pores256.u0)
+        c0 = sim.conservation()
+        st = sim.run_to("rkl2", t_end, tol=tol)
+        d = sim.diagnostics()
+        u, t = sim.get_fields()
+        sim.close()
+        print(f"\n256^3 adaptive RKL2 {prec}: {st.accepted} accepted / {st.rejected} rejected, "
+              f"{st.rhs_evals} RHS; sum c rel change {abs(d['sum_c'] - c0) / abs(c0):.2e}, "
+              f"max |sum phi - 1| {d['max_sum_dev']:.2e}", flush=True)
+        assert t == t_end and st.accepted >= 2
+        assert d["nonfinite"] == 0 and d["min_phi"] >= 0.0 and d["max_phi"] <= 1.0
+        assert d["max_sum_dev"] <= (1e-12 if prec == "fp64" else 1e-6)
+        assert abs(d["sum_c"] - c0) <= (1e-12 if prec == "fp64" else 1e-6) * abs(c0)
+        res[prec] = (st, u)
+    a32, a64 = res["fp32"][0].accepted, res["fp64"][0].accepted
+    assert abs(a32 - a64) <= max(1, a64 // 10)
+    d = res["fp32"][1] - res["fp64"][1]
+    rms = float(np.sqrt(np.mean(d * d)))
+    print(f"FP32 vs FP64: max {np.abs(d).max():.2e}, RMS {rms:.2e}", flush=True)
+    assert np.abs(d).max() <= 1e-2 and rms <= 1e-5
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-4)])
