@@ -14,8 +14,8 @@ Prints one JSON line (metric of the project: Gcell-stage/s, i.e. cells x RHS
 evaluations per second, with the time to solution and the HBM roofline of the
 dominant kernel, the RKL2 inner stage).
 
-Other modes: --workload pores3d|gg3d (3D grains + pores, two fixed RKL2 steps;
-with --adaptive, pores3d runs adaptive RKL2 to t_end = 1e-3), --workload batch
+Other modes: --workload pores3d|gg3d (3D grains + pores, two or ten fixed RKL2
+steps; with --adaptive, pores3d runs adaptive RKL2 to t_end = 1e-3), --workload batch
 (96 uneven 2D instances), --copy-calib for the rocprofv3 counter calibration
 copy kernel.
 """
@@ -353,10 +353,12 @@ def main():
     elif args.adaptive:
         raise SystemExit("--adaptive applies to --workload pores3d")
     else:
+        # 512^3: ten steps of the 5-vector RKL2 scheme (to t = 1000 dt_e); 256^3: two
         integ, tol_kw, tol = "rkl2", None, None
         dt_fixed = 100.0 * dte
-        t_end = 2 * dt_fixed
-        desc = "fixed RKL2 at 100 dt_e (21 stages), 2 steps"
+        nfix = 10 if args.workload == "gg3d" else 2
+        t_end = nfix * dt_fixed
+        desc = f"fixed RKL2 at 100 dt_e (21 stages), {nfix} steps"
 
     sim.init_fields_device(u0_dev)
     tiling = sim.get_tiling()
