@@ -303,6 +303,10 @@ def main():
                     help="batch: steps per launch (0: the autotuner's choice)")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="batch: steps per captured hipGraph (0: direct launches)")
+    ap.add_argument("--integ", default="rkl2", choices=["rkl2", "rkl1"],
+                    help="pores3d/gg3d fixed steps: RKL2 (5-vector storage) or RKL1 (the "
+                         "3-vector ring of Alg. sts1); the roofline then covers all of RKL1's "
+                         "stage launches")
     ap.add_argument("--adaptive", action="store_true",
                     help="pores3d: adaptive RKL2 to t_end = 1e-3 with r = a = 1e-4 (the 256^3 "
                          "sintering run) instead of two fixed steps")
@@ -354,11 +358,15 @@ def main():
         raise SystemExit("--adaptive applies to --workload pores3d")
     else:
         # 512^3: ten steps of the 5-vector RKL2 scheme (to t = 1000 dt_e); 256^3: two
-        integ, tol_kw, tol = "rkl2", None, None
+        integ, tol_kw, tol = args.integ, None, None
         dt_fixed = 100.0 * dte
         nfix = 10 if args.workload == "gg3d" else 2
         t_end = nfix * dt_fixed
-        desc = f"fixed RKL2 at 100 dt_e (21 stages), {nfix} steps"
+        s_fix = pf.rkl_stage_count(integ, dt_fixed, dte)
+        desc = f"fixed {integ.upper()} at 100 dt_e ({s_fix} stages), {nfix} steps"
+    rkl1 = integ == "rkl1"
+    if rkl1 and args.workload not in ("pores3d", "gg3d") or rkl1 and args.adaptive:
+        raise SystemExit("--integ rkl1 applies to fixed steps of --workload pores3d|gg3d")
 
     sim.init_fields_device(u0_dev)
     tiling = sim.get_tiling()
@@ -383,7 +391,8 @@ def main():
     # the timed runs record one event pair per step, around the inner RKL2
     # stages only (events between other launches would add gaps to the time
     # to solution)
-    sim.set_timing(True, families=[pf.FAM_RKL2])
+    fam = pf.FAM_STAGE if rkl1 else pf.FAM_RKL2
+    sim.set_timing(True, families=[fam])
     torch.cuda.synchronize()
     total, rhs, acc, rej = 0.0, 0, 0, 0
     for k in range(args.steps):
@@ -395,7 +404,7 @@ def main():
         print(f"# step {k}: {el * 1e3:.2f} ms, {st.rhs_evals} RHS, {st.accepted} accepted, "
               f"{st.rejected} rejected", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    ms_rkl2, n_rkl2 = sim.kernel_time(pf.FAM_RKL2)
+    ms_rkl2, n_rkl2 = sim.kernel_time(fam)
     # the breakdown by kernel family from one more run, untimed
     sim.set_timing(True)
     one_step()
@@ -407,10 +416,17 @@ def main():
     E = 8 if args.prec == "fp64" else 4
     sref = stream_reference(wl.F * E * wl.cells)
     value = wl.cells * rhs / total / 1e9
-    bytes_per_launch = 5 * wl.F * E * wl.cells      # Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j out
+    if rkl1:
+        # stage 1 reads u and writes Y_1; stages j >= 2 read Y_{j-1}, Y_{j-2}, write Y_j
+        bytes_per_launch = round((2 + 3 * (s_fix - 1)) / s_fix * wl.F * E * wl.cells)
+        key = f"rkl1_stages/{wl.name}/{args.prec}"
+        kname = f"rkl1 stages (euler first stage + rkl1_stage_kernel), {n_rkl2} launches"
+    else:
+        bytes_per_launch = 5 * wl.F * E * wl.cells      # Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j out
+        key = f"rkl2_stage/{wl.name}/{args.prec}"
+        kname = f"rkl2_stage_kernel (RKL2 stages j >= 2), {n_rkl2} launches"
     avg_s = ms_rkl2 / max(n_rkl2, 1) / 1e3
     achieved = bytes_per_launch / avg_s / 1e9 if n_rkl2 else 0.0
-    key = f"rkl2_stage/{wl.name}/{args.prec}"
     traffic = measured_traffic(key)
     out = {
         "metric": METRIC,
@@ -437,8 +453,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": f"rkl2_stage_kernel (RKL2 stages j >= 2), {n_rkl2} launches, "
-                               f"avg {avg_s * 1e6:.2f} us (HIP events), "
+                     "kernel": f"{kname}, avg {avg_s * 1e6:.2f} us (HIP events), "
                                f"{bytes_per_launch} algorithmic B/launch",
                      "stream_ref_GBs": sref,
                      "frac_of_stream_4r1w": round(achieved / sref["4r1w"], 4) if sref else None},
@@ -446,9 +461,9 @@ def main():
     if not args.no_cpu_baseline:
         note = f"full {wl.name} solve ({desc}) on the host CPU"
         if args.workload != "voronoi2d":
-            note = f"one fixed RKL2 step of {wl.name} at 100 dt_e"
+            note = f"one fixed {args.integ.upper()} step of {wl.name} at 100 dt_e"
             dt_fixed = 100.0 * dte
-            integ, tol_kw = "rkl2", None
+            integ, tol_kw = args.integ, None
             t_end_cpu = dt_fixed
         else:
             t_end_cpu = t_end
