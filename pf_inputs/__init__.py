@@ -249,6 +249,24 @@ def single_grain(n: int = 128, R: float = 40.0, W: float = 4.0, M: float = 1.0,
                     [1.0], [M], [500.0], [0.5], [1.0], with_c, u0)
 
 
+def phase_embedding(n: int = 128, r: float = 32.0, W: float = 2.5, D: float = 100.0) -> Workload:
+    """Phase embedding (Sec. 5.1.1): a disc of phase beta (type 1, c0 = 0.98)
+    of radius r (d = r - |X - C|, eq. centersphere, eq. profile) embedded in
+    phase alpha (type 0, c0 = 0.02) on a periodic n^2 grid; Table tab:params
+    otherwise (gamma = M = 1, dx = 1, k = 500) with D = 100 as the paper uses
+    for equilibrium runs.  c is the local equilibrium at mu = 0 (eq. cadef:
+    sum phi c0), shifted uniformly so that its total equals the sharp-interface
+    total pi r^2 c0_beta + (n^2 - pi r^2) c0_alpha (Sec. 4)."""
+    c0a, c0b = 0.02, 0.98
+    phi = circle_fields(n, n, r, W, kind="profile")
+    c = phi[0:1] * c0a + phi[1:2] * c0b
+    area = math.pi * r * r
+    c = c + (area * c0b + (n * n - area) * c0a - c.sum()) / (n * n)
+    u0 = np.concatenate([phi, c], axis=0)
+    return Workload("phase_embedding_%dx%d_r%g" % (n, n, r), 2, n, n, 1, 2, [0, 1], 2, 1.0, W,
+                    [1.0] * 4, [1.0] * 4, [500.0, 500.0], [c0a, c0b], [D, D], True, u0)
+
+
 def voronoi_2d(n: int = 1024, n_grains: int = 200, n_phi: int = 8, W: float = 5.0,
                seed: int = 2, c_seed: int = 3, dmin: float = 12.0, ny: int = None) -> Workload:
     """Periodic 2D Voronoi tessellation, grain g -> field g mod n_phi, eq. profile

@@ -201,6 +201,37 @@ def test_adaptive_3d_pores_fp64_matches_oracle_trace(integ, tolv, tmul):
     assert abs(st32.accepted - st_ref.accepted) <= max(2, st_ref.accepted // 10)
 
 
+def test_phase_embedding_laplace_pressure_gpu():
+    """Phase embedding (Sec. 5.1.1, the oracle pin of the Laplace pressure):
+    adaptive RKL2 to t = 100 on the GPU.  FP64: the oracle's accepted and
+    rejected steps, fields within 1e-10.  FP32: the pressure between the bulk
+    grand potentials within 1e-3 of the oracle's and within 1% of 1/32."""
+    wl = pi.phase_embedding()
+    P = P_of(wl)
+    tol = dict(r_phi=1e-4, a_phi=1e-2, r_c=1e-4, a_c=1e-4)
+    ref, st_ref, rc = oracle.run_to(P, oracle.RKL2, wl.u0, 100.0, tol=oracle.Tol(**tol))
+    assert rc == 0
+
+    def dp(u):
+        phi_a, phi_b, c = u[0].reshape(-1), u[1].reshape(-1), u[2].reshape(-1)
+        m = float((500.0 * (c - (0.02 * phi_a + 0.98 * phi_b)) / (phi_a + phi_b)).mean())
+        return 0.96 * m   # psi_alpha(m) - psi_beta(m) with equal k
+    for prec in ("fp64", "fp32"):
+        sim = make(wl, prec=prec)
+        st = sim.run_to("rkl2", 100.0, tol=pf.Tol(**tol))
+        u, t = sim.get_fields()
+        sim.close()
+        assert t == 100.0
+        ref_u = np.asarray(ref).reshape(u.shape)
+        if prec == "fp64":
+            assert (st.accepted, st.rejected) == (st_ref.accepted, st_ref.rejected)
+            check_fp64(wl, u, ref_u, "phase embedding")
+        else:
+            print(f"\nphase embedding FP32: dP {dp(u):.6e}, oracle {dp(ref_u):.6e}", flush=True)
+            assert abs(dp(u) - dp(ref_u)) <= 1e-3 * dp(ref_u)
+            assert abs(dp(u) * 32.0 - 1.0) < 0.01
+
+
 def test_adaptive_with_outputs_carries_controller():
     wl = pi.single_grain(n=48, R=15.0)
     P = P_of(wl)
