@@ -44,7 +44,8 @@ class _Params(C.Structure):
                 ("type_of", C.c_int * MAXN),
                 ("dx", C.c_double), ("W", C.c_double),
                 ("gamma", C.c_double * (MAXT * MAXT)), ("mob", C.c_double * (MAXT * MAXT)),
-                ("k", C.c_double * MAXT), ("c0", C.c_double * MAXT), ("D", C.c_double * MAXT)]
+                ("k", C.c_double * MAXT), ("c0", C.c_double * MAXT), ("D", C.c_double * MAXT),
+                ("bc", C.c_int * 3), ("c_fixed", C.c_int * 6), ("c_bc", C.c_double * 6)]
 
 
 class _Tol(C.Structure):
@@ -125,6 +126,9 @@ class Params:
     c0: Sequence[float] = (0.5,)
     D: Sequence[float] = (1.0,)
     with_c: bool = True
+    bc: Sequence[int] = (0, 0, 0)          # per axis: 0 periodic, 1 zero-gradient walls
+    c_fixed: Sequence[int] = (0,) * 6      # per face x-, x+, y-, y+, z-, z+ of a walled axis
+    c_bc: Sequence[float] = (0.0,) * 6     # the fixed c of those faces
 
     @property
     def F(self) -> int:
@@ -148,6 +152,11 @@ class Params:
             p.mob[i] = float(self.mob[i])
         for i in range(T):
             p.k[i], p.c0[i], p.D[i] = float(self.k[i]), float(self.c0[i]), float(self.D[i])
+        for a in range(3):
+            p.bc[a] = int(self.bc[a])
+        for f in range(6):
+            p.c_fixed[f] = int(self.c_fixed[f])
+            p.c_bc[f] = float(self.c_bc[f])
         return p
 
 

@@ -16,7 +16,12 @@
  *
  * State vector layout: F = n_phi + with_c planes of V = nx*ny*nz doubles,
  * plane a < n_phi holds phi_a, plane n_phi holds c; x runs fastest, then y,
- * then z.  All boundaries are periodic (Sec. 4, "Common conditions").
+ * then z.  Boundaries are periodic unless stated (Sec. 4, "Common
+ * conditions"); an axis may instead end in walls where phi and c have zero
+ * gradient, and a wall face may hold c at a fixed value (the Dirichlet
+ * condition of the solutal Stefan problem, Sec. 5.2.2; reading in the
+ * design notes: the ghost cell beyond the face takes the wall cell's phi and
+ * the fixed c).
  *
  * Parity status of each part (how each is pinned is in tests/):
  *   variational derivative, RHS, simplex, integrators, stable step, estimator:
@@ -46,6 +51,12 @@ typedef struct {
     double gamma[PFO_MAXT * PFO_MAXT]; /* symmetric pair table over types */
     double mob[PFO_MAXT * PFO_MAXT];   /* symmetric pair table over types */
     double k[PFO_MAXT], c0[PFO_MAXT], D[PFO_MAXT];
+    /* boundaries: bc[axis] 0 periodic, 1 walls (zero gradient); per face
+     * (x-, x+, y-, y+, z-, z+) of a walled axis, c_fixed[face] != 0 holds c
+     * at c_bc[face] in the ghost cell */
+    int bc[3];
+    int c_fixed[6];
+    double c_bc[6];
 } pfo_params;
 
 typedef struct {
@@ -89,21 +100,40 @@ void pfo_pair_constants(const pfo_params *P, double *A, double *B, double *L) {
         }
 }
 
-/* Periodic neighbour list of cell i: x-, x+, y-, y+, (z-, z+). */
-static int neighbours(const pfo_params *P, long long i, long long *nb) {
+/* Neighbour coordinate of q in direction s (-1 or +1) on an axis of n cells:
+ * wrapped when periodic; at a wall the cell itself (zero gradient), and
+ * *ghost = 1. */
+static long long nb_coord(long long q, int s, long long n, int walls, int *ghost) {
+    long long r = q + s;
+    *ghost = 0;
+    if (r >= 0 && r < n) return r;
+    if (!walls) return (r + n) % n;
+    *ghost = 1;
+    return q;
+}
+
+/* Neighbour list of cell i: x-, x+, y-, y+, (z-, z+).  ghost[k] is the face
+ * index k when neighbour k lies beyond a wall (then nb[k] = i), else -1. */
+static int neighbours_g(const pfo_params *P, long long i, long long *nb, int *ghost) {
     long long nx = P->nx, ny = P->ny, nz = P->nz;
     long long x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
-    long long base = z * nx * ny;
-    nb[0] = base + y * nx + (x + nx - 1) % nx;
-    nb[1] = base + y * nx + (x + 1) % nx;
-    nb[2] = base + ((y + ny - 1) % ny) * nx + x;
-    nb[3] = base + ((y + 1) % ny) * nx + x;
-    if (P->dim == 3) {
-        nb[4] = ((z + nz - 1) % nz) * nx * ny + y * nx + x;
-        nb[5] = ((z + 1) % nz) * nx * ny + y * nx + x;
-        return 6;
+    int g;
+    int nnb = P->dim == 3 ? 6 : 4;
+    for (int k = 0; k < nnb; ++k) {
+        const int axis = k / 2, s = (k & 1) ? 1 : -1;
+        long long xx = x, yy = y, zz = z;
+        if (axis == 0) xx = nb_coord(x, s, nx, P->bc[0], &g);
+        else if (axis == 1) yy = nb_coord(y, s, ny, P->bc[1], &g);
+        else zz = nb_coord(z, s, nz, P->bc[2], &g);
+        nb[k] = (zz * ny + yy) * nx + xx;
+        ghost[k] = g ? k : -1;
     }
-    return 4;
+    return nnb;
+}
+
+static int neighbours(const pfo_params *P, long long i, long long *nb) {
+    int ghost[6];
+    return neighbours_g(P, i, nb, ghost);
 }
 
 /* ---------------------------------------------------------------------------
@@ -127,6 +157,21 @@ static void cell_mu_mc(const pfo_params *P, const double *u, long long V, long l
     }
     *mu = (u[(long long)N * V + i] - sc0) / sik;
     *mc = smc;
+}
+
+/* mu of a ghost cell beyond a face that holds c at cf: the wall cell's phi
+ * with c = cf (the same formula as cell_mu_mc). */
+static double ghost_mu(const pfo_params *P, const double *u, long long V, long long i, double cf) {
+    int N = P->n_phi;
+    double sc0 = 0.0, sik = 0.0;
+    for (int a = 0; a < N; ++a) {
+        int t = P->type_of[a];
+        double ik = 1.0 / P->k[t];
+        double p = u[(long long)a * V + i];
+        sc0 = sc0 + p * P->c0[t];
+        sik = sik + p * ik;
+    }
+    return (cf - sc0) / sik;
 }
 
 void pfo_mu(const pfo_params *P, const double *u, double *mu, double *mc) {
@@ -206,7 +251,8 @@ static void cell_rhs(const pfo_params *P, const double *u, long long V, long lon
                      const double *mu, const double *mc, double *ri /* F values */) {
     int N = P->n_phi;
     long long nb[6];
-    int nnb = neighbours(P, i, nb);
+    int ghost[6];
+    int nnb = neighbours_g(P, i, nb, ghost);
     int act[PFO_MAXN];
     int nz = 0;
     for (int a = 0; a < N; ++a) {
@@ -234,7 +280,11 @@ static void cell_rhs(const pfo_params *P, const double *u, long long V, long lon
         double s = 0.0;
         for (int k = 0; k < nnb; ++k) {
             double w = 0.5 * (mc[i] + mc[nb[k]]);
-            s = s + w * (mu[nb[k]] - mu[i]);
+            double muk = mu[nb[k]];
+            /* a ghost cell that holds c fixed: the wall cell's phi (so the
+             * same Mc) with the fixed c */
+            if (ghost[k] >= 0 && P->c_fixed[ghost[k]]) muk = ghost_mu(P, u, V, i, P->c_bc[ghost[k]]);
+            s = s + w * (muk - mu[i]);
         }
         ri[N] = s * (1.0 / (P->dx * P->dx));
     }

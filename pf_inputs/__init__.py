@@ -49,6 +49,11 @@ class Workload:
     D: List[float]
     with_c: bool
     u0: np.ndarray = field(repr=False, default=None)
+    # boundaries (default periodic): per axis 0 periodic / 1 zero-gradient
+    # walls; per face (x-, x+, y-, y+, z-, z+) a fixed c in the ghost cell
+    bc: List[int] = field(default_factory=lambda: [0, 0, 0])
+    c_fixed: List[int] = field(default_factory=lambda: [0] * 6)
+    c_bc: List[float] = field(default_factory=lambda: [0.0] * 6)
 
     @property
     def F(self) -> int:
@@ -59,10 +64,13 @@ class Workload:
         return self.nx * self.ny * self.nz
 
     def param_dict(self) -> dict:
-        return dict(dim=self.dim, nx=self.nx, ny=self.ny, nz=self.nz, n_phi=self.n_phi,
-                    type_of=list(self.type_of), n_types=self.n_types, dx=self.dx, W=self.W,
-                    gamma=list(self.gamma), mob=list(self.mob), k=list(self.k),
-                    c0=list(self.c0), D=list(self.D), with_c=bool(self.with_c))
+        d = dict(dim=self.dim, nx=self.nx, ny=self.ny, nz=self.nz, n_phi=self.n_phi,
+                 type_of=list(self.type_of), n_types=self.n_types, dx=self.dx, W=self.W,
+                 gamma=list(self.gamma), mob=list(self.mob), k=list(self.k),
+                 c0=list(self.c0), D=list(self.D), with_c=bool(self.with_c))
+        if any(self.bc):
+            d.update(bc=list(self.bc), c_fixed=list(self.c_fixed), c_bc=list(self.c_bc))
+        return d
 
 
 def profile(d: np.ndarray, W: float) -> np.ndarray:
@@ -265,6 +273,32 @@ def phase_embedding(n: int = 128, r: float = 32.0, W: float = 2.5, D: float = 10
     u0 = np.concatenate([phi, c], axis=0)
     return Workload("phase_embedding_%dx%d_r%g" % (n, n, r), 2, n, n, 1, 2, [0, 1], 2, 1.0, W,
                     [1.0] * 4, [1.0] * 4, [500.0, 500.0], [c0a, c0b], [D, D], True, u0)
+
+
+# M + F of the thin-interface relation for the phase-field mobility (Sec. 5.2.2)
+STEFAN_MF = 0.3084251
+
+
+def stefan_1d(nx: int = 1800, h: float = 400.0, W: float = 2.5, D: float = 1.0) -> Workload:
+    """Solutal Stefan problem (Sec. 5.2.2) on an nx x 1 grid: phase beta
+    (type 1, c0 = 0.98) on the left up to h (d = h - x, eq. profile), phase
+    alpha (type 0, c0 = 0.02) beyond; k = 1, gamma = 1, D for both; the pair
+    mobility from the thin-interface relation with K = 0 (eq. thin-interface:
+    L = pi^2 / (16 W^2) D dc/dmu / ((c_beta - c_alpha)^2 (M + F)), dc/dmu =
+    1/k, L = pi M / (4 W)).  c = phi_alpha 0.2 + phi_beta 0.98 (the far-field
+    compositions); x ends in walls (zero-gradient phi) with c held at 0.98 on
+    the left and 0.2 on the right; y is periodic (one row)."""
+    c0a, c0b, ca, cb, k = 0.02, 0.98, 0.2, 0.98, 1.0
+    L = math.pi ** 2 / (16 * W * W) * D * (1.0 / k) / ((c0b - c0a) ** 2 * STEFAN_MF)
+    M = 4 * W * L / math.pi
+    x = np.arange(nx, dtype=np.float64)[None, None, None, :]
+    pb = profile(h - x, W)
+    phi = np.concatenate([1.0 - pb, pb], axis=0)
+    c = (1.0 - pb) * ca + pb * cb
+    u0 = np.concatenate([phi, c], axis=0)
+    return Workload("stefan1d_%d" % nx, 2, nx, 1, 1, 2, [0, 1], 2, 1.0, W, [1.0] * 4, [M] * 4,
+                    [k, k], [c0a, c0b], [D, D], True, u0, bc=[1, 0, 0],
+                    c_fixed=[1, 1, 0, 0, 0, 0], c_bc=[cb, ca, 0.0, 0.0, 0.0, 0.0])
 
 
 def voronoi_2d(n: int = 1024, n_grains: int = 200, n_phi: int = 8, W: float = 5.0,
