@@ -87,6 +87,16 @@ typedef struct {
     int with_c;            /* 0: phase-field only (no c plane, no chemical term) */
     pf_precision prec;
     int ssp_stages;        /* s of SSP(s)2, >= 2 */
+    /* Boundaries (Sec. 4: periodic unless stated).  bc[axis] (x, y, z): 0
+     * periodic, 1 walls where phi and c have zero gradient (the neighbour
+     * beyond a wall is the wall cell).  c_fixed[face] (faces x-, x+, y-, y+,
+     * z-, z+) != 0 on a walled axis holds c at c_bc[face] beyond that face:
+     * the ghost cell takes the wall cell's phi and c = c_bc (the Dirichlet
+     * walls of the solutal Stefan problem, Sec. 5.2.2).  A zeroed tail means
+     * periodic.  Batches take periodic instances only. */
+    int bc[3];
+    int c_fixed[6];
+    double c_bc[6];
 } pf_params;
 
 /* Adaptive-step tolerances (Sec. 3.3): per-field relative r and absolute a,

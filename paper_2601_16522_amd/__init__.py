@@ -56,7 +56,8 @@ class _Params(C.Structure):
                 ("gamma", C.POINTER(C.c_double)), ("mob", C.POINTER(C.c_double)),
                 ("k", C.POINTER(C.c_double)), ("c0", C.POINTER(C.c_double)),
                 ("D", C.POINTER(C.c_double)), ("with_c", C.c_int), ("prec", C.c_int),
-                ("ssp_stages", C.c_int)]
+                ("ssp_stages", C.c_int), ("bc", C.c_int * 3), ("c_fixed", C.c_int * 6),
+                ("c_bc", C.c_double * 6)]
 
 
 class _Tol(C.Structure):
@@ -259,9 +260,17 @@ def _cparams(p: dict, prec: str, ssp_stages: int, keep: list) -> _Params:
             (C.c_double * (T * T))(*p["gamma"]), (C.c_double * (T * T))(*p["mob"]),
             (C.c_double * T)(*p["k"]), (C.c_double * T)(*p["c0"]), (C.c_double * T)(*p["D"])]
     keep.extend(arrs)
-    return _Params(int(p["dim"]), int(p["nx"]), int(p["ny"]), int(p.get("nz", 1)),
-                   float(p["dx"]), float(p["W"]), N, arrs[0], T, arrs[1], arrs[2], arrs[3],
-                   arrs[4], arrs[5], int(bool(p["with_c"])), PRECISIONS[prec], int(ssp_stages))
+    cp = _Params(int(p["dim"]), int(p["nx"]), int(p["ny"]), int(p.get("nz", 1)),
+                 float(p["dx"]), float(p["W"]), N, arrs[0], T, arrs[1], arrs[2], arrs[3],
+                 arrs[4], arrs[5], int(bool(p["with_c"])), PRECISIONS[prec], int(ssp_stages))
+    # boundaries (optional keys; periodic when absent)
+    for a, v in enumerate(p.get("bc", (0, 0, 0))):
+        cp.bc[a] = int(v)
+    for f, v in enumerate(p.get("c_fixed", (0,) * 6)):
+        cp.c_fixed[f] = int(v)
+    for f, v in enumerate(p.get("c_bc", (0.0,) * 6)):
+        cp.c_bc[f] = float(v)
+    return cp
 
 
 class Batch:
@@ -376,16 +385,8 @@ class Sim:
         self.shape = (self.F, int(p.get("nz", 1)), int(p["ny"]), int(p["nx"]))
         self.V = self.shape[1] * self.shape[2] * self.shape[3]
         self.prec = prec
-        T = int(p["n_types"])
-        self._keep = [
-            (C.c_int * self.N)(*[int(v) for v in p["type_of"]]),
-            (C.c_double * (T * T))(*p["gamma"]), (C.c_double * (T * T))(*p["mob"]),
-            (C.c_double * T)(*p["k"]), (C.c_double * T)(*p["c0"]), (C.c_double * T)(*p["D"]),
-        ]
-        cp = _Params(int(p["dim"]), int(p["nx"]), int(p["ny"]), int(p.get("nz", 1)),
-                     float(p["dx"]), float(p["W"]), self.N, self._keep[0], T,
-                     self._keep[1], self._keep[2], self._keep[3], self._keep[4], self._keep[5],
-                     int(self.with_c), PRECISIONS[prec], int(ssp_stages))
+        self._keep = []
+        cp = _cparams(p, prec, ssp_stages, self._keep)
         h = C.c_void_p()
         self._chk(self._L.pf_create(C.byref(cp), C.byref(h)), None)
         self._h = h

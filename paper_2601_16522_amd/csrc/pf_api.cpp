@@ -60,6 +60,8 @@ struct pf_sim {
     double dx, W;
     std::vector<int> type_of;
     std::vector<double> gamma, mob, k, c0, D;
+    int walls = 0, cfix = 0;  // boundaries (pf_params bc / c_fixed as bit masks)
+    double cbc[6] = {0, 0, 0, 0, 0, 0};
     int F;
     long long V;
     size_t esz;
@@ -237,6 +239,8 @@ void fill_kconsts(const DevParams<T> &P, KConsts<T> &K) {
     std::memset(&K, 0, sizeof K);
     K.nx = P.nx; K.ny = P.ny; K.nz = P.nz;
     K.with_c = P.with_c; K.n_types = P.n_types; K.uniform = P.uniform;
+    K.walls = P.walls; K.cfix = P.cfix;
+    for (int f = 0; f < 6; ++f) K.cbc[f] = P.cbc[f];
     K.V = P.V; K.idx2 = P.idx2;
     for (int a = 0; a < NMAX; ++a) {
         K.c0[a] = P.c0[a]; K.ik[a] = P.ik[a]; K.Dk[a] = P.Dk[a];
@@ -296,6 +300,9 @@ void fill_params(const pf_sim *s, DevParams<T> &P) {
                    P.L[a * NMAX + b] == P.L[1];
         }
     P.uniform = uni;
+    P.walls = s->walls;
+    P.cfix = s->cfix;
+    for (int f = 0; f < 6; ++f) P.cbc[f] = (T)s->cbc[f];
 }
 
 // Stable Euler step (Sec. 3.2, Gershgorin estimates of the two-phase system):
@@ -901,6 +908,27 @@ pf_status init_meta(pf_sim *s, const pf_params *p) {
         if (p->type_of[a] < 0 || p->type_of[a] >= p->n_types) return PF_EINVAL;
     for (int t = 0; t < p->n_types; ++t)
         if (!(p->k[t] > 0)) return PF_EINVAL;
+    // boundaries: walls per axis, fixed c only on the faces of walled axes
+    int walls = 0, cfix = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (p->bc[a] != 0 && p->bc[a] != 1) return PF_EINVAL;
+        if (p->bc[a] == 1) {
+            if (a == 2 && p->dim == 2) return PF_EINVAL;
+            walls |= 1 << a;
+        }
+    }
+    for (int f = 0; f < 6; ++f)
+        if (p->c_fixed[f]) {
+            if (!((walls >> (f / 2)) & 1) || !p->with_c || !std::isfinite(p->c_bc[f])) return PF_EINVAL;
+            cfix |= 1 << f;
+        }
+    // wall kernels are built for vectors that fit one buffer group
+    if (walls && field_groups_needed(p->n_phi, (long long)p->nx * p->ny * p->nz,
+                                     p->prec == PF_FP64 ? 8 : 4) != 1)
+        return PF_EUNSUPPORTED;
+    s->walls = walls;
+    s->cfix = cfix;
+    for (int f = 0; f < 6; ++f) s->cbc[f] = (cfix >> f) & 1 ? p->c_bc[f] : 0.0;
     s->dim = p->dim; s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
     s->N = p->n_phi; s->T = p->n_types; s->with_c = p->with_c ? 1 : 0;
     s->ssp_s = p->ssp_stages >= 2 ? p->ssp_stages : 5;
@@ -1943,6 +1971,7 @@ pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out) {
         // the batch kernel addresses an instance's whole state as one buffer group
         if (!rc && (unsigned long long)b->meta[i].F * b->meta[i].V * b->meta[i].esz > 0xFFFFFFFFull)
             rc = PF_EUNSUPPORTED;
+        if (!rc && b->meta[i].walls) rc = PF_EUNSUPPORTED;  // batches are periodic
     }
     if (rc) {
         delete b;

@@ -37,6 +37,9 @@ struct DevParams {
     T hik[NMAX];   // 1/(2k) of the phase's type
     int tphi[NMAX];
     int uniform;   // 1 when every pair (a != b) has the same A, B and L
+    int walls;     // bit a: axis a (x, y, z) ends in zero-gradient walls
+    int cfix;      // bit f: face f (x-, x+, y-, y+, z-, z+) holds c at cbc[f]
+    T cbc[6];
     T k2t[TMAX];   // 2k per type (grand potential)
     T hikt[TMAX];  // 1/(2k) per type
     T c0t[TMAX];   // c0 per type
@@ -65,9 +68,11 @@ enum StageKind : int {
 template <typename T>
 struct KConsts {
     int nx, ny, nz, with_c, n_types, uniform;
+    int walls, cfix;  // boundaries as in DevParams
     long long V;
     T idx2;
     T c0[NMAX], ik[NMAX], Dk[NMAX], hik[NMAX], k2[NMAX];
+    T cbc[6];
 };
 
 constexpr int FMAX = NMAX + 1;  // fields of a state vector: N phases + c

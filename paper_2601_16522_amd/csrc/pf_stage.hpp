@@ -225,22 +225,48 @@ __device__ __forceinline__ TileIdx tile_index(int L, int ntx, int nty) {
     return {L, L - rest * ntx, rest % nty, rest / nty};
 }
 
-// Plane offset (column) of the cell (tix * TILE_X + lx, tiy * TY + ly),
-// periodically wrapped; active: the cell lies inside the grid (ragged tiles).
+// Index of coordinate v on an axis of n cells: wrapped on a periodic axis; on
+// an axis that ends in walls, a v beyond a wall is the wall cell (zero
+// gradient) and face becomes the wall's face (lo or hi) if it was unset.
+// GENERAL == false: a periodic axis and v in [-n, 2n).
+template <bool GENERAL>
+__device__ __forceinline__ int bound_index(int v, int n, bool wall, int lo, int hi, int &face) {
+    if constexpr (GENERAL) {
+        if (wall) {
+            if (v < 0) {
+                if (face < 0) face = lo;
+                return 0;
+            }
+            if (v >= n) {
+                if (face < 0) face = hi;
+                return n - 1;
+            }
+            return v;
+        }
+    }
+    return wrap_index<GENERAL>(v, n);
+}
+
+// Plane offset (column) of the cell (tix * TILE_X + lx, tiy * TY + ly), wrapped
+// or held at the walls (walls: bit 0 x, bit 1 y); active: the cell lies inside
+// the grid (ragged tiles); face: the wall face beyond which it lies, or -1.
 template <bool GENERAL>
 __device__ __forceinline__ void own_column(int tix, int tiy, int TY, int lx, int ly, int nx, int ny,
-                                           long long &col, bool &active) {
+                                           int walls, long long &col, bool &active, int &face) {
     const int gx = tix * TILE_X + lx, gy = tiy * TY + ly;
     active = gx < nx && gy < ny;
-    col = (long long)wrap_index<GENERAL>(gy, ny) * nx + wrap_index<GENERAL>(gx, nx);
+    face = -1;
+    const int ix = bound_index<GENERAL>(gx, nx, walls & 1, 0, 1, face);
+    const int iy = bound_index<GENERAL>(gy, ny, (walls >> 1) & 1, 2, 3, face);
+    col = (long long)iy * nx + ix;
 }
 
 // Halo cell h (0 <= h < 2 TILE_X + 2 TY) of tile (tix, tiy) of height TY: the
 // edge neighbours of the tile without corners, periodically wrapped; hslot is
 // its slot in an LDS plane of (TILE_X + 2) x (TY + 2).
 template <bool GENERAL>
-__device__ __forceinline__ void halo_column(int tix, int tiy, int TY, int h, int nx, int ny,
-                                            long long &hcol, int &hslot) {
+__device__ __forceinline__ void halo_column(int tix, int tiy, int TY, int h, int nx, int ny, int walls,
+                                            long long &hcol, int &hslot, int &face) {
     constexpr int TX = TILE_X, TXH = TILE_X + 2;
     int hx, hy;
     if (h < TX) { hx = h; hy = -1; }
@@ -248,9 +274,17 @@ __device__ __forceinline__ void halo_column(int tix, int tiy, int TY, int h, int
     else if (h < 2 * TX + TY) { hx = -1; hy = h - 2 * TX; }
     else { hx = TX; hy = h - 2 * TX - TY; }
     hslot = (hy + 1) * TXH + (hx + 1);
-    const int hgx = wrap_index<GENERAL>(tix * TX + hx, nx);
-    const int hgy = wrap_index<GENERAL>(tiy * TY + hy, ny);
+    face = -1;
+    const int hgx = bound_index<GENERAL>(tix * TX + hx, nx, walls & 1, 0, 1, face);
+    const int hgy = bound_index<GENERAL>(tiy * TY + hy, ny, (walls >> 1) & 1, 2, 3, face);
     hcol = (long long)hgy * nx + hgx;
+}
+
+// A point loaded for a ghost cell beyond face (>= 0) that holds c fixed takes
+// that c (the wall cell's phi are already its own: zero gradient).
+template <typename T, int N>
+__device__ __forceinline__ void fix_ghost_c(const KConsts<T> &K, int face, bool withc, T *v) {
+    if (face >= 0 && withc && ((K.cfix >> face) & 1)) v[N] = K.cbc[face];
 }
 
 // Right-hand side of eqs. phieq and ceq at one cell (the per-cell part of
@@ -546,7 +580,7 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
 // index and coordinates (tile_index, or kept by a caller that walks tiles).
 // The tile is 64 x TY cells, TY = tile_rows(DIM); thread (lx, ly) computes the
 // R = TY / 4 cells (lx, ly + 4 k) of its column (3D: R = 1, marched in z).
-template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true>
+template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true, bool WALLS = false>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx t, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
@@ -574,26 +608,32 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
         const int tix = t.tix, tiy = t.tiy, tiz = t.tiz;
         const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
         const long long nxy = (long long)nx * ny;
-        // own slots hold the periodically wrapped cells
-        int own_slot[R];
+        // own slots hold the periodically wrapped cells (or, beyond a wall,
+        // the ghost cells: the wall cell, with c fixed where the face holds it)
+        int own_slot[R], own_face[R];
         long long col[R];
         bool active[R];
         const bool has_halo = threadIdx.x < 2 * TX + 2 * TY;
         long long hcol = 0;
-        int hslot = 0;
+        int hslot = 0, hface = -1;
+        // walls: compiled in only for grids that have them (the periodic kernels
+        // carry none of their code)
+        const int walls = WALLS ? P.walls : 0;
         auto columns = [&](auto general) __attribute__((always_inline)) {
             constexpr bool G = decltype(general)::value;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 own_slot[k] = (ly + TILE_Y * k + 1) * TXH + (lx + 1);
-                own_column<G>(tix, tiy, TY, lx, ly + TILE_Y * k, nx, ny, col[k], active[k]);
+                own_column<G>(tix, tiy, TY, lx, ly + TILE_Y * k, nx, ny, walls, col[k], active[k],
+                              own_face[k]);
             }
-            if (has_halo) halo_column<G>(tix, tiy, TY, threadIdx.x, nx, ny, hcol, hslot);
+            if (has_halo) halo_column<G>(tix, tiy, TY, threadIdx.x, nx, ny, walls, hcol, hslot, hface);
         };
-        if (wrap_fits(A.ntx, TX, nx) && wrap_fits(A.nty, TY, ny))
+        if (!WALLS && wrap_fits(A.ntx, TX, nx) && wrap_fits(A.nty, TY, ny))
             columns(std::false_type{});
         else
             columns(std::true_type{});
+        const bool wz = DIM == 3 && ((walls >> 2) & 1);
 
         const int z0 = DIM == 3 ? tiz * A.zchunk : 0;
         const int z1 = DIM == 3 ? min(z0 + A.zchunk, nz) : 1;
@@ -603,7 +643,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
         T mu_c[R], mc_c[R];
         // every load of the first plane is issued before the first use of one
         if (DIM == 3) {
-            const int zm = z0 == 0 ? nz - 1 : z0 - 1;
+            const int zm = z0 == 0 ? (wz ? 0 : nz - 1) : z0 - 1;
             load_point32<T, N, GS>(A, 0, (unsigned)(zm * nxy + col[0]) * (unsigned)sizeof(T), withc, prv);
         }
 #pragma unroll
@@ -613,11 +653,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
         if (has_halo)
             load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
                                    hcur);
+        // ghost cells that hold c fixed take it just before their first use,
+        // so that the loads stay in flight; periodic grids skip all of it
+        const bool ghosts = WALLS && P.cfix != 0 && withc;
 
         for (int z = z0; z < z1; ++z) {
             const long long pz = (long long)z * nxy;
             if (DIM == 3) {
-                const int zp = z == nz - 1 ? 0 : z + 1;
+                const int zp = z == nz - 1 ? (wz ? nz - 1 : 0) : z + 1;
                 load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + col[0]) * (unsigned)sizeof(T),
                                        withc, nxt);
                 if (has_halo && z + 1 < z1)
@@ -625,6 +668,15 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
                                            withc, hnxt);
             }
             if (z == z0) {  // later planes rotate their mu and Mc in
+                if (ghosts) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) fix_ghost_c<T, N>(P, own_face[k], true, cur[k]);
+                    if (DIM == 3) {
+                        fix_ghost_c<T, N>(P, own_face[0], true, prv);
+                        if (z0 == 0 && wz) fix_ghost_c<T, N>(P, 4, true, prv);
+                    }
+                    if (has_halo) fix_ghost_c<T, N>(P, hface, true, hcur);
+                }
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     mu_c[k] = T(0);
@@ -650,6 +702,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
                 lds[N * plane_sz + hslot] = hmu;
                 lds[(N + 1) * plane_sz + hslot] = hmc;
             }
+            if (DIM == 3 && ghosts) {
+                fix_ghost_c<T, N>(P, own_face[0], true, nxt);
+                if (z == nz - 1 && wz) fix_ghost_c<T, N>(P, 5, true, nxt);
+            }
             if (DIM == 3 && withc) point_mu_mc<T, N, FAST>(P, kc, nxt, mu_n, mc_n);
             __syncthreads();
 
@@ -674,6 +730,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
                     cur[0][f] = nxt[f];
                     hcur[f] = hnxt[f];
                 }
+                if (ghosts && has_halo) fix_ghost_c<T, N>(P, hface, true, hcur);
                 mu_p = mu_c[0]; mc_p = mc_c[0];
                 mu_c[0] = mu_n; mc_c[0] = mc_n;
             }
@@ -705,14 +762,14 @@ constexpr int min_waves_per_eu() {
 // One named kernel per stage kind, so that profiles separate them; NG is the
 // number of buffer groups of the vectors (1, 2 or 4).
 #define PF_STAGE_KERNEL(name, kind)                                                         \
-    template <typename T, int DIM, int N, int NG>                                          \
+    template <typename T, int DIM, int N, int NG, bool WALLS>                              \
     __global__ void __launch_bounds__(256)                                                 \
         __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, DIM, N>(), 8)))             \
         name(const StageArgs<T> A) {                                                       \
         __shared__ T lds[lds_elems<T, N, DIM>()];                                          \
         __shared__ T pair[3 * N * N];                                                      \
         __shared__ T kc[4 * N];                                                            \
-        stage_body<T, DIM, N, kind, group_planes(N, NG)>(                                  \
+        stage_body<T, DIM, N, kind, group_planes(N, NG), true, WALLS>(                     \
             A, tile_index(xcd_logical_block(), A.ntx, A.nty), lds, pair, kc);              \
     }
 PF_STAGE_KERNEL(rhs_kernel, K_RHS)
@@ -726,22 +783,33 @@ PF_STAGE_KERNEL(rkl2_stage_kernel, K_RKL2)
 PF_STAGE_KERNEL(estimator_kernel, K_EST)
 #undef PF_STAGE_KERNEL
 
-template <typename T, int DIM, int N, int NG>
-hipError_t launch_stage_dn(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
+template <typename T, int DIM, int N, int NG, bool W>
+hipError_t launch_stage_dnw(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
     const dim3 grid(nblocks), block(256);
     switch (A.kind) {
-    case K_RHS: hipLaunchKernelGGL((rhs_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_EULER: hipLaunchKernelGGL((euler_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_SSP2_FINAL: hipLaunchKernelGGL((ssp2_final_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_SSP104_S5: hipLaunchKernelGGL((ssp104_s5_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_SSP104_FINAL: hipLaunchKernelGGL((ssp104_final_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_RKL1: hipLaunchKernelGGL((rkl1_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_RKL2_FIRST: hipLaunchKernelGGL((rkl2_first_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_RKL2: hipLaunchKernelGGL((rkl2_stage_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
-    case K_EST: hipLaunchKernelGGL((estimator_kernel<T, DIM, N, NG>), grid, block, 0, stream, A); break;
+    case K_RHS: hipLaunchKernelGGL((rhs_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_EULER: hipLaunchKernelGGL((euler_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_SSP2_FINAL: hipLaunchKernelGGL((ssp2_final_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_SSP104_S5: hipLaunchKernelGGL((ssp104_s5_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_SSP104_FINAL: hipLaunchKernelGGL((ssp104_final_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_RKL1: hipLaunchKernelGGL((rkl1_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_RKL2_FIRST: hipLaunchKernelGGL((rkl2_first_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_RKL2: hipLaunchKernelGGL((rkl2_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_EST: hipLaunchKernelGGL((estimator_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Grids with walls run kernels built with the wall code, for one buffer group
+// only (the host admits walls on grids whose vectors fit one group).
+template <typename T, int DIM, int N, int NG>
+hipError_t launch_stage_dn(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
+    if (A.K.walls) {
+        if constexpr (NG == 1) return launch_stage_dnw<T, DIM, N, NG, true>(A, nblocks, stream);
+        else return hipErrorInvalidValue;
+    }
+    return launch_stage_dnw<T, DIM, N, NG, false>(A, nblocks, stream);
 }
 
 // One forward-Euler step at a cell whose neighbourhood is in an LDS plane
