@@ -120,7 +120,9 @@ typedef struct {
  * (pf_supported_nphi) or a grid too large to address: the kernels split a
  * state vector's N + 1 planes into 1, 2 or 4 groups of ceil((N + 1) / groups)
  * planes, each group spanning less than 4 GiB (FP32 512^3 with N = 9 needs
- * two, FP64 four). */
+ * two, FP64 four).  Walls need vectors that fit one group (else
+ * PF_EUNSUPPORTED); walls on z of a 2D grid, bc values other than 0 and 1,
+ * and a fixed c on a periodic axis, without c or not finite, are PF_EINVAL. */
 pf_status pf_create(const pf_params *p, pf_sim **out);
 pf_status pf_destroy(pf_sim *sim);
 
@@ -248,7 +250,8 @@ pf_status pf_get_kernel_time(pf_sim *sim, int family, double *ms, long long *lau
 /* ---------------------------------------------------------------------------
  * Batch of independent 2D simulations.  All instances share dim = 2, n_phi,
  * with_c and the precision; grid sizes and every other parameter may differ.
- * Each instance's state must span less than 4 GiB (else PF_EUNSUPPORTED).
+ * Each instance's state must span less than 4 GiB and its boundaries must be
+ * periodic (else PF_EUNSUPPORTED).
  * A launch of the batch advances every instance by one forward-Euler step
  * (Sec. 3.2), or by two (stage-fusion depth 2: a tile computes the first step
  * on itself and a one-cell ring, the second on itself, in one pass over HBM);
