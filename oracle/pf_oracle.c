@@ -27,6 +27,9 @@
  *   variational derivative, RHS, simplex, integrators, stable step, estimator:
  *     pinned (energy brute force, closed forms, Legendre stability
  *     polynomials, Table 3, Taylor order).
+ *   walls and fixed-c faces: pinned (the solutal Stefan growth constant of
+ *     Sec. 5.2.2; plain diffusion against a fixed-c wall, erf solution).
+ *   c coupling at equilibrium: pinned (phase embedding, Laplace pressure).
  *   error norm and PID controller: pinned only by hand-worked cases and
  *     invariants; parity against the paper unpinned (the paper prints no
  *     worked example of either).
