@@ -300,7 +300,8 @@ def main():
     ap.add_argument("--rkl2-dte", type=float, default=50.0,
                     help="batch: RKL2 step in units of dt_e for the RKL2 comparison")
     ap.add_argument("--fusion", type=int, default=0, choices=[0, 1, 2],
-                    help="batch: steps per launch (0: the autotuner's choice)")
+                    help="batch: FE steps per launch; single simulations: RKL2 inner stages per "
+                         "launch (2: fused pairs, 2D); 0: the autotuner's choice")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="batch: steps per captured hipGraph (0: direct launches)")
     ap.add_argument("--integ", default="rkl2", choices=["rkl2", "rkl1"],
@@ -375,7 +376,11 @@ def main():
         tiling = sim.get_tiling()
     elif not args.no_autotune:
         tiling = sim.autotune()[:2]
-    print(f"# tiling tx={tiling[0]} zchunk={tiling[1]}", file=sys.stderr, flush=True)
+    if args.fusion:
+        sim.set_stage_fusion(args.fusion)
+    fusion = sim.get_stage_fusion()
+    print(f"# tiling tx={tiling[0]} zchunk={tiling[1]}, RKL2 stages per launch {fusion}",
+          file=sys.stderr, flush=True)
 
     def one_step():
         sim.init_fields_device(u0_dev)
@@ -421,6 +426,11 @@ def main():
         bytes_per_launch = round((2 + 3 * (s_fix - 1)) / s_fix * wl.F * E * wl.cells)
         key = f"rkl1_stages/{wl.name}/{args.prec}"
         kname = f"rkl1 stages (euler first stage + rkl1_stage_kernel), {n_rkl2} launches"
+    elif fusion == 2:
+        # two stages per launch: Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j, Y_{j+1} out
+        bytes_per_launch = 6 * wl.F * E * wl.cells
+        key = f"rkl2_pair/{wl.name}/{args.prec}"
+        kname = f"rkl2_pair_kernel (RKL2 stages j, j + 1 fused), {n_rkl2} launches"
     else:
         bytes_per_launch = 5 * wl.F * E * wl.cells      # Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j out
         key = f"rkl2_stage/{wl.name}/{args.prec}"
@@ -444,6 +454,7 @@ def main():
         "config": {"workload": f"{wl.name}: {desc}", "cells": wl.cells, "fields": wl.F,
                    "integrator": integ + ("-adaptive" if tol else "-fixed"),
                    "precision": args.prec, "tiling": {"tx": tiling[0], "zchunk": tiling[1]},
+                   "rkl2_stages_per_launch": fusion,
                    "rhs_evals_per_step": rhs / args.steps,
                    "accepted_per_step": acc / args.steps, "rejected_per_step": rej / args.steps,
                    "time_to_solution_ms": round(total / args.steps * 1e3, 4),

@@ -230,10 +230,28 @@ pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
  * the z extents 4..256 (inputs: the current state and copies of it in three
  * work buffers, which it allocates if the handle has not yet; the state is only
  * read), in two interleaved passes keeping each extent's faster time, and
- * keeps the fastest extent.  The launch shape never changes a result bit. */
+ * keeps the fastest extent.  Where fused stage pairs are built (below) it
+ * also times one pair launch (a fifth work buffer takes its second output)
+ * and sets the fusion depth to 2 if a pair takes less than two single
+ * stages, else to 1; best_ms is then the time per stage of the choice.  The
+ * launch shape never changes a result bit. */
 pf_status pf_set_tiling(pf_sim *sim, int tx, int zchunk);
 pf_status pf_get_tiling(pf_sim *sim, int *tx, int *zchunk);
 pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
+
+/* RKL2 inner stages per launch (eq. sts, stages j >= 2): 1, or 2 for stages j
+ * and j + 1 in one pass over memory (four vectors read and two written per
+ * pair instead of five per stage; a step with an odd count of inner stages
+ * runs its first inner stage alone).  Depth 2 keeps a ring of four stage
+ * vectors (one more work buffer than depth 1) and gives the same result bits
+ * as depth 1.  It is built for 2D periodic grids whose vectors fit one
+ * buffer group and whose tile (64 x 8 cells with a two-cell halo, N + 3
+ * planes, and a one-cell ring of N + 2 planes) fits 64 KiB of LDS: in single
+ * precision N <= 8, in double precision N = 2.  Errors: PF_EINVAL for another
+ * depth; PF_EUNSUPPORTED for depth 2 where it is not built.  The default is
+ * 1; pf_autotune chooses by timing. */
+pf_status pf_set_stage_fusion(pf_sim *sim, int depth);
+pf_status pf_get_stage_fusion(const pf_sim *sim, int *depth);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every launch while enabled.  Families: 0 stage kernels (all stage kinds),

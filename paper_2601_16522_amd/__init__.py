@@ -40,7 +40,8 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_batch_stable_dt", "pf_batch_run_to", "pf_batch_run_adaptive", "pf_batch_autotune", "pf_batch_set_blocks",
            "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error",
            "pf_params_stable_dt", "pf_rkl_stage_count", "pf_controller_init",
-           "pf_controller_update", "pf_clip_step", "pf_set_timing_families"]
+           "pf_controller_update", "pf_clip_step", "pf_set_timing_families",
+           "pf_set_stage_fusion", "pf_get_stage_fusion"]
 
 
 class PFError(RuntimeError):
@@ -135,6 +136,8 @@ def lib():
             "pf_set_tiling": [vp, i, i],
             "pf_get_tiling": [vp, C.POINTER(i), C.POINTER(i)],
             "pf_autotune": [vp, C.POINTER(i), C.POINTER(i), pd],
+            "pf_set_stage_fusion": [vp, i],
+            "pf_get_stage_fusion": [vp, C.POINTER(i)],
             "pf_set_timing": [vp, i],
             "pf_set_timing_families": [vp, C.c_uint],
             "pf_get_kernel_time": [vp, i, pd, C.POINTER(ll)],
@@ -535,6 +538,15 @@ class Sim:
         a, b, ms = C.c_int(), C.c_int(), C.c_double()
         self._chk(self._L.pf_autotune(self._h, C.byref(a), C.byref(b), C.byref(ms)))
         return a.value, b.value, ms.value
+
+    def set_stage_fusion(self, depth: int):
+        """RKL2 inner stages per launch: 1, or 2 (fused pairs, 2D where built)."""
+        self._chk(self._L.pf_set_stage_fusion(self._h, int(depth)))
+
+    def get_stage_fusion(self) -> int:
+        d = C.c_int()
+        self._chk(self._L.pf_get_stage_fusion(self._h, C.byref(d)))
+        return d.value
 
     def set_timing(self, on: bool, families=None):
         """Kernel timing on/off; families: iterable of FAM_* to record only those."""

@@ -86,6 +86,8 @@ struct pf_sim {
     std::vector<double> trace;
     std::string err;
     int tx = 64, zchunk = 16;
+    int fuse = 1;            // RKL2 inner stages per launch (2: fused pairs, where built)
+    int inner_launches = 0;  // launches of the last step's inner-stage interval
     bool timing = false;
     unsigned timing_mask = 0;  // families recorded while timing
     std::vector<Pending> pending;
@@ -475,6 +477,45 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     return PF_OK;
 }
 
+// Whether the fused RKL2 stage-pair kernel is built for the simulation: 2D,
+// periodic, vectors in one buffer group, its LDS within one workgroup's.
+bool pair_ok(const pf_sim *s) {
+    return s->dim == 2 && s->walls == 0 && field_groups_needed(s->N, s->V, (int)s->esz) == 1 &&
+           rkl2_pair_fits((int)s->esz, s->N);
+}
+
+// RKL2 stages j and j + 1 in one launch: y1 = Y_{j-1}, y2 = Y_{j-2}, out = Y_j,
+// out2 = Y_{j+1}; c1, c2: the K_RKL2 coefficients of the two stages.
+template <typename T>
+pf_status stage_pair(pf_sim *s, const T *y1, const T *y2, const T *u0, const T *r0, T *out, T *out2,
+                     const double c1[6], const double c2[6]) {
+    StageArgs<T> A;
+    std::memset(&A, 0, sizeof A);
+    A.K = kconsts<T>(s);
+    A.P = (const DevParams<T> *)s->dparams;
+    A.y1 = y1;
+    A.y2 = y2;
+    A.u0 = u0;
+    A.r0 = r0;
+    A.out = out;
+    A.out2 = out2;
+    set_field_bases(A, s->N, s->V);
+    A.kind = K_RKL2_PAIR;
+    A.a = (T)c1[0]; A.b = (T)c1[1]; A.c = (T)c1[2]; A.d = (T)c1[3]; A.e = (T)c1[4]; A.f = (T)c1[5];
+    A.a2 = (T)c2[0]; A.b2 = (T)c2[1]; A.c2 = (T)c2[2]; A.d2 = (T)c2[3]; A.e2 = (T)c2[4]; A.f2 = (T)c2[5];
+    A.tx = P2_TX;
+    A.ty = P2_TY;
+    A.zchunk = 1;
+    A.ntx = (s->nx + P2_TX - 1) / P2_TX;
+    A.nty = (s->ny + P2_TY - 1) / P2_TY;
+    A.nzc = 1;
+    A.ntiles = A.ntx * A.nty;
+    const int nblocks = (A.ntiles + 7) / 8 * 8;
+    hipError_t err = launch_stage<T>(2, s->N, A, nblocks, s->stream);
+    if (err != hipSuccess) return fail(s, PF_EHIP, "stage-pair kernel launch: %s", hipGetErrorString(err));
+    return PF_OK;
+}
+
 // Sommeijer-type estimate (kind 0) or embedded estimate (kind 1) -> norm on host.
 // Waits for the norm kernel's result: it writes the result and then sequence
 // number seq into the coherent host buffer, which is polled here (cheaper than
@@ -575,7 +616,7 @@ pf_status do_step(pf_sim *s, int integ, int nst, double dt, bool want_aux, int *
     hipEvent_t e1 = mark(s, fam | (integ == PF_RKL2 ? FAM_RKL2 : 0u));
     const int n = (int)(s->st.stages - st0);
     add_interval(s, FAM_STAGE | (integ == PF_FEULER ? FAM_FE : 0u), e0, e1, n);
-    if (integ == PF_RKL2) add_interval(s, FAM_RKL2, ei, e1, n - 1);
+    if (integ == PF_RKL2) add_interval(s, FAM_RKL2, ei, e1, s->inner_launches);
     return PF_OK;
 }
 
@@ -590,7 +631,8 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
     if (integ == PF_SSP_S2) need = 2;
     else if (integ == PF_SSP_10_4) need = 3;
     else if (integ == PF_RKL1) need = want_aux ? 4 : 2;
-    else if (integ == PF_RKL2) need = 4;
+    const bool pairs = integ == PF_RKL2 && s->fuse == 2 && pair_ok(s);
+    if (integ == PF_RKL2) need = pairs ? 5 : 4;
     for (int k = 0; k < need; ++k)
         if ((rc = ensure_buf(s, W(k)))) return rc;
     const T *u = bp<T>(s, U);
@@ -674,7 +716,9 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
         // from its first write on and u^{n,0} stays intact.
         const bool inplace = !second && !want_aux;
         const int R0 = keep_r0 ? W(3) : -1;
-        int slot[3] = {U, W(0), W(1)};
+        // fused pairs read two ring slots and write two others: a ring of four
+        const int NR = pairs ? 4 : 3;
+        int slot[4] = {U, W(0), W(1), pairs ? W(4) : -1};
         const int slot0_store = inplace ? U : W(2);
         double mu, nu, mut, gam;
         rkl_coeffs(order, ns, 1, mu, nu, mut, gam);
@@ -689,9 +733,14 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
         if (rc) return rc;
         s->st.rhs_evals++;
         s->st.stages++;
-        if (e_inner) *e_inner = mark(s, FAM_RKL2);
-        for (int j = 2; j <= ns; ++j) {
-            const int jc = j % 3, jp = (j - 1) % 3, jpp = (j - 2) % 3;
+        // fused pairs: stage counts are odd, so the inner stages pair up; an
+        // even count would run its first inner stage alone, ahead of the
+        // timed inner interval, which holds pair launches only
+        const int single_end = pairs ? ((ns - 1) % 2 ? 2 : 1) : ns;
+        s->inner_launches = pairs ? (ns - 1) / 2 : ns - 1;
+        if (e_inner && !pairs) *e_inner = mark(s, FAM_RKL2);
+        for (int j = 2; j <= single_end; ++j) {
+            const int jc = j % NR, jp = (j - 1) % NR, jpp = (j - 2) % NR;
             if (jc == 0) slot[0] = slot0_store;
             rkl_coeffs(order, ns, j, mu, nu, mut, gam);
             if (second) {
@@ -706,7 +755,24 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
             s->st.rhs_evals++;
             s->st.stages++;
         }
-        *res = slot[ns % 3];
+        if (pairs) {
+            if (e_inner && s->inner_launches > 0) *e_inner = mark(s, FAM_RKL2);
+            for (int j = single_end + 1; j < ns; j += 2) {
+                double c1[6], c2[6];
+                rkl_coeffs(order, ns, j, mu, nu, mut, gam);
+                c1[0] = (1.0 - mu) - nu; c1[1] = mu; c1[2] = nu; c1[3] = dt; c1[4] = mut; c1[5] = gam;
+                rkl_coeffs(order, ns, j + 1, mu, nu, mut, gam);
+                c2[0] = (1.0 - mu) - nu; c2[1] = mu; c2[2] = nu; c2[3] = dt; c2[4] = mut; c2[5] = gam;
+                const int jc = j % NR, jn = (j + 1) % NR, jp = (j - 1) % NR, jpp = (j - 2) % NR;
+                if (jc == 0 || jn == 0) slot[0] = slot0_store;
+                rc = stage_pair<T>(s, bp<T>(s, slot[jp]), bp<T>(s, slot[jpp]), u, bp<T>(s, R0),
+                                   bp<T>(s, slot[jc]), bp<T>(s, slot[jn]), c1, c2);
+                if (rc) return rc;
+                s->st.rhs_evals += 2;
+                s->st.stages += 2;
+            }
+        }
+        *res = slot[ns % NR];
         *aux = R0;
         return PF_OK;
     }
@@ -843,7 +909,7 @@ struct CkptHeader {
 // candidates are timed in two interleaved passes and each keeps its faster
 // time, which damps clock and queue noise between candidates.
 template <typename T>
-pf_status autotune_t(pf_sim *s, const int w[4], double &best, int &bzc) {
+pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fuse) {
     const int zcs3[7] = {4, 8, 16, 32, 64, 128, 256};
     const int ncand = s->dim == 3 ? 7 : 1;
     const T *u = bp<T>(s, s->cur);
@@ -852,17 +918,25 @@ pf_status autotune_t(pf_sim *s, const int w[4], double &best, int &bzc) {
     hipEvent_t e0, e1;
     HIPCHK(s, hipEventCreate(&e0));
     HIPCHK(s, hipEventCreate(&e1));
-    double tbest[7];
+    // candidate ncand (2D, where built): the fused stage pair, timed per stage
+    const bool try_pair = pair_ok(s);
+    double tbest[8];
     for (double &t : tbest) t = 1e300;
+    const double cf[6] = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
     for (int pass = 0; pass < 2; ++pass)
-        for (int j = 0; j < ncand; ++j) {
-            s->zchunk = s->dim == 3 ? zcs3[j] : 1;
+        for (int j = 0; j < ncand + (try_pair ? 1 : 0); ++j) {
+            const bool pair = j == ncand;
+            s->zchunk = s->dim == 3 && !pair ? zcs3[j] : 1;
             if (s->dim == 3 && s->zchunk > s->nz && j > 0) continue;
             pf_status rc = PF_OK;
             for (int r = 0; r < 6 && !rc; ++r) {
                 if (r == 1) hipEventRecord(e0, s->stream);
-                rc = stage<T>(s, K_RKL2, u, bp<T>(s, w[1]), bp<T>(s, w[2]), bp<T>(s, w[3]), bp<T>(s, w[0]),
-                              nullptr, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0);
+                if (pair)
+                    rc = stage_pair<T>(s, u, bp<T>(s, w[1]), bp<T>(s, w[2]), bp<T>(s, w[3]), bp<T>(s, w[0]),
+                                       bp<T>(s, w[4]), cf, cf);
+                else
+                    rc = stage<T>(s, K_RKL2, u, bp<T>(s, w[1]), bp<T>(s, w[2]), bp<T>(s, w[3]),
+                                  bp<T>(s, w[0]), nullptr, cf[0], cf[1], cf[2], cf[3], cf[4], cf[5], 0);
             }
             if (rc) {
                 hipEventDestroy(e0);
@@ -873,7 +947,7 @@ pf_status autotune_t(pf_sim *s, const int w[4], double &best, int &bzc) {
             HIPCHK(s, hipEventSynchronize(e1));
             float ms = 0.f;
             hipEventElapsedTime(&ms, e0, e1);
-            tbest[j] = std::min(tbest[j], ms / 5.0);
+            tbest[j] = std::min(tbest[j], ms / (pair ? 10.0 : 5.0));
         }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -883,6 +957,11 @@ pf_status autotune_t(pf_sim *s, const int w[4], double &best, int &bzc) {
             best = tbest[j];
             bzc = s->dim == 3 ? zcs3[j] : 1;
         }
+    fuse = 1;
+    if (try_pair && tbest[ncand] < best) {
+        best = tbest[ncand];
+        fuse = 2;
+    }
     return PF_OK;
 }
 
@@ -1240,23 +1319,40 @@ pf_status pf_get_tiling(pf_sim *s, int *tx, int *zchunk) {
 pf_status pf_autotune(pf_sim *s, int *tx_out, int *zc_out, double *best_ms) {
     if (!s) return PF_EINVAL;
     if (pf_status rc = need_fields(s)) return rc;
-    int w[4];
-    for (int k = 0; k < 4; ++k) {
+    int w[5] = {-1, -1, -1, -1, -1};
+    for (int k = 0; k < (pair_ok(s) ? 5 : 4); ++k) {
         w[k] = work_index(s, k);
         if (pf_status rc = ensure_buf(s, w[k])) return rc;
     }
     const bool was_timing = s->timing;
     s->timing = false;
     double best;
-    int bzc = s->zchunk;
-    pf_status rc = s->prec == PF_FP64 ? autotune_t<double>(s, w, best, bzc)
-                                      : autotune_t<float>(s, w, best, bzc);
+    int bzc = s->zchunk, fuse = 1;
+    pf_status rc = s->prec == PF_FP64 ? autotune_t<double>(s, w, best, bzc, fuse)
+                                      : autotune_t<float>(s, w, best, bzc, fuse);
     s->timing = was_timing;
     if (rc) return rc;
     s->zchunk = bzc;
+    s->fuse = fuse;
     if (tx_out) *tx_out = s->tx;
     if (zc_out) *zc_out = bzc;
     if (best_ms) *best_ms = best;
+    return PF_OK;
+}
+
+pf_status pf_set_stage_fusion(pf_sim *s, int depth) {
+    if (!s) return PF_EINVAL;
+    if (depth != 1 && depth != 2) return fail(s, PF_EINVAL, "stage fusion depth %d (1 or 2)", depth);
+    if (depth == 2 && !pair_ok(s))
+        return fail(s, PF_EUNSUPPORTED, "fused RKL2 stage pairs are built for 2D periodic grids "
+                                        "whose vectors fit one buffer group and whose LDS fits");
+    s->fuse = depth;
+    return PF_OK;
+}
+
+pf_status pf_get_stage_fusion(const pf_sim *s, int *depth) {
+    if (!s || !depth) return PF_EINVAL;
+    *depth = s->fuse;
     return PF_OK;
 }
 

@@ -60,7 +60,8 @@ enum StageKind : int {
     K_RKL2_FIRST = 6,   // y* = y1 + a r; out = S(y*); out2 = R0 (corrected where S acted)
     K_RKL2 = 7,         // out = S(((a u0 + b y1) + c y2) + d ((e r) + (f r0)));
                         // FP32: u0 + b (y1 - u0) + c (y2 - u0) for the first three terms
-    K_EST = 8           // Sommeijer estimate of u^{n+1} = y1 against u^n = u0, R0 = r0
+    K_EST = 8,          // Sommeijer estimate of u^{n+1} = y1 against u^n = u0, R0 = r0
+    K_RKL2_PAIR = 9     // two K_RKL2 stages j, j + 1 in one pass (2D): out = Y_j, out2 = Y_{j+1}
 };
 
 // Uniform per-simulation constants the stage kernels read: passed by value as
@@ -101,6 +102,7 @@ struct StageArgs {
     long long *redn;
     int kind;
     T a, b, c, d, e, f;
+    T a2, b2, c2, d2, e2, f2;  // K_RKL2_PAIR: coefficients of the second stage
     // estimator
     T r_phi, a_phi, r_c, a_c, dt6, hdt;
     // tiling
@@ -162,6 +164,21 @@ constexpr int F2_IN_X = TILE_X + 4, F2_IN = F2_IN_X * (tile_rows(2) + 4);
 constexpr int F2_MID_X = TILE_X + 2, F2_MID = F2_MID_X * (tile_rows(2) + 2);
 constexpr bool batch_depth2_fits(int esz, int n) {
     return n <= DEPTH2_MAX_N && esz * ((n + 3) * (F2_IN + F2_MID) + 3 * n * n + 4 * n) <= 65536;
+}
+
+// Fused RKL2 stage pairs (2D): a block of P2_THREADS threads computes a tile
+// of P2_TX x P2_TY cells, one per thread.  Its LDS holds the stage input with a
+// two-cell halo, (P2_TX + 4) x (P2_TY + 4) cells of N + 3 planes (phi, mu, Mc,
+// c), and the first stage on the tile and a one-cell ring, (P2_TX + 2) x
+// (P2_TY + 2) cells of N + 2 planes (phi, mu, Mc), plus the pair and
+// per-phase tables; built where that fits P2_LDS_MAX bytes.
+constexpr int P2_TX = 64, P2_TY = 8, P2_THREADS = P2_TX * P2_TY, P2_LDS_MAX = 65536;
+constexpr int P2_IN_X = P2_TX + 4, P2_IN_Y = P2_TY + 4, P2_IN = P2_IN_X * P2_IN_Y;
+constexpr int P2_MID_X = P2_TX + 2, P2_MID_Y = P2_TY + 2, P2_MID = P2_MID_X * P2_MID_Y;
+constexpr int P2_RING = P2_MID - P2_TX * P2_TY;  // cells of the one-cell ring
+static_assert(P2_RING <= P2_THREADS, "one ring cell per thread");
+constexpr bool rkl2_pair_fits(int esz, int n) {
+    return esz * ((n + 3) * P2_IN + (n + 2) * P2_MID + 3 * n * n + 4 * n) <= P2_LDS_MAX;
 }
 
 template <typename T>

@@ -420,6 +420,18 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
     else r[N] = withc ? flux * idx2 : T(0);
 }
 
+// One value of an RKL2 stage (eq. sts): (1 - mu_j - nu_j) u0 + mu_j Y_{j-1} +
+// nu_j Y_{j-2} + dt (mut_j r + gam_j R0) with a = 1 - mu_j - nu_j, b = mu_j,
+// c = nu_j, d = dt, e = mut_j, f = gam_j; y1 = Y_{j-1}, r = rhs(Y_{j-1}).  The
+// fast form is u0 + mu_j (Y_{j-1} - u0) + nu_j (Y_{j-2} - u0), the same
+// combination, whose weights sum to 1 exactly whatever the rounding of mu_j
+// and nu_j (the total of c is kept).
+template <typename T, bool FAST>
+__device__ __forceinline__ T rkl2_value(T a, T b, T c, T d, T e, T f, T y1, T r, T u, T y2, T r0) {
+    if constexpr (FAST) return fma_t(d, fma_t(e, r, f * r0), fma_t(c, y2 - u, fma_t(b, y1 - u, u)));
+    else return ((a * u + b * y1) + c * y2) + d * (e * r + f * r0);
+}
+
 // Stage combination, projection and store at one cell (byte offset idx in a
 // plane) from its own values cur, its right-hand side r and the operands
 // o0 (u0), o1 (y2), o2 (r0) of the stage kind; the estimator kind adds its
@@ -501,17 +513,8 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
             }
         } else {  // K_RKL2
 #pragma unroll
-            for (int f = 0; f <= N; ++f) {
-                const T u = o0[f], v2 = o1[f], q0 = o2[f];
-                // the fast form: u + mu_j (Y_{j-1} - u) + nu_j (Y_{j-2} - u), the
-                // same combination, whose weights sum to 1 exactly whatever the
-                // rounding of mu_j and nu_j (the total of c is kept)
-                if constexpr (FAST)
-                    yv[f] = fma_t(A.d, fma_t(A.e, r[f], A.f * q0),
-                                  fma_t(A.c, v2 - u, fma_t(A.b, cur[f] - u, u)));
-                else
-                    yv[f] = ((A.a * u + A.b * cur[f]) + A.c * v2) + A.d * (A.e * r[f] + A.f * q0);
-            }
+            for (int f = 0; f <= N; ++f)
+                yv[f] = rkl2_value<T, FAST>(A.a, A.b, A.c, A.d, A.e, A.f, cur[f], r[f], o0[f], o1[f], o2[f]);
         }
 
         if constexpr (KIND == K_RKL2_FIRST) {
@@ -783,6 +786,184 @@ PF_STAGE_KERNEL(rkl2_stage_kernel, K_RKL2)
 PF_STAGE_KERNEL(estimator_kernel, K_EST)
 #undef PF_STAGE_KERNEL
 
+// One RKL2 stage value at a 2D cell whose neighbourhood is in an LDS plane
+// tile (N phi planes, mu, Mc; PLANE values apart, rows ROW apart): the same
+// arithmetic as the single-stage kernel's K_RKL2 path.  cur: the cell's
+// Y_{j-1}; y2, u, r0: its Y_{j-2}, u0 and R0; cf: a..f of the stage.
+template <typename T, int N, bool FAST, int PLANE, int ROW>
+__device__ __forceinline__ void rkl2_point(const KConsts<T> &P, const T *__restrict__ lds,
+                                           const T *__restrict__ pair, const T *__restrict__ kc,
+                                           const int slot, const T *cur, const T *y2, const T *u,
+                                           const T *r0, const T (&cf)[6], T *y) {
+    T r[N + 1];
+    rhs_point<T, 2, N, FAST, PLANE, ROW>(P, lds, pair, kc, slot, cur, lds[N * PLANE + slot],
+                                         lds[(N + 1) * PLANE + slot], nullptr, T(0), T(0), nullptr,
+                                         T(0), T(0), r);
+#pragma unroll
+    for (int f = 0; f <= N; ++f)
+        y[f] = rkl2_value<T, FAST>(cf[0], cf[1], cf[2], cf[3], cf[4], cf[5], cur[f], r[f], u[f], y2[f], r0[f]);
+    project<T, N, FAST>(y);
+}
+
+// Two consecutive RKL2 inner stages j and j + 1 (eq. sts) of one 2D tile of
+// P2_TX x P2_TY cells in one pass over memory.  Stage j needs Y_{j-1} on the
+// five-point stencil and Y_{j-2}, u0, R0 at the cell; stage j + 1 needs Y_j on
+// the stencil and Y_{j-1}, u0, R0 at the cell.  The block stages Y_{j-1} with a
+// two-cell halo (periodically wrapped) in LDS with its mu and Mc, computes Y_j
+// on the tile (stored) and on a one-cell ring around it (LDS only), then
+// Y_{j+1} on the tile.  Per cell that is four vectors read and two written for
+// two stages, against five per stage one at a time.  Every value is computed
+// with the single-stage kernel's arithmetic, so the results equal two single
+// stages bit for bit.  Vectors: y1 = Y_{j-1}, y2 = Y_{j-2}, u0, r0 = R0, out =
+// Y_j, out2 = Y_{j+1}, one buffer group each; coefficients a..f of stage j and
+// a2..f2 of stage j + 1.  Thread i computes tile cell (i mod P2_TX, i / P2_TX) in
+// both stages and, for i < P2_RING, one ring cell of stage j.
+template <typename T, int N>
+__device__ __forceinline__ void rkl2_pair_tile(const StageArgs<T> &A, const TileIdx t, T *__restrict__ in,
+                                               T *__restrict__ mid, T *__restrict__ pair,
+                                               T *__restrict__ kc) {
+    constexpr bool FAST = std::is_same<T, float>::value;
+    constexpr int GS = N + 1;
+    constexpr int NP0 = (P2_IN + P2_THREADS - 1) / P2_THREADS;
+    const KConsts<T> &P = A.K;
+    const int nx = P.nx, ny = P.ny;
+    const bool withc = P.with_c != 0;
+    const int tid = threadIdx.x;
+    const int lx = tid % P2_TX, ly = tid / P2_TX;
+    const int x0 = t.tix * P2_TX - 2, y0 = t.tiy * P2_TY - 2;  // corner of the input region
+    // the thread's ring cell (qx, qy) of the middle region: its top row, its
+    // bottom row, then its left and right columns
+    const bool ring = tid < P2_RING;
+    int qx = 0, qy = 0;
+    if (tid < 2 * P2_MID_X) {
+        qx = tid < P2_MID_X ? tid : tid - P2_MID_X;
+        qy = tid < P2_MID_X ? 0 : P2_MID_Y - 1;
+    } else if (ring) {
+        const int i = tid - 2 * P2_MID_X;
+        qx = i < P2_TY ? 0 : P2_MID_X - 1;
+        qy = 1 + (i < P2_TY ? i : i - P2_TY);
+    }
+    // byte offsets (one plane) of the thread's input-region points, its tile
+    // cell and its ring cell, periodically wrapped
+    unsigned ioff[NP0], coff = 0, roff = 0;
+    auto offsets = [&](auto general) __attribute__((always_inline)) {
+        constexpr bool G = decltype(general)::value;
+        const auto at = [&](int px, int py) __attribute__((always_inline)) {
+            return (unsigned)(wrap_index<G>(y0 + py, ny) * nx + wrap_index<G>(x0 + px, nx)) *
+                   (unsigned)sizeof(T);
+        };
+#pragma unroll
+        for (int k = 0; k < NP0; ++k) {
+            const int p = tid + P2_THREADS * k;
+            ioff[k] = p < P2_IN ? at(p % P2_IN_X, p / P2_IN_X) : 0u;
+        }
+        coff = at(lx + 2, ly + 2);
+        roff = at(qx + 1, qy + 1);
+    };
+    if (wrap_fits(A.ntx, P2_TX, nx) && wrap_fits(A.nty, P2_TY, ny))
+        offsets(std::false_type{});
+    else
+        offsets(std::true_type{});
+
+    // every load of the input region is issued before the first use of one
+    T v[NP0][N + 1];
+#pragma unroll
+    for (int k = 0; k < NP0; ++k)
+        if (tid + P2_THREADS * k < P2_IN) load_point32<T, N, GS>(A, 0, ioff[k], withc, v[k]);
+    stage_tables<T, N>(A.P, pair, kc);
+    __syncthreads();  // the tables are read from here on
+#pragma unroll
+    for (int k = 0; k < NP0; ++k) {
+        const int p = tid + P2_THREADS * k;
+        if (p < P2_IN) {
+            T mu = T(0), mc = T(0);
+            if (withc) point_mu_mc<T, N, FAST>(P, kc, v[k], mu, mc);
+#pragma unroll
+            for (int a = 0; a < N; ++a) in[a * P2_IN + p] = v[k][a];
+            in[N * P2_IN + p] = mu;
+            in[(N + 1) * P2_IN + p] = mc;
+            in[(N + 2) * P2_IN + p] = v[k][N];
+        }
+    }
+    // the tile cell's operands, in flight across the barrier and the
+    // right-hand side of stage j
+    T u[N + 1], y2[N + 1], q0[N + 1];
+    load_operands<T, N, K_RKL2, GS, 0>(A, coff, withc, u, y2, q0);
+    __syncthreads();
+
+    const T cf1[6] = {A.a, A.b, A.c, A.d, A.e, A.f};
+    const T cf2[6] = {A.a2, A.b2, A.c2, A.d2, A.e2, A.f2};
+    const int gx = t.tix * P2_TX + lx, gy = t.tiy * P2_TY + ly;
+    const bool inside = gx < nx && gy < ny;
+    auto to_mid = [&](const int q, const T *y) __attribute__((always_inline)) {
+        T mu = T(0), mc = T(0);
+        if (withc) point_mu_mc<T, N, FAST>(P, kc, y, mu, mc);
+#pragma unroll
+        for (int a = 0; a < N; ++a) mid[a * P2_MID + q] = y[a];
+        mid[N * P2_MID + q] = mu;
+        mid[(N + 1) * P2_MID + q] = mc;
+    };
+
+    // stage j on the tile cell: stored and put in LDS (its c is kept for
+    // stage j + 1, its phi are read back from LDS)
+    const int si = (ly + 2) * P2_IN_X + (lx + 2), sm = (ly + 1) * P2_MID_X + (lx + 1);
+    auto in_point = [&](const int q, T *y) __attribute__((always_inline)) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) y[a] = in[a * P2_IN + q];
+        y[N] = in[(N + 2) * P2_IN + q];
+    };
+    T yj_c;
+    {
+        T ym[N + 1], yj[N + 1];
+        in_point(si, ym);
+        rkl2_point<T, N, FAST, P2_IN, P2_IN_X>(P, in, pair, kc, si, ym, y2, u, q0, cf1, yj);
+        if (inside) {
+#pragma unroll
+            for (int f = 0; f < N; ++f) stv<T, GS>(A, 4, f, coff, yj[f]);
+            if (withc) stv<T, GS>(A, 4, N, coff, yj[N]);
+        }
+        to_mid(sm, yj);
+        yj_c = yj[N];
+    }
+    // stage j on the ring cell (LDS only)
+    if (ring) {
+        T rc[N + 1], ru[N + 1], ry2[N + 1], rq0[N + 1], ry[N + 1];
+        load_operands<T, N, K_RKL2, GS, 0>(A, roff, withc, ru, ry2, rq0);
+        const int sr = (qy + 1) * P2_IN_X + (qx + 1);
+        in_point(sr, rc);
+        rkl2_point<T, N, FAST, P2_IN, P2_IN_X>(P, in, pair, kc, sr, rc, ry2, ru, rq0, cf1, ry);
+        to_mid(qy * P2_MID_X + qx, ry);
+    }
+    __syncthreads();
+
+    // stage j + 1 on the tile cell: Y_j on the stencil, Y_{j-1} at the cell
+    T yj[N + 1], ym[N + 1], y[N + 1];
+#pragma unroll
+    for (int a = 0; a < N; ++a) yj[a] = mid[a * P2_MID + sm];
+    yj[N] = yj_c;
+    in_point(si, ym);
+    rkl2_point<T, N, FAST, P2_MID, P2_MID_X>(P, mid, pair, kc, sm, yj, ym, u, q0, cf2, y);
+    if (inside) {
+#pragma unroll
+        for (int f = 0; f < N; ++f) stv<T, GS>(A, 5, f, coff, y[f]);
+        if (withc) stv<T, GS>(A, 5, N, coff, y[N]);
+    }
+}
+
+// One block per tile; built where the LDS of rkl2_pair_tile fits (the launch
+// refuses the others).
+template <typename T, int N>
+__global__ void __launch_bounds__(P2_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8)))
+    rkl2_pair_kernel(const StageArgs<T> A) {
+    __shared__ T in[(N + 3) * P2_IN];
+    __shared__ T mid[(N + 2) * P2_MID];
+    __shared__ T pair[3 * N * N];
+    __shared__ T kc[4 * N];
+    const TileIdx t = tile_index(xcd_logical_block(), A.ntx, A.nty);
+    if (t.L >= A.ntiles) return;  // uniform over the block
+    rkl2_pair_tile<T, N>(A, t, in, mid, pair, kc);
+}
+
 template <typename T, int DIM, int N, int NG, bool W>
 hipError_t launch_stage_dnw(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
     const dim3 grid(nblocks), block(256);
@@ -796,6 +977,12 @@ hipError_t launch_stage_dnw(const StageArgs<T> &A, int nblocks, hipStream_t stre
     case K_RKL2_FIRST: hipLaunchKernelGGL((rkl2_first_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
     case K_RKL2: hipLaunchKernelGGL((rkl2_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
     case K_EST: hipLaunchKernelGGL((estimator_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_RKL2_PAIR:
+        if constexpr (DIM == 2 && NG == 1 && !W && rkl2_pair_fits((int)sizeof(T), N))
+            hipLaunchKernelGGL((rkl2_pair_kernel<T, N>), grid, dim3(P2_THREADS), 0, stream, A);
+        else
+            return hipErrorInvalidValue;
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -69,6 +69,23 @@ def test_stage_kernels_do_not_spill(tmp_path):
         batch = [k for k in names if "batch_kernel" in k]
         expect = 8 + sum(_depth2_fits(esz, n) for esz in (4, 8))
         assert len(batch) == (expect if g == 1 else 0), (n, g, batch)
+        # fused RKL2 stage pairs: one group, where the LDS fits; 512-thread
+        # blocks, two per CU by LDS, so four waves per SIMD need <= 128 VGPRs
+        pairs = [k for k in names if "rkl2_pair_kernel" in k]
+        expect = sum(_pair_fits(esz, n) for esz in (4, 8))
+        assert len(pairs) == (expect if g == 1 else 0), (n, g, pairs)
+        for k in pairs:
+            assert kernels[k].get("VGPRs", 999) <= 128, (n, g, k, kernels[k])
+
+
+def _pair_fits(esz, n):
+    """The LDS rule of the fused RKL2 stage-pair kernel (pf_internal.h)."""
+    txt = open(os.path.join(ROOT, "paper_2601_16522_amd", "csrc", "pf_internal.h")).read()
+    m = re.search(r"constexpr int P2_TX = (\d+), P2_TY = (\d+), P2_THREADS = P2_TX \* P2_TY, "
+                  r"P2_LDS_MAX = (\d+);", txt)
+    tx, ty, cap = (int(g) for g in m.groups())
+    lds = (n + 3) * (tx + 4) * (ty + 4) + (n + 2) * (tx + 2) * (ty + 2) + 3 * n * n + 4 * n
+    return esz * lds <= cap
 
 
 def _depth2_fits(esz, n):
