@@ -5,7 +5,8 @@ single-stage arithmetic, so every result must equal depth 1 bit for bit:
 
 * fixed steps of 3, 5, 9 and 15 stages (the stage count of eq. sts-limit is
   odd, so the inner stages always form pairs), on ragged grids of several
-  tiles, a grid smaller than one tile (the general wrapping path), two- to
+  tiles, grids smaller than one tile (the general wrapping path; one and
+  three rows, thinner than the two-cell halo), two- to
   eight-phase workloads in single precision, two-phase in double precision,
   and without c;
 * a whole adaptive RKL2 run (same accepted / rejected steps, same fields);
@@ -55,6 +56,10 @@ WORKLOADS = {
     "grain2_fp32": (lambda: pi.single_grain(n=130, R=40.0, ny=70), "fp32"),
     "grain2_fp64": (lambda: pi.single_grain(n=130, R=40.0, ny=70), "fp64"),
     "voronoi8_noc_fp32": (lambda: no_c(voronoi8(n=150, ny=40)), "fp32"),
+    # grids thinner than the two-cell halo: one row, three rows
+    "strip2_fp32": (lambda: pi.single_grain(n=97, R=30.0, ny=1), "fp32"),
+    "thin4_fp32": (lambda: pi.voronoi_2d(n=70, ny=3, n_grains=5, n_phi=4, dmin=6.0, seed=9, c_seed=10),
+                   "fp32"),
 }
 
 
