@@ -249,7 +249,7 @@ pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
  * planes, and a one-cell ring of N + 2 planes) fits 64 KiB of LDS: in single
  * precision N <= 8, in double precision N = 2.  Errors: PF_EINVAL for another
  * depth; PF_EUNSUPPORTED for depth 2 where it is not built.  The default is
- * 1; pf_autotune chooses by timing. */
+ * 2 where it is built, else 1; pf_autotune chooses by timing. */
 pf_status pf_set_stage_fusion(pf_sim *sim, int depth);
 pf_status pf_get_stage_fusion(const pf_sim *sim, int *depth);
 

@@ -1043,6 +1043,7 @@ pf_status pf_create(const pf_params *p, pf_sim **out) {
         delete s;
         return rc;
     }
+    s->fuse = pair_ok(s) ? 2 : 1;  // same result bits either way; fewer bytes per stage fused
     if (p->prec == PF_FP64) {
         DevParams<double> P;
         fill_params(s, P);

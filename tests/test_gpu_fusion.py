@@ -76,8 +76,7 @@ def dt_for_stages(dte, s):
 def make(wl, prec, depth):
     sim = pf.Sim(wl.param_dict(), prec=prec)
     sim.init_fields(wl.u0)
-    if depth == 2:
-        sim.set_stage_fusion(2)
+    sim.set_stage_fusion(depth)
     assert sim.get_stage_fusion() == depth
     return sim
 
@@ -137,7 +136,11 @@ def test_pairs_fp32_against_oracle():
 
 
 def test_fusion_setting_checked():
-    sim = make(voronoi8(n=64, ny=16), "fp32", 1)
+    wl = voronoi8(n=64, ny=16)
+    sim = pf.Sim(wl.param_dict(), prec="fp32")
+    assert sim.get_stage_fusion() == 2  # the default where pairs are built
+    sim.close()
+    sim = make(wl, "fp32", 1)
     for bad in (0, 3):
         with pytest.raises(pf.PFError) as e:
             sim.set_stage_fusion(bad)
