@@ -466,6 +466,8 @@ def main():
                      "traffic": traffic,
                      "kernel": f"{kname}, avg {avg_s * 1e6:.2f} us (HIP events), "
                                f"{bytes_per_launch} algorithmic B/launch",
+                     "stages_per_launch": 2 if (fusion == 2 and not rkl1) else 1,
+                     "us_per_stage": round(avg_s * 1e6 / (2 if (fusion == 2 and not rkl1) else 1), 3),
                      "stream_ref_GBs": sref,
                      "frac_of_stream_4r1w": round(achieved / sref["4r1w"], 4) if sref else None},
     }
