@@ -275,6 +275,36 @@ def phase_embedding(n: int = 128, r: float = 32.0, W: float = 2.5, D: float = 10
                     [1.0] * 4, [1.0] * 4, [500.0, 500.0], [c0a, c0b], [D, D], True, u0)
 
 
+def double_triple_junction(nx: int = 96, ny: int = 192, r: float = 32.0, W: float = 3.0,
+                           D: float = 100.0, g_ab: float = 2.0, g_bb: float = 1.0) -> Workload:
+    """Double triple junction (Sec. 5.1.2): a disc of phase alpha (field 0,
+    type 0, c0 = 0.02) of radius r (eq. centersphere, eq. profile) on the
+    grain boundary x = nx / 2 between two grains of phase beta (fields 1 and 2,
+    type 1, c0 = 0.98; d = C_x - x and its complement), the beta fields
+    rescaled to fill 1 - phi_alpha with their ratio kept (eq. distfix).  The
+    long side runs along the grain boundary; x ends in zero-gradient walls (so
+    the boundary meets no second one), y is periodic.  gamma_ab = g_ab,
+    gamma_bb = g_bb, M = 1, k = 500, D for both types (the paper's equilibrium
+    value), W = 3 (its coarsest resolution, dx = 1).  c is the local
+    equilibrium at mu = 0, shifted uniformly so that its total equals the
+    sharp-interface total pi r^2 c0_alpha + (nx ny - pi r^2) c0_beta (Sec. 4)."""
+    c0a, c0b = 0.02, 0.98
+    cx, cy = nx / 2.0, ny / 2.0
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    pa = profile(r - np.sqrt((x - cx) ** 2 + (y - cy) ** 2), W)
+    b1, b2 = profile(cx - x, W), profile(x - cx, W)
+    rest = b1 + b2
+    scale = np.where(rest > 0.0, (1.0 - pa) / np.where(rest > 0.0, rest, 1.0), 0.0)
+    phi = np.stack([pa, b1 * scale, b2 * scale])[:, None]
+    c = phi[0:1] * c0a + (phi[1:2] + phi[2:3]) * c0b
+    area = math.pi * r * r
+    c = c + (area * c0a + (nx * ny - area) * c0b - c.sum()) / (nx * ny)
+    u0 = np.concatenate([phi, c], axis=0)
+    return Workload("double_triple_junction_%dx%d" % (nx, ny), 2, nx, ny, 1, 3, [0, 1, 1], 2, 1.0, W,
+                    [1.0, g_ab, g_ab, g_bb], [1.0] * 4, [500.0, 500.0], [c0a, c0b], [D, D], True, u0,
+                    bc=[1, 0, 0])
+
+
 # M + F of the thin-interface relation for the phase-field mobility (Sec. 5.2.2)
 STEFAN_MF = 0.3084251
 

@@ -1,4 +1,4 @@
-"""The paper's single-grain benchmark at its own size, on the GPU (-m gpu).
+"""Two of the paper's benchmarks at their own sizes, on the GPU (-m gpu).
 
 Sec. 5.2.1: a disc of radius 220 of one grain inside another on a 512^2 grid
 (W = 2.5, M = gamma = 1, no concentration), the obstacle profile of the
@@ -15,6 +15,19 @@ Checked here, with the area sampled every 1000 time units:
   relative error between 2.4% and 3.0%;
 * FP32 and FP64 rates within 1e-4 of each other (the error is spatial);
 * a_phi = 1e-2 gives a smaller error than 1e-4, with fewer RHS evaluations.
+
+Sec. 5.1.2, the double triple junction at the coarsest resolution of the
+paper's study (dx = 1, W = 3, D = 100, gamma_bb = 1, gamma_ab = 2; a disc of
+radius 32 on the grain boundary of a 96 x 192 grid, the long side along the
+boundary): the lens relaxes towards the dihedral angle 2 arccos(1/4) =
+151.04 deg; its angle 4 arctan(S / L) from the 0.5 crossings on the two centre
+lines (the paper's estimate for detecting equilibrium).  The paper reports
+1.4% error at this resolution.  Checked with adaptive RKL2 in FP32 (a_phi =
+1e-2, steps up to 2e4 dt_e): the angle at t = 1e5 within 1.5% of the
+equilibrium value and within 0.1 deg of the angle at t = 5e4 (a plateau;
+longer runs drift on to about 152.8 deg by t = 5e5, 1.2% off), total c
+conserved to 1e-4 (single-precision storage over some 10^4 steps) and phi on
+the simplex.
 """
 import math
 
@@ -84,3 +97,45 @@ def test_single_grain_area_rate(grain):
     loose, tight = res[("fp32", "rkl2", 1e-2)], res[("fp32", "rkl2", 1e-4)]
     assert rel_err(loose[0]) < rel_err(tight[0])
     assert loose[1] < tight[1] < res[("fp32", "fe", None)][1]
+
+
+def _crossings(line):
+    """Positions of the 0.5 crossings of a 1D profile (linear interpolation)."""
+    d = line - 0.5
+    idx = np.where((d[:-1] > 0) != (d[1:] > 0))[0]
+    return [i + d[i] / (d[i] - d[i + 1]) for i in idx]
+
+
+def lens_angle(u, nx, ny):
+    """4 arctan(S / L) of the alpha lens: L along the grain boundary (the
+    column x = nx / 2), S across it (the row y = ny / 2)."""
+    along = _crossings(u[0, 0][:, nx // 2])
+    across = _crossings(u[0, 0][ny // 2, :])
+    return math.degrees(4.0 * math.atan((across[-1] - across[0]) / (along[-1] - along[0])))
+
+
+def test_double_triple_junction_angle():
+    wl = pi.double_triple_junction()
+    theta_eq = math.degrees(2.0 * math.acos(1.0 / 4.0))
+    assert abs(lens_angle(wl.u0, wl.nx, wl.ny) - 180.0) < 1e-9
+    sim = pf.Sim(wl.param_dict(), prec="fp32")
+    sim.init_fields(wl.u0)
+    c0 = sim.conservation()
+    tol = pf.Tol(r_phi=1e-4, a_phi=1e-2, r_c=1e-4, a_c=1e-4, dt_max_over_dte=2e4)
+    angles = {}
+    for t_end in (5e3, 5e4, 1e5):
+        sim.run_to("rkl2", t_end, tol=tol)
+        u, t = sim.get_fields()
+        assert t == t_end
+        angles[t_end] = lens_angle(u, wl.nx, wl.ny)
+        print(f"\ndouble triple junction, t = {t_end:g}: {angles[t_end]:.3f} deg "
+              f"(equilibrium {theta_eq:.3f})", flush=True)
+    dg = sim.diagnostics()
+    c1 = sim.conservation()
+    sim.close()
+    assert angles[5e3] > angles[5e4] + 5.0
+    assert abs(angles[1e5] - theta_eq) / theta_eq < 0.015
+    assert abs(angles[1e5] - angles[5e4]) < 0.1
+    print(f"total c drift {abs(c1 - c0) / abs(c0):.2e} (relative)", flush=True)
+    assert abs(c1 - c0) < 1e-4 * abs(c0)
+    assert dg["max_sum_dev"] < 1e-6 and dg["min_phi"] >= 0.0 and dg["max_phi"] <= 1.0
