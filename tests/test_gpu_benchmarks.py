@@ -28,6 +28,14 @@ equilibrium value and within 0.1 deg of the angle at t = 5e4 (a plateau;
 longer runs drift on to about 152.8 deg by t = 5e5, 1.2% off), total c
 conserved to 1e-4 (single-precision storage over some 10^4 steps) and phi on
 the simplex.
+
+Temporal order (the paper's reference-solution comparison on the single-grain
+benchmark, Sec. 5.2.1): a 128^2 grain of radius 40 (W = 2.5) to t = 20 in
+FP64 with fixed steps halved three times, against SSP(10)4 at 0.1 dt_e.  The
+least-squares slope of log RMS error against log dt is about 1 for FE and
+RKL1 and about 2 for SSP(3)2, SSP(5)2 and RKL2; SSP(10)4 shows about 2 as
+well: the projection S after every stage is not smooth, which caps its
+fourth order on this problem.
 """
 import math
 
@@ -139,3 +147,32 @@ def test_double_triple_junction_angle():
     print(f"total c drift {abs(c1 - c0) / abs(c0):.2e} (relative)", flush=True)
     assert abs(c1 - c0) < 1e-4 * abs(c0)
     assert dg["max_sum_dev"] < 1e-6 and dg["min_phi"] >= 0.0 and dg["max_phi"] <= 1.0
+
+
+@pytest.mark.parametrize("integ,ssp,base,lo,hi", [
+    ("fe", 3, 0.8, 0.9, 1.1), ("rkl1", 3, 20.0, 0.8, 1.3), ("ssp2", 3, 1.6, 1.6, 2.6),
+    ("ssp2", 5, 3.2, 1.6, 2.6), ("rkl2", 3, 20.0, 1.6, 2.6), ("ssp104", 3, 4.0, 1.6, 4.5)])
+def test_temporal_order_single_grain(integ, ssp, base, lo, hi):
+    wl = pi.single_grain(n=128, R=40.0, W=2.5, M=1.0, with_c=False, profile_kind="obstacle")
+    T = 20.0
+    dte = pf.params_stable_dt(wl.param_dict())
+
+    def run(name, dt, s_ssp=3):
+        sim = pf.Sim(wl.param_dict(), prec="fp64", ssp_stages=s_ssp)
+        sim.init_fields(wl.u0)
+        sim.run_to(name, T, dt_fixed=dt)
+        u, t = sim.get_fields()
+        sim.close()
+        assert t == T
+        return u
+
+    ref = run("ssp104", T / math.ceil(T / (0.1 * dte)))
+    dts, errs = [], []
+    for k in range(4):
+        dt = T / (math.ceil(T / (base * dte)) * 2 ** k)
+        dts.append(dt)
+        errs.append(math.sqrt(float(((run(integ, dt, ssp) - ref) ** 2).mean())))
+    slope = np.polyfit(np.log(dts), np.log(errs), 1)[0]
+    print(f"\n{integ} (s = {ssp}) from {base} dt_e: RMS errors {['%.2e' % e for e in errs]}, "
+          f"order {slope:.2f}", flush=True)
+    assert lo <= slope <= hi, (integ, slope, errs)
