@@ -104,6 +104,7 @@ def lib():
         L.pfo_energy.restype = C.c_double
         L.pfo_pair_constants.argtypes = [P, D, D, D]
         L.pfo_num_threads.restype = I
+        L.pfo_set_rkl2_r0_correction.argtypes = [I]
         _lib = L
     return _lib
 
@@ -345,3 +346,17 @@ def _stats(st: _Stats) -> Stats:
 
 def num_threads() -> int:
     return lib().pfo_num_threads()
+
+
+class rkl2_r0_correction_off:
+    """Context in which the oracle's RKL2 skips the first-stage correction of
+    rhs(u^n) (Sec. 3.2, end): only for tests that measure what the correction
+    does to the error."""
+
+    def __enter__(self):
+        lib().pfo_set_rkl2_r0_correction(0)
+        return self
+
+    def __exit__(self, *exc):
+        lib().pfo_set_rkl2_r0_correction(1)
+        return False

@@ -430,8 +430,9 @@ static void step_fe(const pfo_params *P, double dt, double *u, double *r, pfo_st
 }
 
 /* SSP(s)2, Alg. ssp2 with the last line read as using the newest stage
- * (reading R7): s-1 projected Euler sub-steps of dt/(s-1), then
- * u^{n+1} = S(((s-1) q1 + u^n + dt rhs(q1)) / s).
+ * (reading R7): s-1 projected Euler sub-steps q3 = S(q1 + dt (rhs(q1) / (s-1)))
+ * in the algorithm's printed order (the RHS divided by s-1, then times dt),
+ * then u^{n+1} = S(((s-1) q1 + u^n + dt rhs(q1)) / s).
  * z (optional) receives the last sub-step q1 = Y_{s-1}, the embedded
  * first-order solution of reading R9. */
 static void step_ssp2(const pfo_params *P, int s, double dt, double *u, double *z,
@@ -441,7 +442,7 @@ static void step_ssp2(const pfo_params *P, int s, double dt, double *u, double *
     for (int i = 1; i <= s - 1; ++i) {
         pfo_rhs(P, q1, r);
         st->rhs_evals++; st->stages++;
-        for (long long e = 0; e < n; ++e) q3[e] = q1[e] + dt / (s - 1) * r[e];
+        for (long long e = 0; e < n; ++e) q3[e] = q1[e] + dt * (r[e] / (s - 1));
         project(P, q3);
         double *tmp = q1; q1 = q3; q3 = tmp;
     }
@@ -507,10 +508,18 @@ static void step_rkl1(const pfo_params *P, int s, double dt, double *u, double *
     memcpy(u, q[s % 3], (size_t)n * sizeof(double));
 }
 
+/* Whether step_rkl2 applies the first-stage correction of rhs(u^{n,0})
+ * (Sec. 3.2, end).  Always on except where a test switches it off to measure
+ * its effect on the error (the paper reports that it improves the error). */
+static int rkl2_r0_correction = 1;
+void pfo_set_rkl2_r0_correction(int on) { rkl2_r0_correction = on != 0; }
+
 /* RKL2, eq. sts with the stored old solution u^{n,0} (kept in u, apart from
  * the three-slot ring of stages) and initial RHS, and the
  * first-stage correction of rhs(u^{n,0}) where S changed a cell (reading R13):
- *   R0_phi <- (S(u^{n,1}) - u^{n,0}) / (mut_1 dt)   on those cells only. */
+ *   R0_phi <- (S(u^{n,1}) - u^{n,0}) / (mut_1 dt)   on those cells only.
+ * The corrected R0 is the rhs(u^n) of every later stage and of the error
+ * estimate of Sec. 3.3 (reading R14). */
 static void step_rkl2(const pfo_params *P, int s, double dt, double *u, double *r0_out,
                       double *r0, double *r, double *q[3], pfo_stats *st) {
     long long V = ncells(P);
@@ -526,7 +535,7 @@ static void step_rkl2(const pfo_params *P, int s, double dt, double *u, double *
     unsigned char *changed = (unsigned char *)calloc((size_t)V, 1);
     pfo_simplex(P, q[1], changed);
     for (long long i = 0; i < V; ++i) {
-        if (!changed[i]) continue;
+        if (!changed[i] || !rkl2_r0_correction) continue;
         for (int a = 0; a < N; ++a) {
             long long e = (long long)a * V + i;
             r0[e] = (q[1][e] - u[e]) / (mut1 * dt);
