@@ -198,14 +198,33 @@ pf_status pf_step(pf_sim *sim, pf_integrator integ, double dt, pf_stats *stats);
 pf_status pf_run_to(pf_sim *sim, pf_integrator integ, double t_end, const pf_tol *tol,
                     double dt_fixed, pf_stats *stats);
 
-/* Weighted RMS error norm of Sec. 3.3 (eq. error_norm) on device state
- * vectors in the handle's precision, computed on the GPU with FP64
- * accumulation.  kind 0: Sommeijer estimate from u_old = u^n, u_new =
- * u^{n+1}, aux = rhs(u^n), step dt (one extra RHS of u_new is evaluated);
- * kind 1: embedded estimate e = u_new - aux.  Writes the norm and, if
- * non-NULL, the DoF count N. */
-pf_status pf_error_norm(pf_sim *sim, int kind, double dt, const void *u_old, const void *u_new,
-                        const void *aux, const pf_tol *tol, double *norm, long long *ndof);
+/* Weighted RMS error norm of Sec. 3.3 (eq. error_norm) of a given local
+ * error estimate, on host arrays: a pure function, no handle, no device.
+ * e, u_old (u^n) and u_new (u^{n+1}) are F*cells doubles each in the state
+ * layout, F = p->n_phi + (p->with_c != 0); only n_phi and with_c of p are
+ * read.  Each entry is weighted by r max(|u^n|, |u^{n+1}|) + a with the
+ * field's r and a from tol; the phi entries counted are those with e != 0
+ * (the estimate's phi filter of Sec. 3.3 is the caller's, already in e), a
+ * cell with none counts two degrees of freedom, and every c entry counts one.
+ * Sums run over the cells in order (phi ascending, then c), so the result is
+ * reproducible.  *out = sqrt(sum / N).  Errors: PF_EINVAL for null pointers,
+ * cells < 1, n_phi outside 1..16 or negative tolerances; no other effect.
+ * The adaptive steps of pf_run_to compute their norms on the device
+ * (pf_error_norm_device); this form serves callers whose estimate is on the
+ * host. */
+pf_status pf_error_norm(const pf_params *p, long long cells, const double *e, const double *u_old,
+                        const double *u_new, const pf_tol *tol, double *out);
+
+/* The same norm with the estimate formed on the GPU from device state vectors
+ * in the handle's precision, FP64 accumulation in a fixed order.  kind 0:
+ * the estimate of Sec. 3.3 after Sommeijer from u_old = u^n, u_new = u^{n+1},
+ * aux = rhs(u^n) and the step dt (one extra RHS of u_new is evaluated), with
+ * the phi filter; kind 1: the embedded estimate e = u_new - aux.  Writes the
+ * norm and, if non-NULL, the DoF count N.  Allocates the handle's per-tile
+ * partial sums on first use. */
+pf_status pf_error_norm_device(pf_sim *sim, int kind, double dt, const void *u_old,
+                               const void *u_new, const void *aux, const pf_tol *tol,
+                               double *norm, long long *ndof);
 
 /* FP64 sum of c over all cells of the current state (GPU reduction, fixed
  * order, so repeated calls give identical bits). */
@@ -238,6 +257,17 @@ pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
 pf_status pf_set_tiling(pf_sim *sim, int tx, int zchunk);
 pf_status pf_get_tiling(pf_sim *sim, int *tx, int *zchunk);
 pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
+
+/* Least number of buffer groups per state vector (0: the fewest that address
+ * the vectors, the default; 1, 2 or 4).  The stage kernels are compiled per
+ * group count and read each field plane through its group's descriptor; more
+ * groups than the grid needs address the same planes and give the same result
+ * bits.  Errors: PF_EINVAL for other values or fewer groups than the grid
+ * needs; PF_EUNSUPPORTED for more than one group on a grid with walls.
+ * Fused RKL2 stage pairs (below) run only with one group.
+ * pf_get_field_groups reports the count the kernels use. */
+pf_status pf_set_field_groups(pf_sim *sim, int ng);
+pf_status pf_get_field_groups(const pf_sim *sim, int *ng);
 
 /* RKL2 inner stages per launch (eq. sts, stages j >= 2): 1, or 2 for stages j
  * and j + 1 in one pass over memory (four vectors read and two written per

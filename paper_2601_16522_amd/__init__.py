@@ -32,7 +32,8 @@ STATUS = {0: "PF_OK", -1: "PF_EINVAL", -2: "PF_ENOMEM", -3: "PF_EHIP", -4: "PF_E
 # every symbol include/pf.h declares
 EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_init_fields_device",
            "pf_get_fields", "pf_get_fields_device", "pf_rhs", "pf_rhs_device", "pf_stable_dt",
-           "pf_stage_count", "pf_step", "pf_run_to", "pf_error_norm", "pf_conservation",
+           "pf_stage_count", "pf_step", "pf_run_to", "pf_error_norm", "pf_error_norm_device",
+           "pf_conservation", "pf_set_field_groups", "pf_get_field_groups",
            "pf_diagnostics", "pf_get_trace", "pf_get_state", "pf_set_state", "pf_set_tiling",
            "pf_get_tiling", "pf_autotune", "pf_set_timing", "pf_get_kernel_time",
            "pf_supported_nphi", "pf_last_error", "pf_batch_create", "pf_batch_destroy",
@@ -127,7 +128,9 @@ def lib():
             "pf_stage_count": [vp, i, d, C.POINTER(i)],
             "pf_step": [vp, i, d, C.POINTER(_Stats)],
             "pf_run_to": [vp, i, d, C.POINTER(_Tol), d, C.POINTER(_Stats)],
-            "pf_error_norm": [vp, i, d, vp, vp, vp, C.POINTER(_Tol), pd, C.POINTER(ll)],
+            "pf_error_norm_device": [vp, i, d, vp, vp, vp, C.POINTER(_Tol), pd, C.POINTER(ll)],
+            "pf_set_field_groups": [vp, i],
+            "pf_get_field_groups": [vp, C.POINTER(i)],
             "pf_conservation": [vp, pd],
             "pf_diagnostics": [vp, pd],
             "pf_get_trace": [vp, pd, ll, C.POINTER(ll)],
@@ -176,6 +179,7 @@ def lib():
             "pf_controller_init": [C.POINTER(_Controller)],
             "pf_controller_update": [C.POINTER(_Controller), i, d, d, C.POINTER(i), pd],
             "pf_clip_step": [d, d, d, pd, C.POINTER(i)],
+            "pf_error_norm": [C.POINTER(_Params), ll, pd, pd, pd, C.POINTER(_Tol), pd],
         }
         for name, args in hsigs.items():
             fn = getattr(L, name)
@@ -246,6 +250,24 @@ def clip_step(t: float, t_end: float, h: float):
 
 def _dp(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def error_norm(params: dict, e, u_old, u_new, tol: "Tol") -> float:
+    """Weighted RMS norm of a local error estimate e on host arrays
+    (pf_error_norm): e, u_old, u_new are F x V float64 arrays in the state
+    layout; the phi filter is whatever e already holds."""
+    keep = []
+    cp = _cparams(params, "fp64", 0, keep)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (e, u_old, u_new)]
+    V = int(params["nx"]) * int(params["ny"]) * int(params.get("nz", 1))
+    F = int(params["n_phi"]) + (1 if params["with_c"] else 0)
+    if any(a.size != F * V for a in arrs):
+        raise ValueError(f"expected {F * V} values per array")
+    out = C.c_double()
+    ctol = tol._c()
+    _hchk(lib().pf_error_norm(C.byref(cp), V, _dp(arrs[0]), _dp(arrs[1]), _dp(arrs[2]),
+                              C.byref(ctol), C.byref(out)), "pf_error_norm")
+    return out.value
 
 
 def _tptr(t) -> C.c_void_p:
@@ -489,10 +511,12 @@ class Sim:
         return Stats(*[getattr(st, f) for f, _ in _Stats._fields_])
 
     def error_norm(self, kind: int, dt: float, u_old, u_new, aux, tol: Tol):
+        """Error norm of an adaptive step on device state vectors
+        (pf_error_norm_device): (norm, degrees of freedom)."""
         v = C.c_double()
         n = C.c_longlong()
         ctol = tol._c()
-        self._chk(self._L.pf_error_norm(self._h, kind, dt, self._state_ptr(u_old),
+        self._chk(self._L.pf_error_norm_device(self._h, kind, dt, self._state_ptr(u_old),
                                         self._state_ptr(u_new), self._state_ptr(aux),
                                         C.byref(ctol), C.byref(v), C.byref(n)))
         return v.value, n.value
@@ -538,6 +562,15 @@ class Sim:
         a, b, ms = C.c_int(), C.c_int(), C.c_double()
         self._chk(self._L.pf_autotune(self._h, C.byref(a), C.byref(b), C.byref(ms)))
         return a.value, b.value, ms.value
+
+    def set_field_groups(self, ng: int):
+        """Least buffer groups per state vector (0 automatic, 1, 2 or 4)."""
+        self._chk(self._L.pf_set_field_groups(self._h, int(ng)))
+
+    def field_groups(self) -> int:
+        v = C.c_int()
+        self._chk(self._L.pf_get_field_groups(self._h, C.byref(v)))
+        return v.value
 
     def set_stage_fusion(self, depth: int):
         """RKL2 inner stages per launch: 1, or 2 (fused pairs, 2D where built)."""

@@ -86,6 +86,7 @@ struct pf_sim {
     std::vector<double> trace;
     std::string err;
     int tx = 64, zchunk = 16;
+    int groups_min = 1;      // least buffer groups per state vector (pf_set_field_groups)
     int fuse = 1;            // RKL2 inner stages per launch (2: fused pairs, where built)
     int inner_launches = 0;  // launches of the last step's inner-stage interval
     bool timing = false;
@@ -119,6 +120,12 @@ pf_status fail(pf_sim *s, pf_status code, const char *fmt, ...) {
     } while (0)
 
 size_t state_bytes(const pf_sim *s) { return (size_t)s->F * (size_t)s->V * s->esz; }
+
+// Buffer groups of the handle's state vectors: the fewest that address them,
+// or more when pf_set_field_groups asked for more.
+int sim_groups(const pf_sim *s) {
+    return std::max(field_groups_needed(s->N, s->V, (int)s->esz), s->groups_min);
+}
 
 pf_status ensure_buf(pf_sim *s, int i) {
     if (!s->buf[i]) {
@@ -459,7 +466,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     A.r0 = r0;
     A.out = out;
     A.out2 = out2;
-    set_field_bases(A, s->N, s->V);
+    set_field_bases(A, s->N, s->V, s->groups_min);
     A.kind = kind;
     A.a = (T)a; A.b = (T)b; A.c = (T)c; A.d = (T)d; A.e = (T)e; A.f = (T)f;
     int ntx, nty, nzc, ntiles, nblocks;
@@ -480,8 +487,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
 // Whether the fused RKL2 stage-pair kernel is built for the simulation: 2D,
 // periodic, vectors in one buffer group, its LDS within one workgroup's.
 bool pair_ok(const pf_sim *s) {
-    return s->dim == 2 && s->walls == 0 && field_groups_needed(s->N, s->V, (int)s->esz) == 1 &&
-           rkl2_pair_fits((int)s->esz, s->N);
+    return s->dim == 2 && s->walls == 0 && sim_groups(s) == 1 && rkl2_pair_fits((int)s->esz, s->N);
 }
 
 // RKL2 stages j and j + 1 in one launch: y1 = Y_{j-1}, y2 = Y_{j-2}, out = Y_j,
@@ -499,7 +505,7 @@ pf_status stage_pair(pf_sim *s, const T *y1, const T *y2, const T *u0, const T *
     A.r0 = r0;
     A.out = out;
     A.out2 = out2;
-    set_field_bases(A, s->N, s->V);
+    set_field_bases(A, s->N, s->V, s->groups_min);
     A.kind = K_RKL2_PAIR;
     A.a = (T)c1[0]; A.b = (T)c1[1]; A.c = (T)c1[2]; A.d = (T)c1[3]; A.e = (T)c1[4]; A.f = (T)c1[5];
     A.a2 = (T)c2[0]; A.b2 = (T)c2[1]; A.c2 = (T)c2[2]; A.d2 = (T)c2[3]; A.e2 = (T)c2[4]; A.f2 = (T)c2[5];
@@ -556,7 +562,7 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
         A.y1 = unew;
         A.u0 = uold;
         A.r0 = aux;
-        set_field_bases(A, s->N, s->V);
+        set_field_bases(A, s->N, s->V, s->groups_min);
         A.kind = K_EST;
         A.red = s->red;
         A.redn = s->redn;
@@ -654,8 +660,9 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
         int which = 0;
         for (int i = 1; i <= ns - 1; ++i) {
             const int dst = pp[which];
+            // Alg. ssp2: q3 = q1 + dt (rhs(q1) / (s - 1))
             rc = stage<T>(s, K_EULER, bp<T>(s, q1), nullptr, nullptr, nullptr, bp<T>(s, dst), nullptr,
-                          dt / (ns - 1), 0, 0, 0, 0, 0, 0);
+                          dt, (double)(ns - 1), 0, 0, 0, 0, 0);
             if (rc) return rc;
             q1 = dst;
             which ^= 1;
@@ -1211,8 +1218,8 @@ pf_status pf_run_to(pf_sim *s, pf_integrator integ, double t_end, const pf_tol *
     return rc;
 }
 
-pf_status pf_error_norm(pf_sim *s, int kind, double dt, const void *u_old, const void *u_new,
-                        const void *aux, const pf_tol *tol, double *norm, long long *ndof) {
+pf_status pf_error_norm_device(pf_sim *s, int kind, double dt, const void *u_old, const void *u_new,
+                               const void *aux, const pf_tol *tol, double *norm, long long *ndof) {
     if (!s || !u_old || !u_new || !aux || !tol || !norm) return PF_EINVAL;
     if (kind != 0 && kind != 1) return PF_EINVAL;
     if (s->prec == PF_FP64)
@@ -1220,6 +1227,62 @@ pf_status pf_error_norm(pf_sim *s, int kind, double dt, const void *u_old, const
                                   (const double *)aux, *tol, norm, ndof);
     return error_norm<float>(s, kind, dt, (const float *)u_old, (const float *)u_new,
                              (const float *)aux, *tol, norm, ndof);
+}
+
+pf_status pf_error_norm(const pf_params *p, long long cells, const double *e, const double *u_old,
+                        const double *u_new, const pf_tol *tol, double *out) {
+    if (!p || !e || !u_old || !u_new || !tol || !out || cells < 1) return PF_EINVAL;
+    if (p->n_phi < 1 || p->n_phi > NMAX) return PF_EINVAL;
+    if (!(tol->r_phi >= 0.0) || !(tol->a_phi >= 0.0) || !(tol->r_c >= 0.0) || !(tol->a_c >= 0.0))
+        return PF_EINVAL;
+    const int N = p->n_phi;
+    const long long V = cells;
+    // eq. error_norm: cells in order; in each cell the phi entries with a
+    // nonzero estimate (phases ascending), or two degrees of freedom where
+    // there are none, then the cell's c entry
+    double sum = 0.0;
+    long long ndof = 0;
+    for (long long i = 0; i < V; ++i) {
+        int nt = 0;
+        for (int a = 0; a < N; ++a) {
+            const long long k = (long long)a * V + i;
+            if (e[k] != 0.0) {
+                const double w = tol->r_phi * std::fmax(std::fabs(u_old[k]), std::fabs(u_new[k])) + tol->a_phi;
+                const double q = e[k] / w;
+                sum = sum + q * q;
+                ++nt;
+            }
+        }
+        ndof += nt > 0 ? nt : 2;
+        if (p->with_c) {
+            const long long k = (long long)N * V + i;
+            const double w = tol->r_c * std::fmax(std::fabs(u_old[k]), std::fabs(u_new[k])) + tol->a_c;
+            const double q = e[k] / w;
+            sum = sum + q * q;
+            ndof += 1;
+        }
+    }
+    *out = std::sqrt(sum / (double)ndof);
+    return PF_OK;
+}
+
+pf_status pf_set_field_groups(pf_sim *s, int ng) {
+    if (!s) return PF_EINVAL;
+    if (ng != 0 && ng != 1 && ng != 2 && ng != 4)
+        return fail(s, PF_EINVAL, "buffer groups %d (0, 1, 2 or 4)", ng);
+    const int need = field_groups_needed(s->N, s->V, (int)s->esz);
+    if (ng != 0 && ng < need)
+        return fail(s, PF_EINVAL, "the vectors need at least %d buffer groups", need);
+    if (ng > 1 && s->walls)
+        return fail(s, PF_EUNSUPPORTED, "wall kernels are built for one buffer group");
+    s->groups_min = ng == 0 ? 1 : ng;
+    return PF_OK;
+}
+
+pf_status pf_get_field_groups(const pf_sim *s, int *ng) {
+    if (!s || !ng) return PF_EINVAL;
+    *ng = sim_groups(s);
+    return PF_OK;
 }
 
 pf_status pf_diagnostics(pf_sim *s, double out[5]) {

@@ -52,7 +52,8 @@ struct DevParams {
 // planes onto the simplex (except RHS and EST, which project nothing).
 enum StageKind : int {
     K_RHS = 0,          // out = rhs(y1)
-    K_EULER = 1,        // out = S(y1 + a r); out2 (optional) = r
+    K_EULER = 1,        // out = S(y1 + a r), or S(y1 + a (r / b)) when b != 0 (the
+                        // SSP(s)2 sub-step of Alg. ssp2); out2 (optional) = r
     K_SSP2_FINAL = 2,   // out = S(((a y1 + u0) + b r) / c)
     K_SSP104_S5 = 3,    // y = S(y1 + a r); out2 = b u0 + c y; out = S(d out2 - e y)
     K_SSP104_FINAL = 4, // out = S((u0 + a y1) + b r)
@@ -124,11 +125,14 @@ inline int field_groups_needed(int n, long long V, int esz) {
     return 0;
 }
 
-// Fills the buffer-group bases of a StageArgs from its vector pointers.  The
-// caller guarantees field_groups_needed(n, V, sizeof(T)) > 0.
+// Fills the buffer-group bases of a StageArgs from its vector pointers, with
+// at least ng_min groups (1, 2 or 4; more groups than the size needs address
+// the same planes through more descriptors).  The caller guarantees
+// field_groups_needed(n, V, sizeof(T)) > 0.
 template <typename T>
-inline void set_field_bases(StageArgs<T> &A, int n, long long V) {
-    const int ng = field_groups_needed(n, V, (int)sizeof(T));
+inline void set_field_bases(StageArgs<T> &A, int n, long long V, int ng_min = 1) {
+    int ng = field_groups_needed(n, V, (int)sizeof(T));
+    if (ng < ng_min) ng = ng_min;
     const int GS = group_planes(n, ng);
     A.ng = ng;
     A.plane_bytes = (unsigned)((unsigned long long)V * sizeof(T));

@@ -487,7 +487,27 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
             cnt += 1;
         }
     } else {
-        if constexpr (KIND == K_EULER || KIND == K_SSP104_S5 || KIND == K_RKL2_FIRST) {
+        if constexpr (KIND == K_EULER) {
+            // b != 0: the sub-step of Alg. ssp2, y + dt (r / (s - 1)) with a = dt
+            // and b = s - 1, in the printed order (the fast form scales r by
+            // the quotient a / b in one fused multiply-add)
+            if (A.b != T(0)) {
+                if constexpr (FAST) {
+                    const T ab = A.a / A.b;
+#pragma unroll
+                    for (int f = 0; f <= N; ++f) yv[f] = fma_t(ab, r[f], cur[f]);
+                } else {
+#pragma unroll
+                    for (int f = 0; f <= N; ++f) yv[f] = cur[f] + A.a * (r[f] / A.b);
+                }
+            } else {
+#pragma unroll
+                for (int f = 0; f <= N; ++f) {
+                    if constexpr (FAST) yv[f] = fma_t(A.a, r[f], cur[f]);
+                    else yv[f] = cur[f] + A.a * r[f];
+                }
+            }
+        } else if constexpr (KIND == K_SSP104_S5 || KIND == K_RKL2_FIRST) {
 #pragma unroll
             for (int f = 0; f <= N; ++f) {
                 if constexpr (FAST) yv[f] = fma_t(A.a, r[f], cur[f]);

@@ -104,3 +104,55 @@ def test_tolerance_marshalling():
     assert (c.r_phi, c.a_phi, c.r_c, c.a_c, c.dt_max_over_dte, c.dt0) == (1e-5, 2e-5, 3e-5, 4e-5, 50.0, 1e-3)
     d = pf.Tol()
     assert (d.r_phi, d.a_phi, d.r_c, d.a_c) == (1e-4, 1e-2, 1e-4, 1e-4)
+
+
+def test_host_error_norm_matches_oracle_embedded():
+    """pf_error_norm (host arrays, a given estimate e) against the oracle's norm
+    of the embedded estimate e = u^{n+1} - z (Sec. 3.3, eq. error_norm): the
+    same cells, weights, degree-of-freedom rule and summation order, so the
+    same bits.  Phi entries with e = 0 are left out and bulk cells count two."""
+    rng = np.random.default_rng(11)
+    for p in _param_sets()[:4]:
+        P = oracle.Params(**p)
+        shape = P.shape
+        un = rng.uniform(0.0, 1.0, size=shape)
+        unp1 = un + rng.normal(0.0, 1e-3, size=shape)
+        z = unp1 - rng.normal(0.0, 1e-4, size=shape)
+        # entries without error: whole cells, and single phi entries
+        N = P.n_phi
+        z[:N, ..., ::3] = unp1[:N, ..., ::3]
+        z[0, ..., 1::5] = unp1[0, ..., 1::5]
+        tol = oracle.Tol(r_phi=1e-3, a_phi=1e-2, r_c=2e-4, a_c=1e-4)
+        ref, ndof, _ = oracle.error_norm(P, 1, 0.1, un, unp1, z, tol)
+        got = pf.error_norm(p, unp1 - z, un, unp1, pf.Tol(1e-3, 1e-2, 2e-4, 1e-4))
+        assert got == ref, (got, ref)
+
+
+def test_host_error_norm_hand_worked():
+    """The hand-worked 2 x 1 case of the oracle's pins: one nontrivial phi entry
+    in cell 0, none in cell 1 (2 DoF), one c entry per cell."""
+    p = dict(pi.single_grain(n=2, R=1.0).param_dict())
+    p.update(nx=2, ny=1)
+    e = np.zeros((3, 1, 1, 2))
+    un = np.zeros_like(e)
+    unp1 = np.zeros_like(e)
+    unp1[0] = 1.0
+    unp1[2] = 0.5
+    un[:] = unp1
+    un[0, 0, 0, 0], un[1, 0, 0, 0], un[2, 0, 0, 0] = 0.98, 0.02, 0.51
+    e[0, 0, 0, 0] = (12 * (0.98 - 1.0) + 6 * 0.5 * 0.01) / 15
+    e[2, 0, 0, 0] = (12 * (0.51 - 0.5)) / 15
+    e[2, 0, 0, 1] = (6 * 0.5 * 0.02) / 15
+    got = pf.error_norm(p, e, un, unp1, pf.Tol(0.1, 0.01, 0.2, 0.001))
+    ss = (e[0, 0, 0, 0] / (0.1 * 1.0 + 0.01)) ** 2 + (e[2, 0, 0, 0] / (0.2 * 0.51 + 0.001)) ** 2 \
+        + (e[2, 0, 0, 1] / (0.2 * 0.5 + 0.001)) ** 2
+    assert got == pytest.approx(math.sqrt(ss / 5), rel=1e-14)
+
+
+def test_host_error_norm_errors():
+    p = pi.single_grain(n=4, R=1.0).param_dict()
+    a = np.zeros((3, 1, 4, 4))
+    with pytest.raises(pf.PFError):
+        pf.error_norm(p, a, a, a, pf.Tol(-1.0, 1e-2, 1e-4, 1e-4))
+    L = pf.lib()
+    assert L.pf_error_norm(None, 16, None, None, None, None, None) == -1
