@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import pf_inputs as pi
+from _parity import check_fp32_multi, mixed_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -29,18 +30,6 @@ def _gpu():
     pf.lib()
 
 
-def mixed_2d(nx=70, ny=45, seed=21):
-    """Three phases of two thermodynamic types with c: Voronoi grains (6 seeds,
-    round-robin to 3 fields), ragged grid, c near the local equilibrium."""
-    rng = np.random.default_rng(seed)
-    seeds = pi.seeds_min_distance(6, (nx, ny), 8.0, rng)
-    phi = pi.voronoi_fields((1, ny, nx), seeds, 3, 3.0)
-    c0 = [0.1, 0.9]
-    tof = [0, 1, 1]
-    c = sum(phi[a] * c0[tof[a]] for a in range(3)) + rng.normal(0, 0.01, size=phi[0].shape)
-    u0 = np.concatenate([phi, c[None]])
-    return pi.Workload("mixed2d", 2, nx, ny, 1, 3, tof, 2, 1.0, 3.0, [1.0, 0.8, 0.8, 1.2],
-                       [1.0, 2.0, 2.0, 0.5], [500.0, 300.0], c0, [1.0, 0.3], True, u0)
 
 
 def pores_3d(n=20, nyz=(18, 13)):
@@ -193,8 +182,16 @@ def test_adaptive_3d_pores_fp64_matches_oracle_trace(integ, tolv, tmul):
     st32 = s32.run_to(integ, t_end, tol=pf.Tol(**tol))
     d = s32.diagnostics()
     u32, t32 = s32.get_fields()
-    print(f"3D pores {integ} FP32: {st32.accepted} accepted / {st32.rejected} rejected (FP64 "
-          f"{st_ref.accepted}), max |dphi| vs oracle {np.abs(u32[:-1] - ref[:-1]).max():.2e}", flush=True)
+    # the oracle takes the FP32 run's accepted steps: FP32 against FP64 on
+    # the same steps, by the multi-grain bar (tests/_parity.py)
+    tr32 = s32.trace()
+    ref32 = wl.u0
+    for h, ns, _, acc in tr32:
+        if acc:
+            ref32, _, _ = oracle.step(P, INTEG[integ], h, ref32, s=int(ns))
+    smax = int(tr32[tr32[:, 3] == 1, 1].max())
+    check_fp32_multi(wl, u32, ref32, smax, f"3D pores adaptive {integ} FP32 ({st32.accepted} "
+                     f"accepted / {st32.rejected} rejected; FP64 {st_ref.accepted})", 1e-4)
     assert t32 == t_end and d["nonfinite"] == 0
     assert abs(d["sum_c"] - c0) <= 1e-6 * abs(c0)
     assert d["max_sum_dev"] <= 1e-6 and d["min_phi"] >= 0.0 and d["max_phi"] <= 1.0
@@ -395,5 +392,5 @@ def test_cfg2_full_size_one_rkl2_step_fp64_and_fp32():
           f"three-phase cell {far:.2f} cells", flush=True)
     assert math.sqrt((d ** 2).mean()) <= 1e-5
     assert d.max() <= 1e-2
-    assert (d > 1e-4).sum() <= 1e-4 * d.size  # a sanity bound on how many decisions flip
+    assert (d > 1e-4).sum() <= 1e-5 * d.size  # measured 30 of 8.4M (3.6e-6)
     assert far <= s
