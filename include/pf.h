@@ -226,6 +226,23 @@ pf_status pf_error_norm_device(pf_sim *sim, int kind, double dt, const void *u_o
                                const void *u_new, const void *aux, const pf_tol *tol,
                                double *norm, long long *ndof);
 
+/* pf_error_norm_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same estimate, norm, arguments and result bits, but its
+ * partial sums go to a static device array of the library (2 MiB, held by
+ * each GPU the library runs on until the process ends) instead of memory the
+ * handle allocates, and it creates no timing events.  It calls no hipMalloc,
+ * hipFree or other allocating routine.  Limit: kind 0 needs one partial per
+ * tile (64 x 4 cells times the z extent of pf_set_tiling), at most 131072;
+ * kind 1 needs 1024.  A larger request returns PF_EINVAL and launches
+ * nothing.  Every call on one GPU uses that GPU's one array, so calls that
+ * overlap on a GPU (other threads, other streams) race and must be
+ * serialised by the caller; the array keeps the last call's contents, and
+ * each call writes every entry it reads. */
+pf_status pf_error_norm_device_noalloc(pf_sim *sim, int kind, double dt, const void *u_old,
+                                       const void *u_new, const void *aux, const pf_tol *tol,
+                                       double *norm, long long *ndof);
+
 /* FP64 sum of c over all cells of the current state (GPU reduction, fixed
  * order, so repeated calls give identical bits). */
 pf_status pf_conservation(pf_sim *sim, double *sum_c);

@@ -33,6 +33,7 @@ STATUS = {0: "PF_OK", -1: "PF_EINVAL", -2: "PF_ENOMEM", -3: "PF_EHIP", -4: "PF_E
 EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_init_fields_device",
            "pf_get_fields", "pf_get_fields_device", "pf_rhs", "pf_rhs_device", "pf_stable_dt",
            "pf_stage_count", "pf_step", "pf_run_to", "pf_error_norm", "pf_error_norm_device",
+           "pf_error_norm_device_noalloc",
            "pf_conservation", "pf_set_field_groups", "pf_get_field_groups",
            "pf_diagnostics", "pf_get_trace", "pf_get_state", "pf_set_state", "pf_set_tiling",
            "pf_get_tiling", "pf_autotune", "pf_set_timing", "pf_get_kernel_time",
@@ -129,6 +130,8 @@ def lib():
             "pf_step": [vp, i, d, C.POINTER(_Stats)],
             "pf_run_to": [vp, i, d, C.POINTER(_Tol), d, C.POINTER(_Stats)],
             "pf_error_norm_device": [vp, i, d, vp, vp, vp, C.POINTER(_Tol), pd, C.POINTER(ll)],
+            "pf_error_norm_device_noalloc": [vp, i, d, vp, vp, vp, C.POINTER(_Tol), pd,
+                                             C.POINTER(ll)],
             "pf_set_field_groups": [vp, i],
             "pf_get_field_groups": [vp, C.POINTER(i)],
             "pf_conservation": [vp, pd],
@@ -519,6 +522,17 @@ class Sim:
         self._chk(self._L.pf_error_norm_device(self._h, kind, dt, self._state_ptr(u_old),
                                         self._state_ptr(u_new), self._state_ptr(aux),
                                         C.byref(ctol), C.byref(v), C.byref(n)))
+        return v.value, n.value
+
+    def error_norm_noalloc(self, kind: int, dt: float, u_old, u_new, aux, tol: Tol):
+        """pf_error_norm_device_noalloc: the same norm with its partial sums in
+        the library's static device scratch (no device allocation)."""
+        v = C.c_double()
+        n = C.c_longlong()
+        ctol = tol._c()
+        self._chk(self._L.pf_error_norm_device_noalloc(
+            self._h, kind, dt, self._state_ptr(u_old), self._state_ptr(u_new),
+            self._state_ptr(aux), C.byref(ctol), C.byref(v), C.byref(n)))
         return v.value, n.value
 
     def conservation(self) -> float:

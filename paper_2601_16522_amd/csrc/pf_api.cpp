@@ -545,14 +545,28 @@ pf_status wait_result(pf_sim *s, double seq) {
     return PF_OK;
 }
 
-template <typename T>
-pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *unew, const T *aux,
-                     const pf_tol &tol, double *norm, long long *ndof) {
+// Partial sums of an error norm: one per tile for the estimate of Sec. 3.3
+// (kind 0), one per block of the grid-stride embedded estimate (kind 1).
+constexpr int EMBED_BLOCKS = 1024;
+int norm_partials(const pf_sim *s, int kind) {
     int ntx, nty, nzc, ntiles, nblocks;
     tiles(s, ntx, nty, nzc, ntiles, nblocks);
-    const int nred = kind == 0 ? ntiles : 1024;
-    pf_status rc = ensure_red(s, std::max(nred, 1024));
-    if (rc) return rc;
+    return kind == 0 ? ntiles : EMBED_BLOCKS;
+}
+
+// The estimate and its norm with the partial sums in red / redn (at least
+// norm_partials(s, kind) entries each); timed: record the timing events (the
+// allocation-free path records none, since events may be created on demand).
+template <typename T>
+pf_status error_norm_with(pf_sim *s, int kind, double dt, const T *uold, const T *unew, const T *aux,
+                          const pf_tol &tol, double *red, long long *redn, bool timed, double *norm,
+                          long long *ndof) {
+    int ntx, nty, nzc, ntiles, nblocks;
+    tiles(s, ntx, nty, nzc, ntiles, nblocks);
+    const int nred = norm_partials(s, kind);
+    const bool was_timing = s->timing;
+    if (!timed) s->timing = false;
+    pf_status rc = PF_OK;
     Pending p;
     if (kind == 0) {
         StageArgs<T> A;
@@ -564,8 +578,8 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
         A.r0 = aux;
         set_field_bases(A, s->N, s->V, s->groups_min);
         A.kind = K_EST;
-        A.red = s->red;
-        A.redn = s->redn;
+        A.red = red;
+        A.redn = redn;
         A.r_phi = (T)tol.r_phi; A.a_phi = (T)tol.a_phi;
         A.r_c = (T)tol.r_c; A.a_c = (T)tol.a_c;
         A.dt6 = (T)(6.0 * dt);
@@ -574,27 +588,39 @@ pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *une
         A.ntx = ntx; A.nty = nty; A.nzc = nzc; A.ntiles = ntiles;
         begin_timed(s, FAM_EST, p);
         hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
-        if (err != hipSuccess) return fail(s, PF_EHIP, "estimator launch: %s", hipGetErrorString(err));
+        if (err != hipSuccess) rc = fail(s, PF_EHIP, "estimator launch: %s", hipGetErrorString(err));
         end_timed(s, p);
     } else {
         begin_timed(s, FAM_EST, p);
         hipError_t err = launch_embed_est<T>((const DevParams<T> *)s->dparams, s->N, s->with_c, s->V,
                                              unew, aux, uold, (T)tol.r_phi, (T)tol.a_phi,
-                                             (T)tol.r_c, (T)tol.a_c, s->red, s->redn, nred,
-                                             s->stream);
-        if (err != hipSuccess) return fail(s, PF_EHIP, "embedded estimator launch: %s", hipGetErrorString(err));
+                                             (T)tol.r_c, (T)tol.a_c, red, redn, nred, s->stream);
+        if (err != hipSuccess) rc = fail(s, PF_EHIP, "embedded estimator launch: %s", hipGetErrorString(err));
         end_timed(s, p);
     }
-    begin_timed(s, FAM_RED, p);
-    s->res_seq += 1.0;
-    HIPCHK(s, launch_finalize_norm(s->red, s->redn, nred, s->hres_dev + RES_NORM, s->res_seq,
-                                   s->stream));
-    end_timed(s, p);
-    if (pf_status rc = wait_result(s, s->res_seq)) return rc;
+    if (!rc) {
+        begin_timed(s, FAM_RED, p);
+        s->res_seq += 1.0;
+        const hipError_t err = launch_finalize_norm(red, redn, nred, s->hres_dev + RES_NORM, s->res_seq,
+                                                    s->stream);
+        if (err != hipSuccess) rc = fail(s, PF_EHIP, "norm launch: %s", hipGetErrorString(err));
+        end_timed(s, p);
+    }
+    s->timing = was_timing;
+    if (rc) return rc;
+    if ((rc = wait_result(s, s->res_seq))) return rc;
     *norm = s->hres[RES_NORM + 2];
     if (ndof) *ndof = (long long)s->hres[RES_NORM + 1];
     s->st.rhs_evals += kind == 0 ? 1 : 0;
     return PF_OK;
+}
+
+template <typename T>
+pf_status error_norm(pf_sim *s, int kind, double dt, const T *uold, const T *unew, const T *aux,
+                     const pf_tol &tol, double *norm, long long *ndof) {
+    pf_status rc = ensure_red(s, std::max(norm_partials(s, kind), EMBED_BLOCKS));
+    if (rc) return rc;
+    return error_norm_with<T>(s, kind, dt, uold, unew, aux, tol, s->red, s->redn, true, norm, ndof);
 }
 
 // ---------------------------------------------------------------------------
@@ -1227,6 +1253,34 @@ pf_status pf_error_norm_device(pf_sim *s, int kind, double dt, const void *u_old
                                   (const double *)aux, *tol, norm, ndof);
     return error_norm<float>(s, kind, dt, (const float *)u_old, (const float *)u_new,
                              (const float *)aux, *tol, norm, ndof);
+}
+
+pf_status pf_error_norm_device_noalloc(pf_sim *s, int kind, double dt, const void *u_old,
+                                       const void *u_new, const void *aux, const pf_tol *tol,
+                                       double *norm, long long *ndof) {
+    if (!s || !u_old || !u_new || !aux || !tol || !norm) return PF_EINVAL;
+    if (kind != 0 && kind != 1) return PF_EINVAL;
+    // the partial sums go to the static scratch: nred doubles, then nred
+    // counts from the next 256-byte boundary; every entry is written before
+    // the final sum reads it, so nothing needs clearing between calls
+    const size_t nred = (size_t)norm_partials(s, kind);
+    const size_t cnt_off = (nred * sizeof(double) + 255) / 256 * 256;
+    if (cnt_off + nred * sizeof(long long) > SCRATCH_BYTES)
+        return fail(s, PF_EINVAL,
+                    "%zu partial sums (one per tile of 64 x 4 cells and z extent %d) exceed the "
+                    "static scratch of %zu bytes (at most %zu); use a larger z extent "
+                    "(pf_set_tiling) or pf_error_norm_device",
+                    nred, s->zchunk, (size_t)SCRATCH_BYTES,
+                    (size_t)SCRATCH_BYTES / (sizeof(double) + sizeof(long long)));
+    void *base = nullptr;
+    HIPCHK(s, scratch_address(&base));
+    double *red = (double *)base;
+    long long *redn = (long long *)((char *)base + cnt_off);
+    if (s->prec == PF_FP64)
+        return error_norm_with<double>(s, kind, dt, (const double *)u_old, (const double *)u_new,
+                                       (const double *)aux, *tol, red, redn, false, norm, ndof);
+    return error_norm_with<float>(s, kind, dt, (const float *)u_old, (const float *)u_new,
+                                  (const float *)aux, *tol, red, redn, false, norm, ndof);
 }
 
 pf_status pf_error_norm(const pf_params *p, long long cells, const double *e, const double *u_old,

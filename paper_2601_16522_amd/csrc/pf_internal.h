@@ -248,6 +248,11 @@ template <typename T>
 hipError_t launch_batch_euler(int nphi, const BatchArgs<T> &args, int nblocks, hipStream_t stream);
 hipError_t launch_batch_tick(int *step_base, int k, hipStream_t stream);
 
+// Static device scratch of the allocation-free error norm: its size in bytes,
+// and the device address of the current GPU's copy (looked up once per device).
+constexpr size_t SCRATCH_BYTES = size_t(2) << 20;
+hipError_t scratch_address(void **ptr);
+
 bool nphi_supported(int nphi);
 int supported_nphi_list(int *out, int cap);
 

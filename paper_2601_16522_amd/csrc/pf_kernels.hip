@@ -2,10 +2,38 @@
 // fused stage kernels (pf_stage.hpp) over the compiled numbers of order
 // parameters.
 #include <algorithm>
+#include <mutex>
 
 #include "pf_device.hpp"
 
 namespace pf {
+
+// Device scratch of the allocation-free error norm (pf_error_norm_device_noalloc):
+// its per-tile partial sums live here instead of in memory the handle
+// allocates.  Each GPU holds its own copy for the life of the process.
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+// Device address of this GPU's scratch array.  The array's name is only a
+// host-side stand-in for it, so host code uses the address looked up here,
+// once per device with that device current, and cached.
+hipError_t scratch_address(void **ptr) {
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void *addr[MAXDEV] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 // Embedded-solution estimate (SSP(s)2, e = u^{n+1} - z) with the same norm
 // terms; grid-stride over cells, deterministic per-block partials.
