@@ -1,23 +1,29 @@
 """Benchmark of the explicit phase-field + concentration time step on one MI355X.
 
-Default workload: the 1024^2 periodic Voronoi microstructure with 8 order
-parameters and c (200 grains, round-robin onto 8 fields, interface parameter
-W = 5 cells, c = 0.3 + N(0, 0.01^2)), integrated with adaptive RKL2 (error
-estimate and PID controller of Sec. 3.3, a_phi = 1e-2, r = a_c = 1e-4) from
-t = 0 to t_end = 100 in the chosen FP32 form.  One benchmark step is one whole
-time-to-solution run: every stage kernel (RHS + stage combination + simplex),
-the first-stage RHS correction, the estimator with its FP64 reduction, the
-controller and the FP64 conservation sum.  The initial state is copied into the
-handle (device to device, untimed) before each step.
+Default workload: 3D periodic grain growth with pores at 512^3 (2000 seeded
+Voronoi grains round-robin onto 8 order parameters, a pore phase of 400
+seeded spheres of radius 3-8 cells, c = 1 in the pores and 0 in the solid;
+the paper's mobile-pore parameter set of Sec. 5.3), ten fixed RKL2 steps of
+100 dt_e (21 stages each, eq. sts with the five-vector storage) to
+t_end = 1000 dt_e in the chosen FP32 form, with the FP64 conservation sum at
+the end.  One benchmark step is that whole run: every stage kernel (RHS +
+stage combination + simplex projection), the first-stage RHS correction and
+the FP64 sum of c.  The initial state is copied into the handle (device to
+device, untimed) before each step.
 
-Prints one JSON line (metric of the project: Gcell-stage/s, i.e. cells x RHS
-evaluations per second, with the time to solution and the HBM roofline of the
-dominant kernel, the RKL2 inner stage).
+Prints one JSON line: Gcell-stage/s (cells x RHS evaluations per second), the
+time to solution, the HBM roofline of the dominant kernel (the RKL2 inner
+stage), the FP64 oracle timed on the host on a bounded sample of the same
+workload, and, under config.batch_equal_error, the spec comparison at
+equal sharp-interface error: 96 uneven 2D shrinking grains batched in FP32
+against the plain FP64 form instance by instance.
 
-Other modes: --workload pores3d|gg3d (3D grains + pores, two or ten fixed RKL2
-steps; with --adaptive, pores3d runs adaptive RKL2 to t_end = 1e-3), --workload batch
-(96 uneven 2D instances), --copy-calib for the rocprofv3 counter calibration
-copy kernel.
+Other modes: --workload pores3d (256^3 sintering, two fixed RKL2 steps; with
+--adaptive, adaptive RKL2 to t_end = 1e-3), --workload voronoi2d (the
+1024^2 eight-field microstructure, adaptive RKL2 to t = 100; its 189 MB
+footprint is resident in the 256 MB last-level cache), --workload batch (the
+96-instance batch with its RKL2 and adaptive legs), --copy-calib for the
+rocprofv3 counter calibration copy kernel.
 """
 from __future__ import annotations
 
@@ -107,8 +113,19 @@ def stream_reference(vector_bytes: int):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def z_slab(wl, planes: int):
+    """The first `planes` z planes of a 3D workload as a periodic grid of their
+    own: the same fields and value distribution, a bounded sample for timing
+    the CPU oracle."""
+    import dataclasses
+    if wl.dim != 3 or planes >= wl.nz:
+        return wl
+    u0 = np.ascontiguousarray(wl.u0[:, :planes])
+    return dataclasses.replace(wl, name=f"{wl.name}[z<{planes}]", nz=planes, u0=u0)
+
+
 def cpu_baseline(wl, integ: str, t_end: float, tol_kw: dict, dt_fixed: float, sample_note: str):
-    """Time the FP64 CPU oracle (as it stands) on the same workload."""
+    """Time the FP64 CPU oracle (as it stands) on a workload."""
     import oracle
     oracle.build(force=False)
     P = oracle.Params(**wl.param_dict())
@@ -128,6 +145,63 @@ def area_slope_error(u0, u, t, M, dx=1.0, gamma=1.0):
     (phase 1) against the curvature-flow law -2 pi M gamma (Sec. 5.2.1)."""
     rate = (u[1].sum() - u0[1].sum()) * dx * dx / t
     return abs(rate / (-2 * math.pi * M * gamma) - 1.0)
+
+
+def batch_equal_error():
+    """The spec comparison at equal sharp-interface error: the 96
+    shrinking-grain instances, 2000 forward-Euler steps each at 0.9 dt_e,
+    batched in FP32 (one fused launch per step, autotuned, hipGraphs of 50
+    launches) against the plain FP64 form run instance by instance; the error
+    is that of the mean area rate against dA/dt = -2 pi M gamma (Sec. 5.2.1).
+    One untimed run each to warm up, then one timed run each."""
+    import torch
+    import paper_2601_16522_amd as pf
+    import pf_inputs as pi
+    nsteps = 2000
+    wls = pi.batch_instances()
+    stream = torch.cuda.Stream()
+    b = pf.Batch([w.param_dict() for w in wls], prec="fp32")
+    b.set_stream(stream)
+    for i, w in enumerate(wls):
+        b.init_fields(i, w.u0)
+    dts = [0.9 * b.stable_dt(i) for i in range(len(wls))]
+    t_end = [nsteps * d for d in dts]
+    b.autotune()
+
+    def run32():
+        for i, w in enumerate(wls):
+            b.init_fields(i, w.u0)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        b.run_to(t_end, dt=dts, graph_steps=50)
+        stream.synchronize()
+        return time.perf_counter() - t0
+
+    run32()
+    t32 = run32()
+    err32 = [area_slope_error(w.u0, b.get_fields(i)[0], t_end[i], w.mob[0]) for i, w in enumerate(wls)]
+    b.close()
+    t64, err64 = 0.0, []
+    for i, w in enumerate(wls):
+        s = pf.Sim(w.param_dict(), prec="fp64")
+        s.set_stream(stream)
+        for rep in range(2 if i == 0 else 1):  # the first instance once more, to warm up
+            s.init_fields(w.u0)
+            stream.synchronize()
+            ts = time.perf_counter()
+            s.run_to("fe", t_end[i], dt_fixed=dts[i])
+            stream.synchronize()
+        t64 += time.perf_counter() - ts
+        err64.append(area_slope_error(w.u0, s.get_fields()[0], t_end[i], w.mob[0]))
+        s.close()
+    return {"workload": f"{len(wls)} 2D shrinking grains (side 64..512, R 0.2..0.4 side, "
+                        f"M 0.5..2), {sum(w.cells for w in wls)} cells, {nsteps} FE steps each "
+                        f"at 0.9 dt_e",
+            "fp32_batched_ms": round(t32 * 1e3, 3), "fp64_per_instance_ms": round(t64 * 1e3, 3),
+            "speedup": round(t64 / t32, 2),
+            "area_rate_rel_error_fp32_batched": float(np.mean(err32)),
+            "area_rate_rel_error_fp64_per_instance": float(np.mean(err64)),
+            "area_rate_rel_error_max_abs_diff": float(np.max(np.abs(np.subtract(err32, err64))))}
 
 
 def batch_bench(args):
@@ -284,9 +358,9 @@ def batch_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="voronoi2d",
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gg3d",
                     choices=["voronoi2d", "pores3d", "gg3d", "batch"])
     ap.add_argument("--size", type=int, default=0)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
@@ -313,6 +387,11 @@ def main():
                          "sintering run) instead of two fixed steps")
     ap.add_argument("--no-fp64-ref", action="store_true",
                     help="batch: skip the FP64 instance-by-instance comparison")
+    ap.add_argument("--no-batch-leg", action="store_true",
+                    help="skip the batched FP32 against per-instance FP64 comparison of the "
+                         "default line")
+    ap.add_argument("--cpu-planes", type=int, default=64,
+                    help="3D workloads: z planes of the sample the CPU oracle is timed on")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -471,16 +550,26 @@ def main():
                      "stream_ref_GBs": sref,
                      "frac_of_stream_4r1w": round(achieved / sref["4r1w"], 4) if sref else None},
     }
+    if args.workload == "gg3d" and not args.no_batch_leg:
+        print("# batch leg: FP32 batched against FP64 per instance", file=sys.stderr, flush=True)
+        out["config"]["batch_equal_error"] = batch_equal_error()
     if not args.no_cpu_baseline:
         note = f"full {wl.name} solve ({desc}) on the host CPU"
+        cwl = wl
         if args.workload != "voronoi2d":
-            note = f"one fixed {args.integ.upper()} step of {wl.name} at 100 dt_e"
+            # a bounded sample: one fixed step at 100 dt_e (the same stage count
+            # and mix) on the first z planes of the same state, periodic in z
+            cwl = z_slab(wl, args.cpu_planes)
+            note = (f"one fixed {args.integ.upper()} step at 100 dt_e "
+                    f"({pf.rkl_stage_count(args.integ, 100.0 * dte, dte)} stages) on {cwl.name}, "
+                    f"{cwl.cells} cells (the first {cwl.nz} z planes of the same state, periodic)")
             dt_fixed = 100.0 * dte
             integ, tol_kw = args.integ, None
             t_end_cpu = dt_fixed
         else:
             t_end_cpu = t_end
-        out["cpu_baseline"] = cpu_baseline(wl, integ, t_end_cpu, tol_kw, dt_fixed, note)
+        print(f"# cpu baseline: {note}", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cwl, integ, t_end_cpu, tol_kw, dt_fixed, note)
     print(json.dumps(out), flush=True)
 
 
