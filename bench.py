@@ -368,6 +368,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--zchunk", type=int, default=0,
                     help="z planes per block (3D); skips the tiling autotuner")
+    ap.add_argument("--pair-zchunk", type=int, default=0,
+                    help="z planes per block of the 3D fused RKL2 stage pairs; skips the "
+                         "tiling autotuner")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB")
     ap.add_argument("--blocks", type=int, default=0,
                     help="batch: persistent grid size (skips the block-count autotuner)")
@@ -450,16 +453,20 @@ def main():
 
     sim.init_fields_device(u0_dev)
     tiling = sim.get_tiling()
-    if args.zchunk:
-        sim.set_tiling(tiling[0], args.zchunk)
+    if args.zchunk or args.pair_zchunk:
+        if args.zchunk:
+            sim.set_tiling(tiling[0], args.zchunk)
+        if args.pair_zchunk:
+            sim.set_pair_zchunk(args.pair_zchunk)
         tiling = sim.get_tiling()
     elif not args.no_autotune:
         tiling = sim.autotune()[:2]
     if args.fusion:
         sim.set_stage_fusion(args.fusion)
     fusion = sim.get_stage_fusion()
-    print(f"# tiling tx={tiling[0]} zchunk={tiling[1]}, RKL2 stages per launch {fusion}",
-          file=sys.stderr, flush=True)
+    pair_zc = sim.get_pair_zchunk()
+    print(f"# tiling tx={tiling[0]} zchunk={tiling[1]} pair zchunk={pair_zc}, RKL2 stages per "
+          f"launch {fusion}", file=sys.stderr, flush=True)
 
     def one_step():
         sim.init_fields_device(u0_dev)
@@ -532,7 +539,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {desc}", "cells": wl.cells, "fields": wl.F,
                    "integrator": integ + ("-adaptive" if tol else "-fixed"),
-                   "precision": args.prec, "tiling": {"tx": tiling[0], "zchunk": tiling[1]},
+                   "precision": args.prec,
+                   "tiling": {"tx": tiling[0], "zchunk": tiling[1], "pair_zchunk": pair_zc},
                    "rkl2_stages_per_launch": fusion,
                    "rhs_evals_per_step": rhs / args.steps,
                    "accepted_per_step": acc / args.steps, "rejected_per_step": rej / args.steps,

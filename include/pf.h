@@ -193,8 +193,12 @@ pf_status pf_step(pf_sim *sim, pf_integrator integ, double dt, pf_stats *stats);
 
 /* Integrate to t_end, landing on it exactly (Sec. 5 opening).  tol == NULL:
  * fixed steps of dt_fixed, the last clipped.  tol != NULL: adaptive RKL1,
- * RKL2 (estimate of Sec. 3.3 after Sommeijer) or SSP(s)2 (embedded first-order
- * solution), PID controller; SSP(10)4 and FE return PF_EUNSUPPORTED. */
+ * RKL2 (estimate of Sec. 3.3 after Sommeijer), SSP(s)2 (embedded first-order
+ * solution: the last Euler sub-step) or SSP(10)4 (embedded solution: the
+ * tenth stage value, second order in general and third on linear problems),
+ * PID controller with the method's order; steps are capped at
+ * tol->dt_max_over_dte dt_e and, for SSP(s)2 and SSP(10)4, at 0.9 times their
+ * stability limits (s - 1) dt_e and 6 dt_e; FE returns PF_EUNSUPPORTED. */
 pf_status pf_run_to(pf_sim *sim, pf_integrator integ, double t_end, const pf_tol *tol,
                     double dt_fixed, pf_stats *stats);
 
@@ -267,10 +271,11 @@ pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
  * work buffers, which it allocates if the handle has not yet; the state is only
  * read), in two interleaved passes keeping each extent's faster time, and
  * keeps the fastest extent.  Where fused stage pairs are built (below) it
- * also times one pair launch (a fifth work buffer takes its second output)
- * and sets the fusion depth to 2 if a pair takes less than two single
- * stages, else to 1; best_ms is then the time per stage of the choice.  The
- * launch shape never changes a result bit. */
+ * also times pair launches (a fifth work buffer takes their second output;
+ * in 3D at the pair z extents 8..128) and sets the fusion depth to 2 if a
+ * pair takes less than two single stages, else to 1; best_ms is then the
+ * time per stage of the choice.  The launch shape never changes a result
+ * bit. */
 pf_status pf_set_tiling(pf_sim *sim, int tx, int zchunk);
 pf_status pf_get_tiling(pf_sim *sim, int *tx, int *zchunk);
 pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
@@ -291,14 +296,22 @@ pf_status pf_get_field_groups(const pf_sim *sim, int *ng);
  * pair instead of five per stage; a step with an odd count of inner stages
  * runs its first inner stage alone).  Depth 2 keeps a ring of four stage
  * vectors (one more work buffer than depth 1) and gives the same result bits
- * as depth 1.  It is built for 2D periodic grids whose vectors fit one
- * buffer group and whose tile (64 x 8 cells with a two-cell halo, N + 3
- * planes, and a one-cell ring of N + 2 planes) fits 64 KiB of LDS: in single
- * precision N <= 8, in double precision N = 2.  Errors: PF_EINVAL for another
- * depth; PF_EUNSUPPORTED for depth 2 where it is not built.  The default is
- * 2 where it is built, else 1; pf_autotune chooses by timing. */
+ * as depth 1.  It is built for periodic grids: in 2D where the vectors fit one
+ * buffer group and the tile (64 x 8 cells with a two-cell halo, N + 3 planes,
+ * and a one-cell ring of N + 2 planes) fits 64 KiB of LDS (single precision
+ * N <= 8, double precision N = 2); in 3D (a tile of 32 x 8 cells marched
+ * through the z extent of pf_set_pair_zchunk, 448 threads per block, one z
+ * window of each stage per thread in registers) in single precision for
+ * N <= 9 and in double precision for N <= 4, with any buffer-group count.
+ * Errors: PF_EINVAL for another depth; PF_EUNSUPPORTED for depth 2 where it
+ * is not built.  The default is 2 in 2D where it is built, else 1;
+ * pf_autotune chooses by timing. */
 pf_status pf_set_stage_fusion(pf_sim *sim, int depth);
 pf_status pf_get_stage_fusion(const pf_sim *sim, int *depth);
+/* z planes per block of the 3D fused stage pairs (>= 1; default 32; the
+ * autotuner times 8..128).  Never changes a result bit. */
+pf_status pf_set_pair_zchunk(pf_sim *sim, int zchunk);
+pf_status pf_get_pair_zchunk(const pf_sim *sim, int *zchunk);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around
  * every launch while enabled.  Families: 0 stage kernels (all stage kinds),

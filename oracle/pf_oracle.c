@@ -456,8 +456,15 @@ static void step_ssp2(const pfo_params *P, int s, double dt, double *u, double *
 
 /* SSP(10)4, the low-storage ten-stage fourth-order scheme of Ketcheson (2008),
  * with S after every stage; the two linear combinations after the fifth stage
- * belong to that stage's output and the new q1 is projected. */
-static void step_ssp104(const pfo_params *P, double dt, double *u, double *r,
+ * belong to that stage's output and the new q1 is projected.
+ * z (optional) receives the tenth stage value Y_10 (q1 before the final
+ * combination): as a Runge-Kutta solution its weights are 1/15 on the first
+ * five stage RHS and 1/6 on the next four, which satisfy the conditions of
+ * order 2 (sum b = 1, sum b c = 1/2) and not all of order 3 (sum b c^2 =
+ * 11/36; on linear problems it is third order), so it is an embedded
+ * lower-order solution that costs nothing (the embedded SSP estimate of
+ * Sec. 3.3; reading R9). */
+static void step_ssp104(const pfo_params *P, double dt, double *u, double *z, double *r,
                         double *q1, double *q2, double *q3, pfo_stats *st) {
     long long n = (long long)nfields(P) * ncells(P);
     memcpy(q1, u, (size_t)n * sizeof(double));
@@ -478,6 +485,7 @@ static void step_ssp104(const pfo_params *P, double dt, double *u, double *r,
     st->rhs_evals++; st->stages++;
     for (long long e = 0; e < n; ++e) u[e] = q2[e] + 3.0 / 5.0 * q1[e] + dt / 10.0 * r[e];
     project(P, u);
+    if (z) memcpy(z, q1, (size_t)n * sizeof(double));
 }
 
 /* RKL1, Alg. sts1 with readings R10 (stage 1 uses mut_1; coefficients indexed
@@ -558,7 +566,8 @@ static void step_rkl2(const pfo_params *P, int s, double dt, double *u, double *
 
 /* One step of the chosen integrator at a fixed dt.  s is the stage count of
  * SSP(s)2 or of the RKL scheme.  aux (optional) receives rhs(u^n) (corrected
- * for RKL2) for RKL1/RKL2, or the embedded solution for SSP(s)2. */
+ * for RKL2) for RKL1/RKL2, or the embedded solution for SSP(s)2 and
+ * SSP(10)4. */
 int pfo_step(const pfo_params *P, int integ, int s, double dt, double *u, double *aux,
              pfo_stats *st) {
     long long n = (long long)nfields(P) * ncells(P);
@@ -574,7 +583,7 @@ int pfo_step(const pfo_params *P, int integ, int s, double dt, double *u, double
         if (s < 2) { rc = -1; break; }
         step_ssp2(P, s, dt, u, aux, w[0], w[1], w[2], st);
         break;
-    case PFO_SSP104: step_ssp104(P, dt, u, w[0], w[1], w[2], w[3], st); break;
+    case PFO_SSP104: step_ssp104(P, dt, u, aux, w[0], w[1], w[2], w[3], st); break;
     case PFO_RKL1: {
         if (s < 1) { rc = -1; break; }
         double *q[3] = {w[1], w[2], w[3]};
@@ -783,9 +792,11 @@ static int method_order(int integ) {
  * land on it; an RKL stage count is recomputed for the clipped step.
  *
  * tol == NULL: fixed steps of dt_fixed (RKL stage count from dt and dt_e).
- * tol != NULL: adaptive RKL1/RKL2 (Sommeijer estimate) or SSP(s)2 (embedded
- * estimate), PID controller, dt <= dt_max_over_dte * dt_e (SSP(s)2 also
- * <= 0.9 (s-1) dt_e), dt0 = tol->dt0 or 0.9 dt_e when that is <= 0.
+ * tol != NULL: adaptive RKL1/RKL2 (Sommeijer estimate) or SSP(s)2 and
+ * SSP(10)4 (embedded estimate), PID controller, dt <= dt_max_over_dte * dt_e
+ * (SSP(s)2 also <= 0.9 (s-1) dt_e, SSP(10)4 <= 0.9 * 6 dt_e: the schemes'
+ * stability limits of Sec. 3.2 with the safety factor of the RKL stage
+ * count), dt0 = tol->dt0 or 0.9 dt_e when that is <= 0.
  * trace (optional, 4 doubles per attempt: dt, s, e, accepted) records up to
  * trace_cap attempts.  ctrl_io/dt_io (optional): when *dt_io > 0 the adaptive
  * loop resumes that controller state and proposed step; both are written back.  Returns 0, or -5 when dt underflows, -4 after three
@@ -825,11 +836,17 @@ int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_en
         if (ntrace) *ntrace = nt;
         return 0;
     }
-    if (integ != PFO_RKL1 && integ != PFO_RKL2 && integ != PFO_SSP2) return -7;
+    if (integ != PFO_RKL1 && integ != PFO_RKL2 && integ != PFO_SSP2 && integ != PFO_SSP104)
+        return -7;
     int order = method_order(integ);
+    int embedded = integ == PFO_SSP2 || integ == PFO_SSP104;
     double dtmax = tol->dt_max_over_dte * dte;
     if (integ == PFO_SSP2) {
         double lim = 0.9 * (s_ssp - 1) * dte;
+        if (lim < dtmax) dtmax = lim;
+    }
+    if (integ == PFO_SSP104) {
+        double lim = 0.9 * 6.0 * dte;
         if (lim < dtmax) dtmax = lim;
     }
     double dt = tol->dt0 > 0.0 ? tol->dt0 : 0.9 * dte;
@@ -853,11 +870,12 @@ int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_en
         if (rem <= h * (1.0 + 1e-10)) { h = rem; last = 1; }
         if (!last && h < 1e-12 * dte) { rc = -5; break; }
         int s = s_ssp;
-        if (integ != PFO_SSP2) s = pfo_stage_count(order, h, dte);
+        if (integ == PFO_SSP104) s = 10;
+        else if (integ != PFO_SSP2) s = pfo_stage_count(order, h, dte);
         memcpy(y, u, (size_t)n * sizeof(double));
         rc = pfo_step(P, integ, s, h, y, aux, st);
         if (rc) break;
-        double e = pfo_error_norm(P, integ == PFO_SSP2 ? 1 : 0, h, u, y, aux, tol, NULL, NULL, st);
+        double e = pfo_error_norm(P, embedded ? 1 : 0, h, u, y, aux, tol, NULL, NULL, st);
         int acc;
         double hn = pfo_ctrl_update(&ctrl, order, e, h, &acc);
         if (trace && nt < trace_cap) {

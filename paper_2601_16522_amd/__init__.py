@@ -43,7 +43,7 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error",
            "pf_params_stable_dt", "pf_rkl_stage_count", "pf_controller_init",
            "pf_controller_update", "pf_clip_step", "pf_set_timing_families",
-           "pf_set_stage_fusion", "pf_get_stage_fusion"]
+           "pf_set_stage_fusion", "pf_get_stage_fusion", "pf_set_pair_zchunk", "pf_get_pair_zchunk"]
 
 
 class PFError(RuntimeError):
@@ -144,6 +144,8 @@ def lib():
             "pf_autotune": [vp, C.POINTER(i), C.POINTER(i), pd],
             "pf_set_stage_fusion": [vp, i],
             "pf_get_stage_fusion": [vp, C.POINTER(i)],
+            "pf_set_pair_zchunk": [vp, i],
+            "pf_get_pair_zchunk": [vp, C.POINTER(i)],
             "pf_set_timing": [vp, i],
             "pf_set_timing_families": [vp, C.c_uint],
             "pf_get_kernel_time": [vp, i, pd, C.POINTER(ll)],
@@ -587,13 +589,22 @@ class Sim:
         return v.value
 
     def set_stage_fusion(self, depth: int):
-        """RKL2 inner stages per launch: 1, or 2 (fused pairs, 2D where built)."""
+        """RKL2 inner stages per launch: 1, or 2 (fused pairs, where built)."""
         self._chk(self._L.pf_set_stage_fusion(self._h, int(depth)))
 
     def get_stage_fusion(self) -> int:
         d = C.c_int()
         self._chk(self._L.pf_get_stage_fusion(self._h, C.byref(d)))
         return d.value
+
+    def set_pair_zchunk(self, zchunk: int):
+        """z planes per block of the 3D fused RKL2 stage pairs."""
+        self._chk(self._L.pf_set_pair_zchunk(self._h, int(zchunk)))
+
+    def get_pair_zchunk(self) -> int:
+        v = C.c_int()
+        self._chk(self._L.pf_get_pair_zchunk(self._h, C.byref(v)))
+        return v.value
 
     def set_timing(self, on: bool, families=None):
         """Kernel timing on/off; families: iterable of FAM_* to record only those."""

@@ -86,6 +86,7 @@ struct pf_sim {
     std::vector<double> trace;
     std::string err;
     int tx = 64, zchunk = 16;
+    int zchunk2 = 32;        // z extent of the fused RKL2 stage pairs (3D)
     int groups_min = 1;      // least buffer groups per state vector (pf_set_field_groups)
     int fuse = 1;            // RKL2 inner stages per launch (2: fused pairs, where built)
     int inner_launches = 0;  // launches of the last step's inner-stage interval
@@ -484,10 +485,13 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     return PF_OK;
 }
 
-// Whether the fused RKL2 stage-pair kernel is built for the simulation: 2D,
-// periodic, vectors in one buffer group, its LDS within one workgroup's.
+// Whether the fused RKL2 stage-pair kernel is built for the simulation:
+// periodic grids; in 2D with vectors in one buffer group and the kernel's LDS
+// within one workgroup's, in 3D where its two z windows fit the registers.
 bool pair_ok(const pf_sim *s) {
-    return s->dim == 2 && s->walls == 0 && sim_groups(s) == 1 && rkl2_pair_fits((int)s->esz, s->N);
+    if (s->walls != 0) return false;
+    if (s->dim == 2) return sim_groups(s) == 1 && rkl2_pair_fits((int)s->esz, s->N);
+    return rkl2_pair3_built((int)s->esz, s->N);
 }
 
 // RKL2 stages j and j + 1 in one launch: y1 = Y_{j-1}, y2 = Y_{j-2}, out = Y_j,
@@ -509,15 +513,16 @@ pf_status stage_pair(pf_sim *s, const T *y1, const T *y2, const T *u0, const T *
     A.kind = K_RKL2_PAIR;
     A.a = (T)c1[0]; A.b = (T)c1[1]; A.c = (T)c1[2]; A.d = (T)c1[3]; A.e = (T)c1[4]; A.f = (T)c1[5];
     A.a2 = (T)c2[0]; A.b2 = (T)c2[1]; A.c2 = (T)c2[2]; A.d2 = (T)c2[3]; A.e2 = (T)c2[4]; A.f2 = (T)c2[5];
-    A.tx = P2_TX;
-    A.ty = P2_TY;
-    A.zchunk = 1;
-    A.ntx = (s->nx + P2_TX - 1) / P2_TX;
-    A.nty = (s->ny + P2_TY - 1) / P2_TY;
-    A.nzc = 1;
-    A.ntiles = A.ntx * A.nty;
+    const bool d3 = s->dim == 3;
+    A.tx = d3 ? P3_TX : P2_TX;
+    A.ty = d3 ? P3_TY : P2_TY;
+    A.zchunk = d3 ? s->zchunk2 : 1;
+    A.ntx = (s->nx + A.tx - 1) / A.tx;
+    A.nty = (s->ny + A.ty - 1) / A.ty;
+    A.nzc = d3 ? (s->nz + A.zchunk - 1) / A.zchunk : 1;
+    A.ntiles = A.ntx * A.nty * A.nzc;
     const int nblocks = (A.ntiles + 7) / 8 * 8;
-    hipError_t err = launch_stage<T>(2, s->N, A, nblocks, s->stream);
+    hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
     if (err != hipSuccess) return fail(s, PF_EHIP, "stage-pair kernel launch: %s", hipGetErrorString(err));
     return PF_OK;
 }
@@ -715,7 +720,7 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
             const int dst = pp[which];
             if (i == 5) {
                 rc = stage<T>(s, K_SSP104_S5, bp<T>(s, q1), nullptr, q2, nullptr, bp<T>(s, dst),
-                              bp<T>(s, Q2), dt / 6.0, 1.0 / 25.0, 9.0 / 25.0, 15.0, 5.0, 0, 0);
+                              bp<T>(s, Q2), dt / 6.0, 1.0 / 25.0, 9.0 / 25.0, 15.0, 5.0, 2.0 / 5.0, 0);
                 q2 = bp<T>(s, Q2);
             } else {
                 rc = stage<T>(s, K_EULER, bp<T>(s, q1), nullptr, nullptr, nullptr, bp<T>(s, dst),
@@ -728,12 +733,14 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
             s->st.stages++;
         }
         const int dst = pp[which];
-        rc = stage<T>(s, K_SSP104_FINAL, bp<T>(s, q1), nullptr, q2, nullptr, bp<T>(s, dst), nullptr,
-                      3.0 / 5.0, dt / 10.0, 0, 0, 0, 0, 0);
+        // (the single-precision form reads u^n as y2 and uses c = 9/25)
+        rc = stage<T>(s, K_SSP104_FINAL, bp<T>(s, q1), u, q2, nullptr, bp<T>(s, dst), nullptr,
+                      3.0 / 5.0, dt / 10.0, 9.0 / 25.0, 0, 0, 0, 0);
         if (rc) return rc;
         s->st.rhs_evals++;
         s->st.stages++;
         *res = dst;
+        *aux = q1;  // embedded solution: the tenth stage value Y_10 (second order)
         return PF_OK;
     }
     case PF_RKL1:
@@ -842,12 +849,15 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
         s->st.t = s->t;
         return PF_OK;
     }
-    if (integ != PF_RKL1 && integ != PF_RKL2 && integ != PF_SSP_S2)
-        return fail(s, PF_EUNSUPPORTED, "adaptive stepping needs RKL1, RKL2 or SSP(s)2");
+    if (integ != PF_RKL1 && integ != PF_RKL2 && integ != PF_SSP_S2 && integ != PF_SSP_10_4)
+        return fail(s, PF_EUNSUPPORTED, "adaptive stepping needs RKL1, RKL2, SSP(s)2 or SSP(10)4");
     const int order = method_order(integ);
+    // the SSP schemes estimate the error with their embedded solutions
+    const bool embedded = integ == PF_SSP_S2 || integ == PF_SSP_10_4;
     const double dtmax_ratio = tol->dt_max_over_dte > 0.0 ? tol->dt_max_over_dte : 200.0;
     double dtmax = dtmax_ratio * dte;
     if (integ == PF_SSP_S2) dtmax = std::min(dtmax, 0.9 * (s->ssp_s - 1) * dte);
+    if (integ == PF_SSP_10_4) dtmax = std::min(dtmax, 0.9 * 6.0 * dte);
     // the controller (bias, accepted history, proposed step) carries over from
     // the previous pf_run_to of this handle; pf_init_fields resets it
     double dt = tol->dt0 > 0.0 ? tol->dt0 : (s->dt_next > 0.0 ? s->dt_next : 0.9 * dte);
@@ -858,11 +868,12 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
         if (!clip_step(s->t, t_end, std::min(dt, dtmax), h, last)) break;
         if (!last && h < 1e-12 * dte) return fail(s, PF_EDTMIN, "adaptive step underflow (dt = %g)", h);
         int ns = s->ssp_s;
-        if (integ != PF_SSP_S2) ns = stage_count(order, h, dte);
+        if (integ == PF_SSP_10_4) ns = 10;
+        else if (integ != PF_SSP_S2) ns = stage_count(order, h, dte);
         int res, aux;
         if ((rc = do_step<T>(s, integ, ns, h, true, &res, &aux))) return rc;
         double e;
-        if ((rc = error_norm<T>(s, integ == PF_SSP_S2 ? 1 : 0, h, bp<T>(s, s->cur), bp<T>(s, res),
+        if ((rc = error_norm<T>(s, embedded ? 1 : 0, h, bp<T>(s, s->cur), bp<T>(s, res),
                                 bp<T>(s, aux), *tol, &e, nullptr)))
             return rc;
         bool acc;
@@ -942,25 +953,32 @@ struct CkptHeader {
 // candidates are timed in two interleaved passes and each keeps its faster
 // time, which damps clock and queue noise between candidates.
 template <typename T>
-pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fuse) {
+pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fuse, int &bzc2) {
     const int zcs3[7] = {4, 8, 16, 32, 64, 128, 256};
     const int ncand = s->dim == 3 ? 7 : 1;
+    // fused pairs: one candidate in 2D, the z extents 8..128 in 3D
+    const int zcp[5] = {8, 16, 32, 64, 128};
+    const int npair = !pair_ok(s) ? 0 : (s->dim == 3 ? 5 : 1);
     const T *u = bp<T>(s, s->cur);
     for (int k = 1; k < 4; ++k)
         HIPCHK(s, hipMemcpyAsync(s->buf[w[k]], u, state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
     hipEvent_t e0, e1;
     HIPCHK(s, hipEventCreate(&e0));
     HIPCHK(s, hipEventCreate(&e1));
-    // candidate ncand (2D, where built): the fused stage pair, timed per stage
-    const bool try_pair = pair_ok(s);
-    double tbest[8];
+    // candidates from ncand on (where built): the fused stage pair, timed per stage
+    double tbest[16];
     for (double &t : tbest) t = 1e300;
     const double cf[6] = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
     for (int pass = 0; pass < 2; ++pass)
-        for (int j = 0; j < ncand + (try_pair ? 1 : 0); ++j) {
-            const bool pair = j == ncand;
-            s->zchunk = s->dim == 3 && !pair ? zcs3[j] : 1;
-            if (s->dim == 3 && s->zchunk > s->nz && j > 0) continue;
+        for (int j = 0; j < ncand + npair; ++j) {
+            const bool pair = j >= ncand;
+            if (pair) {
+                s->zchunk2 = s->dim == 3 ? zcp[j - ncand] : 1;
+                if (s->dim == 3 && s->zchunk2 > s->nz && j > ncand) continue;
+            } else {
+                s->zchunk = s->dim == 3 ? zcs3[j] : 1;
+                if (s->dim == 3 && s->zchunk > s->nz && j > 0) continue;
+            }
             pf_status rc = PF_OK;
             for (int r = 0; r < 6 && !rc; ++r) {
                 if (r == 1) hipEventRecord(e0, s->stream);
@@ -991,10 +1009,12 @@ pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fus
             bzc = s->dim == 3 ? zcs3[j] : 1;
         }
     fuse = 1;
-    if (try_pair && tbest[ncand] < best) {
-        best = tbest[ncand];
-        fuse = 2;
-    }
+    for (int j = ncand; j < ncand + npair; ++j)
+        if (tbest[j] < best) {
+            best = tbest[j];
+            fuse = 2;
+            bzc2 = s->dim == 3 ? zcp[j - ncand] : 1;
+        }
     return PF_OK;
 }
 
@@ -1076,7 +1096,10 @@ pf_status pf_create(const pf_params *p, pf_sim **out) {
         delete s;
         return rc;
     }
-    s->fuse = pair_ok(s) ? 2 : 1;  // same result bits either way; fewer bytes per stage fused
+    // same result bits either way: pairs by default where they measured faster
+    // (2D); in 3D they are an autotuner candidate (latency-bound at two waves
+    // per SIMD, slower than single stages on the 512^3 workload)
+    s->fuse = pair_ok(s) && s->dim == 2 ? 2 : 1;
     if (p->prec == PF_FP64) {
         DevParams<double> P;
         fill_params(s, P);
@@ -1445,12 +1468,13 @@ pf_status pf_autotune(pf_sim *s, int *tx_out, int *zc_out, double *best_ms) {
     const bool was_timing = s->timing;
     s->timing = false;
     double best;
-    int bzc = s->zchunk, fuse = 1;
-    pf_status rc = s->prec == PF_FP64 ? autotune_t<double>(s, w, best, bzc, fuse)
-                                      : autotune_t<float>(s, w, best, bzc, fuse);
+    int bzc = s->zchunk, fuse = 1, bzc2 = s->zchunk2;
+    pf_status rc = s->prec == PF_FP64 ? autotune_t<double>(s, w, best, bzc, fuse, bzc2)
+                                      : autotune_t<float>(s, w, best, bzc, fuse, bzc2);
     s->timing = was_timing;
     if (rc) return rc;
     s->zchunk = bzc;
+    s->zchunk2 = bzc2;
     s->fuse = fuse;
     if (tx_out) *tx_out = s->tx;
     if (zc_out) *zc_out = bzc;
@@ -1462,8 +1486,10 @@ pf_status pf_set_stage_fusion(pf_sim *s, int depth) {
     if (!s) return PF_EINVAL;
     if (depth != 1 && depth != 2) return fail(s, PF_EINVAL, "stage fusion depth %d (1 or 2)", depth);
     if (depth == 2 && !pair_ok(s))
-        return fail(s, PF_EUNSUPPORTED, "fused RKL2 stage pairs are built for 2D periodic grids "
-                                        "whose vectors fit one buffer group and whose LDS fits");
+        return fail(s, PF_EUNSUPPORTED, "fused RKL2 stage pairs are built for periodic grids: in 2D "
+                                        "where the vectors fit one buffer group and the LDS fits, "
+                                        "in 3D for single precision with N <= %d and double "
+                                        "precision with N <= %d", P3_NMAX32, P3_NMAX64);
     s->fuse = depth;
     return PF_OK;
 }
@@ -1471,6 +1497,19 @@ pf_status pf_set_stage_fusion(pf_sim *s, int depth) {
 pf_status pf_get_stage_fusion(const pf_sim *s, int *depth) {
     if (!s || !depth) return PF_EINVAL;
     *depth = s->fuse;
+    return PF_OK;
+}
+
+pf_status pf_set_pair_zchunk(pf_sim *s, int zchunk) {
+    if (!s) return PF_EINVAL;
+    if (zchunk < 1) return fail(s, PF_EINVAL, "zchunk must be >= 1");
+    s->zchunk2 = zchunk;
+    return PF_OK;
+}
+
+pf_status pf_get_pair_zchunk(const pf_sim *s, int *zchunk) {
+    if (!s || !zchunk) return PF_EINVAL;
+    *zchunk = s->zchunk2;
     return PF_OK;
 }
 

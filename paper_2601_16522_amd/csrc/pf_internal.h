@@ -55,14 +55,16 @@ enum StageKind : int {
     K_EULER = 1,        // out = S(y1 + a r), or S(y1 + a (r / b)) when b != 0 (the
                         // SSP(s)2 sub-step of Alg. ssp2); out2 (optional) = r
     K_SSP2_FINAL = 2,   // out = S(((a y1 + u0) + b r) / c)
-    K_SSP104_S5 = 3,    // y = S(y1 + a r); out2 = b u0 + c y; out = S(d out2 - e y)
-    K_SSP104_FINAL = 4, // out = S((u0 + a y1) + b r)
+    K_SSP104_S5 = 3,    // y = S(y1 + a r); out2 = b u0 + c y; out = S(d out2 - e y);
+                        // FP32: out2 = y, out = S(u0 + f (y - u0))
+    K_SSP104_FINAL = 4, // out = S((u0 + a y1) + b r);
+                        // FP32: S(y2 + c (u0 - y2) + a (y1 - y2) + b r), y2 = u^n
     K_RKL1 = 5,         // out = S((a y1 + b y2) + c r); FP32: S(y1 + b (y2 - y1) + c r), a + b = 1
     K_RKL2_FIRST = 6,   // y* = y1 + a r; out = S(y*); out2 = R0 (corrected where S acted)
     K_RKL2 = 7,         // out = S(((a u0 + b y1) + c y2) + d ((e r) + (f r0)));
                         // FP32: u0 + b (y1 - u0) + c (y2 - u0) for the first three terms
     K_EST = 8,          // Sommeijer estimate of u^{n+1} = y1 against u^n = u0, R0 = r0
-    K_RKL2_PAIR = 9     // two K_RKL2 stages j, j + 1 in one pass (2D): out = Y_j, out2 = Y_{j+1}
+    K_RKL2_PAIR = 9     // two K_RKL2 stages j, j + 1 in one pass: out = Y_j, out2 = Y_{j+1}
 };
 
 // Uniform per-simulation constants the stage kernels read: passed by value as
@@ -183,6 +185,26 @@ constexpr int P2_RING = P2_MID - P2_TX * P2_TY;  // cells of the one-cell ring
 static_assert(P2_RING <= P2_THREADS, "one ring cell per thread");
 constexpr bool rkl2_pair_fits(int esz, int n) {
     return esz * ((n + 3) * P2_IN + (n + 2) * P2_MID + 3 * n * n + 4 * n) <= P2_LDS_MAX;
+}
+
+// Fused RKL2 stage pairs (3D): a block of P3_THREADS threads marches a tile of
+// P3_TX x P3_TY cells through a z extent.  Thread i owns one column of the
+// tile's two-cell halo region (P3_IX x P3_IY columns): the first P3_T threads
+// the tile, the next P3_M - P3_T the one-cell ring, the rest the outer ring.
+// LDS holds one plane of the stage input on the halo region and one plane of
+// the first stage's result on the tile and its ring, N + 2 planes each (phi,
+// mu, Mc), plus the pair and per-phase tables.  Built in single precision
+// for N <= P3_NMAX32 and in double precision for N <= P3_NMAX64, where the
+// per-thread planes of the two z windows fit the registers of two waves per
+// SIMD.
+constexpr int P3_TX = 32, P3_TY = 8, P3_T = P3_TX * P3_TY;
+constexpr int P3_MX = P3_TX + 2, P3_MY = P3_TY + 2, P3_M = P3_MX * P3_MY;
+constexpr int P3_IX = P3_TX + 4, P3_IY = P3_TY + 4, P3_I = P3_IX * P3_IY;
+constexpr int P3_THREADS = 448, P3_LDS_MAX = 65536, P3_NMAX32 = 9, P3_NMAX64 = 4;
+static_assert(P3_I <= P3_THREADS && P3_THREADS % 64 == 0, "one halo-region column per thread");
+constexpr bool rkl2_pair3_built(int esz, int n) {
+    return (esz == 4 ? n <= P3_NMAX32 : n <= P3_NMAX64) &&
+           esz * ((n + 2) * (P3_I + P3_M) + 3 * n * n + 4 * n) <= P3_LDS_MAX;
 }
 
 template <typename T>

@@ -178,7 +178,9 @@ __device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool wit
                                               T *o2) {
     constexpr bool U0 = KIND == K_SSP2_FINAL || KIND == K_SSP104_S5 || KIND == K_SSP104_FINAL ||
                         KIND == K_RKL2 || KIND == K_EST;
-    constexpr bool Y2 = KIND == K_RKL1 || KIND == K_RKL2;
+    // the single-precision SSP(10)4 final stage is formed relative to u^n (y2)
+    constexpr bool Y2 = KIND == K_RKL1 || KIND == K_RKL2 ||
+                        (KIND == K_SSP104_FINAL && std::is_same<T, float>::value);
     constexpr bool R0 = KIND == K_RKL2 || KIND == K_EST;
 #pragma unroll
     for (int f = 0; f <= N; ++f) {
@@ -519,9 +521,16 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
                 yv[f] = ((A.a * cur[f] + o0[f]) + A.b * r[f]) / A.c;
             }
         } else if constexpr (KIND == K_SSP104_FINAL) {
+            // fast form, with o0 = the fifth stage value Y6' and o1 = u^n:
+            // u^n + c (Y6' - u^n) + a (Y10 - u^n) + b r, the same combination
+            // as q2 + a Y10 + b r, whose weights sum to one whatever the
+            // rounding of a and c (the total of c is kept)
 #pragma unroll
             for (int f = 0; f <= N; ++f) {
-                yv[f] = (o0[f] + A.a * cur[f]) + A.b * r[f];
+                if constexpr (FAST)
+                    yv[f] = fma_t(A.b, r[f], fma_t(A.a, cur[f] - o1[f], fma_t(A.c, o0[f] - o1[f], o1[f])));
+                else
+                    yv[f] = (o0[f] + A.a * cur[f]) + A.b * r[f];
             }
         } else if constexpr (KIND == K_RKL1) {
             // the fast form uses mu_j + nu_j = 1: Y_{j-1} + nu_j (Y_{j-2} -
@@ -566,15 +575,25 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
             }
         } else if constexpr (KIND == K_SSP104_S5) {
             // Fifth SSP(10)4 stage plus the two linear updates of the
-            // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1).
+            // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1),
+            // with q2 = u^n (o0) before them.  The fast form keeps the fifth
+            // stage value Y6' itself in the q2 vector and forms
+            // q1 = S(u^n + f (Y6' - u^n)), f = 2/5: the same values, with
+            // weights that sum to one whatever their rounding (the final stage
+            // takes the 9/25 (Y6' - u^n) part of q2).
             project<T, N, FAST>(yv);
             T q1n[N + 1];
 #pragma unroll
             for (int f = 0; f <= N; ++f) {
                 const bool have = f < N || withc;
-                const T q2n = A.b * o0[f] + A.c * yv[f];
-                if (have) stv<T, GS, SCP>(A, 5, f, idx, q2n);
-                q1n[f] = A.d * q2n - A.e * yv[f];
+                if constexpr (FAST) {
+                    if (have) stv<T, GS, SCP>(A, 5, f, idx, yv[f]);
+                    q1n[f] = fma_t(A.f, yv[f] - o0[f], o0[f]);
+                } else {
+                    const T q2n = A.b * o0[f] + A.c * yv[f];
+                    if (have) stv<T, GS, SCP>(A, 5, f, idx, q2n);
+                    q1n[f] = A.d * q2n - A.e * yv[f];
+                }
             }
             project<T, N, FAST>(q1n);
 #pragma unroll
@@ -984,6 +1003,219 @@ __global__ void __launch_bounds__(P2_THREADS) __attribute__((amdgpu_waves_per_eu
     rkl2_pair_tile<T, N>(A, t, in, mid, pair, kc);
 }
 
+// Column of the 3D pair tile's halo region owned by thread t: (ix, iy) in
+// [0, P3_IX) x [0, P3_IY), the tile at [2, P3_TX + 2) x [2, P3_TY + 2).
+// Threads [0, P3_T) take the tile row by row (a wavefront covers two rows of
+// P3_TX cells), [P3_T, P3_M) the one-cell ring (top row, bottom row, left and
+// right columns), [P3_M, P3_I) the outer ring in the same order; the rest
+// own no column (ix = iy = -1).
+__device__ __forceinline__ void pair3_column(int t, int &ix, int &iy) {
+    if (t < P3_T) {
+        ix = 2 + t % P3_TX;
+        iy = 2 + t / P3_TX;
+        return;
+    }
+    t -= P3_T;
+    if (t < 2 * P3_MX) {
+        ix = 1 + (t < P3_MX ? t : t - P3_MX);
+        iy = t < P3_MX ? 1 : P3_MY;
+        return;
+    }
+    t -= 2 * P3_MX;
+    if (t < 2 * P3_TY) {
+        ix = t < P3_TY ? 1 : P3_MX;
+        iy = 2 + (t < P3_TY ? t : t - P3_TY);
+        return;
+    }
+    t -= 2 * P3_TY;
+    if (t < 2 * P3_IX) {
+        ix = t < P3_IX ? t : t - P3_IX;
+        iy = t < P3_IX ? 0 : P3_IY - 1;
+        return;
+    }
+    t -= 2 * P3_IX;
+    if (t < 2 * (P3_IY - 2)) {
+        ix = t < P3_IY - 2 ? 0 : P3_IX - 1;
+        iy = 1 + (t < P3_IY - 2 ? t : t - (P3_IY - 2));
+        return;
+    }
+    ix = iy = -1;
+}
+
+// Two consecutive RKL2 inner stages j and j + 1 (eq. sts) of one 3D tile
+// column block in one pass over memory.  Stage j at plane k needs Y_{j-1} on
+// the seven-point stencil and Y_{j-2}, u0, R0 at the cell; stage j + 1 at
+// plane k - 1 needs Y_j on the stencil (its x-y neighbours on the tile's
+// one-cell ring, its z neighbours at planes k - 2 and k) and Y_{j-1}, u0, R0
+// at the cell.  March step k computes stage j at plane k on the tile and its
+// ring, then stage j + 1 at plane k - 1 on the tile, for k from z0 - 1 to z1
+// (stage j on the two planes around the extent is computed for the z
+// stencil of stage j + 1 and not stored).  Each thread keeps the planes k - 1,
+// k, k + 1 of Y_{j-1} at its column (and k + 2 in flight), and, on the tile,
+// Y_j at planes k - 2, k - 1 and u0, R0 at plane k - 1, in registers; LDS
+// holds Y_{j-1} at plane k on the halo region and Y_j at plane k - 1 on the
+// tile and ring, with mu and Mc.  Per cell that is four vectors read and two
+// written for two stages (plus the four z-halo planes of the extent), against
+// five per stage one at a time.  Every value is computed with the
+// single-stage kernel's arithmetic (rhs_point, rkl2_value, project), so the
+// results equal two single stages bit for bit.  Vectors: y1 = Y_{j-1}, y2 =
+// Y_{j-2}, u0, r0 = R0, out = Y_j, out2 = Y_{j+1}; coefficients a..f of stage
+// j and a2..f2 of stage j + 1.  Periodic grids.
+template <typename T, int N, int GS>
+__device__ __forceinline__ void rkl2_pair3_tile(const StageArgs<T> &A, const TileIdx t, T *__restrict__ la,
+                                                T *__restrict__ lb, T *__restrict__ pair,
+                                                T *__restrict__ kc) {
+    constexpr bool FAST = std::is_same<T, float>::value;
+    constexpr int LCP = operand_load_cp<3>(), SCP = out_store_cp<3>();
+    const KConsts<T> &P = A.K;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const bool withc = P.with_c != 0;
+    const int tid = threadIdx.x;
+    const bool hasI = tid < P3_I, hasM = tid < P3_M, isT = tid < P3_T;
+    int ix, iy;
+    pair3_column(tid, ix, iy);
+    const int sI = iy * P3_IX + ix;              // slot in an LDS plane of the halo region
+    const int sM = (iy - 1) * P3_MX + (ix - 1);  // slot in an LDS plane of the tile and ring
+    const int gx = t.tix * P3_TX + ix - 2, gy = t.tiy * P3_TY + iy - 2;
+    const bool inside = isT && gx < nx && gy < ny;
+    long long col = 0;
+    if (hasI) {
+        if (wrap_fits(A.ntx, P3_TX, nx) && wrap_fits(A.nty, P3_TY, ny))
+            col = (long long)wrap_index<false>(gy, ny) * nx + wrap_index<false>(gx, nx);
+        else
+            col = (long long)wrap_index<true>(gy, ny) * nx + wrap_index<true>(gx, nx);
+    }
+    const long long nxy = (long long)nx * ny;
+    const auto zwrap = [nz](int k) __attribute__((always_inline)) {
+        const int r = k % nz;
+        return r < 0 ? r + nz : r;
+    };
+    const auto off = [&](int k) __attribute__((always_inline)) {
+        return (unsigned)((long long)zwrap(k) * nxy + col) * (unsigned)sizeof(T);
+    };
+    const int z0 = t.tiz * A.zchunk, z1 = min(z0 + A.zchunk, nz);
+
+    // Y_{j-1} at the column: planes z0 - 2, z0 - 1, z0 (the window of step
+    // z0 - 1) and z0 + 1 in flight; every load is issued before the first use
+    T prv[N + 1], cur[N + 1], nxt[N + 1], pre[N + 1];
+    if (hasI) {
+        load_point32<T, N, GS>(A, 0, off(z0 - 2), withc, prv);
+        load_point32<T, N, GS>(A, 0, off(z0 - 1), withc, cur);
+        load_point32<T, N, GS>(A, 0, off(z0), withc, nxt);
+        load_point32<T, N, GS>(A, 0, off(z0 + 1), withc, pre);
+    }
+    stage_tables<T, N>(A.P, pair, kc);
+    __syncthreads();  // the tables are read from here on
+    T mup = T(0), mcp = T(0), muc = T(0), mcc = T(0), mun = T(0), mcn = T(0);
+    if (hasI && withc) {
+        point_mu_mc<T, N, FAST>(P, kc, prv, mup, mcp);
+        point_mu_mc<T, N, FAST>(P, kc, cur, muc, mcc);
+        point_mu_mc<T, N, FAST>(P, kc, nxt, mun, mcn);
+    }
+    // on the tile: Y_j at planes k - 2 and k - 1, u0 and R0 at plane k - 1
+    T yjp[N + 1], yjc[N + 1], ku[N + 1], kr[N + 1];
+    T mujp = T(0), mcjp = T(0), mujc = T(0), mcjc = T(0);
+#pragma unroll
+    for (int f = 0; f <= N; ++f) yjp[f] = yjc[f] = ku[f] = kr[f] = T(0);
+    const T c1[6] = {A.a, A.b, A.c, A.d, A.e, A.f};
+    const T c2[6] = {A.a2, A.b2, A.c2, A.d2, A.e2, A.f2};
+
+    for (int k = z0 - 1; k <= z1; ++k) {
+        const unsigned ok = off(k);
+        // operands of stage j at plane k, in flight across the barrier (loading
+        // them a whole march step ahead measured slower)
+        T u0o[N + 1], y2o[N + 1], r0o[N + 1];
+        if (hasM) load_operands<T, N, K_RKL2, GS, LCP>(A, ok, withc, u0o, y2o, r0o);
+        if (hasI) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) la[a * P3_I + sI] = cur[a];
+            la[N * P3_I + sI] = muc;
+            la[(N + 1) * P3_I + sI] = mcc;
+        }
+        __syncthreads();
+        // stage j at plane k on the tile and its ring
+        T yj[N + 1];
+        T muj = T(0), mcj = T(0);
+        if (hasM) {
+            T r[N + 1];
+            rhs_point<T, 3, N, FAST, P3_I, P3_IX>(P, la, pair, kc, sI, cur, muc, mcc, prv, mup, mcp, nxt,
+                                                   mun, mcn, r);
+#pragma unroll
+            for (int f = 0; f <= N; ++f)
+                yj[f] = rkl2_value<T, FAST>(c1[0], c1[1], c1[2], c1[3], c1[4], c1[5], cur[f], r[f], u0o[f],
+                                            y2o[f], r0o[f]);
+            project<T, N, FAST>(yj);
+            if (withc) point_mu_mc<T, N, FAST>(P, kc, yj, muj, mcj);
+            if (inside && k >= z0 && k < z1) {
+#pragma unroll
+                for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, ok, yj[f]);
+                if (withc) stv<T, GS, SCP>(A, 4, N, ok, yj[N]);
+            }
+        }
+        // stage j + 1 at plane k - 1 on the tile: Y_j on the stencil (LDS holds
+        // plane k - 1), Y_{j-1} (prv), u0 and R0 at the cell
+        if (isT && k > z0) {
+            T r[N + 1], y[N + 1];
+            rhs_point<T, 3, N, FAST, P3_M, P3_MX>(P, lb, pair, kc, sM, yjc, mujc, mcjc, yjp, mujp, mcjp, yj,
+                                                   muj, mcj, r);
+#pragma unroll
+            for (int f = 0; f <= N; ++f)
+                y[f] = rkl2_value<T, FAST>(c2[0], c2[1], c2[2], c2[3], c2[4], c2[5], yjc[f], r[f], ku[f],
+                                           prv[f], kr[f]);
+            project<T, N, FAST>(y);
+            if (inside) {
+                const unsigned op = off(k - 1);
+#pragma unroll
+                for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 5, f, op, y[f]);
+                if (withc) stv<T, GS, SCP>(A, 5, N, op, y[N]);
+            }
+        }
+        __syncthreads();  // both LDS planes are read; the next step may overwrite them
+        if (hasM) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) lb[a * P3_M + sM] = yj[a];
+            lb[N * P3_M + sM] = muj;
+            lb[(N + 1) * P3_M + sM] = mcj;
+        }
+        if (isT) {
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                yjp[f] = yjc[f];
+                yjc[f] = yj[f];
+                ku[f] = u0o[f];
+                kr[f] = r0o[f];
+            }
+            mujp = mujc; mcjp = mcjc;
+            mujc = muj; mcjc = mcj;
+        }
+        if (hasI) {
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                prv[f] = cur[f];
+                cur[f] = nxt[f];
+                nxt[f] = pre[f];
+            }
+            mup = muc; mcp = mcc;
+            muc = mun; mcc = mcn;
+            if (withc) point_mu_mc<T, N, FAST>(P, kc, nxt, mun, mcn);
+            if (k + 3 <= z1 + 1) load_point32<T, N, GS>(A, 0, off(k + 3), withc, pre);
+        }
+    }
+}
+
+// One block per tile column block; built where rkl2_pair3_built (the launch
+// refuses the others).
+template <typename T, int N, int NG>
+__global__ void __launch_bounds__(P3_THREADS) rkl2_pair3_kernel(const StageArgs<T> A) {
+    __shared__ T la[(N + 2) * P3_I];
+    __shared__ T lb[(N + 2) * P3_M];
+    __shared__ T pair[3 * N * N];
+    __shared__ T kc[4 * N];
+    const TileIdx t = tile_index(xcd_logical_block(), A.ntx, A.nty);
+    if (t.L >= A.ntiles) return;  // uniform over the block
+    rkl2_pair3_tile<T, N, group_planes(N, NG)>(A, t, la, lb, pair, kc);
+}
+
 template <typename T, int DIM, int N, int NG, bool W>
 hipError_t launch_stage_dnw(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
     const dim3 grid(nblocks), block(256);
@@ -1000,6 +1232,8 @@ hipError_t launch_stage_dnw(const StageArgs<T> &A, int nblocks, hipStream_t stre
     case K_RKL2_PAIR:
         if constexpr (DIM == 2 && NG == 1 && !W && rkl2_pair_fits((int)sizeof(T), N))
             hipLaunchKernelGGL((rkl2_pair_kernel<T, N>), grid, dim3(P2_THREADS), 0, stream, A);
+        else if constexpr (DIM == 3 && !W && rkl2_pair3_built((int)sizeof(T), N))
+            hipLaunchKernelGGL((rkl2_pair3_kernel<T, N, NG>), grid, dim3(P3_THREADS), 0, stream, A);
         else
             return hipErrorInvalidValue;
         break;

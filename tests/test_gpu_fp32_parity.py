@@ -115,6 +115,7 @@ def replay(P, integ, u0, trace, ssp):
     ("graingrowth3d", "rkl2", 1e-4, 600.0),
     ("graingrowth3d", "rkl1", 1e-4, 200.0),
     ("voronoi2d", "ssp2", 1e-4, 30.0),
+    ("sintering3d", "ssp104", 1e-4, 40.0),
 ])
 def test_adaptive_fp32_replayed_in_oracle(wlname, integ, tolv, tmul):
     """An FP32 adaptive run (Sec. 3.3) and the oracle taking the same accepted

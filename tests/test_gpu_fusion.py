@@ -26,7 +26,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 pf = pytest.importorskip("paper_2601_16522_amd")
 
-from test_gpu_parity import mixed_2d, pores_3d  # noqa: E402
+from _parity import mixed_2d  # noqa: E402
+
+
+def pores_3d(n=20, nyz=(18, 13), nphi=4):
+    return pi.grains_pores_3d(n=n, nyz=nyz, n_grains=5 if nphi <= 4 else 12,
+                              n_grain_fields=nphi - 1, n_pores=3, r_range=(2.0, 4.0), dmin=4.0)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -150,8 +155,10 @@ def test_fusion_setting_checked():
     assert sim.get_stage_fusion() == 1
     sim.close()
     walls = dataclasses.replace(mixed_2d(), bc=[1, 0, 0], c_fixed=[0] * 6, c_bc=[0.0] * 6)
-    refused = [(pores_3d(), "fp32"), (walls, "fp32"), (mixed_2d(), "fp64"),
-               (pi.voronoi_2d(n=64, ny=16, n_grains=12, n_phi=9, dmin=4.0), "fp32")]
+    p13 = pi.grains_pores_3d(n=20, nyz=(18, 13), n_grains=14, n_grain_fields=12, n_pores=3,
+                             r_range=(2.0, 4.0), dmin=4.0)
+    refused = [(p13, "fp32"), (pores_3d(n=20, nyz=(18, 13), nphi=8), "fp64"), (walls, "fp32"),
+               (mixed_2d(), "fp64"), (pi.voronoi_2d(n=64, ny=16, n_grains=12, n_phi=9, dmin=4.0), "fp32")]
     for wl, prec in refused:
         sim = pf.Sim(wl.param_dict(), prec=prec)
         with pytest.raises(pf.PFError) as e:

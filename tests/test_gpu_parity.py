@@ -124,7 +124,7 @@ def test_fixed_fe_run_single_grain():
         assert np.abs(u - ref).max() <= tol, (prec, np.abs(u - ref).max())
 
 
-@pytest.mark.parametrize("integ", ["rkl2", "rkl1", "ssp2"])
+@pytest.mark.parametrize("integ", ["rkl2", "rkl1", "ssp2", "ssp104"])
 def test_adaptive_run_fp64_matches_oracle_trace(integ):
     wl = pi.single_grain(n=64, R=20.0)
     P = P_of(wl)
@@ -150,7 +150,8 @@ def test_adaptive_run_fp64_matches_oracle_trace(integ):
     check_fp64(wl, u, ref, integ)
 
 
-@pytest.mark.parametrize("integ,tolv,tmul", [("rkl2", 1e-5, 1000.0), ("ssp2", 1e-4, 60.0)])
+@pytest.mark.parametrize("integ,tolv,tmul", [("rkl2", 1e-5, 1000.0), ("ssp2", 1e-4, 60.0),
+                                            ("ssp104", 1e-4, 60.0)])
 def test_adaptive_3d_pores_fp64_matches_oracle_trace(integ, tolv, tmul):
     """The sintering geometry (12 grains on 12 fields plus a pore phase of a
     second type, c = phi_pore; mobile-pore parameters) at 32^3: adaptive RKL2
@@ -188,7 +189,7 @@ def test_adaptive_3d_pores_fp64_matches_oracle_trace(integ, tolv, tmul):
     ref32 = wl.u0
     for h, ns, _, acc in tr32:
         if acc:
-            ref32, _, _ = oracle.step(P, INTEG[integ], h, ref32, s=int(ns))
+            ref32, _, _ = oracle.step(P, INTEG[integ], h, ref32, s=int(ns) if integ != "ssp104" else 0)
     smax = int(tr32[tr32[:, 3] == 1, 1].max())
     check_fp32_multi(wl, u32, ref32, smax, f"3D pores adaptive {integ} FP32 ({st32.accepted} "
                      f"accepted / {st32.rejected} rejected; FP64 {st_ref.accepted})", 1e-4)

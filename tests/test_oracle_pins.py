@@ -448,6 +448,86 @@ def test_dahlquist_order(integ, s, p):
     assert abs(order - p) < 5e-2 * max(1, p), (order, errs)
 
 
+def _embedded_amplification(z, m=32):
+    P, u, mode, lam = _mode_problem(m=m)
+    _, aux, _ = oracle.step(P, oracle.SSP104, z / lam, u, want_aux=True)
+    return float(np.dot(aux[2].ravel() - 0.5, mode) / np.dot(u[2].ravel() - 0.5, mode))
+
+
+def _ssp104_tableau():
+    """Butcher coefficients of the low-storage SSP(10)4 steps (five Euler
+    sub-steps of h/6, q2 = u/25 + 9 q1/25, q1 = 15 q2 - 5 q1, four more
+    sub-steps, u^{n+1} = q2 + 3/5 q1 + h/10 F(q1)), in exact fractions: each
+    value is kept as its coefficients on (u, h F_1 .. h F_10)."""
+    def f(i):
+        v = [Fraction(0)] * 11
+        v[i] = Fraction(1)
+        return v
+
+    def lin(*terms):
+        return [sum(c * v[k] for c, v in terms) for k in range(11)]
+
+    Y = {1: f(0)}
+    for i in range(1, 6):
+        Y[i + 1] = lin((1, Y[i]), (Fraction(1, 6), f(i)))
+    q2 = lin((Fraction(1, 25), Y[1]), (Fraction(9, 25), Y[6]))
+    Y[6] = lin((15, q2), (-5, Y[6]))
+    for i in range(6, 10):
+        Y[i + 1] = lin((1, Y[i]), (Fraction(1, 6), f(i)))
+    unew = lin((1, q2), (Fraction(3, 5), Y[10]), (Fraction(1, 10), f(10)))
+    A = [Y[i][1:] for i in range(1, 11)]
+    return A, unew[1:], Y[10][1:]
+
+
+def test_ssp104_embedded_solution():
+    """The embedded solution of adaptive SSP(10)4 is the tenth stage value Y_10.
+    As a Runge-Kutta solution its weights (1/15 on the first five stage RHS,
+    1/6 on the next four) meet the order conditions sum b = 1, sum b c = 1/2 and
+    sum b A c = 1/6 but not sum b c^2 = 1/3 (it is 11/36): second order in
+    general, third order on linear problems, while the scheme's own weights
+    meet all eight conditions to order 4.  On the Dahlquist problem its
+    stability function, from the low-storage scheme, is
+    R(z) = (3/5 + 2/5 (1 + z/6)^5) (1 + z/6)^4, and |R - e^z| = O(z^4)."""
+    A, b, bh = _ssp104_tableau()
+    c = [sum(r) for r in A]
+    Ac = [sum(a * x for a, x in zip(r, c)) for r in A]
+    dot = lambda u, v: sum(x * y for x, y in zip(u, v))  # noqa: E731
+    assert [dot(b, [1] * 10), dot(b, c), dot(b, [x * x for x in c]), dot(b, Ac)] == \
+        [1, Fraction(1, 2), Fraction(1, 3), Fraction(1, 6)]
+    assert dot(b, [x ** 3 for x in c]) == Fraction(1, 4)
+    assert bh == [Fraction(1, 15)] * 5 + [Fraction(1, 6)] * 4 + [0]
+    assert [dot(bh, [1] * 10), dot(bh, c), dot(bh, Ac)] == [1, Fraction(1, 2), Fraction(1, 6)]
+    assert dot(bh, [x * x for x in c]) == Fraction(11, 36)
+    for z in (-0.5, -3.0, -8.0, -12.0):
+        w = 1 + z / 6
+        assert _embedded_amplification(z) == pytest.approx((0.6 + 0.4 * w ** 5) * w ** 4, abs=1e-12)
+    zs = [-0.08, -0.04]
+    errs = [abs(_embedded_amplification(z, m=1) - math.exp(z)) for z in zs]
+    order = math.log(errs[0] / errs[1]) / math.log(2) - 1
+    assert abs(order - 3) < 5e-2 * 3, (order, errs)
+
+
+def test_adaptive_ssp104_converges_with_the_tolerance():
+    """Adaptive SSP(10)4 with the embedded estimate on pure c diffusion of one
+    Fourier mode (exact solution known): it lands on t_end, its steps stay
+    within 0.9 * 6 dt_e, and the error against the exact decay falls with the
+    tolerance."""
+    P, u, mode, lam = _mode_problem(m=6)
+    dte = oracle.stable_dt(P)
+    t_end = 40.0 * dte
+    errs = []
+    for a in (1e-6, 1e-9, 1e-12):
+        tol = oracle.Tol(r_phi=a, a_phi=a, r_c=a, a_c=a)
+        v, st, rc = oracle.run_to(P, oracle.SSP104, u, t_end, tol=tol)
+        assert rc == 0 and st.t == t_end
+        assert (st.trace[:, 0] <= 0.9 * 6 * dte * (1 + 1e-12)).all()
+        assert (st.trace[:, 1] == 10).all()
+        exact = 0.5 + 1e-3 * math.exp(lam * t_end) * mode
+        errs.append(float(np.abs(v[2].ravel() - exact).max()))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-12
+
+
 # -----------------------------------------------------------------------------
 # Stable step (reading of the Gershgorin estimates) against Table 3
 # -----------------------------------------------------------------------------
