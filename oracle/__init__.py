@@ -45,7 +45,8 @@ class _Params(C.Structure):
                 ("dx", C.c_double), ("W", C.c_double),
                 ("gamma", C.c_double * (MAXT * MAXT)), ("mob", C.c_double * (MAXT * MAXT)),
                 ("k", C.c_double * MAXT), ("c0", C.c_double * MAXT), ("D", C.c_double * MAXT),
-                ("bc", C.c_int * 3), ("c_fixed", C.c_int * 6), ("c_bc", C.c_double * 6)]
+                ("bc", C.c_int * 3), ("c_fixed", C.c_int * 6), ("c_bc", C.c_double * 6),
+                ("n_p", C.c_int)]
 
 
 class _Tol(C.Structure):
@@ -105,6 +106,9 @@ def lib():
         L.pfo_pair_constants.argtypes = [P, D, D, D]
         L.pfo_num_threads.restype = I
         L.pfo_set_rkl2_r0_correction.argtypes = [I]
+        L.pfo_store.argtypes = [P, D]
+        L.pfo_store.restype = LL
+        L.pfo_store_truncations.restype = LL
         _lib = L
     return _lib
 
@@ -130,6 +134,7 @@ class Params:
     bc: Sequence[int] = (0, 0, 0)          # per axis: 0 periodic, 1 zero-gradient walls
     c_fixed: Sequence[int] = (0,) * 6      # per face x-, x+, y-, y+, z-, z+ of a walled axis
     c_bc: Sequence[float] = (0.0,) * 6     # the fixed c of those faces
+    n_p: int = 0                           # sparse storage: nonzero phi kept per cell (0: all)
 
     @property
     def F(self) -> int:
@@ -153,6 +158,7 @@ class Params:
             p.mob[i] = float(self.mob[i])
         for i in range(T):
             p.k[i], p.c0[i], p.D[i] = float(self.k[i]), float(self.c0[i]), float(self.D[i])
+        p.n_p = int(self.n_p)
         for a in range(3):
             p.bc[a] = int(self.bc[a])
         for f in range(6):
@@ -238,6 +244,19 @@ def simplex(P: Params, u):
     ch = np.zeros(u.shape[1:], dtype=np.uint8)
     lib().pfo_simplex(C.byref(P._c()), _dp(u), ch.ctypes.data_as(C.POINTER(C.c_ubyte)))
     return u, ch.astype(bool)
+
+
+def store(P: Params, u):
+    """The sparse storage rule alone applied to every cell of u (a copy);
+    returns (u, number of cells it changed)."""
+    u = _state(P, u).copy()
+    n = lib().pfo_store(C.byref(P._c()), _dp(u))
+    return u, int(n)
+
+
+def store_truncations() -> int:
+    """Cells the sparse storage rule changed since the last call (resets)."""
+    return int(lib().pfo_store_truncations())
 
 
 def rkl_coeffs(order: int, s: int, j: int):

@@ -60,6 +60,10 @@ typedef struct {
     int bc[3];
     int c_fixed[6];
     double c_bc[6];
+    /* sparse phase storage (Sec. 3.1 "Phase-field details"; reading R23):
+     * n_p > 0 keeps at most n_p nonzero phi per cell, see cell_store; 0 keeps
+     * all N (dense) */
+    int n_p;
 } pfo_params;
 
 typedef struct {
@@ -356,6 +360,65 @@ static int cell_simplex(int N, double *p /* N values */) {
     return changed;
 }
 
+/* Sparse phase storage (Sec. 3.1, "Phase-field details"): a cell holds at
+ * most n_p phase values and their phase ids, the others being zero.  Reading
+ * R23 for a cell with more than n_p nonzero phi: the n_p largest are kept
+ * (equal values: the lower phase index first), the others become 0, and the
+ * kept ones are divided by their sum, as the last step of S does.  A cell with
+ * at most n_p nonzero values is left exactly as it is, so with n_p at least
+ * the largest local phase count sparse storage gives the dense results.
+ * Returns 1 when the cell changed. */
+static long long store_truncations = 0; /* cells changed by the rule since the last reset */
+
+static int cell_store(int N, int n_p, double *p) {
+    int cnt = 0;
+    for (int a = 0; a < N; ++a) cnt += p[a] != 0.0;
+    if (n_p <= 0 || cnt <= n_p) return 0;
+#pragma omp atomic
+    store_truncations++;
+    int keep[PFO_MAXN] = {0};
+    for (int k = 0; k < n_p; ++k) {
+        int m = -1;
+        for (int a = 0; a < N; ++a)
+            if (!keep[a] && p[a] != 0.0 && (m < 0 || p[a] > p[m])) m = a;
+        keep[m] = 1;
+    }
+    double s = 0.0;
+    for (int a = 0; a < N; ++a) {
+        if (!keep[a]) p[a] = 0.0;
+        s = s + p[a];
+    }
+    if (s > 0.0)
+        for (int a = 0; a < N; ++a) p[a] = p[a] / s;
+    return 1;
+}
+
+/* Number of cells the storage rule changed since the last call (the call
+ * resets it): tells whether a sparse run ever dropped a phase. */
+long long pfo_store_truncations(void) {
+    long long n = store_truncations;
+    store_truncations = 0;
+    return n;
+}
+
+/* The storage rule alone on every cell (an initial state in sparse storage). */
+long long pfo_store(const pfo_params *P, double *u) {
+    long long V = ncells(P);
+    int N = P->n_phi;
+    long long n = 0;
+    if (P->n_p <= 0) return 0;
+#pragma omp parallel for schedule(static) reduction(+ : n)
+    for (long long i = 0; i < V; ++i) {
+        double p[PFO_MAXN];
+        for (int a = 0; a < N; ++a) p[a] = u[(long long)a * V + i];
+        int ch = cell_store(N, P->n_p, p);
+        for (int a = 0; a < N; ++a) u[(long long)a * V + i] = p[a];
+        n += ch;
+    }
+    return n;
+}
+
+/* S followed by the storage rule (every stored stage of a sparse run). */
 long long pfo_simplex(const pfo_params *P, double *u, unsigned char *changed_out) {
     long long V = ncells(P);
     int N = P->n_phi;
@@ -365,6 +428,7 @@ long long pfo_simplex(const pfo_params *P, double *u, unsigned char *changed_out
         double p[PFO_MAXN];
         for (int a = 0; a < N; ++a) p[a] = u[(long long)a * V + i];
         int ch = cell_simplex(N, p);
+        ch |= cell_store(N, P->n_p, p);
         for (int a = 0; a < N; ++a) u[(long long)a * V + i] = p[a];
         if (changed_out) changed_out[i] = (unsigned char)ch;
         nchanged += ch;
@@ -571,6 +635,7 @@ static void step_rkl2(const pfo_params *P, int s, double dt, double *u, double *
 int pfo_step(const pfo_params *P, int integ, int s, double dt, double *u, double *aux,
              pfo_stats *st) {
     long long n = (long long)nfields(P) * ncells(P);
+    pfo_store(P, u);  /* a state held in sparse storage (no-op when dense) */
     double *w[5];
     for (int k = 0; k < 5; ++k) {
         w[k] = (double *)calloc((size_t)n, sizeof(double));
@@ -809,6 +874,7 @@ int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_en
     long long n = (long long)nfields(P) * ncells(P);
     double dte = pfo_stable_dt(P);
     double t = t0;
+    pfo_store(P, u);  /* a state held in sparse storage (no-op when dense) */
     long long nt = 0;
     if (ntrace) *ntrace = 0;
     if (!tol) {

@@ -649,6 +649,62 @@ def test_rkl2_first_stage_correction_lowers_the_error():
 
 
 # -----------------------------------------------------------------------------
+# Sparse phase storage (Sec. 3.1 "Phase-field details", reading R23)
+# -----------------------------------------------------------------------------
+
+def _one_cell(vals, n_p):
+    P = oracle.Params(nx=1, ny=1, n_phi=len(vals), with_c=False, n_p=n_p)
+    u = np.array(vals, dtype=float).reshape(len(vals), 1, 1, 1)
+    out, n = oracle.store(P, u)
+    return out.ravel(), n
+
+
+def test_sparse_storage_hand_cases():
+    """At most n_p nonzero phi per cell: more are cut to the n_p largest (equal
+    values: lower index first) and renormalised; fewer are left bit for bit."""
+    out, n = _one_cell([0.1, 0.4, 0.2, 0.3], 2)
+    assert n == 1
+    assert np.array_equal(out, np.array([0.0, 0.4 / 0.7, 0.0, 0.3 / 0.7]))
+    out, n = _one_cell([0.25, 0.25, 0.25, 0.25], 3)
+    assert n == 1
+    assert np.array_equal(out, np.array([0.25 / 0.75, 0.25 / 0.75, 0.25 / 0.75, 0.0]))
+    vals = [0.0, 0.3, 0.0, 0.7]
+    out, n = _one_cell(vals, 2)
+    assert n == 0 and np.array_equal(out, np.array(vals))
+    out, n = _one_cell([0.1, 0.4, 0.2, 0.3], 0)     # n_p = 0: dense, never cut
+    assert n == 0 and np.array_equal(out, np.array([0.1, 0.4, 0.2, 0.3]))
+
+
+@pytest.mark.parametrize("integ", [oracle.FE, oracle.RKL2, oracle.RKL1])
+def test_sparse_equals_dense_when_nothing_is_cut(integ):
+    """Sparse storage with n_p at least the largest count of nonzero phases
+    any stored stage reaches gives the dense results bit for bit (the cut
+    counter stays 0); with a smaller n_p cells are cut, every stored state
+    keeps at most n_p nonzero phi per cell and stays on the simplex."""
+    wl = pi.voronoi_2d(n=48, ny=40, n_grains=12, n_phi=8, W=3.0, dmin=6.0)
+    P = oracle.Params(**wl.param_dict())
+    dte = oracle.stable_dt(P)
+    dt = {oracle.FE: 0.9, oracle.RKL2: 20.0, oracle.RKL1: 10.0}[integ] * dte
+    dense, _, rc = oracle.run_to(P, integ, wl.u0, 3 * dt, dt_fixed=dt)
+    assert rc == 0
+    oracle.store_truncations()
+    for n_p in (8, 6, 5):
+        Ps = oracle.Params(**wl.param_dict(), n_p=n_p)
+        sp, _, rc = oracle.run_to(Ps, integ, wl.u0, 3 * dt, dt_fixed=dt)
+        assert rc == 0
+        cut = oracle.store_truncations()
+        assert cut == 0, (n_p, cut)
+        assert np.array_equal(sp, dense), n_p
+    Ps = oracle.Params(**wl.param_dict(), n_p=2)
+    sp, _, rc = oracle.run_to(Ps, integ, wl.u0, 3 * dt, dt_fixed=dt)
+    assert rc == 0 and oracle.store_truncations() > 0
+    assert not np.array_equal(sp, dense)
+    N = wl.n_phi
+    assert (sp[:N] > 0).sum(axis=0).max() <= 2
+    assert np.abs(sp[:N].sum(axis=0) - 1).max() < 1e-14 and sp[:N].min() >= 0
+
+
+# -----------------------------------------------------------------------------
 # Error estimate and norm (Sec. 3.3)
 # -----------------------------------------------------------------------------
 
