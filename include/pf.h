@@ -291,6 +291,26 @@ pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
 pf_status pf_set_field_groups(pf_sim *sim, int ng);
 pf_status pf_get_field_groups(const pf_sim *sim, int *ng);
 
+/* Sparse phase storage (Sec. 3.1 "Phase-field details"): with n_p > 0 each
+ * cell of a state vector holds c, the values of at most n_p nonzero phases
+ * (ascending phase order) and a 32-bit word of their phase ids (4 bits each),
+ * instead of all N phase values; the stage kernels read the slots into the
+ * dense values they compute with, so while no cell has more than n_p nonzero
+ * phases the results equal dense storage bit for bit.  A projected stage with
+ * more nonzero phases keeps the n_p largest (equal values: the lower phase),
+ * divided by their sum; pf_sparse_cuts returns (and resets) the number of
+ * cells so cut since pf_set_sparse_storage.  n_p = 0 returns to dense
+ * storage.  The call frees the work buffers and clears the fields (call
+ * pf_init_fields after it); host and device field arrays keep the dense
+ * layout in every call.  Built for periodic grids whose vectors need one or
+ * two buffer groups; it runs forward Euler, RKL1 and RKL2 fixed steps and the
+ * RHS (SSP schemes, adaptive steps, error norms and checkpoints return
+ * PF_EUNSUPPORTED; fused stage pairs are not used).  Errors: PF_EINVAL for n_p
+ * outside 0..min(8, N); PF_EUNSUPPORTED for walls or more buffer groups. */
+pf_status pf_set_sparse_storage(pf_sim *sim, int n_p);
+pf_status pf_get_sparse_storage(const pf_sim *sim, int *n_p);
+pf_status pf_sparse_cuts(pf_sim *sim, long long *cuts);
+
 /* RKL2 inner stages per launch (eq. sts, stages j >= 2): 1, or 2 for stages j
  * and j + 1 in one pass over memory (four vectors read and two written per
  * pair instead of five per stage; a step with an odd count of inner stages

@@ -43,7 +43,8 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error",
            "pf_params_stable_dt", "pf_rkl_stage_count", "pf_controller_init",
            "pf_controller_update", "pf_clip_step", "pf_set_timing_families",
-           "pf_set_stage_fusion", "pf_get_stage_fusion", "pf_set_pair_zchunk", "pf_get_pair_zchunk"]
+           "pf_set_stage_fusion", "pf_get_stage_fusion", "pf_set_pair_zchunk", "pf_get_pair_zchunk",
+           "pf_set_sparse_storage", "pf_get_sparse_storage", "pf_sparse_cuts"]
 
 
 class PFError(RuntimeError):
@@ -145,6 +146,9 @@ def lib():
             "pf_set_stage_fusion": [vp, i],
             "pf_get_stage_fusion": [vp, C.POINTER(i)],
             "pf_set_pair_zchunk": [vp, i],
+            "pf_set_sparse_storage": [vp, i],
+            "pf_get_sparse_storage": [vp, C.POINTER(i)],
+            "pf_sparse_cuts": [vp, C.POINTER(ll)],
             "pf_get_pair_zchunk": [vp, C.POINTER(i)],
             "pf_set_timing": [vp, i],
             "pf_set_timing_families": [vp, C.c_uint],
@@ -596,6 +600,22 @@ class Sim:
         d = C.c_int()
         self._chk(self._L.pf_get_stage_fusion(self._h, C.byref(d)))
         return d.value
+
+    def set_sparse_storage(self, n_p: int):
+        """Sparse phase storage with n_p slots per cell (0: dense); clears the
+        fields (call init_fields after it)."""
+        self._chk(self._L.pf_set_sparse_storage(self._h, int(n_p)))
+
+    def sparse_storage(self) -> int:
+        v = C.c_int()
+        self._chk(self._L.pf_get_sparse_storage(self._h, C.byref(v)))
+        return v.value
+
+    def sparse_cuts(self) -> int:
+        """Cells the sparse storage rule cut since the last call."""
+        v = C.c_longlong()
+        self._chk(self._L.pf_sparse_cuts(self._h, C.byref(v)))
+        return v.value
 
     def set_pair_zchunk(self, zchunk: int):
         """z planes per block of the 3D fused RKL2 stage pairs."""

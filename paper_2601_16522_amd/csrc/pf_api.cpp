@@ -88,6 +88,11 @@ struct pf_sim {
     int tx = 64, zchunk = 16;
     int zchunk2 = 32;        // z extent of the fused RKL2 stage pairs (3D)
     int groups_min = 1;      // least buffer groups per state vector (pf_set_field_groups)
+    // sparse phase storage (pf_set_sparse_storage): slots per cell (0: dense),
+    // byte offset of the id words in a buffer, device count of cut cells
+    int n_p = 0;
+    unsigned long long ids_off = 0;
+    unsigned long long *dcut = nullptr;
     int fuse = 1;            // RKL2 inner stages per launch (2: fused pairs, where built)
     int inner_launches = 0;  // launches of the last step's inner-stage interval
     bool timing = false;
@@ -122,17 +127,34 @@ pf_status fail(pf_sim *s, pf_status code, const char *fmt, ...) {
 
 size_t state_bytes(const pf_sim *s) { return (size_t)s->F * (size_t)s->V * s->esz; }
 
+// Bytes of one work buffer: a dense vector, or with sparse phase storage the
+// larger of a dense vector (R0, RHS) and a sparse one (c, n_p value planes,
+// then the id words at ids_off).
+size_t buf_bytes(const pf_sim *s) {
+    if (s->n_p <= 0) return state_bytes(s);
+    return std::max(state_bytes(s), (size_t)s->ids_off + 4 * (size_t)s->V);
+}
+
+// Buffer-group mask of the state vectors of a stage (y1, y2, u0 and, except
+// for the RHS kind, out) under sparse phase storage.
+unsigned sparse_mask(const pf_sim *s, int kind) {
+    if (s->n_p <= 0) return 0u;
+    return kind == K_RHS ? 0x7u : 0x17u;
+}
+
 // Buffer groups of the handle's state vectors: the fewest that address them,
 // or more when pf_set_field_groups asked for more.
 int sim_groups(const pf_sim *s) {
-    return std::max(field_groups_needed(s->N, s->V, (int)s->esz), s->groups_min);
+    int ng = std::max(field_groups_needed(s->N, s->V, (int)s->esz), s->groups_min);
+    if (s->n_p > 0) ng = std::max(ng, field_groups_needed(SPMAX, s->V, (int)s->esz));
+    return ng;
 }
 
 pf_status ensure_buf(pf_sim *s, int i) {
     if (!s->buf[i]) {
-        if (hipMalloc(&s->buf[i], state_bytes(s)) != hipSuccess) {
+        if (hipMalloc(&s->buf[i], buf_bytes(s)) != hipSuccess) {
             s->buf[i] = nullptr;
-            return fail(s, PF_ENOMEM, "hipMalloc of %zu bytes failed", state_bytes(s));
+            return fail(s, PF_ENOMEM, "hipMalloc of %zu bytes failed", buf_bytes(s));
         }
     }
     return PF_OK;
@@ -467,7 +489,10 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     A.r0 = r0;
     A.out = out;
     A.out2 = out2;
-    set_field_bases(A, s->N, s->V, s->groups_min);
+    set_field_bases(A, s->N, s->V, s->groups_min, sparse_mask(s, kind));
+    A.n_p = s->n_p;
+    A.ids_off = s->ids_off;
+    A.cut = s->dcut;
     A.kind = kind;
     A.a = (T)a; A.b = (T)b; A.c = (T)c; A.d = (T)d; A.e = (T)e; A.f = (T)f;
     int ntx, nty, nzc, ntiles, nblocks;
@@ -489,7 +514,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
 // periodic grids; in 2D with vectors in one buffer group and the kernel's LDS
 // within one workgroup's, in 3D where its two z windows fit the registers.
 bool pair_ok(const pf_sim *s) {
-    if (s->walls != 0) return false;
+    if (s->walls != 0 || s->n_p > 0) return false;
     if (s->dim == 2) return sim_groups(s) == 1 && rkl2_pair_fits((int)s->esz, s->N);
     return rkl2_pair3_built((int)s->esz, s->N);
 }
@@ -909,6 +934,16 @@ pf_status upload(pf_sim *s, const double *phi, const double *c) {
         const double *cc = c ? c : phi + (long long)s->N * V;
         for (long long i = 0; i < V; ++i) h[(long long)s->N * V + i] = (T)cc[i];
     }
+    if (s->n_p > 0) {
+        // dense into a work buffer, then packed into the state
+        const int w = work_index(s, 0);
+        if (pf_status rc = ensure_buf(s, w)) return rc;
+        HIPCHK(s, hipMemcpyAsync(s->buf[w], h.data(), state_bytes(s), hipMemcpyHostToDevice, s->stream));
+        HIPCHK(s, launch_pack_sparse<T>((const T *)s->buf[w], (T *)s->buf[s->cur], s->N, s->with_c, s->V,
+                                        s->n_p, s->ids_off, s->dcut, s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        return PF_OK;
+    }
     HIPCHK(s, hipMemcpyAsync(s->buf[s->cur], h.data(), state_bytes(s), hipMemcpyHostToDevice,
                              s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -916,9 +951,16 @@ pf_status upload(pf_sim *s, const double *phi, const double *c) {
 }
 
 template <typename T>
-pf_status download(pf_sim *s, const void *dev, double *phi, double *c) {
+pf_status download(pf_sim *s, const void *dev, double *phi, double *c, bool sparse = false) {
     const long long V = s->V;
     std::vector<T> h((size_t)s->F * V);
+    if (sparse) {  // a state in sparse storage: unpacked into a work buffer first
+        const int w = work_index(s, 0);
+        if (pf_status rc = ensure_buf(s, w)) return rc;
+        HIPCHK(s, launch_unpack_sparse<T>((const T *)dev, (T *)s->buf[w], s->N, s->with_c, s->V, s->n_p,
+                                          s->ids_off, s->stream));
+        dev = s->buf[w];
+    }
     HIPCHK(s, hipMemcpyAsync(h.data(), dev, state_bytes(s), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     if (phi)
@@ -961,7 +1003,7 @@ pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fus
     const int npair = !pair_ok(s) ? 0 : (s->dim == 3 ? 5 : 1);
     const T *u = bp<T>(s, s->cur);
     for (int k = 1; k < 4; ++k)
-        HIPCHK(s, hipMemcpyAsync(s->buf[w[k]], u, state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(s, hipMemcpyAsync(s->buf[w[k]], u, buf_bytes(s), hipMemcpyDeviceToDevice, s->stream));
     hipEvent_t e0, e1;
     HIPCHK(s, hipEventCreate(&e0));
     HIPCHK(s, hipEventCreate(&e1));
@@ -1136,6 +1178,7 @@ pf_status pf_destroy(pf_sim *s) {
     for (int i = 0; i < NBUF; ++i)
         if (s->buf[i]) hipFree(s->buf[i]);
     if (s->dparams) hipFree(s->dparams);
+    if (s->dcut) hipFree(s->dcut);
     if (s->red) hipFree(s->red);
     if (s->redn) hipFree(s->redn);
     if (s->hres) hipHostFree(s->hres);
@@ -1168,8 +1211,17 @@ pf_status pf_init_fields(pf_sim *s, const double *phi, const double *c, double t
 
 pf_status pf_init_fields_device(pf_sim *s, const void *state, double t0) {
     if (!s || !state) return PF_EINVAL;
-    HIPCHK(s, hipMemcpyAsync(s->buf[s->cur], state, state_bytes(s), hipMemcpyDeviceToDevice,
-                             s->stream));
+    if (s->n_p > 0) {
+        const hipError_t e = s->prec == PF_FP64
+            ? launch_pack_sparse<double>((const double *)state, (double *)s->buf[s->cur], s->N, s->with_c,
+                                         s->V, s->n_p, s->ids_off, s->dcut, s->stream)
+            : launch_pack_sparse<float>((const float *)state, (float *)s->buf[s->cur], s->N, s->with_c,
+                                        s->V, s->n_p, s->ids_off, s->dcut, s->stream);
+        if (e != hipSuccess) return fail(s, PF_EHIP, "pack launch: %s", hipGetErrorString(e));
+    } else {
+        HIPCHK(s, hipMemcpyAsync(s->buf[s->cur], state, state_bytes(s), hipMemcpyDeviceToDevice,
+                                 s->stream));
+    }
     s->t = t0;
     s->have_fields = true;
     s->ctrl = ctrl_initial();
@@ -1182,12 +1234,21 @@ pf_status pf_get_fields(pf_sim *s, double *phi, double *c, double *t) {
     if (pf_status rc = need_fields(s)) return rc;
     if (t) *t = s->t;
     if (!phi && !c) return PF_OK;
-    return DISPATCH(s, download, s->buf[s->cur], phi, c);
+    return DISPATCH(s, download, s->buf[s->cur], phi, c, s->n_p > 0);
 }
 
 pf_status pf_get_fields_device(pf_sim *s, void *state) {
     if (!s || !state) return PF_EINVAL;
     if (pf_status rc = need_fields(s)) return rc;
+    if (s->n_p > 0) {
+        const hipError_t e = s->prec == PF_FP64
+            ? launch_unpack_sparse<double>((const double *)s->buf[s->cur], (double *)state, s->N, s->with_c,
+                                           s->V, s->n_p, s->ids_off, s->stream)
+            : launch_unpack_sparse<float>((const float *)s->buf[s->cur], (float *)state, s->N, s->with_c,
+                                          s->V, s->n_p, s->ids_off, s->stream);
+        if (e != hipSuccess) return fail(s, PF_EHIP, "unpack launch: %s", hipGetErrorString(e));
+        return PF_OK;
+    }
     HIPCHK(s, hipMemcpyAsync(state, s->buf[s->cur], state_bytes(s), hipMemcpyDeviceToDevice,
                              s->stream));
     return PF_OK;
@@ -1235,9 +1296,18 @@ pf_status pf_stage_count(pf_sim *s, pf_integrator integ, double dt, int *ns) {
     }
 }
 
+// Sparse phase storage runs forward Euler, RKL1 and RKL2 fixed steps.
+static pf_status sparse_integ_ok(pf_sim *s, int integ, const pf_tol *tol) {
+    if (s->n_p <= 0) return PF_OK;
+    if (tol || (integ != PF_FEULER && integ != PF_RKL1 && integ != PF_RKL2))
+        return fail(s, PF_EUNSUPPORTED, "sparse phase storage runs fixed FE, RKL1 and RKL2 steps");
+    return PF_OK;
+}
+
 pf_status pf_step(pf_sim *s, pf_integrator integ, double dt, pf_stats *stats) {
     if (!s) return PF_EINVAL;
     if (pf_status rc = need_fields(s)) return rc;
+    if (pf_status rc = sparse_integ_ok(s, integ, nullptr)) return rc;
     if (!(dt > 0.0)) return fail(s, PF_EINVAL, "dt must be > 0");
     s->st = pf_stats{};
     int ns = s->ssp_s;
@@ -1259,6 +1329,7 @@ pf_status pf_run_to(pf_sim *s, pf_integrator integ, double t_end, const pf_tol *
                     double dt_fixed, pf_stats *stats) {
     if (!s) return PF_EINVAL;
     if (pf_status rc = need_fields(s)) return rc;
+    if (pf_status rc = sparse_integ_ok(s, integ, tol)) return rc;
     s->st = pf_stats{};
     pf_status rc = s->prec == PF_FP64 ? run_to_t<double>(s, integ, t_end, tol, dt_fixed)
                                       : run_to_t<float>(s, integ, t_end, tol, dt_fixed);
@@ -1270,6 +1341,7 @@ pf_status pf_run_to(pf_sim *s, pf_integrator integ, double t_end, const pf_tol *
 pf_status pf_error_norm_device(pf_sim *s, int kind, double dt, const void *u_old, const void *u_new,
                                const void *aux, const pf_tol *tol, double *norm, long long *ndof) {
     if (!s || !u_old || !u_new || !aux || !tol || !norm) return PF_EINVAL;
+    if (s->n_p > 0) return fail(s, PF_EUNSUPPORTED, "error norms need dense storage");
     if (kind != 0 && kind != 1) return PF_EINVAL;
     if (s->prec == PF_FP64)
         return error_norm<double>(s, kind, dt, (const double *)u_old, (const double *)u_new,
@@ -1283,6 +1355,7 @@ pf_status pf_error_norm_device_noalloc(pf_sim *s, int kind, double dt, const voi
                                        double *norm, long long *ndof) {
     if (!s || !u_old || !u_new || !aux || !tol || !norm) return PF_EINVAL;
     if (kind != 0 && kind != 1) return PF_EINVAL;
+    if (s->n_p > 0) return fail(s, PF_EUNSUPPORTED, "error norms need dense storage");
     // the partial sums go to the static scratch: nred doubles, then nred
     // counts from the next 256-byte boundary; every entry is written before
     // the final sum reads it, so nothing needs clearing between calls
@@ -1362,6 +1435,59 @@ pf_status pf_get_field_groups(const pf_sim *s, int *ng) {
     return PF_OK;
 }
 
+pf_status pf_set_sparse_storage(pf_sim *s, int n_p) {
+    if (!s) return PF_EINVAL;
+    if (n_p < 0 || n_p > SPMAX || n_p > s->N)
+        return fail(s, PF_EINVAL, "n_p = %d (0 for dense, else 1..%d and at most N)", n_p, SPMAX);
+    if (n_p > 0) {
+        if (s->walls) return fail(s, PF_EUNSUPPORTED, "sparse phase storage needs periodic grids");
+        int ng = std::max(std::max(field_groups_needed(s->N, s->V, (int)s->esz),
+                                   field_groups_needed(SPMAX, s->V, (int)s->esz)), s->groups_min);
+        if (ng == 0 || ng > 2)
+            return fail(s, PF_EUNSUPPORTED, "sparse phase storage is built for one or two buffer groups");
+    }
+    if (s->stream) hipStreamSynchronize(s->stream);
+    else hipDeviceSynchronize();
+    for (int i = 0; i < NBUF; ++i)
+        if (s->buf[i]) {
+            hipFree(s->buf[i]);
+            s->buf[i] = nullptr;
+        }
+    s->cur = 0;
+    s->have_fields = false;
+    s->n_p = n_p;
+    s->ids_off = n_p > 0 ? ((unsigned long long)(n_p + 1) * (unsigned long long)s->V * s->esz + 255) / 256 * 256 : 0;
+    if (n_p > 0 && !s->dcut) {
+        if (hipMalloc(&s->dcut, sizeof(unsigned long long)) != hipSuccess) {
+            s->dcut = nullptr;
+            s->n_p = 0;
+            s->ids_off = 0;
+            return fail(s, PF_ENOMEM, "cut counter");
+        }
+    }
+    if (s->dcut) HIPCHK(s, hipMemset(s->dcut, 0, sizeof(unsigned long long)));
+    s->fuse = pair_ok(s) && s->dim == 2 ? 2 : 1;
+    return ensure_buf(s, 0);
+}
+
+pf_status pf_get_sparse_storage(const pf_sim *s, int *n_p) {
+    if (!s || !n_p) return PF_EINVAL;
+    *n_p = s->n_p;
+    return PF_OK;
+}
+
+pf_status pf_sparse_cuts(pf_sim *s, long long *cuts) {
+    if (!s || !cuts) return PF_EINVAL;
+    *cuts = 0;
+    if (!s->dcut) return PF_OK;
+    unsigned long long v = 0;
+    HIPCHK(s, hipMemcpyAsync(&v, s->dcut, sizeof v, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    HIPCHK(s, hipMemsetAsync(s->dcut, 0, sizeof v, s->stream));
+    *cuts = (long long)v;
+    return PF_OK;
+}
+
 pf_status pf_diagnostics(pf_sim *s, double out[5]) {
     if (!s || !out) return PF_EINVAL;
     if (pf_status rc = need_fields(s)) return rc;
@@ -1369,10 +1495,16 @@ pf_status pf_diagnostics(pf_sim *s, double out[5]) {
     if (pf_status rc = ensure_red(s, nb)) return rc;
     Pending p;
     begin_timed(s, FAM_RED, p);
+    // dense: N phase planes then c; sparse: c, then n_p slots (empty ones 0)
+    const bool sp = s->n_p > 0;
+    const int nphi = sp ? s->n_p : s->N;
+    const long long po = sp ? s->V : 0, co = sp ? 0 : (long long)s->N * s->V;
     hipError_t e = s->prec == PF_FP64
-                       ? launch_diag<double>((const double *)s->buf[s->cur], s->N, s->with_c, s->V,
-                                             s->red, nb, s->stream)
-                       : launch_diag<float>((const float *)s->buf[s->cur], s->N, s->with_c, s->V,
+                       ? launch_diag<double>((const double *)s->buf[s->cur] + po,
+                                             (const double *)s->buf[s->cur] + co, nphi, s->with_c,
+                                             s->V, s->red, nb, s->stream)
+                       : launch_diag<float>((const float *)s->buf[s->cur] + po,
+                                            (const float *)s->buf[s->cur] + co, nphi, s->with_c, s->V,
                                             s->red, nb, s->stream);
     if (e != hipSuccess) return fail(s, PF_EHIP, "diag launch: %s", hipGetErrorString(e));
     HIPCHK(s, launch_finalize_diag(s->red, nb, s->hres_dev + RES_DIAG, s->stream));
@@ -1402,6 +1534,7 @@ pf_status pf_get_trace(pf_sim *s, double *buf, long long cap, long long *n) {
 
 pf_status pf_get_state(pf_sim *s, void *buf, size_t *len) {
     if (!s || !len) return PF_EINVAL;
+    if (s->n_p > 0) return fail(s, PF_EUNSUPPORTED, "checkpoints need dense storage");
     if (pf_status rc = need_fields(s)) return rc;
     const size_t need = sizeof(CkptHeader) + state_bytes(s);
     if (!buf) {
@@ -1425,6 +1558,7 @@ pf_status pf_get_state(pf_sim *s, void *buf, size_t *len) {
 
 pf_status pf_set_state(pf_sim *s, const void *buf, size_t len) {
     if (!s || !buf) return PF_EINVAL;
+    if (s->n_p > 0) return fail(s, PF_EUNSUPPORTED, "checkpoints need dense storage");
     CkptHeader h;
     if (len < sizeof h) return fail(s, PF_EINVAL, "checkpoint too short");
     std::memcpy(&h, buf, sizeof h);

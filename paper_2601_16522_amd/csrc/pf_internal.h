@@ -103,6 +103,14 @@ struct StageArgs {
     unsigned plane_bytes;
     double *red;    // per-block partial sums (EST)
     long long *redn;
+    // Sparse phase storage (n_p > 0): the state vectors (y1, y2, u0 and, except
+    // for the RHS kind, out) hold c in plane 0, up to n_p nonzero phase values
+    // in planes 1..n_p and, ids_off bytes past their base, one 32-bit word of
+    // nibble phase ids per cell; r0 and out2 stay dense.  cut (may be null)
+    // counts the cells the storage rule cut.
+    int n_p;
+    unsigned long long ids_off;
+    unsigned long long *cut;
     int kind;
     T a, b, c, d, e, f;
     T a2, b2, c2, d2, e2, f2;  // K_RKL2_PAIR: coefficients of the second stage
@@ -118,6 +126,12 @@ struct StageArgs {
 // Planes per buffer group for N order parameters (+ c) split into ng groups.
 constexpr int group_planes(int n, int ng) { return (n + 1 + ng - 1) / ng; }
 
+// Sparse phase storage: at most SPMAX slots per cell (their ids are the
+// nibbles of one 32-bit word, 15 marking an empty slot); the value planes of
+// a sparse vector are grouped as those of a dense vector of SPMAX phases.
+constexpr int SPMAX = 8;
+constexpr unsigned SP_EMPTY = 15u;
+
 // The smallest group count (1, 2 or 4) whose groups span at most 2^32 - 1
 // bytes for planes of V values of esz bytes, or 0 when even four do not.
 inline int field_groups_needed(int n, long long V, int esz) {
@@ -130,18 +144,24 @@ inline int field_groups_needed(int n, long long V, int esz) {
 // Fills the buffer-group bases of a StageArgs from its vector pointers, with
 // at least ng_min groups (1, 2 or 4; more groups than the size needs address
 // the same planes through more descriptors).  The caller guarantees
-// field_groups_needed(n, V, sizeof(T)) > 0.
+// field_groups_needed(n, V, sizeof(T)) > 0.  sparse_mask: bit v marks vector
+// v (y1, y2, u0, r0, out, out2) as held in sparse storage, whose planes are
+// grouped as those of SPMAX phases.
 template <typename T>
-inline void set_field_bases(StageArgs<T> &A, int n, long long V, int ng_min = 1) {
+inline void set_field_bases(StageArgs<T> &A, int n, long long V, int ng_min = 1,
+                            unsigned sparse_mask = 0) {
     int ng = field_groups_needed(n, V, (int)sizeof(T));
+    if (sparse_mask && field_groups_needed(SPMAX, V, (int)sizeof(T)) > ng)
+        ng = field_groups_needed(SPMAX, V, (int)sizeof(T));
     if (ng < ng_min) ng = ng_min;
-    const int GS = group_planes(n, ng);
     A.ng = ng;
     A.plane_bytes = (unsigned)((unsigned long long)V * sizeof(T));
     const T *vec[6] = {A.y1, A.y2, A.u0, A.r0, A.out, A.out2};
-    for (int v = 0; v < 6; ++v)
+    for (int v = 0; v < 6; ++v) {
+        const int GS = group_planes((sparse_mask >> v) & 1u ? SPMAX : n, ng);
         for (int g = 0; g < 4; ++g)
             A.gb[v][g] = (vec[v] && g < ng) ? vec[v] + (long long)g * GS * V : vec[v];
+    }
 }
 
 // One instance of a batch of independent 2D simulations that share N, the
@@ -247,8 +267,17 @@ hipError_t launch_embed_est(const DevParams<T> *P, int nphi, int with_c, long lo
                             T a_c, double *red, long long *redn, int nblocks,
                             hipStream_t stream);
 template <typename T>
-hipError_t launch_diag(const T *u, int nphi, int with_c, long long V, double *red,
+hipError_t launch_diag(const T *u, const T *cpl, int nphi, int with_c, long long V, double *red,
                        int nblocks, hipStream_t stream);
+// Conversion between dense state vectors and sparse phase storage (packing
+// applies the storage rule and counts the cells it cut into *cut, if non-null).
+template <typename T>
+hipError_t launch_pack_sparse(const T *dense, T *sp, int nphi, int with_c, long long V, int n_p,
+                              unsigned long long ids_off, unsigned long long *cut,
+                              hipStream_t stream);
+template <typename T>
+hipError_t launch_unpack_sparse(const T *sp, T *dense, int nphi, int with_c, long long V, int n_p,
+                                unsigned long long ids_off, hipStream_t stream);
 hipError_t launch_finalize_norm(const double *red, const long long *redn, int nparts,
                                 double *out, double seq, hipStream_t stream);
 hipError_t launch_finalize_diag(const double *red, int nparts, double *out,

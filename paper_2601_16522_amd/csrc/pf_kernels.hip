@@ -3,6 +3,7 @@
 // parameters.
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "pf_device.hpp"
 
@@ -78,7 +79,8 @@ embed_kernel(const DevParams<T> *P, int nphi, int withc, long long V, const T *_
 // min phi, max phi, non-finite count), FP64, fixed order.
 template <typename T>
 __global__ void __launch_bounds__(256)
-diag_kernel(const T *__restrict__ u, int nphi, int withc, long long V, double *red) {
+diag_kernel(const T *__restrict__ u, const T *__restrict__ cpl, int nphi, int withc, long long V,
+            double *red) {
     double sc = 0.0, dev = 0.0, lo = 1e300, hi = -1e300, bad = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
@@ -93,7 +95,7 @@ diag_kernel(const T *__restrict__ u, int nphi, int withc, long long V, double *r
         const double d = s > 1.0 ? s - 1.0 : 1.0 - s;
         dev = d > dev ? d : dev;
         if (withc) {
-            const double c = (double)u[nphi * V + i];
+            const double c = (double)cpl[i];
             if (!isfinite(c)) bad += 1.0;
             sc += c;
         }
@@ -336,10 +338,101 @@ hipError_t launch_embed_est(const DevParams<T> *P, int nphi, int with_c, long lo
 }
 
 template <typename T>
-hipError_t launch_diag(const T *u, int nphi, int with_c, long long V, double *red,
+hipError_t launch_diag(const T *u, const T *cpl, int nphi, int with_c, long long V, double *red,
                        int nblocks, hipStream_t stream) {
-    hipLaunchKernelGGL(diag_kernel<T>, dim3(nblocks), dim3(256), 0, stream, u, nphi, with_c,
+    hipLaunchKernelGGL(diag_kernel<T>, dim3(nblocks), dim3(256), 0, stream, u, cpl, nphi, with_c,
                        V, red);
+    return hipGetLastError();
+}
+
+// Sparse phase storage (Sec. 3.1 "Phase-field details"): conversion of whole
+// state vectors between the dense layout (N phase planes, then c) and the
+// sparse one (c in plane 0, up to n_p nonzero phase values in planes 1..n_p in
+// ascending phase order, a word of nibble phase ids per cell at byte offset
+// ids_off).  Packing applies the storage rule of the stage kernels: a cell
+// with more than n_p nonzero phases keeps the n_p largest (equal values: the
+// lower phase), divided by their sum; cut counts such cells.
+template <typename T>
+__global__ void __launch_bounds__(256)
+pack_sparse_kernel(const T *__restrict__ dense, T *__restrict__ sp, int nphi, int withc, long long V,
+                   int n_p, unsigned long long ids_off, unsigned long long *cut) {
+    unsigned *ids = (unsigned *)((char *)sp + ids_off);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
+        T p[NMAX];
+        int cnt = 0;
+        for (int a = 0; a < nphi; ++a) {
+            p[a] = dense[a * V + i];
+            cnt += p[a] != T(0) ? 1 : 0;
+        }
+        if (cnt > n_p) {
+            unsigned keep = 0u;
+            for (int k = 0; k < n_p; ++k) {
+                int m = -1;
+                for (int a = 0; a < nphi; ++a)
+                    if (!((keep >> a) & 1u) && p[a] != T(0) && (m < 0 || p[a] > p[m])) m = a;
+                keep |= 1u << m;
+            }
+            T sum = T(0);
+            for (int a = 0; a < nphi; ++a) {
+                if (!((keep >> a) & 1u)) p[a] = T(0);
+                sum = sum + p[a];
+            }
+            if (sum > T(0)) {
+                if constexpr (std::is_same<T, float>::value) {
+                    const T inv = __builtin_amdgcn_rcpf(sum);
+                    for (int a = 0; a < nphi; ++a) p[a] = p[a] * inv;
+                } else {
+                    for (int a = 0; a < nphi; ++a) p[a] = p[a] / sum;
+                }
+            }
+            if (cut) atomicAdd(cut, 1ull);
+        }
+        unsigned w = 0xFFFFFFFFu;
+        int k = 0;
+        for (int a = 0; a < nphi; ++a)
+            if (p[a] != T(0)) {
+                sp[(k + 1) * V + i] = p[a];
+                w = (w & ~(15u << (4 * k))) | ((unsigned)a << (4 * k));
+                ++k;
+            }
+        for (; k < n_p; ++k) sp[(k + 1) * V + i] = T(0);
+        sp[i] = withc ? dense[nphi * V + i] : T(0);
+        ids[i] = w;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+unpack_sparse_kernel(const T *__restrict__ sp, T *__restrict__ dense, int nphi, int withc, long long V,
+                     int n_p, unsigned long long ids_off) {
+    const unsigned *ids = (const unsigned *)((const char *)sp + ids_off);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < V; i += stride) {
+        for (int a = 0; a < nphi; ++a) dense[a * V + i] = T(0);
+        const unsigned w = ids[i];
+        for (int k = 0; k < n_p; ++k) {
+            const unsigned id = (w >> (4 * k)) & 15u;
+            if (id < (unsigned)nphi) dense[id * V + i] = sp[(k + 1) * V + i];
+        }
+        if (withc) dense[nphi * V + i] = sp[i];
+    }
+}
+
+template <typename T>
+hipError_t launch_pack_sparse(const T *dense, T *sp, int nphi, int with_c, long long V, int n_p,
+                              unsigned long long ids_off, unsigned long long *cut,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(pack_sparse_kernel<T>, dim3(2048), dim3(256), 0, stream, dense, sp, nphi,
+                       with_c, V, n_p, ids_off, cut);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_unpack_sparse(const T *sp, T *dense, int nphi, int with_c, long long V, int n_p,
+                                unsigned long long ids_off, hipStream_t stream) {
+    hipLaunchKernelGGL(unpack_sparse_kernel<T>, dim3(2048), dim3(256), 0, stream, sp, dense, nphi,
+                       with_c, V, n_p, ids_off);
     return hipGetLastError();
 }
 
@@ -395,9 +488,17 @@ template hipError_t launch_embed_est<double>(const DevParams<double> *, int, int
                                              const double *, const double *, const double *,
                                              double, double, double, double, double *,
                                              long long *, int, hipStream_t);
-template hipError_t launch_diag<float>(const float *, int, int, long long, double *, int,
-                                       hipStream_t);
-template hipError_t launch_diag<double>(const double *, int, int, long long, double *, int,
-                                        hipStream_t);
+template hipError_t launch_diag<float>(const float *, const float *, int, int, long long, double *,
+                                       int, hipStream_t);
+template hipError_t launch_diag<double>(const double *, const double *, int, int, long long, double *,
+                                        int, hipStream_t);
+template hipError_t launch_pack_sparse<float>(const float *, float *, int, int, long long, int,
+                                              unsigned long long, unsigned long long *, hipStream_t);
+template hipError_t launch_pack_sparse<double>(const double *, double *, int, int, long long, int,
+                                               unsigned long long, unsigned long long *, hipStream_t);
+template hipError_t launch_unpack_sparse<float>(const float *, float *, int, int, long long, int,
+                                                unsigned long long, hipStream_t);
+template hipError_t launch_unpack_sparse<double>(const double *, double *, int, int, long long, int,
+                                                 unsigned long long, hipStream_t);
 
 }  // namespace pf

@@ -134,6 +134,122 @@ __device__ __forceinline__ void project(T *p) {
     }
 }
 
+// ---- sparse phase storage (Sec. 3.1 "Phase-field details") -------------------
+// A state vector in sparse storage holds, per cell, c in plane 0, the values
+// of its nonzero phases in slots 1..n_p (ascending phase order; empty slots
+// hold 0) and a 32-bit word whose nibble s is the phase of slot s (15: empty),
+// ids_off bytes past the vector's base.  Loads scatter the slots into the N
+// dense values the stage arithmetic works on, so a stage in sparse storage
+// computes exactly what it computes in dense storage; stores keep the nonzero
+// phases.
+
+// Id words of vector v (y1, y2, u0, r0, out, out2 by role).
+template <typename T, typename S>
+__device__ __forceinline__ unsigned *sparse_ids(const S &A, int v) {
+    const T *b = v == 0 ? A.y1 : v == 1 ? A.y2 : v == 2 ? A.u0 : v == 3 ? A.r0 : v == 4 ? A.out : A.out2;
+    return (unsigned *)((char *)const_cast<T *>(b) + A.ids_off);
+}
+
+// The N dense phase values and c of sparse vector v at byte offset boff.
+template <typename T, int N, int GSS, int CP, typename S>
+__device__ __forceinline__ void load_sparse(const S &A, int v, unsigned boff, bool withc, T *x) {
+    const unsigned w = sparse_ids<T>(A, v)[boff / (unsigned)sizeof(T)];
+    T val[SPMAX];
+#pragma unroll
+    for (int k = 0; k < SPMAX; ++k) val[k] = k < A.n_p ? ldv<T, GSS, CP>(A, v, k + 1, boff) : T(0);
+    x[N] = withc ? ldv<T, GSS, CP>(A, v, 0, boff) : T(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) x[a] = T(0);
+#pragma unroll
+    for (int k = 0; k < SPMAX; ++k) {
+        if (k < A.n_p) {  // uniform
+            const unsigned id = (w >> (4 * k)) & 15u;
+#pragma unroll
+            for (int a = 0; a < N; ++a) x[a] = id == (unsigned)a ? val[k] : x[a];
+        }
+    }
+}
+
+// Stores the N dense phase values (at most n_p of them nonzero) and c into
+// sparse vector v at byte offset boff.
+template <typename T, int N, int GSS, int CP, typename S>
+__device__ __forceinline__ void store_sparse(const S &A, int v, unsigned boff, bool withc, const T *y) {
+    T slot[SPMAX];
+#pragma unroll
+    for (int k = 0; k < SPMAX; ++k) slot[k] = T(0);
+    unsigned w = 0xFFFFFFFFu;
+    // phases pushed from the highest down, so the slots end up ascending
+#pragma unroll
+    for (int a = N - 1; a >= 0; --a) {
+        if (y[a] != T(0)) {
+#pragma unroll
+            for (int k = SPMAX - 1; k > 0; --k) slot[k] = slot[k - 1];
+            slot[0] = y[a];
+            w = (w << 4) | (unsigned)a;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SPMAX; ++k)
+        if (k < A.n_p) stv<T, GSS, CP>(A, v, k + 1, boff, slot[k]);
+    if (withc) stv<T, GSS, CP>(A, v, 0, boff, y[N]);
+    sparse_ids<T>(A, v)[boff / (unsigned)sizeof(T)] = w;
+}
+
+// The storage rule on a projected cell: with more than n_p nonzero phases the
+// n_p largest are kept (equal values: the lower phase first), the rest set to
+// 0 and the kept ones divided by their sum (the fast form multiplies by a
+// hardware reciprocal).  Returns whether it cut.
+template <typename T, int N, bool FAST>
+__device__ __forceinline__ bool sparse_cut(T *p, int n_p) {
+    int cnt = 0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) cnt += p[a] != T(0) ? 1 : 0;
+    if (cnt <= n_p) return false;
+    unsigned keep = 0u;
+    for (int k = 0; k < n_p; ++k) {
+        int m = -1;
+        T pm = T(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+            if (!((keep >> a) & 1u) && p[a] != T(0) && (m < 0 || p[a] > pm)) {
+                m = a;
+                pm = p[a];
+            }
+        keep |= 1u << m;
+    }
+    T sum = T(0);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        if (!((keep >> a) & 1u)) p[a] = T(0);
+        sum = sum + p[a];
+    }
+    if (sum > T(0)) {
+        if constexpr (FAST) {
+            const T inv = fast_rcp(sum);
+#pragma unroll
+            for (int a = 0; a < N; ++a) p[a] = p[a] * inv;
+        } else {
+#pragma unroll
+            for (int a = 0; a < N; ++a) p[a] = p[a] / sum;
+        }
+    }
+    return true;
+}
+
+// A state point of vector v: dense (GSS == 0) or in sparse storage.
+template <typename T, int N, int GS, int GSS, int CP = 0, typename S>
+__device__ __forceinline__ void load_state(const S &A, int v, unsigned boff, bool withc, T *x) {
+    if constexpr (GSS > 0) {
+        load_sparse<T, N, GSS, CP>(A, v, boff, withc, x);
+    } else if constexpr (CP == 0) {
+        load_point32<T, N, GS>(A, v, boff, withc, x);
+    } else {
+#pragma unroll
+        for (int f = 0; f < N; ++f) x[f] = ldv<T, GS, CP>(A, v, f, boff);
+        x[N] = withc ? ldv<T, GS, CP>(A, v, N, boff) : T(0);
+    }
+}
+
 // The hardware dispatches workgroup b to XCD (b mod 8).  Each XCD gets a
 // contiguous range of logical tiles (x fastest, then y, then z chunk), so tiles
 // that share halo rows run on the same XCD and share its L2.  gridDim.x is a
@@ -173,7 +289,7 @@ template <int DIM> constexpr int out_store_cp() { return DIM == 3 ? 2 : 0; }
 
 // Operands of the stage combination at one cell: o0 from u0 (vector 2), o1
 // from y2 (vector 1), o2 from r0 (vector 3), as far as the stage kind uses them.
-template <typename T, int N, int KIND, int GS, int OPERAND_CP, typename S>
+template <typename T, int N, int KIND, int GS, int OPERAND_CP, typename S, int GSS = 0>
 __device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool withc, T *o0, T *o1,
                                               T *o2) {
     constexpr bool U0 = KIND == K_SSP2_FINAL || KIND == K_SSP104_S5 || KIND == K_SSP104_FINAL ||
@@ -182,6 +298,16 @@ __device__ __forceinline__ void load_operands(const S &A, unsigned idx, bool wit
     constexpr bool Y2 = KIND == K_RKL1 || KIND == K_RKL2 ||
                         (KIND == K_SSP104_FINAL && std::is_same<T, float>::value);
     constexpr bool R0 = KIND == K_RKL2 || KIND == K_EST;
+    if constexpr (GSS > 0) {  // sparse states u0 and y2, dense R0
+        if constexpr (U0) load_sparse<T, N, GSS, OPERAND_CP>(A, 2, idx, withc, o0);
+        if constexpr (Y2) load_sparse<T, N, GSS, OPERAND_CP>(A, 1, idx, withc, o1);
+#pragma unroll
+        for (int f = 0; f <= N; ++f) {
+            const bool have = f < N || withc;
+            if constexpr (R0) o2[f] = have ? ldv<T, GS, OPERAND_CP>(A, 3, f, idx) : T(0);
+        }
+        return;
+    }
 #pragma unroll
     for (int f = 0; f <= N; ++f) {
         const bool have = f < N || withc;
@@ -438,11 +564,26 @@ __device__ __forceinline__ T rkl2_value(T a, T b, T c, T d, T e, T f, T y1, T r,
 // plane) from its own values cur, its right-hand side r and the operands
 // o0 (u0), o1 (y2), o2 (r0) of the stage kind; the estimator kind adds its
 // weighted squares to acc and its degrees of freedom to cnt.
-template <typename T, int N, int KIND, int GS, int SCP, bool FAST>
+template <typename T, int N, int KIND, int GS, int SCP, bool FAST, int GSS = 0>
 __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsigned idx,
                                              const bool withc, const T *cur, const T *r,
                                              const T *o0, const T *o1, const T *o2, double &acc,
                                              long long &cnt) {
+    // sparse storage: the storage rule after S, the state output in slots
+    const auto cut = [&](T *p) __attribute__((always_inline)) {
+        if constexpr (GSS > 0) {
+            if (sparse_cut<T, N, FAST>(p, A.n_p) && A.cut) atomicAdd(A.cut, 1ull);
+        }
+    };
+    const auto store_out = [&](const T *p) __attribute__((always_inline)) {
+        if constexpr (GSS > 0) {
+            store_sparse<T, N, GSS, SCP>(A, 4, idx, withc, p);
+        } else {
+#pragma unroll
+            for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, p[f]);
+            if (withc) stv<T, GS, SCP>(A, 4, N, idx, p[N]);
+        }
+    };
     T yv[N + 1];
     if constexpr (KIND == K_RHS) {
 #pragma unroll
@@ -549,19 +690,21 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
         if constexpr (KIND == K_RKL2_FIRST) {
             // First RKL2 stage: where S changes the cell, replace rhs(u^{n,0}) of
             // the phi planes by (S(u^{n,1}) - u^{n,0}) / (mut_1 dt) (Sec. 3.2).
-            T ys[N];
+            T ys[N + 1];
 #pragma unroll
             for (int a = 0; a < N; ++a) ys[a] = yv[a];
+            ys[N] = yv[N];
             project<T, N, FAST>(ys);
+            cut(ys);
             bool changed = false;
 #pragma unroll
             for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
             // (the fast form multiplies by a hardware reciprocal of mut_1 dt)
             T inv_a = T(0);
             if constexpr (FAST) inv_a = fast_rcp(A.a);
+            store_out(ys);
 #pragma unroll
             for (int a = 0; a < N; ++a) {
-                stv<T, GS, SCP>(A, 4, a, idx, ys[a]);
                 T ra = r[a];
                 if (changed) {
                     if constexpr (FAST) ra = (ys[a] - cur[a]) * inv_a;
@@ -569,10 +712,7 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
                 }
                 stv<T, GS, SCP>(A, 5, a, idx, ra);
             }
-            if (withc) {
-                stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
-                stv<T, GS, SCP>(A, 5, N, idx, r[N]);
-            }
+            if (withc) stv<T, GS, SCP>(A, 5, N, idx, r[N]);
         } else if constexpr (KIND == K_SSP104_S5) {
             // Fifth SSP(10)4 stage plus the two linear updates of the
             // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1),
@@ -601,9 +741,8 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
             if (withc) stv<T, GS, SCP>(A, 4, N, idx, q1n[N]);
         } else {
             project<T, N, FAST>(yv);
-#pragma unroll
-            for (int f = 0; f < N; ++f) stv<T, GS, SCP>(A, 4, f, idx, yv[f]);
-            if (withc) stv<T, GS, SCP>(A, 4, N, idx, yv[N]);
+            cut(yv);
+            store_out(yv);
             if constexpr (KIND == K_EULER) {
                 if (A.out2 != nullptr) {
 #pragma unroll
@@ -622,7 +761,8 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
 // index and coordinates (tile_index, or kept by a caller that walks tiles).
 // The tile is 64 x TY cells, TY = tile_rows(DIM); thread (lx, ly) computes the
 // R = TY / 4 cells (lx, ly + 4 k) of its column (3D: R = 1, marched in z).
-template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true, bool WALLS = false>
+template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true, bool WALLS = false,
+          int GSS = 0>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx t, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
@@ -686,14 +826,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
         // every load of the first plane is issued before the first use of one
         if (DIM == 3) {
             const int zm = z0 == 0 ? (wz ? 0 : nz - 1) : z0 - 1;
-            load_point32<T, N, GS>(A, 0, (unsigned)(zm * nxy + col[0]) * (unsigned)sizeof(T), withc, prv);
+            load_state<T, N, GS, GSS>(A, 0, (unsigned)(zm * nxy + col[0]) * (unsigned)sizeof(T), withc, prv);
         }
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + col[k]) * (unsigned)sizeof(T), withc,
+            load_state<T, N, GS, GSS>(A, 0, (unsigned)((long long)z0 * nxy + col[k]) * (unsigned)sizeof(T), withc,
                                    cur[k]);
         if (has_halo)
-            load_point32<T, N, GS>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
+            load_state<T, N, GS, GSS>(A, 0, (unsigned)((long long)z0 * nxy + hcol) * (unsigned)sizeof(T), withc,
                                    hcur);
         // ghost cells that hold c fixed take it just before their first use,
         // so that the loads stay in flight; periodic grids skip all of it
@@ -703,10 +843,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
             const long long pz = (long long)z * nxy;
             if (DIM == 3) {
                 const int zp = z == nz - 1 ? (wz ? nz - 1 : 0) : z + 1;
-                load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + col[0]) * (unsigned)sizeof(T),
+                load_state<T, N, GS, GSS>(A, 0, (unsigned)((long long)zp * nxy + col[0]) * (unsigned)sizeof(T),
                                        withc, nxt);
                 if (has_halo && z + 1 < z1)
-                    load_point32<T, N, GS>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
+                    load_state<T, N, GS, GSS>(A, 0, (unsigned)((long long)zp * nxy + hcol) * (unsigned)sizeof(T),
                                            withc, hnxt);
             }
             if (z == z0) {  // later planes rotate their mu and Mc in
@@ -760,8 +900,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
                                                           prv, mu_p, mc_p, nxt, mu_n, mc_n, r);
                 // ---- stage combination, projection, store -----------------------
                 T o0[N + 1], o1[N + 1], o2[N + 1];
-                load_operands<T, N, KIND, GS, LCP>(A, idx, withc, o0, o1, o2);
-                cell_combine<T, N, KIND, GS, SCP, FAST>(A, idx, withc, cur[k], r, o0, o1, o2, acc, cnt);
+                load_operands<T, N, KIND, GS, LCP, StageArgs<T>, GSS>(A, idx, withc, o0, o1, o2);
+                cell_combine<T, N, KIND, GS, SCP, FAST, GSS>(A, idx, withc, cur[k], r, o0, o1, o2, acc, cnt);
             });
             __syncthreads();  // plane z of LDS is read; the next plane may overwrite it
 
@@ -804,14 +944,15 @@ constexpr int min_waves_per_eu() {
 // One named kernel per stage kind, so that profiles separate them; NG is the
 // number of buffer groups of the vectors (1, 2 or 4).
 #define PF_STAGE_KERNEL(name, kind)                                                         \
-    template <typename T, int DIM, int N, int NG, bool WALLS>                              \
+    template <typename T, int DIM, int N, int NG, bool WALLS, bool SPARSE = false>         \
     __global__ void __launch_bounds__(256)                                                 \
         __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, DIM, N>(), 8)))             \
         name(const StageArgs<T> A) {                                                       \
         __shared__ T lds[lds_elems<T, N, DIM>()];                                          \
         __shared__ T pair[3 * N * N];                                                      \
         __shared__ T kc[4 * N];                                                            \
-        stage_body<T, DIM, N, kind, group_planes(N, NG), true, WALLS>(                     \
+        stage_body<T, DIM, N, kind, group_planes(N, NG), true, WALLS,                      \
+                   SPARSE ? group_planes(SPMAX, NG) : 0>(                                  \
             A, tile_index(xcd_logical_block(), A.ntx, A.nty), lds, pair, kc);              \
     }
 PF_STAGE_KERNEL(rhs_kernel, K_RHS)
@@ -1216,8 +1357,32 @@ __global__ void __launch_bounds__(P3_THREADS) rkl2_pair3_kernel(const StageArgs<
     rkl2_pair3_tile<T, N, group_planes(N, NG)>(A, t, la, lb, pair, kc);
 }
 
+// Stage kinds built for sparse phase storage (forward Euler, RKL1 and RKL2
+// fixed steps and the RHS), periodic grids, one or two buffer groups.
+template <typename T, int DIM, int N, int NG>
+hipError_t launch_stage_sparse(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
+    if constexpr (NG > 2) {
+        return hipErrorInvalidValue;
+    } else {
+        const dim3 grid(nblocks), block(256);
+        switch (A.kind) {
+        case K_RHS: hipLaunchKernelGGL((rhs_kernel<T, DIM, N, NG, false, true>), grid, block, 0, stream, A); break;
+        case K_EULER: hipLaunchKernelGGL((euler_stage_kernel<T, DIM, N, NG, false, true>), grid, block, 0, stream, A); break;
+        case K_RKL1: hipLaunchKernelGGL((rkl1_stage_kernel<T, DIM, N, NG, false, true>), grid, block, 0, stream, A); break;
+        case K_RKL2_FIRST: hipLaunchKernelGGL((rkl2_first_stage_kernel<T, DIM, N, NG, false, true>), grid, block, 0, stream, A); break;
+        case K_RKL2: hipLaunchKernelGGL((rkl2_stage_kernel<T, DIM, N, NG, false, true>), grid, block, 0, stream, A); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+}
+
 template <typename T, int DIM, int N, int NG, bool W>
 hipError_t launch_stage_dnw(const StageArgs<T> &A, int nblocks, hipStream_t stream) {
+    if (A.n_p > 0) {
+        if constexpr (W) return hipErrorInvalidValue;
+        else return launch_stage_sparse<T, DIM, N, NG>(A, nblocks, stream);
+    }
     const dim3 grid(nblocks), block(256);
     switch (A.kind) {
     case K_RHS: hipLaunchKernelGGL((rhs_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;

@@ -63,13 +63,20 @@ def test_stage_kernels_do_not_spill(tmp_path):
             assert r.get("VGPRs Spill", 0) == 0, (n, g, k, r)
             # single precision: no SGPR spills either, except in the 3D fused
             # stage pair (an autotuner candidate, off by default), whose six
-            # vectors' buffer descriptors per group fill the scalar file: at
-            # two groups a few spill into vector lanes (never to memory)
-            if "IfLi" in k and "rkl2_pair3_kernel" not in k:
+            # vectors' buffer descriptors per group fill the scalar file, and
+            # in the sparse-storage instances (last template flag set), which
+            # add the id-word bases of four vectors: a few spill into vector
+            # lanes (never to memory)
+            sparse = "Lb1EEEvNS" in k
+            if "IfLi" in k and "rkl2_pair3_kernel" not in k and not sparse:
                 assert r.get("SGPRs Spill", 0) == 0, (n, g, k, r)
         # batch kernels (built with one group), per precision: forward Euler at
         # depth 1, the two RKL2 stage kinds, the error estimate, and forward
         # Euler at depth 2 where it is built
+        # sparse phase storage: RHS, Euler, RKL1 and both RKL2 stage kinds
+        # x {float, double} x {2D, 3D}, for one and two buffer groups
+        sp = [k for k in names if "Lb1EEEvNS" in k]
+        assert len(sp) == (5 * 2 * 2 if g <= 2 else 0), (n, g, sorted(sp))
         batch = [k for k in names if "batch_kernel" in k]
         expect = 8 + sum(_depth2_fits(esz, n) for esz in (4, 8))
         assert len(batch) == (expect if g == 1 else 0), (n, g, batch)
