@@ -303,8 +303,11 @@ def batch_bench(args):
     value = cells * nsteps / (total / args.steps) / 1e9
     E = 4 if args.prec == "fp32" else 8
     F = wls[0].F
-    # one launch reads the state once and writes it once, for `depth` steps
-    bytes_per_launch = 2 * F * E * cells
+    # algorithmic bytes: 2 F E per cell and forward-Euler step, times the
+    # cell-steps of one launch (depth steps); the fused launch itself reads
+    # the state once and writes it once
+    bytes_per_launch = 2 * F * E * cells * depth
+    min_bytes_per_launch = 2 * F * E * cells
     launches = -(-nsteps // depth)
     avg_s = ev_ms / args.steps / launches / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
@@ -343,6 +346,9 @@ def batch_bench(args):
                      "kernel": f"batch_kernel (forward Euler, depth {depth}), avg {avg_s * 1e6:.2f} us per launch "
                                f"of {depth} step(s) (HIP events over graph replays), "
                                f"{bytes_per_launch} algorithmic B/launch",
+                     "steps_per_launch": depth,
+                     "fused_min_bytes_per_launch": min_bytes_per_launch,
+                     "frac_of_fused_min": round(min_bytes_per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4),
                      "stream_ref_GBs": sref,
                      "frac_of_stream_copy": round(achieved / sref["copy"], 4) if sref else None},
     }
@@ -513,10 +519,13 @@ def main():
         key = f"rkl1_stages/{wl.name}/{args.prec}"
         kname = f"rkl1 stages (euler first stage + rkl1_stage_kernel), {n_rkl2} launches"
     elif fusion == 2:
-        # two stages per launch: Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j, Y_{j+1} out
-        bytes_per_launch = 6 * wl.F * E * wl.cells
+        # two stages per launch: 5 F E per cell and stage times two stages; the
+        # fused launch itself reads Y_{j-1}, Y_{j-2}, Y_0, R_0 and writes Y_j,
+        # Y_{j+1} once (6 F E per cell)
+        bytes_per_launch = 10 * wl.F * E * wl.cells
         key = f"rkl2_pair/{wl.name}/{args.prec}"
-        kname = f"rkl2_pair_kernel (RKL2 stages j, j + 1 fused), {n_rkl2} launches"
+        kname = (f"rkl2_pair{'3' if wl.dim == 3 else ''}_kernel (RKL2 stages j, j + 1 fused), "
+                 f"{n_rkl2} launches")
     else:
         bytes_per_launch = 5 * wl.F * E * wl.cells      # Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j out
         key = f"rkl2_stage/{wl.name}/{args.prec}"
@@ -554,6 +563,11 @@ def main():
                      "kernel": f"{kname}, avg {avg_s * 1e6:.2f} us (HIP events), "
                                f"{bytes_per_launch} algorithmic B/launch",
                      "stages_per_launch": 2 if (fusion == 2 and not rkl1) else 1,
+                     "fused_min_bytes_per_launch": (6 * wl.F * E * wl.cells
+                                                    if (fusion == 2 and not rkl1) else bytes_per_launch),
+                     "frac_of_fused_min": round((6 * wl.F * E * wl.cells if (fusion == 2 and not rkl1)
+                                                 else bytes_per_launch) / max(avg_s, 1e-12) / 1e9
+                                                / HBM_PEAK_GBS, 4),
                      "us_per_stage": round(avg_s * 1e6 / (2 if (fusion == 2 and not rkl1) else 1), 3),
                      "stream_ref_GBs": sref,
                      "frac_of_stream_4r1w": round(achieved / sref["4r1w"], 4) if sref else None},

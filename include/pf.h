@@ -237,7 +237,9 @@ pf_status pf_error_norm_device(pf_sim *sim, int kind, double dt, const void *u_o
  * each GPU the library runs on until the process ends) instead of memory the
  * handle allocates, and it creates no timing events.  It calls no hipMalloc,
  * hipFree or other allocating routine.  Limit: kind 0 needs one partial per
- * tile (64 x 4 cells times the z extent of pf_set_tiling), at most 131072;
+ * tile of the stage kernels (64 x 4 cells times the z extent of
+ * pf_set_tiling in 3D; 64 x 8 cells in 2D with N <= 4, else 64 x 4), at most
+ * 131072;
  * kind 1 needs 1024.  A larger request returns PF_EINVAL and launches
  * nothing.  Every call on one GPU uses that GPU's one array, so calls that
  * overlap on a GPU (other threads, other streams) race and must be

@@ -172,7 +172,7 @@ int work_index(const pf_sim *s, int k) {
 }
 
 void tiles(const pf_sim *s, int &ntx, int &nty, int &nzc, int &ntiles, int &nblocks) {
-    const int tx = s->tx, ty = tile_rows(s->dim);
+    const int tx = s->tx, ty = tile_rows(s->dim, s->N);
     ntx = (s->nx + tx - 1) / tx;
     nty = (s->ny + ty - 1) / ty;
     nzc = s->dim == 3 ? (s->nz + s->zchunk - 1) / s->zchunk : 1;
@@ -498,7 +498,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     int ntx, nty, nzc, ntiles, nblocks;
     tiles(s, ntx, nty, nzc, ntiles, nblocks);
     A.tx = s->tx;
-    A.ty = tile_rows(s->dim);
+    A.ty = tile_rows(s->dim, s->N);
     A.zchunk = s->zchunk;
     A.ntx = ntx;
     A.nty = nty;
@@ -614,7 +614,7 @@ pf_status error_norm_with(pf_sim *s, int kind, double dt, const T *uold, const T
         A.r_c = (T)tol.r_c; A.a_c = (T)tol.a_c;
         A.dt6 = (T)(6.0 * dt);
         A.hdt = (T)(dt / 2.0);
-        A.tx = s->tx; A.ty = tile_rows(s->dim); A.zchunk = s->zchunk;
+        A.tx = s->tx; A.ty = tile_rows(s->dim, s->N); A.zchunk = s->zchunk;
         A.ntx = ntx; A.nty = nty; A.nzc = nzc; A.ntiles = ntiles;
         begin_timed(s, FAM_EST, p);
         hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
@@ -1363,10 +1363,10 @@ pf_status pf_error_norm_device_noalloc(pf_sim *s, int kind, double dt, const voi
     const size_t cnt_off = (nred * sizeof(double) + 255) / 256 * 256;
     if (cnt_off + nred * sizeof(long long) > SCRATCH_BYTES)
         return fail(s, PF_EINVAL,
-                    "%zu partial sums (one per tile of 64 x 4 cells and z extent %d) exceed the "
+                    "%zu partial sums (one per tile of 64 x %d cells and z extent %d) exceed the "
                     "static scratch of %zu bytes (at most %zu); use a larger z extent "
                     "(pf_set_tiling) or pf_error_norm_device",
-                    nred, s->zchunk, (size_t)SCRATCH_BYTES,
+                    nred, tile_rows(s->dim, s->N), s->dim == 3 ? s->zchunk : 1, (size_t)SCRATCH_BYTES,
                     (size_t)SCRATCH_BYTES / (sizeof(double) + sizeof(long long)));
     void *base = nullptr;
     HIPCHK(s, scratch_address(&base));
@@ -2381,7 +2381,7 @@ pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out) {
         b->total += (long long)b->meta[i].F * b->meta[i].V;
         b->total = (b->total + 63) / 64 * 64;  // 256-byte aligned instance starts
         b->ntx[i] = (b->meta[i].nx + TILE_X - 1) / TILE_X;
-        b->nty[i] = (b->meta[i].ny + tile_rows(2) - 1) / tile_rows(2);
+        b->nty[i] = (b->meta[i].ny + tile_rows(2, b->meta[i].N) - 1) / tile_rows(2, b->meta[i].N);
         b->tile0[i] = b->total_tiles;
         b->total_tiles += b->ntx[i] * b->nty[i];
         tile_inst.insert(tile_inst.end(), (size_t)b->ntx[i] * b->nty[i], i);

@@ -9,13 +9,16 @@ namespace pf {
 constexpr int NMAX = 16;  // largest number of order parameters a kernel is built for
 constexpr int TMAX = 4;   // largest number of thermodynamic types
 constexpr int TILE_X = 64, TILE_Y = 4;  // 256 threads: one wavefront per row of 64 cells
-// Cells per thread in y of a 2D tile: the tile is 64 x (4 ROWS2D) cells, each
-// thread computing ROWS2D cells of one column.  Two rows halve the barriers
-// and the halo share per cell; they gained 3% on the two-phase batch but
-// double the registers of the eight-phase kernels, so one row is built.  A 3D
-// tile is 64 x 4 cells marched in z.
-constexpr int ROWS2D = 1;
-constexpr int tile_rows(int dim) { return dim == 2 ? TILE_Y * ROWS2D : TILE_Y; }
+// Cells per thread in y of a 2D tile with n order parameters: the tile is
+// 64 x (4 rows2d(n)) cells, each thread computing rows2d(n) cells of one
+// column.  Two rows halve the barriers and the halo share per cell (the halo
+// is loaded and its mu and Mc computed by the same 256 threads); for few
+// fields that is instruction time saved, while for eight or more fields the
+// second row's values cost the kernels a wave per SIMD, so they keep one row.
+// A 3D tile is 64 x 4 cells marched in z.
+constexpr int ROWS2D_MAX_N = 4;
+constexpr int rows2d(int n) { return n <= ROWS2D_MAX_N ? 2 : 1; }
+constexpr int tile_rows(int dim, int n) { return dim == 2 ? TILE_Y * rows2d(n) : TILE_Y; }
 // Largest number of order parameters built with stage-fusion depth 2.
 constexpr int DEPTH2_MAX_N = 4;
 
@@ -117,7 +120,7 @@ struct StageArgs {
     // estimator
     T r_phi, a_phi, r_c, a_c, dt6, hdt;
     // tiling
-    int tx, ty;      // tile of tx columns and ty rows (tile_rows(dim)), one block of 256 threads
+    int tx, ty;      // tile of tx columns and ty rows (tile_rows(dim, N)), one block of 256 threads
     int zchunk;      // z planes per block (3D)
     int ntx, nty, nzc;
     int ntiles;
@@ -186,10 +189,11 @@ struct BatchInst {
 // built for few-field instances only (N <= DEPTH2_MAX_N): a thread holds
 // N + 1 values of up to three region cells at once, which above that leaves
 // one wave per SIMD.
-constexpr int F2_IN_X = TILE_X + 4, F2_IN = F2_IN_X * (tile_rows(2) + 4);
-constexpr int F2_MID_X = TILE_X + 2, F2_MID = F2_MID_X * (tile_rows(2) + 2);
+constexpr int F2_IN_X = TILE_X + 4, F2_MID_X = TILE_X + 2;
+constexpr int f2_in(int n) { return F2_IN_X * (tile_rows(2, n) + 4); }
+constexpr int f2_mid(int n) { return F2_MID_X * (tile_rows(2, n) + 2); }
 constexpr bool batch_depth2_fits(int esz, int n) {
-    return n <= DEPTH2_MAX_N && esz * ((n + 3) * (F2_IN + F2_MID) + 3 * n * n + 4 * n) <= 65536;
+    return n <= DEPTH2_MAX_N && esz * ((n + 3) * (f2_in(n) + f2_mid(n)) + 3 * n * n + 4 * n) <= 65536;
 }
 
 // Fused RKL2 stage pairs (2D): a block of P2_THREADS threads computes a tile

@@ -759,7 +759,7 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
 // buffer group of the vectors (see set_field_bases).  TABLES: stage the LDS
 // tables of A.P first (false: the caller has staged them).  t: the tile's
 // index and coordinates (tile_index, or kept by a caller that walks tiles).
-// The tile is 64 x TY cells, TY = tile_rows(DIM); thread (lx, ly) computes the
+// The tile is 64 x TY cells, TY = tile_rows(DIM, N); thread (lx, ly) computes the
 // R = TY / 4 cells (lx, ly + 4 k) of its column (3D: R = 1, marched in z).
 template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true, bool WALLS = false,
           int GSS = 0>
@@ -769,7 +769,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
     constexpr int LCP = operand_load_cp<DIM>(), SCP = out_store_cp<DIM>();
     // the tile shape is fixed at compile time (one wavefront per row) so that
     // every LDS plane offset is an instruction immediate
-    constexpr int TX = TILE_X, TY = tile_rows(DIM), R = TY / TILE_Y;
+    constexpr int TX = TILE_X, TY = tile_rows(DIM, N), R = TY / TILE_Y;
     constexpr int TXH = TX + 2, TYH = TY + 2;
     constexpr int plane_sz = TXH * TYH;
     static_assert(DIM == 2 || R == 1, "3D tiles march one row set in z");
@@ -930,7 +930,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
 
 // LDS per block: (N + 2) planes of (TILE_X + 2) x (tile rows + 2) values.
 template <typename T, int N, int DIM>
-constexpr int lds_elems() { return (N + 2) * (TILE_X + 2) * (tile_rows(DIM) + 2); }
+constexpr int lds_elems() { return (N + 2) * (TILE_X + 2) * (tile_rows(DIM, N) + 2); }
 
 // Occupancy hint: the single-precision 3D kernels with up to 9 order
 // parameters fit three wavefronts per SIMD (<= 168 VGPRs) without scratch;
@@ -1460,20 +1460,20 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const TileIdx
     const KConsts<T> &P = A.K;
     const int nx = P.nx, ny = P.ny;
     const bool withc = P.with_c != 0;
-    constexpr int TY = tile_rows(2), R = TY / TILE_Y;  // tile height, cells per thread
+    constexpr int TY = tile_rows(2, N), R = TY / TILE_Y;  // tile height, cells per thread
     const int tix = t.tix, tiy = t.tiy;
     const int x0 = tix * TILE_X - 2, y0 = tiy * TY - 2;  // corner of the input region
     const bool fits = wrap_fits(A.ntx, TILE_X, nx) && wrap_fits(A.nty, TY, ny);
 
     // input region: every load is issued before the first use of one
-    constexpr int NP0 = (F2_IN + 255) / 256;
+    constexpr int NP0 = (f2_in(N) + 255) / 256;
     T v[NP0][N + 1];
     auto load_region = [&](auto general) __attribute__((always_inline)) {
         constexpr bool G = decltype(general)::value;
 #pragma unroll
         for (int k = 0; k < NP0; ++k) {
             const int p = threadIdx.x + 256 * k;
-            if (p < F2_IN) {
+            if (p < f2_in(N)) {
                 const int px = p % F2_IN_X, py = p / F2_IN_X;
                 const long long col = (long long)wrap_index<G>(y0 + py, ny) * nx + wrap_index<G>(x0 + px, nx);
                 load_point32<T, N, N + 1>(A, 0, (unsigned)col * (unsigned)sizeof(T), withc, v[k]);
@@ -1487,14 +1487,14 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const TileIdx
 #pragma unroll
     for (int k = 0; k < NP0; ++k) {
         const int p = threadIdx.x + 256 * k;
-        if (p < F2_IN) {
+        if (p < f2_in(N)) {
             T mu = T(0), mc = T(0);
             if (withc) point_mu_mc<T, N, FAST>(P, kc, v[k], mu, mc);
 #pragma unroll
-            for (int a = 0; a < N; ++a) in[a * F2_IN + p] = v[k][a];
-            in[N * F2_IN + p] = mu;
-            in[(N + 1) * F2_IN + p] = mc;
-            in[(N + 2) * F2_IN + p] = v[k][N];
+            for (int a = 0; a < N; ++a) in[a * f2_in(N) + p] = v[k][a];
+            in[N * f2_in(N) + p] = mu;
+            in[(N + 1) * f2_in(N) + p] = mc;
+            in[(N + 2) * f2_in(N) + p] = v[k][N];
         }
     }
     __syncthreads();
@@ -1505,32 +1505,32 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const TileIdx
     if (!two) {
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            euler_point<T, N, FAST, F2_IN, F2_IN_X>(P, in, pair, kc,
+            euler_point<T, N, FAST, f2_in(N), F2_IN_X>(P, in, pair, kc,
                                                     (ly + TILE_Y * k + 2) * F2_IN_X + (lx + 2), dt1, y[k]);
     } else {
         // first step on the tile and its one-cell ring
-        constexpr int NP1 = (F2_MID + 255) / 256;
+        constexpr int NP1 = (f2_mid(N) + 255) / 256;
 #pragma unroll
         for (int k = 0; k < NP1; ++k) {
             const int q = threadIdx.x + 256 * k;
-            if (q < F2_MID) {
+            if (q < f2_mid(N)) {
                 const int qx = q % F2_MID_X, qy = q / F2_MID_X;
                 T w[N + 1];
-                euler_point<T, N, FAST, F2_IN, F2_IN_X>(P, in, pair, kc, (qy + 1) * F2_IN_X + (qx + 1),
+                euler_point<T, N, FAST, f2_in(N), F2_IN_X>(P, in, pair, kc, (qy + 1) * F2_IN_X + (qx + 1),
                                                         dt1, w);
                 T mu = T(0), mc = T(0);
                 if (withc) point_mu_mc<T, N, FAST>(P, kc, w, mu, mc);
 #pragma unroll
-                for (int a = 0; a < N; ++a) mid[a * F2_MID + q] = w[a];
-                mid[N * F2_MID + q] = mu;
-                mid[(N + 1) * F2_MID + q] = mc;
-                mid[(N + 2) * F2_MID + q] = w[N];
+                for (int a = 0; a < N; ++a) mid[a * f2_mid(N) + q] = w[a];
+                mid[N * f2_mid(N) + q] = mu;
+                mid[(N + 1) * f2_mid(N) + q] = mc;
+                mid[(N + 2) * f2_mid(N) + q] = w[N];
             }
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < R; ++k)
-            euler_point<T, N, FAST, F2_MID, F2_MID_X>(P, mid, pair, kc,
+            euler_point<T, N, FAST, f2_mid(N), F2_MID_X>(P, mid, pair, kc,
                                                       (ly + TILE_Y * k + 1) * F2_MID_X + (lx + 1), dt2, y[k]);
     }
 #pragma unroll
@@ -1549,7 +1549,7 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const TileIdx
 // LDS of the batched kernel for a fusion depth.
 template <typename T, int N, int DEPTH>
 constexpr int batch_lds_elems() {
-    return DEPTH == 1 ? lds_elems<T, N, 2>() : (N + 3) * (F2_IN + F2_MID);
+    return DEPTH == 1 ? lds_elems<T, N, 2>() : (N + 3) * (f2_in(N) + f2_mid(N));
 }
 
 // Batched stages over many independent 2D instances.  A persistent grid splits
@@ -1652,7 +1652,7 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
             A.gb[4][0] = A.out;
             A.kind = KIND;
             A.tx = TILE_X;
-            A.ty = tile_rows(2);
+            A.ty = tile_rows(2, N);
             A.zchunk = 1;
             A.ntx = I.ntx;
             A.nty = I.nty;
@@ -1664,7 +1664,7 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
             __syncthreads();
         }
         if constexpr (KIND == K_EULER && DEPTH == 2)
-            euler2_tile<T, N>(A, t, lds, lds + (N + 3) * F2_IN, pair, kc, A.a, dt2, two);
+            euler2_tile<T, N>(A, t, lds, lds + (N + 3) * f2_in(N), pair, kc, A.a, dt2, two);
         else
             stage_body<T, 2, N, KIND, N + 1, false>(A, t, lds, pair, kc);
         ++t.L;

@@ -117,20 +117,21 @@ def test_batch_autotune_keeps_state():
 
 
 def test_batch_fusion_depth_limits():
-    """Depth 2 is built for N <= 4, where (N + 3) LDS planes of the two
-    regions fit one workgroup: N = 2 and 4 take it in both precisions; N = 8
-    and 9 are refused; bad depths are refused."""
+    """Depth 2 is built for N <= 4 where (N + 3) LDS planes of the two regions
+    of a 64 x 8 tile fit one workgroup's 64 KiB: N = 2 in both precisions and
+    N = 4 in single precision take it; N = 4 in double precision, N = 8 and 9
+    are refused; bad depths are refused."""
     def batch(n_phi, prec):
         wl = pi.voronoi_2d(n=64, n_grains=2 * n_phi, n_phi=n_phi, dmin=5.0)
         return pf.Batch([wl.param_dict()], prec=prec)
-    for n_phi, prec in [(9, "fp32"), (8, "fp64"), (8, "fp32")]:
+    for n_phi, prec in [(9, "fp32"), (8, "fp64"), (8, "fp32"), (4, "fp64")]:
         b = batch(n_phi, prec)
         with pytest.raises(pf.PFError) as e:
             b.set_fusion(2)
         assert e.value.code == -7, (n_phi, prec)
         assert b.config()[1] == 1
         b.close()
-    for n_phi, prec in [(4, "fp32"), (4, "fp64"), (2, "fp64")]:
+    for n_phi, prec in [(4, "fp32"), (2, "fp32"), (2, "fp64")]:
         b = batch(n_phi, prec)
         b.set_fusion(2)
         with pytest.raises(pf.PFError):

@@ -104,6 +104,7 @@ def _depth2_fits(esz, n):
     txt = open(os.path.join(ROOT, "paper_2601_16522_amd", "csrc", "pf_internal.h")).read()
     if n > int(re.search(r"constexpr int DEPTH2_MAX_N = (\d+);", txt).group(1)):
         return False
-    ty = 4 * int(re.search(r"constexpr int ROWS2D = (\d+);", txt).group(1))
+    rows = 2 if n <= int(re.search(r"constexpr int ROWS2D_MAX_N = (\d+);", txt).group(1)) else 1
+    ty = 4 * rows
     f2 = 68 * (ty + 4) + 66 * (ty + 2)
     return esz * ((n + 3) * f2 + 3 * n * n + 4 * n) <= 65536

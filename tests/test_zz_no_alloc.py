@@ -52,10 +52,13 @@ def test_noalloc_norm_equals_device_norm(prec):
 
 
 def test_noalloc_norm_refuses_more_partials_than_the_scratch_holds():
-    # 2 x 65537 tiles of 64 x 4 cells: one more partial than 2 MiB holds
-    p = dict(pi.single_grain(n=128, R=30.0).param_dict())
-    p["ny"] = 4 * 65537
+    # 2 x 65537 tiles of 64 x 4 cells at z extent 1: two more partials than
+    # 2 MiB holds
+    p = dict(pi.grains_pores_3d(n=16, n_grains=2, n_grain_fields=1, n_pores=1,
+                                r_range=(2.0, 3.0), dmin=4.0).param_dict())
+    p.update(nx=128, ny=4, nz=65537)
     sim = pf.Sim(p, prec="fp32")
+    sim.set_tiling(64, 1)
     vec = sim.empty_device()
     tol = pf.Tol()
     with pytest.raises(pf.PFError) as ei:
