@@ -86,7 +86,7 @@ typedef struct {
     const double *D;       /* [n_types] diffusivities */
     int with_c;            /* 0: phase-field only (no c plane, no chemical term) */
     pf_precision prec;
-    int ssp_stages;        /* s of SSP(s)2, >= 2 */
+    int ssp_stages;        /* s of SSP(s)2, >= 2 (0 selects 5) */
     /* Boundaries (Sec. 4: periodic unless stated).  bc[axis] (x, y, z): 0
      * periodic, 1 walls where phi and c have zero gradient (the neighbour
      * beyond a wall is the wall cell).  c_fixed[face] (faces x-, x+, y-, y+,
@@ -122,7 +122,9 @@ typedef struct {
  * planes, each group spanning less than 4 GiB (FP32 512^3 with N = 9 needs
  * two, FP64 four).  Walls need vectors that fit one group (else
  * PF_EUNSUPPORTED); walls on z of a 2D grid, bc values other than 0 and 1,
- * and a fixed c on a periodic axis, without c or not finite, are PF_EINVAL. */
+ * and a fixed c on a periodic axis, without c or not finite, are PF_EINVAL,
+ * and so are pair tables that are not symmetric, finite and non-negative,
+ * k <= 0, non-finite c0 or D, D < 0 and ssp_stages 1 or negative. */
 pf_status pf_create(const pf_params *p, pf_sim **out);
 pf_status pf_destroy(pf_sim *sim);
 

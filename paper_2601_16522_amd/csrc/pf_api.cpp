@@ -1080,8 +1080,19 @@ pf_status init_meta(pf_sim *s, const pf_params *p) {
     }
     for (int a = 0; a < p->n_phi; ++a)
         if (p->type_of[a] < 0 || p->type_of[a] >= p->n_types) return PF_EINVAL;
-    for (int t = 0; t < p->n_types; ++t)
-        if (!(p->k[t] > 0)) return PF_EINVAL;
+    // pair tables symmetric, finite and non-negative; per-type constants finite
+    const int TN = p->n_types;
+    for (int i = 0; i < TN; ++i)
+        for (int j = 0; j < TN; ++j) {
+            const double g = p->gamma[i * TN + j], m = p->mob[i * TN + j];
+            if (!std::isfinite(g) || !std::isfinite(m) || g < 0 || m < 0) return PF_EINVAL;
+            if (g != p->gamma[j * TN + i] || m != p->mob[j * TN + i]) return PF_EINVAL;
+        }
+    for (int t = 0; t < TN; ++t)
+        if (!(p->k[t] > 0) || !std::isfinite(p->k[t]) || !std::isfinite(p->c0[t]) ||
+            !std::isfinite(p->D[t]) || p->D[t] < 0)
+            return PF_EINVAL;
+    if (p->ssp_stages < 0 || p->ssp_stages == 1) return PF_EINVAL;
     // boundaries: walls per axis, fixed c only on the faces of walled axes
     int walls = 0, cfix = 0;
     for (int a = 0; a < 3; ++a) {
@@ -1577,7 +1588,7 @@ pf_status pf_set_state(pf_sim *s, const void *buf, size_t len) {
 
 pf_status pf_set_tiling(pf_sim *s, int tx, int zchunk) {
     if (!s) return PF_EINVAL;
-    if (tx != 64) return fail(s, PF_EINVAL, "tx must be 64 (the tile is 64 x 4 cells)");
+    if (tx != 64) return fail(s, PF_EINVAL, "tx must be 64 (tiles are 64 cells wide)");
     if (zchunk < 1) return fail(s, PF_EINVAL, "zchunk must be >= 1");
     s->tx = tx;
     s->zchunk = zchunk;

@@ -243,7 +243,14 @@ batch_accept_kernel(const T *src, T *dst, const long long *off, const long long 
 // Dispatch over the compiled (dim, N) instances
 // ------------------------------------------------------------------------
 
+// The build may compile a subset (a debug library): -D'PF_NPHI_LIST(X)=...'
+// and -D'PF_NG_LIST(X)=...' then name the instances it links.
+#ifndef PF_NPHI_LIST
 #define PF_NPHI_LIST(X) X(2) X(3) X(4) X(8) X(9) X(13)
+#endif
+#ifndef PF_NG_LIST
+#define PF_NG_LIST(X) X(1) X(2) X(4)
+#endif
 
 // defined in pf_stage_inst.hip, one object per (N, number of buffer groups)
 #define PF_DECLG(n, g)                                                                       \
@@ -285,18 +292,21 @@ int supported_nphi_list(int *out, int cap) {
     return n;
 }
 
+template <typename T, int N>
+hipError_t launch_stage_g(int dim, const StageArgs<T> &args, int nblocks, hipStream_t stream) {
+    switch (args.ng) {
+#define PF_CASE(g) case g: return launch_stage_n<T, N, g>(dim, args, nblocks, stream);
+        PF_NG_LIST(PF_CASE)
+#undef PF_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_stage(int dim, int nphi, const StageArgs<T> &args, int nblocks,
                         hipStream_t stream) {
     switch (nphi) {
-#define PF_CASE(n)                                                                  \
-    case n:                                                                         \
-        switch (args.ng) {                                                          \
-        case 1: return launch_stage_n<T, n, 1>(dim, args, nblocks, stream);         \
-        case 2: return launch_stage_n<T, n, 2>(dim, args, nblocks, stream);         \
-        case 4: return launch_stage_n<T, n, 4>(dim, args, nblocks, stream);         \
-        default: return hipErrorInvalidValue;                                       \
-        }
+#define PF_CASE(n) case n: return launch_stage_g<T, n>(dim, args, nblocks, stream);
         PF_NPHI_LIST(PF_CASE)
 #undef PF_CASE
     default: return hipErrorInvalidValue;

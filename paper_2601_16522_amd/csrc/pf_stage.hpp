@@ -260,6 +260,22 @@ __device__ __forceinline__ int xcd_logical_block() {
     return (b & 7) * per + (b >> 3);
 }
 
+// Debug builds (-DPF_POISON_LDS) fill an LDS region with NaN before the block
+// writes it: a read of an element that no thread wrote for the current tile
+// or plane then carries NaN into the results, where a comparison with the
+// oracle or the non-finite count sees it.  Every thread of the block calls it
+// (it ends with a barrier); in ordinary builds it is empty.
+template <typename T>
+__device__ __forceinline__ void poison_lds(T *p, int n) {
+#ifdef PF_POISON_LDS
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = T(__builtin_nan(""));
+    __syncthreads();
+#else
+    (void)p;
+    (void)n;
+#endif
+}
+
 // Pair constants A, B, L (N x N each) and the per-phase constants (rows c0,
 // 1/k, D/k, 1/(2k)) of one simulation into LDS: the pairwise sums and the
 // fast mu then read them without holding N^2 scalar registers.  The caller
@@ -869,6 +885,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
             }
 
             // ---- stage plane z in LDS ---------------------------------------
+            poison_lds(lds, (N + 2) * plane_sz);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
 #pragma unroll
@@ -951,6 +968,8 @@ constexpr int min_waves_per_eu() {
         __shared__ T lds[lds_elems<T, N, DIM>()];                                          \
         __shared__ T pair[3 * N * N];                                                      \
         __shared__ T kc[4 * N];                                                            \
+        poison_lds(pair, 3 * N * N);                                                       \
+        poison_lds(kc, 4 * N);                                                             \
         stage_body<T, DIM, N, kind, group_planes(N, NG), true, WALLS,                      \
                    SPARSE ? group_planes(SPMAX, NG) : 0>(                                  \
             A, tile_index(xcd_logical_block(), A.ntx, A.nty), lds, pair, kc);              \
@@ -1141,6 +1160,10 @@ __global__ void __launch_bounds__(P2_THREADS) __attribute__((amdgpu_waves_per_eu
     __shared__ T kc[4 * N];
     const TileIdx t = tile_index(xcd_logical_block(), A.ntx, A.nty);
     if (t.L >= A.ntiles) return;  // uniform over the block
+    poison_lds(in, (N + 3) * P2_IN);
+    poison_lds(mid, (N + 2) * P2_MID);
+    poison_lds(pair, 3 * N * N);
+    poison_lds(kc, 4 * N);
     rkl2_pair_tile<T, N>(A, t, in, mid, pair, kc);
 }
 
@@ -1267,6 +1290,7 @@ __device__ __forceinline__ void rkl2_pair3_tile(const StageArgs<T> &A, const Til
         // them a whole march step ahead measured slower)
         T u0o[N + 1], y2o[N + 1], r0o[N + 1];
         if (hasM) load_operands<T, N, K_RKL2, GS, LCP>(A, ok, withc, u0o, y2o, r0o);
+        poison_lds(la, (N + 2) * P3_I);
         if (hasI) {
 #pragma unroll
             for (int a = 0; a < N; ++a) la[a * P3_I + sI] = cur[a];
@@ -1312,6 +1336,7 @@ __device__ __forceinline__ void rkl2_pair3_tile(const StageArgs<T> &A, const Til
             }
         }
         __syncthreads();  // both LDS planes are read; the next step may overwrite them
+        poison_lds(lb, (N + 2) * P3_M);
         if (hasM) {
 #pragma unroll
             for (int a = 0; a < N; ++a) lb[a * P3_M + sM] = yj[a];
@@ -1354,6 +1379,9 @@ __global__ void __launch_bounds__(P3_THREADS) rkl2_pair3_kernel(const StageArgs<
     __shared__ T kc[4 * N];
     const TileIdx t = tile_index(xcd_logical_block(), A.ntx, A.nty);
     if (t.L >= A.ntiles) return;  // uniform over the block
+    poison_lds(lb, (N + 2) * P3_M);
+    poison_lds(pair, 3 * N * N);
+    poison_lds(kc, 4 * N);
     rkl2_pair3_tile<T, N, group_planes(N, NG)>(A, t, la, lb, pair, kc);
 }
 
@@ -1465,6 +1493,8 @@ __device__ __forceinline__ void euler2_tile(const StageArgs<T> &A, const TileIdx
     const int x0 = tix * TILE_X - 2, y0 = tiy * TY - 2;  // corner of the input region
     const bool fits = wrap_fits(A.ntx, TILE_X, nx) && wrap_fits(A.nty, TY, ny);
 
+    poison_lds(in, (N + 3) * f2_in(N));
+    poison_lds(mid, (N + 3) * f2_mid(N));
     // input region: every load is issued before the first use of one
     constexpr int NP0 = (f2_in(N) + 255) / 256;
     T v[NP0][N + 1];
@@ -1578,6 +1608,8 @@ __global__ void __launch_bounds__(256) batch_kernel(const BatchArgs<T> B) {
     const int g0 = (int)(L * B.total_tiles / gridDim.x);
     const int g1 = (int)((L + 1) * B.total_tiles / gridDim.x);
     if (g0 >= g1) return;
+    poison_lds(pair, 3 * N * N);
+    poison_lds(kc, 4 * N);
     int i = B.tile_inst[g0] - 1;
     int tile0 = 0, end = g0;  // tiles [tile0, end) belong to instance i
     StageArgs<T> A = {};

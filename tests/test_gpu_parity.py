@@ -345,6 +345,34 @@ def test_error_paths():
     assert e.value.code == -1
 
 
+def test_step_underflow_keeps_the_last_accepted_state():
+    """A tolerance no step meets: every attempt is rejected until dt falls
+    below 1e-12 dt_e; the run then fails with PF_EDTMIN, as the oracle does,
+    with the fields and t of the last accepted state (here the initial one)."""
+    wl = pi.single_grain(n=16, R=5.0)
+    tol = pf.Tol(r_phi=1e-30, a_phi=1e-30, r_c=1e-30, a_c=1e-30)
+    _, st_o, rc = oracle.run_to(P_of(wl), oracle.RKL2, wl.u0, 50.0,
+                                tol=oracle.Tol(1e-30, 1e-30, 1e-30, 1e-30))
+    assert rc == -5
+    sim = make(wl)
+    with pytest.raises(pf.PFError) as e:
+        sim.run_to("rkl2", 50.0, tol=tol)
+    assert e.value.code == -5
+    u, t = sim.get_fields()
+    assert t == 0.0 and np.array_equal(u, wl.u0)
+    tr = sim.trace()
+    assert np.all(tr[:, 3] == 0) and np.all(np.isfinite(tr[:, 2]))
+    # the first attempts see the real error (equal to the oracle's); the
+    # controller sits on its limiter floor, so the attempt count matches
+    assert abs(len(tr) - len(st_o.trace)) <= 1
+    np.testing.assert_allclose(tr[:3, 0], st_o.trace[:3, 0], rtol=1e-9)
+    # the handle still works: the controller carried over holds the step that
+    # underflowed, so a new run with a reachable tolerance states its first step
+    dte = sim.stable_dt()
+    sim.run_to("rkl2", 5.0, tol=pf.Tol(dt0=0.9 * dte))
+    assert sim.get_fields()[1] == 5.0
+
+
 def test_nonfinite_state_is_reported():
     wl = pi.single_grain(n=32, R=10.0)
     u = wl.u0.copy()

@@ -858,3 +858,23 @@ def test_fixed_run_hits_t_end_exactly():
     u, st, rc = oracle.run_to(P, oracle.FE, wl.u0, 1.0, dt_fixed=0.225)
     assert rc == 0 and st.t == 1.0 and st.accepted == 5
     assert st.trace[-1, 0] == pytest.approx(1.0 - 4 * 0.225)
+
+
+def test_step_underflow_keeps_the_last_accepted_state():
+    """A tolerance no step can meet: the controller shrinks dt by its limiter
+    floor on every rejection (1 + 5 atan(-1/5) ~ 0.013) until dt < 1e-12 dt_e,
+    where the run stops with the underflow code (Sec. 5 controller; the stop is
+    reading R18 of the adaptive loop), the state and t untouched."""
+    wl = pi.single_grain(n=16, R=5.0)
+    P = oracle.Params(**wl.param_dict())
+    dte = oracle.stable_dt(P)
+    tol = oracle.Tol(r_phi=1e-30, a_phi=1e-30, r_c=1e-30, a_c=1e-30)
+    u, st, rc = oracle.run_to(P, oracle.RKL2, wl.u0, 50.0, tol=tol)
+    assert rc == -5
+    assert st.t == 0.0 and st.accepted == 0 and 5 <= st.rejected <= 12
+    assert np.array_equal(u, wl.u0)
+    # every attempt was rejected with a finite norm, each step <= 0.013x the last
+    dts = st.trace[:, 0]
+    assert np.all(np.isfinite(st.trace[:, 2])) and np.all(st.trace[:, 3] == 0)
+    assert np.all(dts[1:] <= 0.0135 * dts[:-1])
+    assert dts[-1] >= 1e-12 * dte and dts[-1] * 0.0135 < 1e-12 * dte
