@@ -97,16 +97,19 @@ def copy_calibration(mib: int, reps: int):
     print(json.dumps({"copy_calibration_bytes": 4 * n, "reps": reps}), flush=True)
 
 
-def stream_reference(vector_bytes: int):
+def stream_reference(vector_bytes: int, planes=None):
     """Streaming references at the stage's own footprint: the committed
     stream_ref program (built beside the library) run as a child process on
     vectors of `vector_bytes` bytes.  Returns GB/s of its 4-read-1-write,
-    copy and read-only kernels, or None when the program is not built."""
+    copy and read-only kernels, and with planes = (F, nx, ny) also of the
+    stage kernels' own access pattern (F planes per vector, 64 x 4 tiles
+    marched in z), or None when the program is not built."""
     exe = os.path.join(ROOT, "paper_2601_16522_amd", "stream_ref")
     if not os.path.exists(exe):
         return None
     n = max(1024, vector_bytes // 4)
-    r = subprocess.run([exe, str(n), "10"], capture_output=True, text=True, timeout=300)
+    extra = [str(v) for v in planes] if planes else []
+    r = subprocess.run([exe, str(n), "10", *extra], capture_output=True, text=True, timeout=300)
     if r.returncode != 0:
         print(f"# stream_ref failed: {r.stderr.strip()}", file=sys.stderr, flush=True)
         return None
@@ -511,7 +514,7 @@ def main():
     diag = sim.diagnostics()
 
     E = 8 if args.prec == "fp64" else 4
-    sref = stream_reference(wl.F * E * wl.cells)
+    sref = stream_reference(wl.F * E * wl.cells, (wl.F, wl.nx, wl.ny) if wl.dim == 3 and E == 4 else None)
     value = wl.cells * rhs / total / 1e9
     if rkl1:
         # stage 1 reads u and writes Y_1; stages j >= 2 read Y_{j-1}, Y_{j-2}, write Y_j
@@ -570,7 +573,9 @@ def main():
                                                 / HBM_PEAK_GBS, 4),
                      "us_per_stage": round(avg_s * 1e6 / (2 if (fusion == 2 and not rkl1) else 1), 3),
                      "stream_ref_GBs": sref,
-                     "frac_of_stream_4r1w": round(achieved / sref["4r1w"], 4) if sref else None},
+                     "frac_of_stream_4r1w": round(achieved / sref["4r1w"], 4) if sref else None,
+                     "frac_of_stream_4r1w_planes": (round(achieved / sref["4r1w_planes"], 4)
+                                                    if sref and "4r1w_planes" in sref else None)},
     }
     if args.workload == "gg3d" and not args.no_batch_leg:
         print("# batch leg: FP32 batched against FP64 per instance", file=sys.stderr, flush=True)

@@ -268,9 +268,11 @@ pf_status pf_get_trace(pf_sim *sim, double *buf, long long cap, long long *n);
 pf_status pf_get_state(pf_sim *sim, void *buf, size_t *len);
 pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
 
-/* Launch shape of the stencil kernels: tile width tx (64 cells in x: the
- * block is 256 threads over 64 x 4 cells) and the number of z planes a block
- * marches through (3D only, >= 1).  pf_autotune times the RKL2 inner stage at
+/* Launch shape of the stencil kernels: the tile width tx (fixed by the
+ * build: 64 cells, where a block of 256 threads covers 64 x 4 cells, or in 2D
+ * 64 x 8 for N <= 4; a build option makes 3D tiles 32 x 8; pf_set_tiling takes
+ * 0 or that width) and the number of z planes a block marches through (3D
+ * only, >= 1).  pf_autotune times the RKL2 inner stage at
  * the z extents 4..256 (inputs: the current state and copies of it in three
  * work buffers, which it allocates if the handle has not yet; the state is only
  * read), in two interleaved passes keeping each extent's faster time, and

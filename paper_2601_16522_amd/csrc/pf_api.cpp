@@ -1115,6 +1115,7 @@ pf_status init_meta(pf_sim *s, const pf_params *p) {
     s->cfix = cfix;
     for (int f = 0; f < 6; ++f) s->cbc[f] = (cfix >> f) & 1 ? p->c_bc[f] : 0.0;
     s->dim = p->dim; s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
+    s->tx = tile_cols(p->dim);
     s->N = p->n_phi; s->T = p->n_types; s->with_c = p->with_c ? 1 : 0;
     s->ssp_s = p->ssp_stages >= 2 ? p->ssp_stages : 5;
     s->prec = p->prec;
@@ -1588,9 +1589,10 @@ pf_status pf_set_state(pf_sim *s, const void *buf, size_t len) {
 
 pf_status pf_set_tiling(pf_sim *s, int tx, int zchunk) {
     if (!s) return PF_EINVAL;
-    if (tx != 64) return fail(s, PF_EINVAL, "tx must be 64 (tiles are 64 cells wide)");
+    if (tx != 0 && tx != tile_cols(s->dim))
+        return fail(s, PF_EINVAL, "tx must be 0 or %d (the tile width of %dD grids)", tile_cols(s->dim),
+                    s->dim);
     if (zchunk < 1) return fail(s, PF_EINVAL, "zchunk must be >= 1");
-    s->tx = tx;
     s->zchunk = zchunk;
     return PF_OK;
 }

@@ -8,17 +8,29 @@ namespace pf {
 
 constexpr int NMAX = 16;  // largest number of order parameters a kernel is built for
 constexpr int TMAX = 4;   // largest number of thermodynamic types
-constexpr int TILE_X = 64, TILE_Y = 4;  // 256 threads: one wavefront per row of 64 cells
+// Stage kernel blocks are 256 threads.  2D: 64 threads per row (one
+// wavefront per row of 64 cells), TILE_Y = 4 rows of threads.
+constexpr int TILE_X = 64, TILE_Y = 4;
 // Cells per thread in y of a 2D tile with n order parameters: the tile is
 // 64 x (4 rows2d(n)) cells, each thread computing rows2d(n) cells of one
 // column.  Two rows halve the barriers and the halo share per cell (the halo
 // is loaded and its mu and Mc computed by the same 256 threads); for few
 // fields that is instruction time saved, while for eight or more fields the
 // second row's values cost the kernels a wave per SIMD, so they keep one row.
-// A 3D tile is 64 x 4 cells marched in z.
 constexpr int ROWS2D_MAX_N = 4;
 constexpr int rows2d(int n) { return n <= ROWS2D_MAX_N ? 2 : 1; }
-constexpr int tile_rows(int dim, int n) { return dim == 2 ? TILE_Y * rows2d(n) : TILE_Y; }
+// A 3D tile is TILE3_X x TILE3_Y cells, one per thread, marched in z.  The
+// build may choose 32 x 8 (-DPF_TILE3_X=32: half the y-halo per cell, rows of
+// 32 cells still whole 128-byte lines) instead of 64 x 4; on the 512^3 N = 9
+// workload both run at the streaming rate of their own access pattern and
+// 64 x 4 measured marginally faster, so it is the default.
+#ifndef PF_TILE3_X
+#define PF_TILE3_X 64
+#endif
+constexpr int TILE3_X = PF_TILE3_X, TILE3_Y = 256 / PF_TILE3_X;
+constexpr int tile_cols(int dim) { return dim == 3 ? TILE3_X : TILE_X; }
+constexpr int thread_rows(int dim) { return 256 / tile_cols(dim); }
+constexpr int tile_rows(int dim, int n) { return dim == 2 ? TILE_Y * rows2d(n) : TILE3_Y; }
 // Largest number of order parameters built with stage-fusion depth 2.
 constexpr int DEPTH2_MAX_N = 4;
 

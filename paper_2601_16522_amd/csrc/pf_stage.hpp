@@ -13,9 +13,10 @@
 //
 // The path is a memory-bound stencil, so it uses no matrix cores.
 //
-// Decomposition.  A block is 256 threads covering a tile of 64 x 4 cells of
-// the x-y plane (a wavefront covers one full row of 64 cells, so row loads and
-// stores are coalesced).  The tile's plane is staged in LDS
+// Decomposition.  A block is 256 threads covering a tile of the x-y plane:
+// 64 x 4 cells (in 2D 64 x 8, two per thread, for N <= 4; a build option
+// makes the 3D tile 32 x 8); a wavefront covers one full row of 64 cells, so
+// row loads and stores are coalesced.  The tile's plane is staged in LDS
 // with a one-cell halo (phi planes, chemical potential mu and mobility Mc per
 // point): every thread computes mu and Mc of its own cell once, the halo
 // threads those of the halo cells, and the x/y neighbours of the stencil are
@@ -391,13 +392,13 @@ __device__ __forceinline__ int bound_index(int v, int n, bool wall, int lo, int 
     return wrap_index<GENERAL>(v, n);
 }
 
-// Plane offset (column) of the cell (tix * TILE_X + lx, tiy * TY + ly), wrapped
+// Plane offset (column) of the cell (tix * TX + lx, tiy * TY + ly), wrapped
 // or held at the walls (walls: bit 0 x, bit 1 y); active: the cell lies inside
 // the grid (ragged tiles); face: the wall face beyond which it lies, or -1.
-template <bool GENERAL>
+template <bool GENERAL, int TX>
 __device__ __forceinline__ void own_column(int tix, int tiy, int TY, int lx, int ly, int nx, int ny,
                                            int walls, long long &col, bool &active, int &face) {
-    const int gx = tix * TILE_X + lx, gy = tiy * TY + ly;
+    const int gx = tix * TX + lx, gy = tiy * TY + ly;
     active = gx < nx && gy < ny;
     face = -1;
     const int ix = bound_index<GENERAL>(gx, nx, walls & 1, 0, 1, face);
@@ -405,13 +406,13 @@ __device__ __forceinline__ void own_column(int tix, int tiy, int TY, int lx, int
     col = (long long)iy * nx + ix;
 }
 
-// Halo cell h (0 <= h < 2 TILE_X + 2 TY) of tile (tix, tiy) of height TY: the
-// edge neighbours of the tile without corners, periodically wrapped; hslot is
-// its slot in an LDS plane of (TILE_X + 2) x (TY + 2).
-template <bool GENERAL>
+// Halo cell h (0 <= h < 2 TX + 2 TY) of tile (tix, tiy) of TX x TY cells:
+// the edge neighbours of the tile without corners, periodically wrapped;
+// hslot is its slot in an LDS plane of (TX + 2) x (TY + 2).
+template <bool GENERAL, int TX>
 __device__ __forceinline__ void halo_column(int tix, int tiy, int TY, int h, int nx, int ny, int walls,
                                             long long &hcol, int &hslot, int &face) {
-    constexpr int TX = TILE_X, TXH = TILE_X + 2;
+    constexpr int TXH = TX + 2;
     int hx, hy;
     if (h < TX) { hx = h; hy = -1; }
     else if (h < 2 * TX) { hx = h - TX; hy = TY; }
@@ -775,17 +776,18 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
 // buffer group of the vectors (see set_field_bases).  TABLES: stage the LDS
 // tables of A.P first (false: the caller has staged them).  t: the tile's
 // index and coordinates (tile_index, or kept by a caller that walks tiles).
-// The tile is 64 x TY cells, TY = tile_rows(DIM, N); thread (lx, ly) computes the
-// R = TY / 4 cells (lx, ly + 4 k) of its column (3D: R = 1, marched in z).
+// The tile is TX x TY cells, TX = tile_cols(DIM), TY = tile_rows(DIM, N);
+// thread (lx, ly) = (t mod TX, t / TX) computes the R = TY / TR cells
+// (lx, ly + TR k) of its column, TR = 256 / TX (3D: R = 1, marched in z).
 template <typename T, int DIM, int N, int KIND, int GS, bool TABLES = true, bool WALLS = false,
           int GSS = 0>
 __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx t, T *__restrict__ lds,
                                            T *__restrict__ pair, T *__restrict__ kc) {
     constexpr bool FAST = std::is_same<T, float>::value;
     constexpr int LCP = operand_load_cp<DIM>(), SCP = out_store_cp<DIM>();
-    // the tile shape is fixed at compile time (one wavefront per row) so that
-    // every LDS plane offset is an instruction immediate
-    constexpr int TX = TILE_X, TY = tile_rows(DIM, N), R = TY / TILE_Y;
+    // the tile shape is fixed at compile time so that every LDS plane offset
+    // is an instruction immediate; TR rows of TX threads
+    constexpr int TX = tile_cols(DIM), TY = tile_rows(DIM, N), TR = thread_rows(DIM), R = TY / TR;
     constexpr int TXH = TX + 2, TYH = TY + 2;
     constexpr int plane_sz = TXH * TYH;
     static_assert(DIM == 2 || R == 1, "3D tiles march one row set in z");
@@ -821,11 +823,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
             constexpr bool G = decltype(general)::value;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                own_slot[k] = (ly + TILE_Y * k + 1) * TXH + (lx + 1);
-                own_column<G>(tix, tiy, TY, lx, ly + TILE_Y * k, nx, ny, walls, col[k], active[k],
-                              own_face[k]);
+                own_slot[k] = (ly + TR * k + 1) * TXH + (lx + 1);
+                own_column<G, TX>(tix, tiy, TY, lx, ly + TR * k, nx, ny, walls, col[k], active[k],
+                                  own_face[k]);
             }
-            if (has_halo) halo_column<G>(tix, tiy, TY, threadIdx.x, nx, ny, walls, hcol, hslot, hface);
+            if (has_halo) halo_column<G, TX>(tix, tiy, TY, threadIdx.x, nx, ny, walls, hcol, hslot, hface);
         };
         if (!WALLS && wrap_fits(A.ntx, TX, nx) && wrap_fits(A.nty, TY, ny))
             columns(std::false_type{});
@@ -947,7 +949,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &A, const TileIdx 
 
 // LDS per block: (N + 2) planes of (TILE_X + 2) x (tile rows + 2) values.
 template <typename T, int N, int DIM>
-constexpr int lds_elems() { return (N + 2) * (TILE_X + 2) * (tile_rows(DIM, N) + 2); }
+constexpr int lds_elems() { return (N + 2) * (tile_cols(DIM) + 2) * (tile_rows(DIM, N) + 2); }
 
 // Occupancy hint: the single-precision 3D kernels with up to 9 order
 // parameters fit three wavefronts per SIMD (<= 168 VGPRs) without scratch;

@@ -11,9 +11,15 @@
 //   4r1w_nt  the same with non-temporal loads and stores
 //   copy     o = a, 16 B per lane
 //   read     sum of a, 16 B per lane (result kept by a never-taken store)
-// Usage: stream_ref N [reps]; N = floats per vector.  Prints one JSON line
-// with GB/s per kernel (bytes moved / mean launch time over reps launches,
-// timed with HIP events after two warm-up launches).
+//   4r1w_planes  (with F NX NY) the stage kernels' access pattern without
+//            their arithmetic: each vector holds F planes of NX x NY x NZ
+//            values (NZ = N / (F NX NY)); a block of 256 threads takes a
+//            64 x 4 tile of the x-y plane and marches 16 planes in z, reading
+//            the F values of its cell from four vectors and writing them to
+//            the fifth -- 5 F concurrent plane streams, where 4r1w has 5
+// Usage: stream_ref N [reps [F NX NY]]; N = floats per vector.  Prints one
+// JSON line with GB/s per kernel (bytes moved / mean launch time over reps
+// launches, timed with HIP events after two warm-up launches).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -65,6 +71,49 @@ __global__ void __launch_bounds__(256)
     if (s == 12345.678f) o[0] = s;  // the input is zero-filled: never taken
 }
 
+template <int F>
+__global__ void __launch_bounds__(256)
+    k_planes(const float *__restrict__ a, const float *__restrict__ b, const float *__restrict__ c,
+             const float *__restrict__ d, float *__restrict__ o, int nx, int ny, int nz, int zc) {
+    const int ntx = (nx + 63) / 64, nty = (ny + 3) / 4;
+    const int L = blockIdx.x;
+    const int tix = L % ntx, tiy = (L / ntx) % nty, tiz = L / (ntx * nty);
+    const int x = tix * 64 + (int)threadIdx.x % 64, y = tiy * 4 + (int)threadIdx.x / 64;
+    if (x >= nx || y >= ny) return;
+    const long long V = (long long)nx * ny * nz;
+    const int z1 = min(tiz * zc + zc, nz);
+    for (int z = tiz * zc; z < z1; ++z) {
+        const long long i = ((long long)z * ny + y) * nx + x;
+        float va[F], vb[F], vc[F], vd[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            va[f] = a[f * V + i];
+            vb[f] = b[f * V + i];
+            vc[f] = c[f * V + i];
+            vd[f] = d[f * V + i];
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) o[f * V + i] = 0.5f * va[f] + 0.25f * vb[f] + 0.125f * vc[f] + 0.0625f * vd[f];
+    }
+}
+
+template <int F>
+void launch_planes(float *const *p, int nx, int ny, int nz) {
+    const int zc = 16;
+    const unsigned g = (unsigned)((nx + 63) / 64) * (unsigned)((ny + 3) / 4) * (unsigned)((nz + zc - 1) / zc);
+    hipLaunchKernelGGL(k_planes<F>, dim3(g), dim3(256), 0, 0, p[0], p[1], p[2], p[3], p[4], nx, ny, nz, zc);
+}
+
+bool planes_dispatch(int F, float *const *p, int nx, int ny, int nz) {
+    switch (F) {
+#define PF_F(k) case k: launch_planes<k>(p, nx, ny, nz); return true;
+        PF_F(2) PF_F(3) PF_F(4) PF_F(5) PF_F(6) PF_F(7) PF_F(8) PF_F(9) PF_F(10) PF_F(11) PF_F(12)
+        PF_F(13) PF_F(14) PF_F(15) PF_F(16) PF_F(17)
+#undef PF_F
+    default: return false;
+    }
+}
+
 int main(int argc, char **argv) {
     const long long n = argc > 1 ? atoll(argv[1]) : (1LL << 30);
     const int reps = argc > 2 ? atoi(argv[2]) : 10;
@@ -72,6 +121,14 @@ int main(int argc, char **argv) {
         fprintf(stderr, "stream_ref: N must be in [1024, 2^33], reps >= 1\n");
         return 2;
     }
+    const int F = argc > 5 ? atoi(argv[3]) : 0;
+    const int nx = argc > 5 ? atoi(argv[4]) : 0, ny = argc > 5 ? atoi(argv[5]) : 0;
+    const long long nzl = F > 0 && nx > 0 && ny > 0 ? n / ((long long)F * nx * ny) : 0;
+    if (argc > 5 && (F < 2 || F > 17 || nx < 1 || ny < 1 || nzl < 1 || nzl > (1 << 30))) {
+        fprintf(stderr, "stream_ref: F must be in [2, 17] and N >= F NX NY\n");
+        return 2;
+    }
+    const int nz = (int)nzl;
     const long long n4 = n / 4;  // the 16 B kernels cover the first 4*(N/4) floats
     float *p[5];
     for (int k = 0; k < 5; ++k) {
@@ -108,9 +165,16 @@ int main(int argc, char **argv) {
     const double t4 = time_it([&] {
         hipLaunchKernelGGL(k_read, dim3(g4), dim3(T), 0, 0, (const float4 *)p[0], p[4], n4);
     });
+    double planes = 0.0;
+    if (nz > 0) {
+        const double t5 = time_it([&] { planes_dispatch(F, p, nx, ny, nz); });
+        planes = 5.0 * F * (double)nx * ny * nz * sizeof(float) / t5 / 1e9;
+    }
     printf("{\"floats_per_vector\": %lld, \"4r1w\": %.1f, \"4r1w_nt\": %.1f, \"copy\": %.1f, "
-           "\"read\": %.1f}\n",
+           "\"read\": %.1f",
            n, 5 * B / t1 / 1e9, 5 * B / t2 / 1e9, 2 * B4 / t3 / 1e9, B4 / t4 / 1e9);
+    if (nz > 0) printf(", \"4r1w_planes\": %.1f, \"planes\": [%d, %d, %d, %d]", planes, F, nx, ny, nz);
+    printf("}\n");
     for (int k = 0; k < 5; ++k) CK(hipFree(p[k]));
     CK(hipEventDestroy(e0));
     CK(hipEventDestroy(e1));

@@ -40,7 +40,7 @@ def run(wl, prec, ng, fn):
     sim = pf.Sim(wl.param_dict(), prec=prec, ssp_stages=3)
     sim.set_field_groups(ng)
     assert sim.field_groups() == ng
-    sim.set_tiling(64, 5)
+    sim.set_tiling(0, 5)
     sim.init_fields(wl.u0)
     out = fn(sim)
     u, t = sim.get_fields()

@@ -110,7 +110,7 @@ def test_every_stage_kind_sees_no_unwritten_lds(libs, case, prec, integ):
 
     def run(sim):
         if zc:
-            sim.set_tiling(64, zc)  # z chunks that do not divide nz
+            sim.set_tiling(0, zc)  # z chunks that do not divide nz
         sim.step(integ, dt)
 
     u = _both(libs, wl, prec, run)

@@ -56,7 +56,7 @@ def make(wl, prec="fp64", zchunk=0):
     sim = pf.Sim(wl.param_dict(), prec=prec, ssp_stages=3)
     sim.init_fields(wl.u0)
     if zchunk:
-        sim.set_tiling(64, zchunk)
+        sim.set_tiling(0, zchunk)
     return sim
 
 

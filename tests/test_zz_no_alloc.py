@@ -24,7 +24,7 @@ def _gpu():
 def _vectors(wl, prec, zchunk):
     sim = pf.Sim(wl.param_dict(), prec=prec, ssp_stages=3)
     if wl.dim == 3:
-        sim.set_tiling(64, zchunk)
+        sim.set_tiling(0, zchunk)
     sim.init_fields(wl.u0)
     u_old, aux, u_new = sim.empty_device(), sim.empty_device(), sim.empty_device()
     sim.get_fields_device(u_old)
@@ -58,7 +58,7 @@ def test_noalloc_norm_refuses_more_partials_than_the_scratch_holds():
                                 r_range=(2.0, 3.0), dmin=4.0).param_dict())
     p.update(nx=128, ny=4, nz=65537)
     sim = pf.Sim(p, prec="fp32")
-    sim.set_tiling(64, 1)
+    sim.set_tiling(0, 1)
     vec = sim.empty_device()
     tol = pf.Tol()
     with pytest.raises(pf.PFError) as ei:
