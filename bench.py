@@ -402,6 +402,10 @@ def main():
     ap.add_argument("--no-batch-leg", action="store_true",
                     help="skip the batched FP32 against per-instance FP64 comparison of the "
                          "default line")
+    ap.add_argument("--sparse", type=int, default=0, metavar="N_P",
+                    help="3D fixed steps: sparse phase storage with at most N_P nonzero phases per "
+                         "cell (Sec. 3.1); a projected cell with more keeps the N_P largest and the "
+                         "line reports how many cells were cut")
     ap.add_argument("--cpu-planes", type=int, default=64,
                     help="3D workloads: z planes of the sample the CPU oracle is timed on")
     args = ap.parse_args()
@@ -460,6 +464,10 @@ def main():
     if rkl1 and args.workload not in ("pores3d", "gg3d") or rkl1 and args.adaptive:
         raise SystemExit("--integ rkl1 applies to fixed steps of --workload pores3d|gg3d")
 
+    if args.sparse:
+        if wl.dim != 3 or args.adaptive or args.fusion == 2:
+            raise SystemExit("--sparse applies to fixed steps of --workload pores3d|gg3d")
+        sim.set_sparse_storage(args.sparse)
     sim.init_fields_device(u0_dev)
     tiling = sim.get_tiling()
     if args.zchunk or args.pair_zchunk:
@@ -468,7 +476,7 @@ def main():
         if args.pair_zchunk:
             sim.set_pair_zchunk(args.pair_zchunk)
         tiling = sim.get_tiling()
-    elif not args.no_autotune:
+    elif not args.no_autotune and not args.sparse:
         tiling = sim.autotune()[:2]
     if args.fusion:
         sim.set_stage_fusion(args.fusion)
@@ -516,7 +524,16 @@ def main():
     E = 8 if args.prec == "fp64" else 4
     sref = stream_reference(wl.F * E * wl.cells, (wl.F, wl.nx, wl.ny) if wl.dim == 3 and E == 4 else None)
     value = wl.cells * rhs / total / 1e9
-    if rkl1:
+    cuts = sim.sparse_cuts() if args.sparse else None
+    if args.sparse and not rkl1:
+        # Y_{j-1}, Y_{j-2}, Y_0 and Y_j in sparse storage (c, N_P phase slots and
+        # the id word per cell), R_0 dense
+        per_cell = 4 * (args.sparse + (1 if wl.with_c else 0) + 1) + wl.F
+        bytes_per_launch = per_cell * E * wl.cells
+        key = f"rkl2_stage_sparse{args.sparse}/{wl.name}/{args.prec}"
+        kname = (f"rkl2_stage_kernel in sparse storage (N_P = {args.sparse}, RKL2 stages j >= 2), "
+                 f"{n_rkl2} launches")
+    elif rkl1:
         # stage 1 reads u and writes Y_1; stages j >= 2 read Y_{j-1}, Y_{j-2}, write Y_j
         bytes_per_launch = round((2 + 3 * (s_fix - 1)) / s_fix * wl.F * E * wl.cells)
         key = f"rkl1_stages/{wl.name}/{args.prec}"
@@ -577,6 +594,12 @@ def main():
                      "frac_of_stream_4r1w_planes": (round(achieved / sref["4r1w_planes"], 4)
                                                     if sref and "4r1w_planes" in sref else None)},
     }
+    if args.sparse:
+        # cells cut by the storage rule over every run of this process (warm-up,
+        # timed and the untimed breakdown run)
+        out["config"]["sparse_storage"] = {"n_p": args.sparse, "cells_cut": cuts,
+                                           "runs": args.warmup + args.steps + 1,
+                                           "dense_bytes_per_launch": 5 * wl.F * E * wl.cells}
     if args.workload == "gg3d" and not args.no_batch_leg:
         print("# batch leg: FP32 batched against FP64 per instance", file=sys.stderr, flush=True)
         out["config"]["batch_equal_error"] = batch_equal_error()

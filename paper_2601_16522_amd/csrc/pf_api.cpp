@@ -1500,8 +1500,13 @@ pf_status pf_sparse_cuts(pf_sim *s, long long *cuts) {
     return PF_OK;
 }
 
-pf_status pf_diagnostics(pf_sim *s, double out[5]) {
-    if (!s || !out) return PF_EINVAL;
+}  // extern "C"
+
+namespace {
+// The diagnostics reduction over the current state; phases == false reads c
+// only (the sum of c is formed in the same order either way, so it has the
+// same bits).
+pf_status diag_run(pf_sim *s, bool phases, double out[5]) {
     if (pf_status rc = need_fields(s)) return rc;
     const int nb = 1024;
     if (pf_status rc = ensure_red(s, nb)) return rc;
@@ -1509,7 +1514,7 @@ pf_status pf_diagnostics(pf_sim *s, double out[5]) {
     begin_timed(s, FAM_RED, p);
     // dense: N phase planes then c; sparse: c, then n_p slots (empty ones 0)
     const bool sp = s->n_p > 0;
-    const int nphi = sp ? s->n_p : s->N;
+    const int nphi = !phases ? 0 : sp ? s->n_p : s->N;
     const long long po = sp ? s->V : 0, co = sp ? 0 : (long long)s->N * s->V;
     hipError_t e = s->prec == PF_FP64
                        ? launch_diag<double>((const double *)s->buf[s->cur] + po,
@@ -1525,11 +1530,19 @@ pf_status pf_diagnostics(pf_sim *s, double out[5]) {
     for (int k = 0; k < 5; ++k) out[k] = s->hres[RES_DIAG + k];
     return PF_OK;
 }
+}  // namespace
+
+extern "C" {
+
+pf_status pf_diagnostics(pf_sim *s, double out[5]) {
+    if (!s || !out) return PF_EINVAL;
+    return diag_run(s, true, out);
+}
 
 pf_status pf_conservation(pf_sim *s, double *sum_c) {
     if (!s || !sum_c) return PF_EINVAL;
     double d[5];
-    pf_status rc = pf_diagnostics(s, d);
+    pf_status rc = diag_run(s, false, d);
     if (rc) return rc;
     *sum_c = d[0];
     return PF_OK;
