@@ -213,7 +213,7 @@ def batch_bench(args):
     as one fused launch per step replayed from a hipGraph in FP32, against the
     plain FP64 form run instance by instance; then the same end times with
     batched RKL2 steps of --rkl2-dte dt_e, and with adaptive batched RKL2
-    (a controller per instance, the cfg2 tolerances)."""
+    (a controller per instance, the tolerances of the 1024^2 Voronoi run)."""
     import torch
     import paper_2601_16522_amd as pf
     import pf_inputs as pi

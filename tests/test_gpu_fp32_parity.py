@@ -77,19 +77,19 @@ def voronoi_small():
     return pi.voronoi_2d(n=160, n_grains=24, n_phi=8, dmin=12.0)
 
 
-def cfg3_small():
+def sintering_small():
     """The sintering generator (12 grains on 12 fields plus the pore phase,
     radii 4-10 cells) at 48^3."""
     return pi.grains_pores_3d(n=48, n_grains=12, n_grain_fields=12, n_pores=6, dmin=12.0)
 
 
-def cfg5_small():
+def graingrowth_small():
     """The grain-growth generator (grains round-robin on 8 fields plus the pore
     field, radii 3-8 cells) at 56^3."""
     return pi.grain_growth_pores_3d(n=56, n_grains=60, n_pores=8, dmin=4.0)
 
 
-WORKLOADS = {"voronoi2d": voronoi_small, "sintering3d": cfg3_small, "graingrowth3d": cfg5_small}
+WORKLOADS = {"voronoi2d": voronoi_small, "sintering3d": sintering_small, "graingrowth3d": graingrowth_small}
 
 
 @pytest.mark.parametrize("integ", ["fe", "ssp2", "ssp104", "rkl1", "rkl2"])

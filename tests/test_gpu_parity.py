@@ -385,7 +385,7 @@ def test_nonfinite_state_is_reported():
     assert sim.diagnostics()["nonfinite"] == 1
 
 
-def test_cfg2_full_size_one_rkl2_step_fp64_and_fp32():
+def test_voronoi_1024_full_size_one_rkl2_step_fp64_and_fp32():
     """The 1024^2, 8-field Voronoi workload at full size: one RKL2 step at
     100 dt_e (21 stages) against the oracle.  FP64: 1e-10.  FP32: reported
     max / RMS / count above 1e-4 (activity changes at triple junctions can move
@@ -400,7 +400,7 @@ def test_cfg2_full_size_one_rkl2_step_fp64_and_fp32():
     sim = make(wl)
     sim.step("rkl2", dt)
     u, _ = sim.get_fields()
-    check_fp64(wl, u, ref, "cfg2 fp64")
+    check_fp64(wl, u, ref, "voronoi 1024^2 fp64")
     sim32 = make(wl, prec="fp32")
     sim32.step("rkl2", dt)
     u32, _ = sim32.get_fields()
@@ -416,7 +416,7 @@ def test_cfg2_full_size_one_rkl2_step_fp64_and_fp32():
     dist = ndimage.distance_transform_edt(~tails)
     bad = (d > 1e-4).any(axis=0).reshape(wl.ny, wl.nx)
     far = float(dist[bad].max()) if bad.any() else 0.0
-    print(f"\ncfg2 FP32 vs oracle: max {d.max():.3e} rms {math.sqrt((d**2).mean()):.3e} "
+    print(f"\nvoronoi 1024^2 FP32 vs oracle: max {d.max():.3e} rms {math.sqrt((d**2).mean()):.3e} "
           f"count>1e-4 {(d > 1e-4).sum()} of {d.size}; cells {bad.sum()}, farthest from a "
           f"three-phase cell {far:.2f} cells", flush=True)
     assert math.sqrt((d ** 2).mean()) <= 1e-5
