@@ -14,8 +14,8 @@ device, untimed) before each step.
 Prints one JSON line: Gcell-stage/s (cells x RHS evaluations per second), the
 time to solution, the HBM roofline of the dominant kernel (the RKL2 inner
 stage), the FP64 oracle timed on the host on a bounded sample of the same
-workload, and, under config.batch_equal_error, the spec comparison at
-equal sharp-interface error: 96 uneven 2D shrinking grains batched in FP32
+workload, and, under config.batch_equal_error, the comparison at equal
+sharp-interface error: 96 uneven 2D shrinking grains batched in FP32
 against the plain FP64 form instance by instance.
 
 Other modes: --workload pores3d (256^3 sintering, two fixed RKL2 steps; with
@@ -151,7 +151,7 @@ def area_slope_error(u0, u, t, M, dx=1.0, gamma=1.0):
 
 
 def batch_equal_error():
-    """The spec comparison at equal sharp-interface error: the 96
+    """The comparison at equal sharp-interface error: the 96
     shrinking-grain instances, 2000 forward-Euler steps each at 0.9 dt_e,
     batched in FP32 (one fused launch per step, autotuned, hipGraphs of 50
     launches) against the plain FP64 form run instance by instance; the error
@@ -411,7 +411,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU domain decomposition "
+        print("bench.py: runs on one GPU only; the multi-GPU domain decomposition "
               "is a design (z-slab halos over RCCL), not part of this benchmark", file=sys.stderr)
         sys.exit(2)
 

@@ -48,7 +48,7 @@ typedef enum {
     PF_ENONFINITE = -4,    /* non-finite error norm three times in a row */
     PF_EDTMIN = -5,        /* adaptive step fell below 1e-12 dt_e */
     PF_ESTATE = -6,        /* call not valid in the current state (e.g. no fields) */
-    PF_EUNSUPPORTED = -7   /* valid request that this build does not implement */
+    PF_EUNSUPPORTED = -7   /* valid request that this library does not implement */
 } pf_status;
 
 /* Integrators of Sec. 3.2 (Table tab:ints). */
@@ -116,7 +116,7 @@ typedef struct {
 } pf_stats;
 
 /* Handle life cycle.  pf_create returns PF_EINVAL for inconsistent parameters
- * and PF_EUNSUPPORTED for an n_phi this build has no kernels for
+ * and PF_EUNSUPPORTED for an n_phi the library has no kernels for
  * (pf_supported_nphi) or a grid too large to address: the kernels split a
  * state vector's N + 1 planes into 1, 2 or 4 groups of ceil((N + 1) / groups)
  * planes, each group spanning less than 4 GiB (FP32 512^3 with N = 9 needs

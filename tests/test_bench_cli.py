@@ -7,7 +7,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
-    """This build measures one GPU: --gpus N > 1 exits with status 2 and says
+    """bench.py measures one GPU: --gpus N > 1 exits with status 2 and says
     so, before touching a device."""
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
