@@ -510,7 +510,18 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
     }
     T delta[N];
     const T inz = FAST ? fast_rcp(T(nzc > 0 ? nzc : 1)) : T(1) / T(nzc > 0 ? nzc : 1);
-    if (FAST && P.uniform) {
+    if (FAST && N == 2 && P.uniform) {
+        // two phases: both active or no driving force; with both, the pair
+        // form gives r_0 = L (delta_1 - delta_0) / 2 = -r_1, where
+        // delta_1 - delta_0 = A (Lap phi_0 - Lap phi_1) + B (phi_0 - phi_1)
+        // + psi_1 - psi_0 (the sums of the general forms, their equal terms
+        // cancelled)
+        const T A0 = pair[1], B0 = pair[N * N + 1], L0 = pair[2 * N * N + 1];
+        const T d = fma_t(A0, lap[0] - lap[N - 1], fma_t(B0, cur[0] - cur[N - 1], psi[N - 1] - psi[0]));
+        const T r0 = nzc >= 2 ? (T(0.5) * L0) * d : T(0);
+        r[0] = r0;
+        r[N - 1] = -r0;
+    } else if (FAST && P.uniform) {
         const T A0 = pair[1], B0 = pair[N * N + 1], L0 = pair[2 * N * N + 1];
         T slap = lap[0], sp = cur[0];
 #pragma unroll
