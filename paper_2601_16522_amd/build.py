@@ -99,6 +99,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         return obj
 
     main, poison, check = _units(), _poison_units(), _check_units()
+
     def cost(u):  # stage units take longest, growing with N: start those first
         n = [int(x.split("=")[1]) for x in u[2] if x.startswith(("-DPF_NPHI=", "-DPF_NG="))]
         return -(100 * n[0] + n[1]) if n else 0
