@@ -30,9 +30,18 @@
  *   walls and fixed-c faces: pinned (the solutal Stefan growth constant of
  *     Sec. 5.2.2; plain diffusion against a fixed-c wall, erf solution).
  *   c coupling at equilibrium: pinned (phase embedding, Laplace pressure).
- *   error norm and PID controller: pinned only by hand-worked cases and
- *     invariants; parity against the paper unpinned (the paper prints no
- *     worked example of either).
+ *   RKL2 first-stage correction: pinned on clipped cells and by its effect
+ *     on the error (Sec. 3.2 end).
+ *   SSP(10)4 embedded solution: pinned by the order conditions of its
+ *     Butcher tableau and its stability polynomial.
+ *   PID controller: the printed gains recovered from its output through the
+ *     inverted limiter, the reject fallback, bias and limiter invariants.
+ *   error norm: pinned where every entry counts (the textbook weighted RMS
+ *     norm); the phi filter and the degree-of-freedom rule for trivial
+ *     entries are readings checked by hand-worked cases only, parity against
+ *     the paper unpinned (it prints no worked example).
+ *   sparse storage rule: hand-worked cells; equal to dense storage bit for
+ *     bit while nothing is cut.
  */
 #include <math.h>
 #include <omp.h>

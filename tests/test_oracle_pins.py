@@ -760,6 +760,27 @@ def test_error_norm_filter_and_dof_rule():
     assert e == pytest.approx(math.sqrt(expect_ss / 5), rel=1e-13)
 
 
+def test_error_norm_is_the_weighted_rms_norm_when_every_entry_counts():
+    """Special case that reduces to the textbook weighted RMS norm of step
+    control: with the embedded estimate e = u^{n+1} - z nonzero in every entry,
+    every phi and c entry is a degree of freedom, and the norm of eq.
+    error_norm is sqrt(mean((e / (a + r max(|u^n|, |u^{n+1}|)))^2)), formed
+    here with numpy's vector 2-norm over all F x V entries."""
+    rng = np.random.default_rng(12)
+    P = oracle.Params(nx=7, ny=5, n_phi=3, dx=1.0, W=2.0, with_c=True, type_of=[0, 0, 0])
+    shape = (4, 1, 5, 7)
+    un = rng.uniform(0.05, 0.9, shape)
+    unp1 = un + rng.uniform(-1e-3, 1e-3, shape)
+    z = unp1 - rng.uniform(1e-6, 1e-4, shape) * rng.choice([-1.0, 1.0], shape)
+    tol = oracle.Tol(r_phi=3e-3, a_phi=2e-2, r_c=5e-4, a_c=1e-3)
+    e, ndof, _ = oracle.error_norm(P, 1, 0.1, un, unp1, z, tol)
+    r = np.array([tol.r_phi] * 3 + [tol.r_c])[:, None, None, None]
+    a = np.array([tol.a_phi] * 3 + [tol.a_c])[:, None, None, None]
+    w = (unp1 - z) / (a + r * np.maximum(np.abs(un), np.abs(unp1)))
+    assert ndof == w.size
+    assert e == pytest.approx(np.linalg.norm(w.ravel()) / math.sqrt(w.size), rel=1e-12)
+
+
 def test_embedded_norm_scaling():
     """Embedded estimate e = u^{n+1} - z: the norm is homogeneous of degree one in
     the difference and equals the common ratio when every weighted entry is equal."""
