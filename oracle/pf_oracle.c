@@ -37,9 +37,11 @@
  *   PID controller: the printed gains recovered from its output through the
  *     inverted limiter, the reject fallback, bias and limiter invariants.
  *   error norm: pinned where every entry counts (the textbook weighted RMS
- *     norm); the phi filter and the degree-of-freedom rule for trivial
- *     entries are readings checked by hand-worked cases only, parity against
- *     the paper unpinned (it prints no worked example).
+ *     norm) and, for the degree-of-freedom rule, by the paper's reason for it
+ *     (two phases held in more slots give the norm of a direct two-phase
+ *     implementation); the phi filter of the estimate is checked by
+ *     hand-worked cases only, parity against the paper unpinned (it prints no
+ *     worked example).
  *   sparse storage rule: hand-worked cells; equal to dense storage bit for
  *     bit while nothing is cut.
  */

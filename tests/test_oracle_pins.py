@@ -781,6 +781,51 @@ def test_error_norm_is_the_weighted_rms_norm_when_every_entry_counts():
     assert e == pytest.approx(np.linalg.norm(w.ravel()) / math.sqrt(w.size), rel=1e-12)
 
 
+def test_error_norm_of_two_phases_in_more_slots_is_the_two_phase_norm():
+    """The degree-of-freedom rule of Sec. 3.3 (reading R16) counts a cell without
+    nontrivial phi entries as two, because a direct two-phase implementation
+    holds two phi unknowns per cell.  So a state in which only two phases are
+    present, stored in N = 4 slots (present: slots 1 and 3), must give the norm
+    that such a two-phase implementation computes: the weighted RMS over its
+    2V phi entries and V c entries, zero-error bulk entries included.  Counting
+    all N slots, counting bulk cells as N or 1, or counting nonzero phi instead
+    of nonzero error each changes the divisor."""
+    rng = np.random.default_rng(21)
+    nx, ny, N = 9, 6, 4
+    V = nx * ny
+    P = oracle.Params(nx=nx, ny=ny, n_phi=N, dx=1.0, W=2.0, with_c=True, type_of=[0] * N)
+    iface = rng.random((1, ny, nx)) < 0.5
+    iface[0, 0, 0], iface[0, 0, 1] = True, False      # at least one cell of each kind
+    bulk1 = (~iface) & (rng.random((1, ny, nx)) < 0.5)  # bulk of phase 1, else phase 3
+    un = np.zeros((N + 1, 1, ny, nx))
+    p1 = rng.uniform(0.05, 0.95, (1, ny, nx))
+    un[1] = np.where(iface, p1, np.where(bulk1, 1.0, 0.0))
+    un[3] = 1.0 - un[1]
+    un[N] = rng.uniform(0.2, 0.8, (1, ny, nx))
+    unp1 = un.copy()
+    d = rng.uniform(1e-4, 1e-3, (1, ny, nx)) * rng.choice([-1.0, 1.0], (1, ny, nx))
+    unp1[1] = np.where(iface, un[1] + d, un[1])
+    unp1[3] = 1.0 - unp1[1]
+    unp1[N] = un[N] + rng.uniform(-1e-3, 1e-3, (1, ny, nx))
+    # embedded comparison solution: nonzero error on both present phases of an
+    # interface cell and on every c entry, none in bulk phi entries
+    z = unp1.copy()
+    ez = rng.uniform(1e-6, 1e-4, (1, ny, nx)) * rng.choice([-1.0, 1.0], (1, ny, nx))
+    z[1] = np.where(iface, unp1[1] - ez, unp1[1])
+    z[3] = np.where(iface, unp1[3] + 0.5 * ez, unp1[3])
+    z[N] = unp1[N] - rng.uniform(1e-6, 1e-5, (1, ny, nx))
+    tol = oracle.Tol(r_phi=3e-3, a_phi=2e-2, r_c=5e-4, a_c=1e-3)
+    e, ndof, _ = oracle.error_norm(P, 1, 0.1, un, unp1, z, tol)
+
+    two = [1, 3, N]  # the two-phase implementation's unknowns
+    r = np.array([tol.r_phi, tol.r_phi, tol.r_c])[:, None, None, None]
+    a = np.array([tol.a_phi, tol.a_phi, tol.a_c])[:, None, None, None]
+    w = (unp1[two] - z[two]) / (a + r * np.maximum(np.abs(un[two]), np.abs(unp1[two])))
+    assert w.size == 3 * V
+    assert ndof == w.size
+    assert e == pytest.approx(np.linalg.norm(w.ravel()) / math.sqrt(w.size), rel=1e-12)
+
+
 def test_embedded_norm_scaling():
     """Embedded estimate e = u^{n+1} - z: the norm is homogeneous of degree one in
     the difference and equals the common ratio when every weighted entry is equal."""
