@@ -185,12 +185,15 @@ pf_status pf_controller_update(pf_controller *c, int order, double err, double h
 
 /* Exact output times (Sec. 5 opening): the step from t towards t_end has size
  * h unless the remainder is at most h (1 + 1e-10), in which case it is the
- * remainder and *last = 1.  Returns 1 with *h_use set, 0 when t_end is reached
- * (remainder at most 1e-12 h), -1 for invalid arguments. */
+ * remainder and *last = 1 (an infinite h, as 0.9 dt_e is without mobility and
+ * diffusion, always so).  Returns 1 with *h_use set, 0 when t_end is reached
+ * (remainder at most 1e-12 h, or not positive for an infinite h), -1 for
+ * invalid arguments. */
 int pf_clip_step(double t, double t_end, double h, double *h_use, int *last);
 
-/* One step of size dt (RKL stage count from pf_stage_count).  stats may be
- * NULL; otherwise it is overwritten with this call's counters. */
+/* One step of size dt (RKL stage count from pf_stage_count); dt must be
+ * finite and > 0 (else PF_EINVAL).  stats may be NULL; otherwise it is
+ * overwritten with this call's counters. */
 pf_status pf_step(pf_sim *sim, pf_integrator integ, double dt, pf_stats *stats);
 
 /* Integrate to t_end, landing on it exactly (Sec. 5 opening).  tol == NULL:
@@ -200,7 +203,10 @@ pf_status pf_step(pf_sim *sim, pf_integrator integ, double dt, pf_stats *stats);
  * tenth stage value, second order in general and third on linear problems),
  * PID controller with the method's order; steps are capped at
  * tol->dt_max_over_dte dt_e and, for SSP(s)2 and SSP(10)4, at 0.9 times their
- * stability limits (s - 1) dt_e and 6 dt_e; FE returns PF_EUNSUPPORTED. */
+ * stability limits (s - 1) dt_e and 6 dt_e; FE returns PF_EUNSUPPORTED.
+ * t_end must be finite (else PF_EINVAL).  Where dt_e is infinite (no pair
+ * mobility and no diffusivity: the right-hand side is zero) the first step,
+ * 0.9 dt_e, is clipped to the remainder and lands on t_end. */
 pf_status pf_run_to(pf_sim *sim, pf_integrator integ, double t_end, const pf_tol *tol,
                     double dt_fixed, pf_stats *stats);
 
@@ -385,7 +391,7 @@ pf_status pf_batch_stable_dt(pf_batch *b, int i, double *dt_e);
  * the RKL2 ring, R0 and the table are allocated on the first RKL2 run and
  * kept); others return PF_EUNSUPPORTED.  graph_steps > 0 replays a graph of
  * that many launches (forward Euler) or steps (RKL2); 0 launches directly.
- * stats (optional) is [n]. */
+ * Every t_end[i] must be finite (else PF_EINVAL).  stats (optional) is [n]. */
 pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
                           const double *dt, int graph_steps, pf_stats *stats);
 /* Adaptive RKL2 steps of every instance to its t_end[i] (Sec. 3.3): each
@@ -400,7 +406,7 @@ pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
  * keep their state.  integ must be PF_RKL2 and the batch may hold at most
  * 65535 instances (else PF_EUNSUPPORTED).  Errors:
  * PF_EINVAL for negative tolerances, a field kind with zero weight or t_end[i]
- * before the instance's time; PF_EDTMIN on a step underflow; PF_ENONFINITE
+ * before the instance's time or not finite; PF_EDTMIN on a step underflow; PF_ENONFINITE
  * after three non-finite norms of one instance in a row (the instances keep
  * their last accepted states).  Allocates the adaptive work buffers (the new
  * state, per-tile partials, norms) on the first call.  stats (optional) is [n]:

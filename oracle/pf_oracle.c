@@ -892,7 +892,8 @@ int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_en
         if (!(dt_fixed > 0.0)) return -1;
         for (;;) {
             double rem = t_end - t;
-            if (rem <= 1e-12 * dt_fixed) break;
+            /* a step of infinite size (reading R18 below) ends on t_end */
+            if (rem <= 1e-12 * (isinf(dt_fixed) ? rem : dt_fixed)) break;
             double h = dt_fixed;
             int last = 0;
             if (rem <= h * (1.0 + 1e-10)) { h = rem; last = 1; }
@@ -942,10 +943,14 @@ int pfo_run_to(const pfo_params *P, int integ, int s_ssp, double t0, double t_en
     for (;;) {
         double rem = t_end - t;
         double h = dt < dtmax ? dt : dtmax;
-        if (rem <= 1e-12 * h) break;
+        /* reading R18: the step that would pass t_end is clipped to the
+         * remainder, an infinite one too (dt_e is infinite when no pair has
+         * mobility and no phase diffuses: the right-hand side is zero); the
+         * underflow test needs a finite dt_e */
+        if (rem <= 1e-12 * (isinf(h) ? rem : h)) break;
         int last = 0;
         if (rem <= h * (1.0 + 1e-10)) { h = rem; last = 1; }
-        if (!last && h < 1e-12 * dte) { rc = -5; break; }
+        if (!last && isfinite(dte) && h < 1e-12 * dte) { rc = -5; break; }
         int s = s_ssp;
         if (integ == PFO_SSP104) s = 10;
         else if (integ != PFO_SSP2) s = pfo_stage_count(order, h, dte);

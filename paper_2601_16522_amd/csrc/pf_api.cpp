@@ -371,7 +371,10 @@ double stable_dt(const pf_sim *s) {
 // last one.  A remainder at most 1e-12 h means t_end is reached (false).
 bool clip_step(double t, double t_end, double h, double &h_use, bool &last) {
     const double rem = t_end - t;
-    if (rem <= 1e-12 * h) return false;
+    // an infinite step (dt_e is infinite without mobility and diffusion, where
+    // the right-hand side vanishes) is clipped to the remainder like any step
+    // that would pass t_end
+    if (rem <= 1e-12 * (std::isinf(h) ? rem : h)) return false;
     last = rem <= h * (1.0 + 1e-10);
     h_use = last ? rem : h;
     return true;
@@ -891,7 +894,8 @@ pf_status run_to_t(pf_sim *s, int integ, double t_end, const pf_tol *tol, double
         double h;
         bool last;
         if (!clip_step(s->t, t_end, std::min(dt, dtmax), h, last)) break;
-        if (!last && h < 1e-12 * dte) return fail(s, PF_EDTMIN, "adaptive step underflow (dt = %g)", h);
+        if (!last && std::isfinite(dte) && h < 1e-12 * dte)
+            return fail(s, PF_EDTMIN, "adaptive step underflow (dt = %g)", h);
         int ns = s->ssp_s;
         if (integ == PF_SSP_10_4) ns = 10;
         else if (integ != PF_SSP_S2) ns = stage_count(order, h, dte);
@@ -1320,7 +1324,7 @@ pf_status pf_step(pf_sim *s, pf_integrator integ, double dt, pf_stats *stats) {
     if (!s) return PF_EINVAL;
     if (pf_status rc = need_fields(s)) return rc;
     if (pf_status rc = sparse_integ_ok(s, integ, nullptr)) return rc;
-    if (!(dt > 0.0)) return fail(s, PF_EINVAL, "dt must be > 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(s, PF_EINVAL, "dt must be finite and > 0");
     s->st = pf_stats{};
     int ns = s->ssp_s;
     if (integ == PF_RKL1 || integ == PF_RKL2) ns = stage_count(integ == PF_RKL1 ? 1 : 2, dt, stable_dt(s));
@@ -1342,6 +1346,7 @@ pf_status pf_run_to(pf_sim *s, pf_integrator integ, double t_end, const pf_tol *
     if (!s) return PF_EINVAL;
     if (pf_status rc = need_fields(s)) return rc;
     if (pf_status rc = sparse_integ_ok(s, integ, tol)) return rc;
+    if (!std::isfinite(t_end)) return fail(s, PF_EINVAL, "t_end must be finite");
     s->st = pf_stats{};
     pf_status rc = s->prec == PF_FP64 ? run_to_t<double>(s, integ, t_end, tol, dt_fixed)
                                       : run_to_t<float>(s, integ, t_end, tol, dt_fixed);
@@ -2132,7 +2137,7 @@ pf_status batch_run_adaptive(pf_batch *b, const double *t_end, const pf_tol &tol
                 done[i] = 1;
                 continue;
             }
-            if (!li && h[i] < 1e-12 * dte[i])
+            if (!li && std::isfinite(dte[i]) && h[i] < 1e-12 * dte[i])
                 return bfail(b, PF_EDTMIN, "instance %d: adaptive step underflow (dt = %g)", i, h[i]);
             last[i] = li;
             ns[i] = stage_count(2, h[i], dte[i]);
@@ -2497,8 +2502,10 @@ pf_status pf_batch_run_to(pf_batch *b, pf_integrator integ, const double *t_end,
     if (!b || !t_end || graph_steps < 0) return PF_EINVAL;
     if (integ != PF_FEULER && integ != PF_RKL2)
         return bfail(b, PF_EUNSUPPORTED, "the batch advances forward Euler or RKL2 steps");
-    for (int i = 0; i < b->n; ++i)
+    for (int i = 0; i < b->n; ++i) {
         if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
+        if (!std::isfinite(t_end[i])) return bfail(b, PF_EINVAL, "instance %d: t_end must be finite", i);
+    }
     return b->prec == PF_FP64 ? batch_run<double>(b, integ, t_end, dt, graph_steps, stats)
                               : batch_run<float>(b, integ, t_end, dt, graph_steps, stats);
 }
@@ -2513,7 +2520,8 @@ pf_status pf_batch_run_adaptive(pf_batch *b, pf_integrator integ, const double *
         return bfail(b, PF_EINVAL, "tolerances must be >= 0 with a nonzero weight per field kind");
     for (int i = 0; i < b->n; ++i) {
         if (!b->have[i]) return bfail(b, PF_ESTATE, "instance %d has no fields", i);
-        if (!(t_end[i] >= b->t[i])) return bfail(b, PF_EINVAL, "instance %d: t_end before t", i);
+        if (!(t_end[i] >= b->t[i]) || !std::isfinite(t_end[i]))
+            return bfail(b, PF_EINVAL, "instance %d: t_end before t or not finite", i);
     }
     return b->prec == PF_FP64 ? batch_run_adaptive<double>(b, t_end, *tol, stats)
                               : batch_run_adaptive<float>(b, t_end, *tol, stats);

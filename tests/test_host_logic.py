@@ -97,6 +97,16 @@ def test_clip_step_matches_oracle_run():
         assert np.array_equal(np.asarray(steps), st.trace[:, 0]), (n_full, frac)
 
 
+def test_clip_step_infinite_step_lands_on_t_end():
+    """An infinite step (0.9 dt_e without mobility and diffusion) is clipped to
+    the remainder; at or past t_end there is no step."""
+    assert pf.clip_step(0.0, 5.0, math.inf) == (5.0, True)
+    assert pf.clip_step(2.5, 5.0, math.inf) == (2.5, True)
+    assert pf.clip_step(5.0, 5.0, math.inf) is None
+    assert pf.clip_step(6.0, 5.0, math.inf) is None
+    assert pf.clip_step(0.0, 5.0, 2.0) == (2.0, False)
+
+
 def test_tolerance_marshalling():
     """pf.Tol keyword construction and its C struct (every adaptive call uses it)."""
     t = pf.Tol(r_phi=1e-5, a_phi=2e-5, r_c=3e-5, a_c=4e-5, dt_max_over_dte=50.0, dt0=1e-3)

@@ -127,6 +127,56 @@ def _flat_interface(dx, W=4.0):
     return P, u
 
 
+def _eighths_simplex_state(rng, N, shape, with_c=True):
+    """phi in multiples of 1/8 that sum to 1 exactly at every cell (zeros in
+    places), so that the projection S leaves it unchanged bit for bit; c in
+    [0.2, 0.8]."""
+    cuts = np.sort(rng.integers(0, 9, size=(N - 1,) + shape), axis=0)
+    edges = np.concatenate([np.zeros((1,) + shape, int), cuts, np.full((1,) + shape, 8)])
+    phi = np.diff(edges, axis=0) / 8.0
+    if not with_c:
+        return phi
+    return np.concatenate([phi, rng.uniform(0.2, 0.8, (1,) + shape)])
+
+
+def test_no_mobility_no_diffusion_is_stationary_and_runs_land_on_t_end():
+    """Closed form: with every pair mobility and every diffusivity zero the
+    right-hand sides of eq. phieq and of the c equation vanish identically, the
+    Gershgorin bound gives an infinite dt_e, and the solution is the initial
+    state at all times.  The fixed and the adaptive runs (reading R18: the
+    infinite first step, 0.9 dt_e, is clipped to the remainder) take one step
+    to t_end and return the state unchanged up to rounding; a run that stopped
+    at its first infinite step, or took a NaN from inf * 0, fails here."""
+    rng = np.random.default_rng(31)
+    d = dict(dim=2, nx=9, ny=7, nz=1, n_phi=3, type_of=[0, 1, 1], n_types=2, dx=1.0, W=3.0,
+             gamma=[1.0, 0.8, 0.8, 1.2], mob=[0.0] * 4, k=[500.0, 300.0], c0=[0.1, 0.9],
+             D=[0.0, 0.0], with_c=True)
+    P = oracle.Params(**d)
+    u0 = _eighths_simplex_state(rng, 3, (1, 7, 9))
+    assert math.isinf(oracle.stable_dt(P))
+    assert np.abs(oracle.rhs(P, u0)).max() == 0.0
+    t_end = 7.5
+    tol = oracle.Tol(r_phi=1e-4, a_phi=1e-2, r_c=1e-4, a_c=1e-4)
+    # (the stage combinations of eq. sts and of the SSP schemes weight copies
+    # of the same state with coefficients that sum to 1 only up to rounding,
+    # so the state and the error estimate move by rounding only)
+    for integ in (oracle.RKL1, oracle.RKL2, oracle.SSP2, oracle.SSP104):
+        u, st, rc = oracle.run_to(P, integ, u0, t_end, tol=tol, s=3)
+        assert rc == 0 and st.accepted == 1 and st.rejected == 0, integ
+        assert st.t == t_end and st.trace[0, 0] == t_end and st.trace[0, 2] <= 1e-9, integ
+        assert np.abs(u - u0).max() <= 1e-14, integ
+    for integ in (oracle.FE, oracle.RKL2):
+        u, st, rc = oracle.run_to(P, integ, u0, t_end, dt_fixed=math.inf, s=3)
+        assert rc == 0 and st.accepted == 1 and st.t == t_end, integ
+        assert np.abs(u - u0).max() <= 1e-14, integ
+    # a finite first step: the controller grows it (zero error) up to t_end,
+    # with no underflow reported against the infinite dt_e
+    tol0 = oracle.Tol(r_phi=1e-4, a_phi=1e-2, r_c=1e-4, a_c=1e-4, dt0=1e-3)
+    u, st, rc = oracle.run_to(P, oracle.RKL2, u0, t_end, tol=tol0)
+    assert rc == 0 and st.t == t_end and st.rejected == 0 and st.accepted > 1
+    assert np.abs(u - u0).max() <= 1e-13
+
+
 def test_flat_profile_is_stationary_and_converges():
     """eq. profile is the two-phase equilibrium when B/A = 1/W^2 (Sec. 2): a
     periodic pair of flat interfaces relaxes by an amount that vanishes as dx -> 0
