@@ -38,3 +38,27 @@ def test_binding_fails_loudly_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(pf, "_lib", None)
     with pytest.raises(ImportError):
         pf.lib()
+
+
+@pytest.mark.parametrize("prec,esz", [("fp32", 4), ("fp64", 8)])
+def test_largest_addressable_grid(prec, esz):
+    """A plane of the state must span < 4 GiB (32-bit per-lane offsets within a
+    buffer group): a plane of one z row less passes the size check (and then
+    fails without a device, PF_EHIP, or makes a handle where there is one), a
+    4 GiB plane is PF_EUNSUPPORTED."""
+    L = pf.lib()
+    limit = (1 << 32) // esz  # cells of a 4 GiB plane
+    nx = ny = 1024
+    for nz, refused in ((limit // (nx * ny) - 1, False), (limit // (nx * ny), True)):
+        d = dict(dim=3, nx=nx, ny=ny, nz=nz, n_phi=2, type_of=[0, 0], n_types=1, dx=1.0, W=3.0,
+                 gamma=[1.0], mob=[1.0], k=[500.0], c0=[0.5], D=[1.0], with_c=True)
+        keep = []
+        p = pf._cparams(d, prec, 5, keep)
+        h = C.c_void_p()
+        rc = L.pf_create(C.byref(p), C.byref(h))
+        if h.value:
+            L.pf_destroy(h)
+        if refused:
+            assert rc == -7 and not h.value, (prec, nz, rc)
+        else:
+            assert rc in (0, -2), (prec, nz, rc)
