@@ -406,6 +406,9 @@ def main():
                     help="3D fixed steps: sparse phase storage with at most N_P nonzero phases per "
                          "cell (Sec. 3.1); a projected cell with more keeps the N_P largest and the "
                          "line reports how many cells were cut")
+    ap.add_argument("--r0-recompute", default="auto", choices=["auto", "0", "1"],
+                    help="3D RKL2 inner stages: recompute R0 from u0 (1) or read it (0); auto: the "
+                         "autotuner's choice (read it when the autotuner is skipped)")
     ap.add_argument("--cpu-planes", type=int, default=64,
                     help="3D workloads: z planes of the sample the CPU oracle is timed on")
     args = ap.parse_args()
@@ -480,10 +483,13 @@ def main():
         tiling = sim.autotune()[:2]
     if args.fusion:
         sim.set_stage_fusion(args.fusion)
+    if args.r0_recompute != "auto":
+        sim.set_r0_recompute(args.r0_recompute == "1")
     fusion = sim.get_stage_fusion()
     pair_zc = sim.get_pair_zchunk()
+    recompute = sim.get_r0_recompute() and fusion == 1 and not rkl1 and not args.sparse
     print(f"# tiling tx={tiling[0]} zchunk={tiling[1]} pair zchunk={pair_zc}, RKL2 stages per "
-          f"launch {fusion}", file=sys.stderr, flush=True)
+          f"launch {fusion}, R0 recomputed {recompute}", file=sys.stderr, flush=True)
 
     def one_step():
         sim.init_fields_device(u0_dev)
@@ -546,6 +552,11 @@ def main():
         key = f"rkl2_pair/{wl.name}/{args.prec}"
         kname = (f"rkl2_pair{'3' if wl.dim == 3 else ''}_kernel (RKL2 stages j, j + 1 fused), "
                  f"{n_rkl2} launches")
+    elif recompute:
+        # Y_{j-1} and Y_0 (stencils), Y_{j-2} in; Y_j out; R_0 recomputed from Y_0
+        bytes_per_launch = 4 * wl.F * E * wl.cells
+        key = f"rkl2_stage_rc/{wl.name}/{args.prec}"
+        kname = f"rkl2_rc_stage_kernel (RKL2 stages j >= 2, R0 recomputed), {n_rkl2} launches"
     else:
         bytes_per_launch = 5 * wl.F * E * wl.cells      # Y_{j-1}, Y_{j-2}, Y_0, R_0 in; Y_j out
         key = f"rkl2_stage/{wl.name}/{args.prec}"
@@ -571,6 +582,7 @@ def main():
                    "precision": args.prec,
                    "tiling": {"tx": tiling[0], "zchunk": tiling[1], "pair_zchunk": pair_zc},
                    "rkl2_stages_per_launch": fusion,
+                   "r0_recomputed": bool(recompute),
                    "rhs_evals_per_step": rhs / args.steps,
                    "accepted_per_step": acc / args.steps, "rejected_per_step": rej / args.steps,
                    "time_to_solution_ms": round(total / args.steps * 1e3, 4),

@@ -285,9 +285,11 @@ pf_status pf_set_state(pf_sim *sim, const void *buf, size_t len);
  * keeps the fastest extent.  Where fused stage pairs are built (below) it
  * also times pair launches (a fifth work buffer takes their second output;
  * in 3D at the pair z extents 8..128) and sets the fusion depth to 2 if a
- * pair takes less than two single stages, else to 1; best_ms is then the
- * time per stage of the choice.  The launch shape never changes a result
- * bit. */
+ * pair takes less than two single stages, else to 1; on periodic 3D grids it
+ * also times the stages that recompute R0 (pf_set_r0_recompute) at the same z
+ * extents and turns that mode on if one is the fastest single stage, else
+ * off; best_ms is then the time per stage of the choice.  The launch shape
+ * and these modes never change a result bit. */
 pf_status pf_set_tiling(pf_sim *sim, int tx, int zchunk);
 pf_status pf_get_tiling(pf_sim *sim, int *tx, int *zchunk);
 pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
@@ -340,6 +342,22 @@ pf_status pf_sparse_cuts(pf_sim *sim, long long *cuts);
  * pf_autotune chooses by timing. */
 pf_status pf_set_stage_fusion(pf_sim *sim, int depth);
 pf_status pf_get_stage_fusion(const pf_sim *sim, int *depth);
+/* RKL2 inner stages of periodic 3D grids (eq. sts, stages j >= 2) that
+ * recompute R0 instead of reading it: on = 1 reads u^{n,0} as a second
+ * stencil input and forms R0 = rhs(u^{n,0}) with the correction of the first
+ * stage (Sec. 3.2, end) at every cell, so 4 (N + 1) values move per
+ * cell-stage instead of 5 (N + 1), for a second right-hand side per cell.
+ * The results are the same bits as with the stored R0 (which the first stage
+ * still writes, for the error estimate).  on = 0 (the default) reads R0.
+ * Built for single precision N <= 9 and double precision N <= 4 (two z
+ * windows of N + 1 values per thread for two waves per SIMD).  Errors:
+ * PF_EINVAL for other values; PF_EUNSUPPORTED for 2D grids, walls, sparse
+ * storage or an N it is not built for.  With fused stage pairs (depth 2) the
+ * pairs run instead.
+ * pf_autotune times it at the single-stage z extents and keeps it where it
+ * is faster. */
+pf_status pf_set_r0_recompute(pf_sim *sim, int on);
+pf_status pf_get_r0_recompute(const pf_sim *sim, int *on);
 /* z planes per block of the 3D fused stage pairs (>= 1; default 32; the
  * autotuner times 8..128).  Never changes a result bit. */
 pf_status pf_set_pair_zchunk(pf_sim *sim, int zchunk);

@@ -43,7 +43,8 @@ EXPORTS = ["pf_create", "pf_destroy", "pf_set_stream", "pf_init_fields", "pf_ini
            "pf_batch_set_fusion", "pf_batch_get_config", "pf_batch_last_error",
            "pf_params_stable_dt", "pf_rkl_stage_count", "pf_controller_init",
            "pf_controller_update", "pf_clip_step", "pf_set_timing_families",
-           "pf_set_stage_fusion", "pf_get_stage_fusion", "pf_set_pair_zchunk", "pf_get_pair_zchunk",
+           "pf_set_stage_fusion", "pf_get_stage_fusion", "pf_set_r0_recompute",
+           "pf_get_r0_recompute", "pf_set_pair_zchunk", "pf_get_pair_zchunk",
            "pf_set_sparse_storage", "pf_get_sparse_storage", "pf_sparse_cuts"]
 
 
@@ -145,6 +146,8 @@ def lib():
             "pf_autotune": [vp, C.POINTER(i), C.POINTER(i), pd],
             "pf_set_stage_fusion": [vp, i],
             "pf_get_stage_fusion": [vp, C.POINTER(i)],
+            "pf_set_r0_recompute": [vp, i],
+            "pf_get_r0_recompute": [vp, C.POINTER(i)],
             "pf_set_pair_zchunk": [vp, i],
             "pf_set_sparse_storage": [vp, i],
             "pf_get_sparse_storage": [vp, C.POINTER(i)],
@@ -600,6 +603,15 @@ class Sim:
         d = C.c_int()
         self._chk(self._L.pf_get_stage_fusion(self._h, C.byref(d)))
         return d.value
+
+    def set_r0_recompute(self, on: bool):
+        """3D RKL2 inner stages recompute R0 from u^{n,0} (True) or read it."""
+        self._chk(self._L.pf_set_r0_recompute(self._h, int(bool(on))))
+
+    def get_r0_recompute(self) -> bool:
+        v = C.c_int()
+        self._chk(self._L.pf_get_r0_recompute(self._h, C.byref(v)))
+        return bool(v.value)
 
     def set_sparse_storage(self, n_p: int):
         """Sparse phase storage with n_p slots per cell (0: dense); clears the

@@ -94,6 +94,7 @@ struct pf_sim {
     unsigned long long ids_off = 0;
     unsigned long long *dcut = nullptr;
     int fuse = 1;            // RKL2 inner stages per launch (2: fused pairs, where built)
+    int r0rc = 0;            // 3D RKL2 inner stages recompute R0 from u0 (pf_set_r0_recompute)
     int inner_launches = 0;  // launches of the last step's inner-stage interval
     bool timing = false;
     unsigned timing_mask = 0;  // families recorded while timing
@@ -481,7 +482,7 @@ T *bp(pf_sim *s, int i) { return i < 0 ? nullptr : (T *)s->buf[i]; }
 template <typename T>
 pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, const T *r0, T *out,
                 T *out2, double a, double b, double c, double d, double e, double f,
-                unsigned fam) {
+                unsigned fam, double a2 = 0.0) {
     StageArgs<T> A;
     std::memset(&A, 0, sizeof A);
     A.K = kconsts<T>(s);
@@ -498,6 +499,7 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     A.cut = s->dcut;
     A.kind = kind;
     A.a = (T)a; A.b = (T)b; A.c = (T)c; A.d = (T)d; A.e = (T)e; A.f = (T)f;
+    A.a2 = (T)a2;
     int ntx, nty, nzc, ntiles, nblocks;
     tiles(s, ntx, nty, nzc, ntiles, nblocks);
     A.tx = s->tx;
@@ -511,6 +513,12 @@ pf_status stage(pf_sim *s, int kind, const T *y1, const T *y2, const T *u0, cons
     hipError_t err = launch_stage<T>(s->dim, s->N, A, nblocks, s->stream);
     if (err != hipSuccess) return fail(s, PF_EHIP, "stage kernel launch: %s", hipGetErrorString(err));
     return PF_OK;
+}
+
+// Whether RKL2 inner stages can recompute R0 from u0 (K_RKL2_RC): periodic 3D
+// grids in dense storage, where the kernel is built.
+bool rc_ok(const pf_sim *s) {
+    return s->dim == 3 && s->walls == 0 && s->n_p == 0 && rkl2_rc_built((int)s->esz, s->N);
 }
 
 // Whether the fused RKL2 stage-pair kernel is built for the simulation:
@@ -811,7 +819,12 @@ pf_status do_step_impl(pf_sim *s, int integ, int nst, double dt, bool want_aux, 
             const int jc = j % NR, jp = (j - 1) % NR, jpp = (j - 2) % NR;
             if (jc == 0) slot[0] = slot0_store;
             rkl_coeffs(order, ns, j, mu, nu, mut, gam);
-            if (second) {
+            if (second && s->r0rc && rc_ok(s)) {
+                // R0 recomputed from u^{n,0} with the first stage's mut_1 dt
+                rc = stage<T>(s, K_RKL2_RC, bp<T>(s, slot[jp]), bp<T>(s, slot[jpp]), u, nullptr,
+                              bp<T>(s, slot[jc]), nullptr, (1.0 - mu) - nu, mu, nu, dt, mut, gam,
+                              FAM_RKL2, mut1 * dt);
+            } else if (second) {
                 rc = stage<T>(s, K_RKL2, bp<T>(s, slot[jp]), bp<T>(s, slot[jpp]), u, bp<T>(s, R0),
                               bp<T>(s, slot[jc]), nullptr, (1.0 - mu) - nu, mu, nu, dt, mut, gam,
                               FAM_RKL2);
@@ -999,12 +1012,15 @@ struct CkptHeader {
 // candidates are timed in two interleaved passes and each keeps its faster
 // time, which damps clock and queue noise between candidates.
 template <typename T>
-pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fuse, int &bzc2) {
+pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fuse, int &bzc2,
+                     int &r0rc) {
     const int zcs3[7] = {4, 8, 16, 32, 64, 128, 256};
     const int ncand = s->dim == 3 ? 7 : 1;
     // fused pairs: one candidate in 2D, the z extents 8..128 in 3D
     const int zcp[5] = {8, 16, 32, 64, 128};
     const int npair = !pair_ok(s) ? 0 : (s->dim == 3 ? 5 : 1);
+    // stages that recompute R0 (3D): the single-stage z extents again
+    const int nrc = rc_ok(s) ? ncand : 0;
     const T *u = bp<T>(s, s->cur);
     for (int k = 1; k < 4; ++k)
         HIPCHK(s, hipMemcpyAsync(s->buf[w[k]], u, buf_bytes(s), hipMemcpyDeviceToDevice, s->stream));
@@ -1012,18 +1028,19 @@ pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fus
     HIPCHK(s, hipEventCreate(&e0));
     HIPCHK(s, hipEventCreate(&e1));
     // candidates from ncand on (where built): the fused stage pair, timed per stage
-    double tbest[16];
+    double tbest[24];
     for (double &t : tbest) t = 1e300;
     const double cf[6] = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
     for (int pass = 0; pass < 2; ++pass)
-        for (int j = 0; j < ncand + npair; ++j) {
-            const bool pair = j >= ncand;
+        for (int j = 0; j < ncand + npair + nrc; ++j) {
+            const bool pair = j >= ncand && j < ncand + npair, recompute = j >= ncand + npair;
             if (pair) {
                 s->zchunk2 = s->dim == 3 ? zcp[j - ncand] : 1;
                 if (s->dim == 3 && s->zchunk2 > s->nz && j > ncand) continue;
             } else {
-                s->zchunk = s->dim == 3 ? zcs3[j] : 1;
-                if (s->dim == 3 && s->zchunk > s->nz && j > 0) continue;
+                const int k = recompute ? j - ncand - npair : j;
+                s->zchunk = s->dim == 3 ? zcs3[k] : 1;
+                if (s->dim == 3 && s->zchunk > s->nz && k > 0) continue;
             }
             pf_status rc = PF_OK;
             for (int r = 0; r < 6 && !rc; ++r) {
@@ -1031,6 +1048,9 @@ pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fus
                 if (pair)
                     rc = stage_pair<T>(s, u, bp<T>(s, w[1]), bp<T>(s, w[2]), bp<T>(s, w[3]), bp<T>(s, w[0]),
                                        bp<T>(s, w[4]), cf, cf);
+                else if (recompute)
+                    rc = stage<T>(s, K_RKL2_RC, u, bp<T>(s, w[1]), bp<T>(s, w[2]), nullptr, bp<T>(s, w[0]),
+                                  nullptr, cf[0], cf[1], cf[2], cf[3], cf[4], cf[5], 0, 1.0);
                 else
                     rc = stage<T>(s, K_RKL2, u, bp<T>(s, w[1]), bp<T>(s, w[2]), bp<T>(s, w[3]),
                                   bp<T>(s, w[0]), nullptr, cf[0], cf[1], cf[2], cf[3], cf[4], cf[5], 0);
@@ -1055,6 +1075,13 @@ pf_status autotune_t(pf_sim *s, const int w[5], double &best, int &bzc, int &fus
             bzc = s->dim == 3 ? zcs3[j] : 1;
         }
     fuse = 1;
+    r0rc = 0;
+    for (int j = ncand + npair; j < ncand + npair + nrc; ++j)
+        if (tbest[j] < best) {
+            best = tbest[j];
+            r0rc = 1;
+            bzc = zcs3[j - ncand - npair];
+        }
     for (int j = ncand; j < ncand + npair; ++j)
         if (tbest[j] < best) {
             best = tbest[j];
@@ -1633,14 +1660,15 @@ pf_status pf_autotune(pf_sim *s, int *tx_out, int *zc_out, double *best_ms) {
     const bool was_timing = s->timing;
     s->timing = false;
     double best;
-    int bzc = s->zchunk, fuse = 1, bzc2 = s->zchunk2;
-    pf_status rc = s->prec == PF_FP64 ? autotune_t<double>(s, w, best, bzc, fuse, bzc2)
-                                      : autotune_t<float>(s, w, best, bzc, fuse, bzc2);
+    int bzc = s->zchunk, fuse = 1, bzc2 = s->zchunk2, r0rc = 0;
+    pf_status rc = s->prec == PF_FP64 ? autotune_t<double>(s, w, best, bzc, fuse, bzc2, r0rc)
+                                      : autotune_t<float>(s, w, best, bzc, fuse, bzc2, r0rc);
     s->timing = was_timing;
     if (rc) return rc;
     s->zchunk = bzc;
     s->zchunk2 = bzc2;
     s->fuse = fuse;
+    s->r0rc = r0rc;
     if (tx_out) *tx_out = s->tx;
     if (zc_out) *zc_out = bzc;
     if (best_ms) *best_ms = best;
@@ -1656,6 +1684,22 @@ pf_status pf_set_stage_fusion(pf_sim *s, int depth) {
                                         "in 3D for single precision with N <= %d and double "
                                         "precision with N <= %d", P3_NMAX32, P3_NMAX64);
     s->fuse = depth;
+    return PF_OK;
+}
+
+pf_status pf_set_r0_recompute(pf_sim *s, int on) {
+    if (!s) return PF_EINVAL;
+    if (on != 0 && on != 1) return fail(s, PF_EINVAL, "r0 recompute %d (0 or 1)", on);
+    if (on && !rc_ok(s))
+        return fail(s, PF_EUNSUPPORTED, "RKL2 stages that recompute R0 are built for periodic 3D grids "
+                                        "in dense storage, single precision N <= 9, double N <= 4");
+    s->r0rc = on;
+    return PF_OK;
+}
+
+pf_status pf_get_r0_recompute(const pf_sim *s, int *on) {
+    if (!s || !on) return PF_EINVAL;
+    *on = s->r0rc;
     return PF_OK;
 }
 

@@ -79,7 +79,9 @@ enum StageKind : int {
     K_RKL2 = 7,         // out = S(((a u0 + b y1) + c y2) + d ((e r) + (f r0)));
                         // FP32: u0 + b (y1 - u0) + c (y2 - u0) for the first three terms
     K_EST = 8,          // Sommeijer estimate of u^{n+1} = y1 against u^n = u0, R0 = r0
-    K_RKL2_PAIR = 9     // two K_RKL2 stages j, j + 1 in one pass: out = Y_j, out2 = Y_{j+1}
+    K_RKL2_PAIR = 9,    // two K_RKL2 stages j, j + 1 in one pass: out = Y_j, out2 = Y_{j+1}
+    K_RKL2_RC = 10      // K_RKL2 with R0 recomputed from u0 read as a stencil (3D): the
+                        // first stage's R0 (a2 = its mut_1 dt) instead of reading r0
 };
 
 // Uniform per-simulation constants the stage kernels read: passed by value as
@@ -128,7 +130,7 @@ struct StageArgs {
     unsigned long long *cut;
     int kind;
     T a, b, c, d, e, f;
-    T a2, b2, c2, d2, e2, f2;  // K_RKL2_PAIR: coefficients of the second stage
+    T a2, b2, c2, d2, e2, f2;  // K_RKL2_PAIR: coefficients of the second stage; K_RKL2_RC: a2
     // estimator
     T r_phi, a_phi, r_c, a_c, dt6, hdt;
     // tiling
@@ -238,6 +240,10 @@ constexpr int P3_MX = P3_TX + 2, P3_MY = P3_TY + 2, P3_M = P3_MX * P3_MY;
 constexpr int P3_IX = P3_TX + 4, P3_IY = P3_TY + 4, P3_I = P3_IX * P3_IY;
 constexpr int P3_THREADS = 448, P3_LDS_MAX = 65536, P3_NMAX32 = 9, P3_NMAX64 = 4;
 static_assert(P3_I <= P3_THREADS && P3_THREADS % 64 == 0, "one halo-region column per thread");
+// The 3D RKL2 stages that recompute R0 (K_RKL2_RC) hold the z windows of two
+// stencil inputs; they are built where these fit two waves per SIMD without
+// scratch: single precision N <= 9, double precision N <= 4.
+constexpr bool rkl2_rc_built(int esz, int n) { return esz == 4 ? n <= 9 : n <= 4; }
 constexpr bool rkl2_pair3_built(int esz, int n) {
     return (esz == 4 ? n <= P3_NMAX32 : n <= P3_NMAX64) &&
            esz * ((n + 2) * (P3_I + P3_M) + 3 * n * n + 4 * n) <= P3_LDS_MAX;

@@ -588,6 +588,42 @@ __device__ __forceinline__ T rkl2_value(T a, T b, T c, T d, T e, T f, T y1, T r,
     else return ((a * u + b * y1) + c * y2) + d * (e * r + f * r0);
 }
 
+// The first RKL2 stage at one cell (eq. sts with the correction at the end of
+// Sec. 3.2): ys = S(u^{n,0} + a r) with a = mut_1 dt and r = rhs(u^{n,0}) (cut:
+// the sparse storage rule, applied after S), and r0 = R0: r, with the phi
+// planes replaced by (ys - u^{n,0}) / a where S changed the cell.  The stage
+// kernel that stores R0 and the stage kernel that recomputes it share this
+// arithmetic, so both give the same bits.
+template <typename T, int N, bool FAST, typename Cut>
+__device__ __forceinline__ void rkl2_first_point(const T a, const T *cur, const T *r, T *ys, T *r0,
+                                                 Cut &&cut) {
+    T yv[N + 1];
+#pragma unroll
+    for (int f = 0; f <= N; ++f) {
+        if constexpr (FAST) yv[f] = fma_t(a, r[f], cur[f]);
+        else yv[f] = cur[f] + a * r[f];
+        ys[f] = yv[f];
+    }
+    project<T, N, FAST>(ys);
+    cut(ys);
+    bool changed = false;
+#pragma unroll
+    for (int f = 0; f < N; ++f) changed = changed || bits_differ(ys[f], yv[f]);
+    // (the fast form multiplies by a hardware reciprocal of mut_1 dt)
+    T inv_a = T(0);
+    if constexpr (FAST) inv_a = fast_rcp(a);
+#pragma unroll
+    for (int f = 0; f < N; ++f) {
+        T ra = r[f];
+        if (changed) {
+            if constexpr (FAST) ra = (ys[f] - cur[f]) * inv_a;
+            else ra = (ys[f] - cur[f]) / a;
+        }
+        r0[f] = ra;
+    }
+    r0[N] = r[N];
+}
+
 // Stage combination, projection and store at one cell (byte offset idx in a
 // plane) from its own values cur, its right-hand side r and the operands
 // o0 (u0), o1 (y2), o2 (r0) of the stage kind; the estimator kind adds its
@@ -678,12 +714,14 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
                     else yv[f] = cur[f] + A.a * r[f];
                 }
             }
-        } else if constexpr (KIND == K_SSP104_S5 || KIND == K_RKL2_FIRST) {
+        } else if constexpr (KIND == K_SSP104_S5) {
 #pragma unroll
             for (int f = 0; f <= N; ++f) {
                 if constexpr (FAST) yv[f] = fma_t(A.a, r[f], cur[f]);
                 else yv[f] = cur[f] + A.a * r[f];
             }
+        } else if constexpr (KIND == K_RKL2_FIRST) {
+            // formed in rkl2_first_point below
         } else if constexpr (KIND == K_SSP2_FINAL) {
 #pragma unroll
             for (int f = 0; f <= N; ++f) {
@@ -716,31 +754,13 @@ __device__ __forceinline__ void cell_combine(const StageArgs<T> &A, const unsign
         }
 
         if constexpr (KIND == K_RKL2_FIRST) {
-            // First RKL2 stage: where S changes the cell, replace rhs(u^{n,0}) of
-            // the phi planes by (S(u^{n,1}) - u^{n,0}) / (mut_1 dt) (Sec. 3.2).
-            T ys[N + 1];
-#pragma unroll
-            for (int a = 0; a < N; ++a) ys[a] = yv[a];
-            ys[N] = yv[N];
-            project<T, N, FAST>(ys);
-            cut(ys);
-            bool changed = false;
-#pragma unroll
-            for (int a = 0; a < N; ++a) changed = changed || bits_differ(ys[a], yv[a]);
-            // (the fast form multiplies by a hardware reciprocal of mut_1 dt)
-            T inv_a = T(0);
-            if constexpr (FAST) inv_a = fast_rcp(A.a);
+            // First RKL2 stage: Y_1 and R0 with the correction of Sec. 3.2
+            T ys[N + 1], r0[N + 1];
+            rkl2_first_point<T, N, FAST>(A.a, cur, r, ys, r0, cut);
             store_out(ys);
 #pragma unroll
-            for (int a = 0; a < N; ++a) {
-                T ra = r[a];
-                if (changed) {
-                    if constexpr (FAST) ra = (ys[a] - cur[a]) * inv_a;
-                    else ra = (ys[a] - cur[a]) / A.a;
-                }
-                stv<T, GS, SCP>(A, 5, a, idx, ra);
-            }
-            if (withc) stv<T, GS, SCP>(A, 5, N, idx, r[N]);
+            for (int a = 0; a < N; ++a) stv<T, GS, SCP>(A, 5, a, idx, r0[a]);
+            if (withc) stv<T, GS, SCP>(A, 5, N, idx, r0[N]);
         } else if constexpr (KIND == K_SSP104_S5) {
             // Fifth SSP(10)4 stage plus the two linear updates of the
             // low-storage scheme: q2 <- q2/25 + 9 q1/25, q1 <- S(15 q2 - 5 q1),
@@ -997,6 +1017,147 @@ PF_STAGE_KERNEL(rkl2_first_stage_kernel, K_RKL2_FIRST)
 PF_STAGE_KERNEL(rkl2_stage_kernel, K_RKL2)
 PF_STAGE_KERNEL(estimator_kernel, K_EST)
 #undef PF_STAGE_KERNEL
+
+#ifndef PF_RC_WAVES
+#define PF_RC_WAVES 2
+#endif
+// One RKL2 stage j >= 2 of a periodic 3D grid (eq. sts) that recomputes R0
+// instead of reading it.  u^{n,0} is read as a second stencil input, staged in
+// LDS beside Y_{j-1}, and at each cell R0 = rhs(u^{n,0}) with the correction
+// of the first stage (rkl2_first_point with a = A.a2 = mut_1 dt) is formed
+// before the stage combination.  Four vectors move per cell-stage (Y_{j-1}
+// and u^{n,0} with their halos, Y_{j-2}, Y_j) instead of five, for a second
+// right-hand side per cell.  Every value is computed with the arithmetic of
+// the first-stage kernel that stored R0 and of rkl2_stage_kernel, so the
+// stage gives the same bits as that kernel reading the stored R0.  Dense
+// storage; A.y1 = Y_{j-1}, A.y2 = Y_{j-2}, A.u0 = u^{n,0}, A.out = Y_j.
+template <typename T, int N, int NG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF_RC_WAVES, 8)))
+    rkl2_rc_stage_kernel(const StageArgs<T> A) {
+    constexpr bool FAST = std::is_same<T, float>::value;
+    constexpr int GS = group_planes(N, NG);
+    constexpr int LCP = operand_load_cp<3>(), SCP = out_store_cp<3>();
+    constexpr int TX = tile_cols(3), TY = tile_rows(3, N);
+    constexpr int TXH = TX + 2, PS = TXH * (TY + 2);
+    static_assert(TX * TY == 256 && 2 * TX + 2 * TY <= 256, "one column and one halo cell per thread");
+    __shared__ T lds[2 * (N + 2) * PS];  // plane z of Y_{j-1}, then of u^{n,0}: phi, mu, Mc
+    __shared__ T pair[3 * N * N];
+    __shared__ T kc[4 * N];
+    poison_lds(pair, 3 * N * N);
+    poison_lds(kc, 4 * N);
+    const TileIdx t = tile_index(xcd_logical_block(), A.ntx, A.nty);
+    if (t.L >= A.ntiles) return;  // uniform over the block
+    const KConsts<T> &P = A.K;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const bool withc = P.with_c != 0;
+    stage_tables<T, N>(A.P, pair, kc);
+    __syncthreads();  // the tables are read from the first plane on
+
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const long long nxy = (long long)nx * ny;
+    const int own = (ly + 1) * TXH + (lx + 1);
+    long long col = 0, hcol = 0;
+    bool active = false;
+    int face = -1, hslot = 0, hface = -1;
+    const bool has_halo = threadIdx.x < 2 * TX + 2 * TY;
+    if (wrap_fits(A.ntx, TX, nx) && wrap_fits(A.nty, TY, ny)) {
+        own_column<false, TX>(t.tix, t.tiy, TY, lx, ly, nx, ny, 0, col, active, face);
+        if (has_halo) halo_column<false, TX>(t.tix, t.tiy, TY, threadIdx.x, nx, ny, 0, hcol, hslot, hface);
+    } else {
+        own_column<true, TX>(t.tix, t.tiy, TY, lx, ly, nx, ny, 0, col, active, face);
+        if (has_halo) halo_column<true, TX>(t.tix, t.tiy, TY, threadIdx.x, nx, ny, 0, hcol, hslot, hface);
+    }
+    const auto at = [nxy](int z, long long c) __attribute__((always_inline)) {
+        return (unsigned)((long long)z * nxy + c) * (unsigned)sizeof(T);
+    };
+    const int z0 = t.tiz * A.zchunk, z1 = min(z0 + A.zchunk, nz);
+
+    // input i = 0: Y_{j-1} (vector 0); i = 1: u^{n,0} (vector 2)
+    constexpr int VEC[2] = {0, 2};
+    T prv[2][N + 1], cur[2][N + 1], nxt[2][N + 1], hcur[2][N + 1], hnxt[2][N + 1];
+    T mu_p[2], mc_p[2], mu_c[2], mc_c[2], mu_n[2], mc_n[2];
+    // every load of the first plane is issued before the first use of one
+    const int zm = z0 == 0 ? nz - 1 : z0 - 1;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        load_point32<T, N, GS>(A, VEC[i], at(zm, col), withc, prv[i]);
+        load_point32<T, N, GS>(A, VEC[i], at(z0, col), withc, cur[i]);
+        if (has_halo) load_point32<T, N, GS>(A, VEC[i], at(z0, hcol), withc, hcur[i]);
+    }
+    for (int z = z0; z < z1; ++z) {
+        const int zp = z == nz - 1 ? 0 : z + 1;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            load_point32<T, N, GS>(A, VEC[i], at(zp, col), withc, nxt[i]);
+            if (has_halo && z + 1 < z1) load_point32<T, N, GS>(A, VEC[i], at(zp, hcol), withc, hnxt[i]);
+        }
+        if (z == z0) {  // later planes rotate their mu and Mc in
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                mu_c[i] = mc_c[i] = mu_p[i] = mc_p[i] = T(0);
+                if (withc) {
+                    point_mu_mc<T, N, FAST>(P, kc, cur[i], mu_c[i], mc_c[i]);
+                    point_mu_mc<T, N, FAST>(P, kc, prv[i], mu_p[i], mc_p[i]);
+                }
+            }
+        }
+
+        // ---- stage plane z of both inputs in LDS --------------------------
+        poison_lds(lds, 2 * (N + 2) * PS);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            T *const l = lds + i * (N + 2) * PS;
+#pragma unroll
+            for (int a = 0; a < N; ++a) l[a * PS + own] = cur[i][a];
+            l[N * PS + own] = mu_c[i];
+            l[(N + 1) * PS + own] = mc_c[i];
+            if (has_halo) {
+                T hmu = T(0), hmc = T(0);
+                if (withc) point_mu_mc<T, N, FAST>(P, kc, hcur[i], hmu, hmc);
+#pragma unroll
+                for (int a = 0; a < N; ++a) l[a * PS + hslot] = hcur[i][a];
+                l[N * PS + hslot] = hmu;
+                l[(N + 1) * PS + hslot] = hmc;
+            }
+            mu_n[i] = mc_n[i] = T(0);
+            if (withc) point_mu_mc<T, N, FAST>(P, kc, nxt[i], mu_n[i], mc_n[i]);
+        }
+        __syncthreads();
+
+        if (active) {
+            const unsigned idx = at(z, col);
+            T y2[N + 1];
+#pragma unroll
+            for (int f = 0; f <= N; ++f) y2[f] = (f < N || withc) ? ldv<T, GS, LCP>(A, 1, f, idx) : T(0);
+            // R0 = rhs(u^{n,0}) with the first stage's correction, then the stage
+            T q[N + 1], ys[N + 1], r0[N + 1];
+            rhs_point<T, 3, N, FAST, PS, TXH>(P, lds + (N + 2) * PS, pair, kc, own, cur[1], mu_c[1], mc_c[1],
+                                              prv[1], mu_p[1], mc_p[1], nxt[1], mu_n[1], mc_n[1], q);
+            rkl2_first_point<T, N, FAST>(A.a2, cur[1], q, ys, r0, [](T *) {});
+            T r[N + 1];
+            rhs_point<T, 3, N, FAST, PS, TXH>(P, lds, pair, kc, own, cur[0], mu_c[0], mc_c[0], prv[0], mu_p[0],
+                                              mc_p[0], nxt[0], mu_n[0], mc_n[0], r);
+            double acc = 0.0;
+            long long cnt = 0;
+            cell_combine<T, N, K_RKL2, GS, SCP, FAST>(A, idx, withc, cur[0], r, cur[1], y2, r0, acc, cnt);
+        }
+        __syncthreads();  // plane z of LDS is read; the next plane may overwrite it
+
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int f = 0; f <= N; ++f) {
+                prv[i][f] = cur[i][f];
+                cur[i][f] = nxt[i][f];
+                hcur[i][f] = hnxt[i][f];
+            }
+            mu_p[i] = mu_c[i];
+            mc_p[i] = mc_c[i];
+            mu_c[i] = mu_n[i];
+            mc_c[i] = mc_n[i];
+        }
+    }
+}
 
 // One RKL2 stage value at a 2D cell whose neighbourhood is in an LDS plane
 // tile (N phi planes, mu, Mc; PLANE values apart, rows ROW apart): the same
@@ -1435,6 +1596,12 @@ hipError_t launch_stage_dnw(const StageArgs<T> &A, int nblocks, hipStream_t stre
     case K_RKL2_FIRST: hipLaunchKernelGGL((rkl2_first_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
     case K_RKL2: hipLaunchKernelGGL((rkl2_stage_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
     case K_EST: hipLaunchKernelGGL((estimator_kernel<T, DIM, N, NG, W>), grid, block, 0, stream, A); break;
+    case K_RKL2_RC:
+        if constexpr (DIM == 3 && !W && rkl2_rc_built((int)sizeof(T), N))
+            hipLaunchKernelGGL((rkl2_rc_stage_kernel<T, N, NG>), grid, block, 0, stream, A);
+        else
+            return hipErrorInvalidValue;
+        break;
     case K_RKL2_PAIR:
         if constexpr (DIM == 2 && NG == 1 && !W && rkl2_pair_fits((int)sizeof(T), N))
             hipLaunchKernelGGL((rkl2_pair_kernel<T, N>), grid, dim3(P2_THREADS), 0, stream, A);

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     txt = open(os.path.join(ROOT, "include", "pf.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(pf_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_symbols_exported():

@@ -80,6 +80,10 @@ def test_stage_kernels_do_not_spill(tmp_path):
         batch = [k for k in names if "batch_kernel" in k]
         expect = 8 + sum(_depth2_fits(esz, n) for esz in (4, 8))
         assert len(batch) == (expect if g == 1 else 0), (n, g, batch)
+        # 3D stages that recompute R0: single precision N <= 9, double N <= 4
+        # (two z windows per thread within two waves per SIMD, no scratch)
+        rc = [k for k in names if "rkl2_rc_stage_kernel" in k]
+        assert len(rc) == int(n <= 9) + int(n <= 4), (n, g, rc)
         # fused RKL2 stage pairs: one group, where the LDS fits; 512-thread
         # blocks, two per CU by LDS, so four waves per SIMD need <= 128 VGPRs
         pairs = [k for k in names if "rkl2_pair_kernel" in k]
