@@ -112,17 +112,21 @@ __device__ __forceinline__ void project(T *p) {
 #pragma unroll
         for (int a = 0; a < N; ++a)
             if (p[a] < T(0)) p[a] = T(0);
-        int m = -1;
-        T pm = T(0);
+        // the one-hot where a value reaches 1 goes to the largest value, the
+        // lowest index on ties: that value is the maximum of all of them (a
+        // NaN is skipped by the maximum as by the comparisons of the
+        // reference form), and its first occurrence is the phase
+        T pmax = p[0];
 #pragma unroll
-        for (int a = 0; a < N; ++a)
-            if (p[a] >= T(1) && (m < 0 || p[a] > pm)) {
-                m = a;
-                pm = p[a];
+        for (int a = 1; a < N; ++a) pmax = max_num(pmax, p[a]);
+        if (pmax >= T(1)) {
+            bool found = false;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const bool hit = !found && p[a] == pmax;
+                p[a] = hit ? T(1) : T(0);
+                found = found || hit;
             }
-        if (m >= 0) {
-#pragma unroll
-            for (int a = 0; a < N; ++a) p[a] = (a == m) ? T(1) : T(0);
         }
         T sum = p[0];
 #pragma unroll
@@ -432,6 +436,22 @@ __device__ __forceinline__ void fix_ghost_c(const KConsts<T> &K, int face, bool 
     if (face >= 0 && withc && ((K.cfix >> face) & 1)) v[N] = K.cbc[face];
 }
 
+// Activity of the N phases at a cell: one flag per phase up to 9 phases (each
+// flag stays a lane mask, so a test costs no bit extraction), a bit mask
+// above (that many flags would overflow the scalar registers).
+template <int N, bool FLAGS = (N <= 9)>
+struct PhaseFlags {
+    bool on[N];
+    __device__ __forceinline__ void set(int a, bool v) { on[a] = v; }
+    __device__ __forceinline__ bool operator[](int a) const { return on[a]; }
+};
+template <int N>
+struct PhaseFlags<N, false> {
+    unsigned m = 0u;
+    __device__ __forceinline__ void set(int a, bool v) { m |= (v ? 1u : 0u) << a; }
+    __device__ __forceinline__ bool operator[](int a) const { return (m >> a) & 1u; }
+};
+
 // Right-hand side of eqs. phieq and ceq at one cell (the per-cell part of
 // every stage kind): x/y neighbours from an LDS plane tile holding the N phi
 // planes, then mu, then Mc, PLANE values apart, with rows ROW apart (own: the
@@ -486,11 +506,14 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
             flux = flux + (T(0.5) * (mc_c + mck)) * (muk - mu_c);
         }
     }
-    unsigned act = 0u;
+    PhaseFlags<N> on;
+    int nzc = 0;
 #pragma unroll
-    for (int a = 0; a < N; ++a)
-        if (mx[a] > T(0)) act |= 1u << a;
-    const int nzc = __popc(act);
+    for (int a = 0; a < N; ++a) {
+        const bool v = mx[a] > T(0);
+        on.set(a, v);
+        nzc += v ? 1 : 0;
+    }
 #pragma unroll
     for (int a = 0; a < N; ++a) {
         if constexpr (FAST) lap[a] = fma_t(T(-2 * DIM), cur[a], lap[a]) * idx2;
@@ -534,12 +557,12 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
         for (int a = 0; a < N; ++a) {
             const T s = fma_t(A0, slap - lap[a], B0 * (sp - cur[a])) + psi[a];
             delta[a] = s;
-            if ((act >> a) & 1u) dact += s;
+            if (on[a]) dact += s;
         }
         const T mean = dact * inz;
 #pragma unroll
         for (int a = 0; a < N; ++a)
-            r[a] = (((act >> a) & 1u) && nzc >= 2) ? L0 * (mean - delta[a]) : T(0);
+            r[a] = (on[a] && nzc >= 2) ? L0 * (mean - delta[a]) : T(0);
     } else {
 #pragma unroll
         for (int a = 0; a < N; ++a) {
@@ -558,11 +581,11 @@ __device__ __forceinline__ void rhs_point(const KConsts<T> &P, const T *__restri
 #pragma unroll
         for (int a = 0; a < N; ++a) {
             T ra = T(0);
-            if (((act >> a) & 1u) && nzc >= 2) {
+            if (on[a] && nzc >= 2) {
                 T s = T(0);
 #pragma unroll
                 for (int bb = 0; bb < N; ++bb) {
-                    if (bb == a || !((act >> bb) & 1u)) continue;
+                    if (bb == a || !on[bb]) continue;
                     const T Lab = pair[2 * N * N + a * N + bb];
                     if constexpr (FAST) s = fma_t(Lab, delta[a] - delta[bb], s);
                     else s = s + Lab * (delta[a] - delta[bb]);
