@@ -9,8 +9,8 @@ results must agree bit for bit and be finite (FP64 cases are also held to the
 oracle at 1e-10).  Cases cover every stage kind (FE, SSP(3)2, SSP(10)4, RKL1,
 RKL2 first and inner stages, the estimator), the 64 x 8 and 64 x 4 tiles on
 ragged 2D grids, 3D z chunks that do not divide nz, fused RKL2 stage pairs in
-2D and 3D, two buffer groups, sparse phase storage and the batched kernels at
-both fusion depths."""
+2D and 3D, the 3D stages that recompute R0, two buffer groups, sparse phase
+storage and the batched kernels at both fusion depths."""
 import os
 
 import numpy as np
@@ -151,6 +151,26 @@ def test_fused_stage_pairs_see_no_unwritten_lds(libs, prec, case):
         sim.step("rkl2", dt)
 
     _both(libs, wl, prec, run)
+
+
+@pytest.mark.parametrize("prec,case", [("fp32", "nine3d"), ("fp64", "four3d"), ("fp32", "four3d")])
+def test_r0_recompute_stages_see_no_unwritten_lds(libs, prec, case):
+    """The 3D stages that recompute R0 stage two planes (Y_{j-1} and u0) in LDS."""
+    wl = dict(CASES)[case]()
+    dt = 40.0 * oracle.stable_dt(oracle.Params(**wl.param_dict()))
+
+    def run(sim):
+        sim.set_r0_recompute(True)
+        sim.set_tiling(0, 5)  # z chunks that do not divide nz
+        sim.step("rkl2", dt)
+
+    u = _both(libs, wl, prec, run)
+
+    def stored(sim):
+        sim.set_tiling(0, 5)
+        sim.step("rkl2", dt)
+
+    assert np.array_equal(u, _both(libs, wl, prec, stored))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
