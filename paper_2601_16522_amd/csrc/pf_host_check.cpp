@@ -247,6 +247,9 @@ static void host_section() {
     EXPECT(pf_batch_create(nullptr, 2, &b) == PF_EINVAL && !b, "batch null params");
     EXPECT(pf_batch_create(&m.p, 0, &b) == PF_EINVAL && !b, "batch n 0");
     EXPECT(pf_batch_create(&m.p, -3, &b) == PF_EINVAL && !b, "batch n < 0");
+    int on = -1;
+    EXPECT(pf_set_r0_recompute(nullptr, 1) == PF_EINVAL, "r0 recompute null");
+    EXPECT(pf_get_r0_recompute(nullptr, &on) == PF_EINVAL && on == -1, "r0 recompute get null");
     std::printf("null handles: ok\n");
 }
 
@@ -310,6 +313,29 @@ static void check_handle(int dim, int n, int nphi, int with_c, pf_precision prec
     long long launches = 0;
     EXPECT(pf_get_kernel_time(s, 0, &ms, &launches) == PF_OK && launches > 0, "kernel time");
     EXPECT(pf_set_timing(s, 0) == PF_OK, "timing off");
+    {
+        // R0 recomputed in the 3D inner stages: same bits as the stored R0
+        const bool built = dim == 3 && (prec == PF_FP32 ? nphi <= 9 : nphi <= 4);
+        int on = -1;
+        EXPECT(pf_set_r0_recompute(s, 2) == PF_EINVAL, "r0 recompute 2");
+        EXPECT(pf_get_r0_recompute(s, nullptr) == PF_EINVAL, "r0 recompute get null out");
+        EXPECT(pf_set_r0_recompute(s, 1) == (built ? PF_OK : PF_EUNSUPPORTED), "r0 recompute on");
+        EXPECT(pf_get_r0_recompute(s, &on) == PF_OK && on == (built ? 1 : 0), "r0 recompute get");
+        if (built) {
+            fill_state(m.p, u);
+            EXPECT(pf_init_fields(s, u, nullptr, 0.0) == PF_OK, "rc init");
+            EXPECT(pf_step(s, PF_RKL2, 30 * dte, nullptr) == PF_OK, "rc step");
+            double *u1 = exact<double>((size_t)F * V), *u2 = exact<double>((size_t)F * V);
+            EXPECT(pf_get_fields(s, u1, nullptr, &t) == PF_OK, "rc get");
+            EXPECT(pf_set_r0_recompute(s, 0) == PF_OK, "r0 recompute off");
+            EXPECT(pf_init_fields(s, u, nullptr, 0.0) == PF_OK, "stored init");
+            EXPECT(pf_step(s, PF_RKL2, 30 * dte, nullptr) == PF_OK, "stored step");
+            EXPECT(pf_get_fields(s, u2, nullptr, &t) == PF_OK, "stored get");
+            EXPECT(std::memcmp(u1, u2, sizeof(double) * (size_t)F * V) == 0, "rc equals stored R0");
+            std::free(u1);
+            std::free(u2);
+        }
+    }
     if (nphi <= 8) {
         EXPECT(pf_set_sparse_storage(s, nphi < 4 ? nphi : 4) == PF_OK, "sparse on");
         fill_state(m.p, u);
