@@ -1041,9 +1041,6 @@ PF_STAGE_KERNEL(rkl2_stage_kernel, K_RKL2)
 PF_STAGE_KERNEL(estimator_kernel, K_EST)
 #undef PF_STAGE_KERNEL
 
-#ifndef PF_RC_WAVES
-#define PF_RC_WAVES 2
-#endif
 // One RKL2 stage j >= 2 of a periodic 3D grid (eq. sts) that recomputes R0
 // instead of reading it.  u^{n,0} is read as a second stencil input, staged in
 // LDS beside Y_{j-1}, and at each cell R0 = rhs(u^{n,0}) with the correction
@@ -1053,9 +1050,11 @@ PF_STAGE_KERNEL(estimator_kernel, K_EST)
 // right-hand side per cell.  Every value is computed with the arithmetic of
 // the first-stage kernel that stored R0 and of rkl2_stage_kernel, so the
 // stage gives the same bits as that kernel reading the stored R0.  Dense
-// storage; A.y1 = Y_{j-1}, A.y2 = Y_{j-2}, A.u0 = u^{n,0}, A.out = Y_j.
+// storage; A.y1 = Y_{j-1}, A.y2 = Y_{j-2}, A.u0 = u^{n,0}, A.out = Y_j.  The two
+// z windows need two waves per SIMD (up to 256 VGPRs): at three, 168 VGPRs
+// spill to scratch.
 template <typename T, int N, int NG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF_RC_WAVES, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     rkl2_rc_stage_kernel(const StageArgs<T> A) {
     constexpr bool FAST = std::is_same<T, float>::value;
     constexpr int GS = group_planes(N, NG);
