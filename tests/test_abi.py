@@ -62,3 +62,34 @@ def test_largest_addressable_grid(prec, esz):
             assert rc == -7 and not h.value, (prec, nz, rc)
         else:
             assert rc in (0, -2), (prec, nz, rc)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/pf.h is a C header: a C99 program (-pedantic, warnings as errors)
+    includes it, links libpf.so and calls it without a device."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "c_abi.c"
+    src.write_text('#include "pf.h"\n'
+                   "int main(void) {\n"
+                   "    pf_stats st;\n"
+                   "    pf_controller c;\n"
+                   "    double h = 0.0;\n"
+                   "    int last = 0;\n"
+                   "    (void)st;\n"
+                   "    if (pf_create(0, 0) != PF_EINVAL) return 1;\n"
+                   "    if (pf_controller_init(&c) != PF_OK) return 2;\n"
+                   "    if (pf_clip_step(0.0, 1.0, 0.4, &h, &last) != 1 || h != 0.4 || last) return 3;\n"
+                   "    return 0;\n"
+                   "}\n")
+    lib_dir = os.path.dirname(pf.LIB_PATH)
+    exe = tmp_path / "c_abi"
+    cmd = [gcc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+           str(src), "-L", lib_dir, "-l:libpf.so", f"-Wl,-rpath,{lib_dir}", "-o", str(exe)]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    assert p.returncode == 0, p.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
