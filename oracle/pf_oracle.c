@@ -39,9 +39,10 @@
  *   error norm: pinned where every entry counts (the textbook weighted RMS
  *     norm) and, for the degree-of-freedom rule, by the paper's reason for it
  *     (two phases held in more slots give the norm of a direct two-phase
- *     implementation); the phi filter of the estimate is checked by
- *     hand-worked cases only, parity against the paper unpinned (it prints no
- *     worked example).
+ *     implementation); the phi filter of the estimate by hand-worked cases
+ *     (the paper prints no worked example of it) that fail for a full dt in
+ *     the trial value, an open interval, a filtered c entry, a trial without
+ *     rhs(u^{n+1}) and a trial based on u^{n+1}.
  *   sparse storage rule: hand-worked cells; equal to dense storage bit for
  *     bit while nothing is cut.
  */

@@ -810,6 +810,72 @@ def test_error_norm_filter_and_dof_rule():
     assert e == pytest.approx(math.sqrt(expect_ss / 5), rel=1e-13)
 
 
+def test_error_norm_filter_interval_step_and_fields():
+    """Hand-worked case of the phi filter (Sec. 3.3) on a 3x1 grid whose
+    u^{n+1} is bulk of phase 1 with uniform c (rhs(u^{n+1}) = 0 exactly), dt = 1/2:
+    * cell 0: trials u^n + dt/2 R0 = 0.75 + 0.25 = 1 and 0.25 - 0.25 = 0 exactly,
+      on the closed interval [0, 1], so both entries count (an open interval
+      would drop them);
+    * cell 1: trial 0.5 + 0.25 * 1.5 = 0.875 counts (a full dt in the trial
+      would give 1.25 and drop it); its partner's trial 0.5 - 0.375 counts too;
+    * cell 2: c's trial 0.9 + 0.25 * 2 = 1.4 lies outside [0, 1], but c is never
+      filtered."""
+    P = oracle.Params(nx=3, ny=1, n_phi=2, dx=1.0, W=2.0, with_c=True, c0=[0.5], k=[500.0])
+    unp1 = np.zeros((3, 1, 1, 3))
+    unp1[1] = 1.0
+    unp1[2] = 0.5
+    un = unp1.copy()
+    R0 = np.zeros_like(un)
+    dt = 0.5
+    un[0, 0, 0, 0], un[1, 0, 0, 0] = 0.75, 0.25
+    R0[0, 0, 0, 0], R0[1, 0, 0, 0] = 1.0, -1.0
+    un[0, 0, 0, 1], un[1, 0, 0, 1] = 0.5, 0.5
+    R0[0, 0, 0, 1], R0[1, 0, 0, 1] = 1.5, -1.5
+    un[2, 0, 0, 2] = 0.9
+    R0[2, 0, 0, 2] = 2.0
+    assert np.abs(oracle.rhs(P, unp1)).max() == 0.0
+    tol = oracle.Tol(r_phi=0.1, a_phi=0.01, r_c=0.2, a_c=0.001)
+    e, ndof, ss = oracle.error_norm(P, 0, dt, un, unp1, R0, tol)
+    # (12 (u^n - u^{n+1}) + 6 dt R0) / 15 per entry, weight r max(|u^n|, |u^{n+1}|) + a
+    phi = [(0.75, 0.0, 1.0), (0.25, 1.0, -1.0), (0.5, 0.0, 1.5), (0.5, 1.0, -1.5)]
+    expect_ss = sum(((12 * (a - b) + 6 * dt * r) / 15 / (0.1 * max(a, b) + 0.01)) ** 2 for a, b, r in phi)
+    expect_ss += ((12 * (0.9 - 0.5) + 6 * dt * 2.0) / 15 / (0.2 * 0.9 + 0.001)) ** 2
+    assert ndof == 2 + 2 + 2 + 3       # cells 0 and 1: two phi entries each; cell 2: none -> 2; c: 3
+    assert ss == pytest.approx(expect_ss, rel=1e-13)
+    assert e == pytest.approx(math.sqrt(expect_ss / 9), rel=1e-13)
+
+
+def test_error_norm_filter_trial_includes_the_new_rhs():
+    """The trial value of the phi filter is u^n + dt/2 (R0 + rhs(u^{n+1}))
+    (Sec. 3.3), not u^n + dt/2 R0.  With u^{n+1} = u^n (an interface state whose
+    right-hand side r is large) and R0 = d - r, the correct trial is
+    u^n + dt/2 d, inside [0, 1] for every entry, and every error
+    e = 6 dt (R0 + r)/15 = 6 dt d/15 counts; the trial without the new
+    right-hand side, u^n + dt/2 (d - r), leaves [0, 1] for many entries, which
+    a filter that forgot rhs(u^{n+1}) would zero.  r is the oracle's own
+    right-hand side, pinned by the tests above."""
+    rng = np.random.default_rng(41)
+    nx = 16
+    P = oracle.Params(nx=nx, ny=1, n_phi=2, dx=1.0, W=2.0, with_c=False)
+    un = np.zeros((2, 1, 1, nx))
+    un[0] = rng.uniform(0.3, 0.7, (1, 1, nx))
+    un[1] = 1.0 - un[0]
+    r = oracle.rhs(P, un)
+    dt = 1.0 / np.abs(r[:2]).max()     # dt/2 |r| reaches 1/2 somewhere
+    d = rng.uniform(0.01, 0.1, un.shape) * rng.choice([-1.0, 1.0], un.shape)
+    R0 = d - r
+    wrong_trial = un + dt / 2 * R0
+    assert np.count_nonzero((wrong_trial < 0) | (wrong_trial > 1)) >= 2
+    good_trial = un + dt / 2 * (R0 + r)
+    assert good_trial.min() > 0.2 and good_trial.max() < 0.8
+    tol = oracle.Tol(r_phi=0.0, a_phi=1.0, r_c=0.0, a_c=1.0)
+    e, ndof, ss = oracle.error_norm(P, 0, dt, un, un.copy(), R0, tol)
+    assert ndof == 2 * nx
+    ref = 6 * dt * (R0 + r) / 15
+    assert ss == pytest.approx(float(np.sum(ref * ref)), rel=1e-12)
+    assert ss == pytest.approx(float(np.sum((6 * dt * d / 15) ** 2)), rel=1e-9)
+
+
 def test_error_norm_is_the_weighted_rms_norm_when_every_entry_counts():
     """Special case that reduces to the textbook weighted RMS norm of step
     control: with the embedded estimate e = u^{n+1} - z nonzero in every entry,
