@@ -8,7 +8,9 @@
   FP32-rounded state; then one FP32 RKL2 step at 100 dt_e (21 stages) in the
   autotuned launch shape that bench.py times, checked by properties that hold
   at any size (phi in [0, 1], sum of phi, conservation of c) and by the launch
-  shape changing no bit.
+  shape changing no bit; and one RKL2 step of three stages (first and inner
+  stage kernels in that launch shape) against the oracle at sampled cells,
+  each computed on the cell's periodic window of 7^3 cells.
 * 256^3 grains + pores, adaptive RKL2 to t = 2e-4 in FP64 and FP32: end time,
   simplex, conservation, and the two precisions against each other.
 * The 96-instance batch (FE, 2000 steps each): FP32 in the autotuned launch
@@ -22,6 +24,7 @@ import pytest
 
 import oracle
 import pf_inputs as pi
+from _parity import window, windowed_rkl2_step
 
 pytestmark = pytest.mark.gpu
 
@@ -116,6 +119,56 @@ def _check_rkl2_step_properties(wl):
     assert torch.equal(a, b)
 
 
+def _check_rkl2_three_stages_sampled(wl, prec):
+    """One RKL2 step of three stages (the first stage and two inner stages, the
+    kernels of the measured step) at full size, in the launch shape bench.py
+    times (autotuned, FP32), against the oracle at sampled cells: 400 random
+    cells and 400 cells with two or more phases.  FP64: 1e-10.  FP32 on the
+    FP32-rounded state: 1e-4, except values whose window holds a cell with
+    three or more phases > 0 in the GPU result (activity decisions, reading
+    R1), whose count is reported and bounded."""
+    P = oracle.Params(**wl.param_dict())
+    dte = oracle.stable_dt(P)
+    dt = 2.0 * dte
+    s = oracle.stage_count(2, dt, dte)
+    assert s == 3
+    sim = pf.Sim(wl.param_dict(), prec=prec)
+    sim.init_fields(wl.u0)
+    if prec == "fp32":
+        sim.autotune()
+    st = sim.step("rkl2", dt)
+    assert st.stages == s
+    u, _ = sim.get_fields()
+    sim.close()
+    N = wl.n_phi
+    rng = np.random.default_rng(13)
+    iface = np.flatnonzero((wl.u0[:N] > 0).sum(axis=0).ravel() >= 2)
+    cells = np.unique(np.concatenate([rng.choice(wl.cells, 400, replace=False),
+                                      rng.choice(iface, 400, replace=False)]))
+    u_in = wl.u0 if prec == "fp64" else fp32_rounded(wl.u0)
+    ref = windowed_rkl2_step(wl, u_in, cells, dt, s)
+    got = u.reshape(wl.F, -1)[:, cells].T
+    d = np.abs(got - ref)
+    if wl.with_c:
+        d[:, N] /= max(1.0, float(np.abs(ref[:, N]).max()))
+    if prec == "fp64":
+        print(f"\n{wl.name} FP64 RKL2 s=3 at {cells.size} cells: max {d.max():.3e}", flush=True)
+        assert d.max() <= 1e-10
+        return
+    ug = u[:N]
+    multi = np.zeros(cells.size, bool)
+    for k, cell in enumerate(cells):
+        win = window(ug, wl, int(cell), s)
+        multi[k] = ((win > 0).sum(axis=0) >= 3).any()
+    bad = (d > 1e-4).any(axis=1)
+    print(f"\n{wl.name} FP32 RKL2 s=3 at {cells.size} cells: max {d.max():.3e}, "
+          f"max away from multi-phase windows {d[~multi].max() if (~multi).any() else 0.0:.3e}, "
+          f"cells above 1e-4: {bad.sum()} (all in multi-phase windows: {bool(multi[bad].all())})",
+          flush=True)
+    assert not (bad & ~multi).any()
+    assert bad.sum() <= 0.01 * cells.size and d.max() <= 1e-2
+
+
 @pytest.fixture(scope="module")
 def pores256():
     return pi.grains_pores_3d(n=256, n_grains=12, n_grain_fields=12, n_pores=40, r_range=(4.0, 10.0))
@@ -133,6 +186,11 @@ def test_pores256_rhs_sampled(pores256, prec, tol):
 
 def test_pores256_rkl2_step_properties(pores256):
     _check_rkl2_step_properties(pores256)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pores256_rkl2_three_stages_sampled(pores256, prec):
+    _check_rkl2_three_stages_sampled(pores256, prec)
 
 
 def test_pores256_adaptive_rkl2(pores256):
@@ -177,6 +235,11 @@ def test_gg512_rhs_sampled(gg512, prec, tol):
 
 def test_gg512_rkl2_step_properties(gg512):
     _check_rkl2_step_properties(gg512)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gg512_rkl2_three_stages_sampled(gg512, prec):
+    _check_rkl2_three_stages_sampled(gg512, prec)
 
 
 def test_batch96_full_size():
