@@ -10,7 +10,8 @@
   at any size (phi in [0, 1], sum of phi, conservation of c) and by the launch
   shape changing no bit; and one RKL2 step of three stages (first and inner
   stage kernels in that launch shape) against the oracle at sampled cells,
-  each computed on the cell's periodic window of 7^3 cells.
+  each computed on the cell's periodic window of 7^3 cells; and the measured
+  step itself (21 stages at 100 dt_e) the same way on windows of 43^3 cells.
 * 256^3 grains + pores, adaptive RKL2 to t = 2e-4 in FP64 and FP32: end time,
   simplex, conservation, and the two precisions against each other.
 * The 96-instance batch (FE, 2000 steps each): FP32 in the autotuned launch
@@ -169,6 +170,53 @@ def _check_rkl2_three_stages_sampled(wl, prec):
     assert bad.sum() <= 0.01 * cells.size and d.max() <= 1e-2
 
 
+def _check_rkl2_measured_step_sampled(wl, prec, nsample=30):
+    """The measured step itself, RKL2 at 100 dt_e (21 stages), at full size and
+    in the launch shape bench.py times (autotuned, FP32), against the oracle's
+    step on each sampled cell's periodic 43^3 window (radius 21, the step's
+    reach): nsample random cells and nsample cells with two or more phases.
+    FP64: 1e-10.  FP32 on the FP32-rounded state: values above 1e-4 only in
+    windows that hold a cell with three or more phases > 0 (reading R1), at
+    most 1% of the sampled cells, max 1e-2."""
+    P = oracle.Params(**wl.param_dict())
+    dte = oracle.stable_dt(P)
+    dt = 100.0 * dte
+    s = oracle.stage_count(2, dt, dte)
+    assert s == 21
+    sim = pf.Sim(wl.param_dict(), prec=prec)
+    sim.init_fields(wl.u0)
+    if prec == "fp32":
+        sim.autotune()
+    st = sim.step("rkl2", dt)
+    assert st.stages == s
+    u, _ = sim.get_fields()
+    sim.close()
+    N = wl.n_phi
+    rng = np.random.default_rng(17)
+    iface = np.flatnonzero((wl.u0[:N] > 0).sum(axis=0).ravel() >= 2)
+    cells = np.unique(np.concatenate([rng.choice(wl.cells, nsample, replace=False),
+                                      rng.choice(iface, nsample, replace=False)]))
+    u_in = wl.u0 if prec == "fp64" else fp32_rounded(wl.u0)
+    ref = windowed_rkl2_step(wl, u_in, cells, dt, s)
+    got = u.reshape(wl.F, -1)[:, cells].T
+    d = np.abs(got - ref)
+    if wl.with_c:
+        d[:, N] /= max(1.0, float(np.abs(ref[:, N]).max()))
+    if prec == "fp64":
+        print(f"\n{wl.name} FP64 RKL2 at 100 dt_e (s=21) at {cells.size} cells: max {d.max():.3e}",
+              flush=True)
+        assert d.max() <= 1e-10
+        return
+    ug = u[:N]
+    multi = np.array([((window(ug, wl, int(c), s) > 0).sum(axis=0) >= 3).any() for c in cells])
+    bad = (d > 1e-4).any(axis=1)
+    print(f"\n{wl.name} FP32 RKL2 at 100 dt_e (s=21) at {cells.size} cells: max {d.max():.3e}, "
+          f"RMS {math.sqrt(float((d ** 2).mean())):.3e}, cells above 1e-4: {bad.sum()}, "
+          f"windows without a multi-phase cell: {(~multi).sum()}", flush=True)
+    assert not (bad & ~multi).any()
+    assert bad.sum() <= 0.01 * cells.size and d.max() <= 1e-2
+
+
 @pytest.fixture(scope="module")
 def pores256():
     return pi.grains_pores_3d(n=256, n_grains=12, n_grain_fields=12, n_pores=40, r_range=(4.0, 10.0))
@@ -191,6 +239,11 @@ def test_pores256_rkl2_step_properties(pores256):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_pores256_rkl2_three_stages_sampled(pores256, prec):
     _check_rkl2_three_stages_sampled(pores256, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pores256_rkl2_measured_step_sampled(pores256, prec):
+    _check_rkl2_measured_step_sampled(pores256, prec)
 
 
 def test_pores256_adaptive_rkl2(pores256):
@@ -240,6 +293,11 @@ def test_gg512_rkl2_step_properties(gg512):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_gg512_rkl2_three_stages_sampled(gg512, prec):
     _check_rkl2_three_stages_sampled(gg512, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gg512_rkl2_measured_step_sampled(gg512, prec):
+    _check_rkl2_measured_step_sampled(gg512, prec)
 
 
 def test_batch96_full_size():
