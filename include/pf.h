@@ -300,7 +300,7 @@ pf_status pf_autotune(pf_sim *sim, int *tx, int *zchunk, double *best_ms);
  * groups than the grid needs address the same planes and give the same result
  * bits.  Errors: PF_EINVAL for other values or fewer groups than the grid
  * needs; PF_EUNSUPPORTED for more than one group on a grid with walls.
- * Fused RKL2 stage pairs (below) run only with one group.
+ * In 2D, fused RKL2 stage pairs (below) run only with one group.
  * pf_get_field_groups reports the count the kernels use. */
 pf_status pf_set_field_groups(pf_sim *sim, int ng);
 pf_status pf_get_field_groups(const pf_sim *sim, int *ng);
