@@ -93,18 +93,18 @@ def window(u, wl, cell, s):
     return u[np.ix_(np.arange(u.shape[0]), (z + off) % wl.nz, (y + off) % wl.ny, (x + off) % wl.nx)]
 
 
-def windowed_rkl2_step(wl, u, cells, dt, s, radius=None):
-    """The oracle's RKL2 step of s stages at each of `cells`, computed on the
-    cell's periodic window of (2 radius + 1)^3 cells (radius s by default):
-    after s stages a cell depends only on cells at most s stencil steps away
-    (every stage reads the six neighbours, and a fixed step has no global
-    coupling), so with radius s the window's centre equals the cell's value in
-    a step of the whole grid."""
+def windowed_step(wl, u, cells, dt, s, radius=None, integ=oracle.RKL2):
+    """The oracle's step of s stages (RKL2 unless integ says otherwise) at each
+    of `cells`, computed on the cell's periodic window of (2 radius + 1)^3
+    cells (radius s by default): after s stages a cell depends only on cells
+    at most s stencil steps away (every stage reads the six neighbours, and a
+    fixed step has no global coupling), so with radius s the window's centre
+    equals the cell's value in a step of the whole grid."""
     h = s if radius is None else radius
     w = 2 * h + 1
     P = oracle.Params(**dict(wl.param_dict(), nx=w, ny=w, nz=w))
     out = np.empty((len(cells), wl.F))
     for k, cell in enumerate(cells):
-        ref, _, _ = oracle.step(P, oracle.RKL2, dt, window(u, wl, int(cell), h), s=s)
+        ref, _, _ = oracle.step(P, integ, dt, window(u, wl, int(cell), h), s=s)
         out[k] = ref[:, h, h, h]
     return out

@@ -11,7 +11,9 @@
   shape changing no bit; and one RKL2 step of three stages (first and inner
   stage kernels in that launch shape) against the oracle at sampled cells,
   each computed on the cell's periodic window of 7^3 cells; and the measured
-  step itself (21 stages at 100 dt_e) the same way on windows of 43^3 cells.
+  steps themselves the same way (RKL2, 21 stages at 100 dt_e, on windows of
+  43^3 cells; on 512^3 also RKL1, and RKL2 with fused stage pairs and with
+  the recomputed R0).
 * 256^3 grains + pores, adaptive RKL2 to t = 2e-4 in FP64 and FP32: end time,
   simplex, conservation, and the two precisions against each other.
 * The 96-instance batch (FE, 2000 steps each): FP32 in the autotuned launch
@@ -25,7 +27,7 @@ import pytest
 
 import oracle
 import pf_inputs as pi
-from _parity import window, windowed_rkl2_step
+from _parity import window, windowed_step
 
 pytestmark = pytest.mark.gpu
 
@@ -147,7 +149,7 @@ def _check_rkl2_three_stages_sampled(wl, prec):
     cells = np.unique(np.concatenate([rng.choice(wl.cells, 400, replace=False),
                                       rng.choice(iface, 400, replace=False)]))
     u_in = wl.u0 if prec == "fp64" else fp32_rounded(wl.u0)
-    ref = windowed_rkl2_step(wl, u_in, cells, dt, s)
+    ref = windowed_step(wl, u_in, cells, dt, s)
     got = u.reshape(wl.F, -1)[:, cells].T
     d = np.abs(got - ref)
     if wl.with_c:
@@ -170,24 +172,30 @@ def _check_rkl2_three_stages_sampled(wl, prec):
     assert bad.sum() <= 0.01 * cells.size and d.max() <= 1e-2
 
 
-def _check_rkl2_measured_step_sampled(wl, prec, nsample=30):
-    """The measured step itself, RKL2 at 100 dt_e (21 stages), at full size and
-    in the launch shape bench.py times (autotuned, FP32), against the oracle's
-    step on each sampled cell's periodic 43^3 window (radius 21, the step's
-    reach): nsample random cells and nsample cells with two or more phases.
-    FP64: 1e-10.  FP32 on the FP32-rounded state: values above 1e-4 only in
-    windows that hold a cell with three or more phases > 0 (reading R1), at
-    most 1% of the sampled cells, max 1e-2."""
+def _check_measured_step_sampled(wl, prec, integ="rkl2", mode=None, nsample=30):
+    """A measured step, RKL2 (21 stages) or RKL1 (15 stages) at 100 dt_e, at
+    full size and in the launch shape bench.py times (autotuned, FP32; mode
+    "pairs" or "r0rc" then turns on fused stage pairs or the recomputed R0),
+    against the oracle's step on each sampled cell's periodic window of radius
+    s (the step's reach): nsample random cells and nsample cells with two or
+    more phases.  FP64: 1e-10.  FP32 on the FP32-rounded state: values above
+    1e-4 only in windows that hold a cell with three or more phases > 0
+    (reading R1), at most 1% of the sampled cells, max 1e-2."""
     P = oracle.Params(**wl.param_dict())
     dte = oracle.stable_dt(P)
     dt = 100.0 * dte
-    s = oracle.stage_count(2, dt, dte)
-    assert s == 21
+    order = 2 if integ == "rkl2" else 1
+    s = oracle.stage_count(order, dt, dte)
+    assert s == (21 if order == 2 else 15)
     sim = pf.Sim(wl.param_dict(), prec=prec)
     sim.init_fields(wl.u0)
     if prec == "fp32":
         sim.autotune()
-    st = sim.step("rkl2", dt)
+    if mode == "pairs":
+        sim.set_stage_fusion(2)
+    elif mode == "r0rc":
+        sim.set_r0_recompute(True)
+    st = sim.step(integ, dt)
     assert st.stages == s
     u, _ = sim.get_fields()
     sim.close()
@@ -197,20 +205,20 @@ def _check_rkl2_measured_step_sampled(wl, prec, nsample=30):
     cells = np.unique(np.concatenate([rng.choice(wl.cells, nsample, replace=False),
                                       rng.choice(iface, nsample, replace=False)]))
     u_in = wl.u0 if prec == "fp64" else fp32_rounded(wl.u0)
-    ref = windowed_rkl2_step(wl, u_in, cells, dt, s)
+    ref = windowed_step(wl, u_in, cells, dt, s, integ=oracle.RKL2 if order == 2 else oracle.RKL1)
     got = u.reshape(wl.F, -1)[:, cells].T
     d = np.abs(got - ref)
     if wl.with_c:
         d[:, N] /= max(1.0, float(np.abs(ref[:, N]).max()))
+    what = f"{wl.name} {prec.upper()} {integ.upper()}{'' if mode is None else ' ' + mode} at 100 dt_e (s={s})"
     if prec == "fp64":
-        print(f"\n{wl.name} FP64 RKL2 at 100 dt_e (s=21) at {cells.size} cells: max {d.max():.3e}",
-              flush=True)
+        print(f"\n{what} at {cells.size} cells: max {d.max():.3e}", flush=True)
         assert d.max() <= 1e-10
         return
     ug = u[:N]
     multi = np.array([((window(ug, wl, int(c), s) > 0).sum(axis=0) >= 3).any() for c in cells])
     bad = (d > 1e-4).any(axis=1)
-    print(f"\n{wl.name} FP32 RKL2 at 100 dt_e (s=21) at {cells.size} cells: max {d.max():.3e}, "
+    print(f"\n{what} at {cells.size} cells: max {d.max():.3e}, "
           f"RMS {math.sqrt(float((d ** 2).mean())):.3e}, cells above 1e-4: {bad.sum()}, "
           f"windows without a multi-phase cell: {(~multi).sum()}", flush=True)
     assert not (bad & ~multi).any()
@@ -243,7 +251,7 @@ def test_pores256_rkl2_three_stages_sampled(pores256, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_pores256_rkl2_measured_step_sampled(pores256, prec):
-    _check_rkl2_measured_step_sampled(pores256, prec)
+    _check_measured_step_sampled(pores256, prec)
 
 
 def test_pores256_adaptive_rkl2(pores256):
@@ -297,7 +305,17 @@ def test_gg512_rkl2_three_stages_sampled(gg512, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_gg512_rkl2_measured_step_sampled(gg512, prec):
-    _check_rkl2_measured_step_sampled(gg512, prec)
+    _check_measured_step_sampled(gg512, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gg512_rkl1_measured_step_sampled(gg512, prec):
+    _check_measured_step_sampled(gg512, prec, integ="rkl1")
+
+
+@pytest.mark.parametrize("mode", ["pairs", "r0rc"])
+def test_gg512_rkl2_stage_modes_sampled(gg512, mode):
+    _check_measured_step_sampled(gg512, "fp32", mode=mode)
 
 
 def test_batch96_full_size():

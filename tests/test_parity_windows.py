@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import pf_inputs as pi
-from _parity import windowed_rkl2_step
+from _parity import windowed_step
 
 
 @pytest.mark.parametrize("nphi", [4, 9])
@@ -27,8 +27,8 @@ def test_windowed_step_equals_whole_grid_step(nphi):
     iface = np.flatnonzero((wl.u0[:nphi] > 0).sum(axis=0).ravel() >= 3)
     cells = np.unique(np.concatenate([rng.choice(wl.cells, 120, replace=False),
                                       rng.choice(iface, min(120, iface.size), replace=False)]))
-    got = windowed_rkl2_step(wl, wl.u0, cells, dt, s)
+    got = windowed_step(wl, wl.u0, cells, dt, s)
     ref = full.reshape(wl.F, -1)[:, cells].T
     assert np.array_equal(got, ref)
     # a window one cell narrower misses part of the dependence
-    assert not np.array_equal(windowed_rkl2_step(wl, wl.u0, cells, dt, s, radius=s - 1), ref)
+    assert not np.array_equal(windowed_step(wl, wl.u0, cells, dt, s, radius=s - 1), ref)
