@@ -93,16 +93,17 @@ def window(u, wl, cell, s):
     return u[np.ix_(np.arange(u.shape[0]), (z + off) % wl.nz, (y + off) % wl.ny, (x + off) % wl.nx)]
 
 
-def windowed_step(wl, u, cells, dt, s, radius=None, integ=oracle.RKL2):
+def windowed_step(wl, u, cells, dt, s, radius=None, integ=oracle.RKL2, extra=None):
     """The oracle's step of s stages (RKL2 unless integ says otherwise) at each
     of `cells`, computed on the cell's periodic window of (2 radius + 1)^3
     cells (radius s by default): after s stages a cell depends only on cells
     at most s stencil steps away (every stage reads the six neighbours, and a
     fixed step has no global coupling), so with radius s the window's centre
-    equals the cell's value in a step of the whole grid."""
+    equals the cell's value in a step of the whole grid.  extra: further
+    oracle parameters (n_p for sparse storage)."""
     h = s if radius is None else radius
     w = 2 * h + 1
-    P = oracle.Params(**dict(wl.param_dict(), nx=w, ny=w, nz=w))
+    P = oracle.Params(**dict(wl.param_dict(), nx=w, ny=w, nz=w, **(extra or {})))
     out = np.empty((len(cells), wl.F))
     for k, cell in enumerate(cells):
         ref, _, _ = oracle.step(P, integ, dt, window(u, wl, int(cell), h), s=s)

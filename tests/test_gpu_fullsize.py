@@ -187,9 +187,12 @@ def _check_measured_step_sampled(wl, prec, integ="rkl2", mode=None, nsample=30):
     order = 2 if integ == "rkl2" else 1
     s = oracle.stage_count(order, dt, dte)
     assert s == (21 if order == 2 else 15)
+    n_p = 4 if mode == "sparse4" else 0
     sim = pf.Sim(wl.param_dict(), prec=prec)
+    if n_p:
+        sim.set_sparse_storage(n_p)     # as bench.py --sparse: default launch shape
     sim.init_fields(wl.u0)
-    if prec == "fp32":
+    if prec == "fp32" and not n_p:
         sim.autotune()
     if mode == "pairs":
         sim.set_stage_fusion(2)
@@ -198,14 +201,23 @@ def _check_measured_step_sampled(wl, prec, integ="rkl2", mode=None, nsample=30):
     st = sim.step(integ, dt)
     assert st.stages == s
     u, _ = sim.get_fields()
+    cuts = sim.sparse_cuts() if n_p else 0
     sim.close()
     N = wl.n_phi
-    rng = np.random.default_rng(17)
-    iface = np.flatnonzero((wl.u0[:N] > 0).sum(axis=0).ravel() >= 2)
-    cells = np.unique(np.concatenate([rng.choice(wl.cells, nsample, replace=False),
-                                      rng.choice(iface, nsample, replace=False)]))
     u_in = wl.u0 if prec == "fp64" else fp32_rounded(wl.u0)
-    ref = windowed_step(wl, u_in, cells, dt, s, integ=oracle.RKL2 if order == 2 else oracle.RKL1)
+    rng = np.random.default_rng(17)
+    nz_in = (u_in[:N] > 0).sum(axis=0)
+    iface = np.flatnonzero(nz_in.ravel() >= 2)
+    pool = [rng.choice(wl.cells, 4 * nsample, replace=False), rng.choice(iface, 4 * nsample, replace=False)]
+    if n_p:
+        # storing the initial state cuts its cells with more than n_p nonzero
+        # phases (the oracle starts from the uncut state): only windows free
+        # of such cells are compared
+        pool = [c[[(window(nz_in[None], wl, int(x), s) <= n_p).all() for x in c]] for c in pool]
+    cells = np.unique(np.concatenate([c[:nsample] for c in pool]))
+    assert cells.size >= nsample
+    ref = windowed_step(wl, u_in, cells, dt, s, integ=oracle.RKL2 if order == 2 else oracle.RKL1,
+                        extra={"n_p": n_p} if n_p else None)
     got = u.reshape(wl.F, -1)[:, cells].T
     d = np.abs(got - ref)
     if wl.with_c:
@@ -220,7 +232,8 @@ def _check_measured_step_sampled(wl, prec, integ="rkl2", mode=None, nsample=30):
     bad = (d > 1e-4).any(axis=1)
     print(f"\n{what} at {cells.size} cells: max {d.max():.3e}, "
           f"RMS {math.sqrt(float((d ** 2).mean())):.3e}, cells above 1e-4: {bad.sum()}, "
-          f"windows without a multi-phase cell: {(~multi).sum()}", flush=True)
+          f"windows without a multi-phase cell: {(~multi).sum()}"
+          + (f"; {cuts} cells cut by sparse storage on the whole grid" if n_p else ""), flush=True)
     assert not (bad & ~multi).any()
     assert bad.sum() <= 0.01 * cells.size and d.max() <= 1e-2
 
@@ -313,7 +326,7 @@ def test_gg512_rkl1_measured_step_sampled(gg512, prec):
     _check_measured_step_sampled(gg512, prec, integ="rkl1")
 
 
-@pytest.mark.parametrize("mode", ["pairs", "r0rc"])
+@pytest.mark.parametrize("mode", ["pairs", "r0rc", "sparse4"])
 def test_gg512_rkl2_stage_modes_sampled(gg512, mode):
     _check_measured_step_sampled(gg512, "fp32", mode=mode)
 
