@@ -129,7 +129,9 @@ pf_status pf_create(const pf_params *p, pf_sim **out);
 pf_status pf_destroy(pf_sim *sim);
 
 /* Use this HIP stream (hipStream_t) for every launch and copy of the handle;
- * NULL selects the null stream.  The stream must outlive its use. */
+ * NULL selects the null stream.  The stream must outlive its use.  On a change
+ * of stream the call first waits for the handle's work on the previous stream,
+ * so the two streams need not be ordered (PF_EHIP if that wait fails). */
 pf_status pf_set_stream(pf_sim *sim, void *hip_stream);
 
 /* Set the state from host doubles [F*V] (c may be NULL when with_c = 0, else
@@ -394,7 +396,8 @@ typedef struct pf_batch pf_batch;
 pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out);
 pf_status pf_batch_destroy(pf_batch *b);
 /* A non-null HIP stream for the batch's launches (graph capture needs one; by
- * default the batch owns a stream of its own). */
+ * default the batch owns a stream of its own).  On a change of stream the call
+ * first waits for the batch's work on the previous stream. */
 pf_status pf_batch_set_stream(pf_batch *b, void *hip_stream);
 /* Instance i's state from host doubles [F*V_i] and its time. */
 pf_status pf_batch_init_fields(pf_batch *b, int i, const double *u, double t0);

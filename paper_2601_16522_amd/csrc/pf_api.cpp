@@ -1237,7 +1237,12 @@ pf_status pf_destroy(pf_sim *s) {
 pf_status pf_set_stream(pf_sim *s, void *stream) {
     if (!s) return PF_EINVAL;
     collect_timing(s);
-    s->stream = (hipStream_t)stream;
+    const hipStream_t next = (hipStream_t)stream;
+    // the handle's work queued on the previous stream ends before any of its
+    // work on the next one starts (the two streams need not be ordered)
+    if (next != s->stream && hipStreamSynchronize(s->stream) != hipSuccess)
+        return fail(s, PF_EHIP, "hipStreamSynchronize of the previous stream failed");
+    s->stream = next;
     return PF_OK;
 }
 
@@ -2488,8 +2493,11 @@ pf_status pf_batch_create(const pf_params *per_inst, int n, pf_batch **out) {
 
 pf_status pf_batch_set_stream(pf_batch *b, void *stream) {
     if (!b || !stream) return PF_EINVAL;  // graph capture needs a real stream
+    // the batch's work queued on the previous stream ends before any of its
+    // work on the next one starts
+    if ((hipStream_t)stream != b->stream && hipStreamSynchronize(b->stream) != hipSuccess)
+        return bfail(b, PF_EHIP, "hipStreamSynchronize of the previous stream failed");
     if (b->own_stream) {
-        hipStreamSynchronize(b->stream);
         hipStreamDestroy(b->stream);
         b->own_stream = false;
     }
