@@ -12,8 +12,8 @@
   stage kernels in that launch shape) against the oracle at sampled cells,
   each computed on the cell's periodic window of 7^3 cells; and the measured
   steps themselves the same way (RKL2, 21 stages at 100 dt_e, on windows of
-  43^3 cells; on 512^3 also RKL1, and RKL2 with fused stage pairs and with
-  the recomputed R0).
+  43^3 cells; on 512^3 also RKL1, and RKL2 with fused stage pairs, with
+  the recomputed R0 and in sparse storage with n_p = 4).
 * 1024^2 Voronoi workload (eight fields), the adaptive RKL2 solve that
   bench.py times, against the oracle's solve on the whole grid.
 * 256^3 grains + pores, adaptive RKL2 to t = 2e-4 in FP64 and FP32: end time,
